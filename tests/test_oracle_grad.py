@@ -1,0 +1,163 @@
+"""Pins of the oracle's backward (gradients of L = <upstream, outputs>).
+
+  * central finite differences of the FP64 forward on random parameters
+    (picks whose step crosses a decision -- hit, clamp, stop, Top-K set,
+    order -- are rejected and counted);
+  * torch float64 autograd of a separate transcription of the forward that
+    intersects rays with the surfel plane instead of solving the homography;
+  * linearity: with a one-hot upstream gradient, the colour and feature
+    gradients are the blend weights themselves.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2604_10982_amd.scenes import Scene, pinhole, uniform_box, upstream
+
+GROUPS = ("means", "scales", "quats", "opacity", "rgb", "feat")
+
+
+def small_scene(n=150, c=6, seed=4):
+    sc = uniform_box(n, c, seed=seed, xy=1.0, z=(2.0, 5.0), scale_mu=np.log(0.12), scale_sigma=0.4)
+    return sc, pinhole(48, 40, f=48.0)
+
+
+def _loss(orc, sc, cam, g, K, blend, pix):
+    r = orc.render(sc, cam, K, blend, pix=pix)
+    gi = {k: g[k].reshape(cam.width * cam.height, -1)[pix] for k in g}
+    return sum(float((r[k].reshape(len(pix), -1) * gi[k]).sum()) for k in gi)
+
+
+@pytest.mark.parametrize("blend", [0, 1])
+def test_finite_differences(orc, blend):
+    sc, cam = small_scene()
+    K = 3
+    g = upstream(cam.height, cam.width, sc.c, seed=1)
+    grads = orc.backward(sc, cam, g, K=K, blend=blend)
+    rng = np.random.default_rng(2)
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    px, py = xs.ravel() + 0.5, ys.ravel() + 0.5
+    rho_all, _ = orc.eval_points(sc, cam, px, py)
+    active = np.nonzero((rho_all <= 9.0).sum(1) > 3)[0]
+    done = rejected = 0
+    errs = []
+    while done < 32 and rejected < 200:
+        grp = GROUPS[rng.integers(len(GROUPS))]
+        i = int(rng.choice(active))
+        arr = getattr(sc, grp)
+        j = int(rng.integers(arr.shape[1])) if arr.ndim == 2 else None
+        theta = float(arr[i, j] if j is not None else arr[i])
+        h = 2e-5 * max(abs(theta), 0.05)
+        pix = np.nonzero(rho_all[i] <= 9.5)[0]
+        vals = []
+        sigs = []
+        for sgn in (+1, -1):
+            s2 = sc.copy()
+            a2 = getattr(s2, grp)
+            v = np.float32(theta + sgn * h)
+            if j is not None:
+                a2[i, j] = v
+            else:
+                a2[i] = v
+            vals.append((float(v), _loss(orc, s2, cam, g, K, blend, pix)))
+            sigs.append(orc.decisions(s2, cam, pix, K=K, blend=blend))
+        if not np.array_equal(sigs[0], sigs[1]):
+            rejected += 1
+            continue
+        fd = (vals[0][1] - vals[1][1]) / (vals[0][0] - vals[1][0])
+        an = grads[grp][i, j] if j is not None else grads[grp][i]
+        scale = max(abs(an), 1e-2 * np.sqrt(np.mean(grads[grp] ** 2)))
+        errs.append(abs(fd - an) / scale)
+        done += 1
+    assert done == 32, (done, rejected)
+    assert max(errs) < 1e-4, sorted(errs)[-5:]
+
+
+def _torch_render(sc, cam, ks, K, blend, g):
+    """Forward of the same model written with ray-plane intersections, in
+    torch float64; decisions (visibility, orientation flip, order, stop,
+    Top-K set) are taken from values, so autograd differentiates the rest."""
+    dt = torch.float64
+    P = {k: torch.tensor(getattr(sc, k), dtype=dt, requires_grad=True) for k in GROUPS}
+    vis = np.nonzero(ks["cull"] == 0)[0]
+    order = vis[np.lexsort((vis, ks["depth_bits"][vis]))]
+    H, W = cam.height, cam.width
+    ys, xs = np.mgrid[0:H, 0:W]
+    d = torch.tensor(np.stack([(xs.ravel() + 0.5 - cam.cx) / cam.fx,
+                               (ys.ravel() + 0.5 - cam.cy) / cam.fy, np.ones(H * W)], -1), dtype=dt)
+    S = H * W
+    T = torch.ones(S, dtype=dt)
+    alive = torch.ones(S, dtype=torch.bool)
+    rgb = torch.zeros(S, 3, dtype=dt)
+    dep = torch.zeros(S, dtype=dt)
+    nor = torch.zeros(S, 3, dtype=dt)
+    ws = []
+    for i in order:
+        q = P["quats"][i] / torch.linalg.norm(P["quats"][i])
+        w, x, y, z = q
+        tu = torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y + w * z), 2 * (x * z - w * y)])
+        tv = torch.stack([2 * (x * y - w * z), 1 - 2 * (x * x + z * z), 2 * (y * z + w * x)])
+        n = torch.stack([2 * (x * z + w * y), 2 * (y * z - w * x), 1 - 2 * (x * x + y * y)])
+        mu = P["means"][i]
+        t = (mu @ n) / (d @ n)
+        X = d * t[:, None]
+        u = ((X - mu) @ tu) / P["scales"][i, 0]
+        v = ((X - mu) @ tv) / P["scales"][i, 1]
+        rho = u * u + v * v
+        a = torch.clamp(P["opacity"][i] * torch.exp(-0.5 * rho), max=0.99)
+        c = (rho <= 9.0) & (a >= 1 / 255) & alive
+        Tn = T * (1 - a)
+        stop = c & (Tn < 1e-4)
+        alive = alive & ~stop
+        c = c & ~stop
+        wgt = torch.where(c, a * T, torch.zeros_like(T))
+        nc = -n if ks["flip"][i] else n
+        rgb = rgb + wgt[:, None] * P["rgb"][i]
+        dep = dep + wgt * X[:, 2]
+        nor = nor + wgt[:, None] * nc
+        T = torch.where(c, Tn, T)
+        ws.append(wgt)
+    Wm = torch.stack(ws, 0)                                    # (n_vis, S)
+    if blend == 1:
+        kk = min(K, Wm.shape[0])
+        idx = torch.topk(Wm.detach(), kk, dim=0).indices
+        mask = torch.zeros_like(Wm, dtype=torch.bool).scatter_(0, idx, True)
+        Wm = torch.where(mask, Wm, torch.zeros_like(Wm))
+    feat = Wm.T @ P["feat"][torch.tensor(order)]
+    out = {"rgb": rgb, "depth": dep, "normal": nor, "alpha": 1 - T, "feat": feat}
+    L = sum((out[k].reshape(S, -1) * torch.tensor(g[k].reshape(S, -1), dtype=dt)).sum() for k in out)
+    L.backward()
+    return {k: P[k].grad.numpy() for k in GROUPS}
+
+
+@pytest.mark.parametrize("blend", [0, 1])
+def test_matches_torch_autograd_transcription(orc, blend):
+    sc, cam = small_scene(n=40, c=4, seed=9)
+    cam = pinhole(32, 28, f=32.0)
+    K = 2
+    g = upstream(cam.height, cam.width, sc.c, seed=1)
+    ks = orc.keystage(sc, cam, pairs=False)
+    ref = _torch_render(sc, cam, ks, K, blend, g)
+    got = orc.backward(sc, cam, g, K=K, blend=blend)
+    for k in GROUPS:
+        scale = np.abs(ref[k]).max()
+        assert scale > 0, k
+        np.testing.assert_allclose(got[k], ref[k], rtol=1e-8, atol=1e-10 * scale, err_msg=k)
+
+
+def test_one_hot_upstream_gives_blend_weights(orc):
+    sc, cam = small_scene(n=60, c=60, seed=6)
+    sc.feat[:] = np.eye(60, dtype=np.float32)
+    full = orc.render(sc, cam, 3, blend=0)
+    topk = orc.render(sc, cam, 3, blend=1)
+    rng = np.random.default_rng(0)
+    busy = np.argwhere(full["ncontrib"] >= 4)
+    for py, px in busy[rng.choice(len(busy), 5, replace=False)]:
+        g = {k: np.zeros_like(v) for k, v in upstream(cam.height, cam.width, sc.c).items()}
+        g["rgb"][py, px, 1] = 1.0
+        g["feat"][py, px, 7] = 1.0
+        d = orc.backward(sc, cam, g, K=3, blend=1)
+        np.testing.assert_allclose(d["rgb"][:, 1], full["feat"][py, px], rtol=0, atol=1e-15)
+        np.testing.assert_allclose(d["feat"][:, 7], topk["feat"][py, px], rtol=0, atol=1e-15)
+        np.testing.assert_array_equal(np.delete(d["feat"], 7, axis=1), 0.0)
+        np.testing.assert_array_equal(d["rgb"][:, 0], 0.0)

@@ -1,0 +1,287 @@
+#!/usr/bin/env python3
+"""Benchmark of the rendering hot path on one MI355X.
+
+One step = forward + backward of the whole path (preprocess, depth sort,
+count scan, key emission, pair sort, tile ranges, forward walk with Top-K
+heap, Top-K feature blend, feature backward, backward walk, preprocess
+backward) over one 1920x1080 frame of a 1M-surfel plane-structured scene with
+128-d FP32 features, K = 16, exact-ellipse tile lists.  Inputs are synthetic
+(seeded) and already resident in HBM; workspaces and outputs are allocated
+before the timed region.
+
+Prints ONE JSON line.  `value` is fwd+bwd it/s of the Top-K + precise-tile
+form; the same line carries the forward FPS, the dense-blend + AABB form on
+the same GPU (the factor the paper's Sec. 5 is about), the Table-3-style
+ablation, per-stage times from HIP events on the render stream, the roofline
+of the dominant kernel and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd FPS & fwd+bwd it/s, 1080p, 1M surfels, 128-d feat, Top-K vs full blend"
+WORKLOAD = "planes1m_1080p"
+
+# MI355X published peaks (dense; no sparsity)
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, unpacked FP32 FMA
+
+# Algorithmic work per unit (derivations in DESIGN.md, "Roofline")
+FLOP_PER_EVAL = 17.0       # forward walk: one pixel x list-entry test
+FLOP_PER_CONTRIB = 26.0    # forward walk: alpha, transmittance, dense blend, heap test
+BWD_FLOP_PER_EVAL = 17.0
+BWD_FLOP_PER_CONTRIB = 70.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--cpu-tiles", type=int, default=96)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
+    return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of known size: rocprofv3 --pmc FETCH_SIZE /
+    WRITE_SIZE on this run gives the counters' scale for 1 GiB read + 1 GiB written."""
+    import torch
+    n = 1 << 28  # 2^28 float32 = 1 GiB
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 4 * n, "launches": 3}), flush=True)
+
+
+class Form:
+    """One (tile mode, blend) configuration with preallocated buffers."""
+
+    def __init__(self, psm, t, cam, K, tile_mode, blend, gout, device):
+        import torch
+        self.psm, self.t, self.K = psm, t, K
+        self.tile_mode, self.blend = tile_mode, blend
+        self.cam = psm.camera_struct(cam)
+        self.cfg = psm.config_struct(K, tile_mode, blend, psm.FLAG_NO_SYNC | psm.FLAG_PROFILE)
+        self.s = psm._surfels(t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"])
+        _, ws = psm.forward(t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"], self.cam, K,
+                            tile_mode, blend)
+        st = psm.read_stats(ws, self.s.n, self.cam, psm.config_struct(K, tile_mode, blend), self.s.c, ws.capacity)
+        cap = int(st.pairs_required * 1.05 + 4096)
+        self.ws = psm.alloc_workspace(self.s.n, self.cam, self.cfg, self.s.c, cap, device)
+        self.out = psm.alloc_images(self.cam, self.s.c, device)
+        n, c = self.s.n, self.s.c
+        z = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=device)
+        self.grads = {"means": z(n, 3), "scales": z(n, 2), "quats": z(n, 4), "opacity": z(n), "rgb": z(n, 3),
+                      "feat": z(n, c)}
+        self.gout = gout
+        self.ctx = psm.context(device.index or 0)
+
+    def step(self, bwd: bool):
+        self.psm.forward_into(self.ctx, self.s, self.cam, self.cfg, self.ws, self.out)
+        if bwd:
+            self.psm.backward_into(self.ctx, self.s, self.cam, self.cfg, self.ws, self.gout, self.grads)
+
+    def stats(self):
+        return self.psm.read_stats(self.ws, self.s.n, self.cam, self.cfg, self.s.c, self.ws.capacity)
+
+
+def timed(form, bwd, steps, warmup):
+    import torch
+    psm = form.psm
+    for _ in range(warmup):
+        form.step(bwd)
+    torch.cuda.synchronize()
+    psm.profile_reset(form.ctx)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        form.step(bwd)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = psm.profile_read(form.ctx)
+    st = form.stats()
+    if st.pairs_required > st.pair_capacity:
+        raise RuntimeError("pair capacity exceeded inside the timed region")
+    per_stage = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1] > 0}
+    return el * 1000.0 / steps, per_stage, st
+
+
+def roofline(stages, st, K, C, S, bwd):
+    """Roofline object for the dominant stage of the step."""
+    name = max(stages, key=stages.get)
+    ms = stages[name]
+    if name == "walk":
+        flops = FLOP_PER_EVAL * st.pairs_walked + FLOP_PER_CONTRIB * st.contributors
+        a = flops / (ms * 1e-3) / 1e12
+        return {"kernel": name, "bound": "alu", "achieved": a, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": a / FP32_VALU_PEAK_TFLOPS, "traffic": None, "ms": ms,
+                "work": {"pairs_walked": st.pairs_walked, "contributors": st.contributors}}
+    if name == "bwd_walk":
+        flops = BWD_FLOP_PER_EVAL * st.pairs_walked + BWD_FLOP_PER_CONTRIB * st.contributors
+        a = flops / (ms * 1e-3) / 1e12
+        return {"kernel": name, "bound": "alu", "achieved": a, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": a / FP32_VALU_PEAK_TFLOPS, "traffic": None, "ms": ms,
+                "work": {"pairs_walked": st.pairs_walked, "contributors": st.contributors}}
+    # streaming stages: algorithmic bytes
+    P, N = st.pairs, st.n
+    bytes_by = {
+        "feature_blend": S * (8 * K + 4 * C),
+        "bwd_feature": S * (8 * K + 4 * C + 4 * K),
+        "preprocess": N * (40 + 12) + st.visible * (64 + 48) + N * 12,
+        "depth_sort": N * 8 * 2,
+        "pair_sort": P * 8 * 2,
+        "emit": P * 8 + st.visible * 56,
+        "count_scan": N * 8,
+        "bwd_preprocess": N * (64 + 40 + 52),
+        "ranges": P * 4,
+        "fill": N * 4 * (16 + C),
+    }
+    b = bytes_by.get(name, 0)
+    a = b / (ms * 1e-3) / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": a / HBM_PEAK_GBS, "traffic": None, "ms": ms}
+
+
+def cpu_baseline(sc, cam, K, feat64, tiles):
+    """The FP64 oracle (test infrastructure) on a bounded sample of the same
+    frame: forward + backward of the pixels of `tiles` random 16x16 tiles.
+    The whole-scene key stage and binning are timed separately and counted
+    once per frame; the per-pixel cost is scaled to the full frame."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2604_10982_amd import scenes
+    rng = np.random.default_rng(0)
+    ntx, nty = (cam.width + 15) // 16, (cam.height + 15) // 16
+    pick = rng.choice(ntx * nty, tiles, replace=False)
+    pix = []
+    for t in pick:
+        ty, tx = divmod(int(t), ntx)
+        ys, xs = np.mgrid[ty * 16:min(ty * 16 + 16, cam.height), tx * 16:min(tx * 16 + 16, cam.width)]
+        pix.append((ys * cam.width + xs).ravel())
+    pix = np.concatenate(pix).astype(np.int64)
+    one = pix[:1]
+    t0 = time.perf_counter()
+    O.render(sc, cam, K, O.TOPK, feat=feat64, pix=one)
+    t_prep = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.render(sc, cam, K, O.TOPK, feat=feat64, pix=pix)
+    t_fwd = time.perf_counter() - t0
+    g = scenes.upstream(cam.height, cam.width, sc.c, seed=1)
+    gs = {k: v.reshape(cam.width * cam.height, -1)[pix] for k, v in g.items()}
+    t0 = time.perf_counter()
+    O.backward(sc, cam, gs, K=K, blend=O.TOPK, feat=feat64, pix=pix)
+    t_bwd = time.perf_counter() - t0
+    S = cam.width * cam.height
+    scale = S / len(pix)
+    frame = 2 * t_prep + (t_fwd - t_prep) * scale + (t_bwd - t_prep) * scale
+    return {"value": 1.0 / frame, "unit": "it/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": (f"FP64 oracle fwd+bwd (Top-K, exact ellipse) on {tiles} random 16x16 tiles ({len(pix)} px) "
+                       f"of the same frame; whole-scene key stage + binning {t_prep:.2f}s counted once per pass, "
+                       f"per-pixel cost scaled to {S} px"),
+            "sample_seconds": {"prepare": t_prep, "fwd": t_fwd, "bwd": t_bwd}, "est_frame_s": frame}
+
+
+def main():
+    args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2604_10982_amd import psm, scenes
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a HIP device")
+    device = torch.device("cuda:0")
+    psm.lib()
+    sc, cam, K, dtype = scenes.config(args.workload)
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
+    t = {k: torch.tensor(getattr(sc, k), device=device) for k in ("means", "scales", "quats", "opacity", "rgb")}
+    t["feat"] = torch.tensor(sc.feat, device=device).to(tdt).contiguous()
+    g = scenes.upstream(cam.height, cam.width, sc.c, seed=1)
+    gout = {k: torch.tensor(v, device=device) for k, v in g.items()}
+    S = cam.width * cam.height
+    print(f"[bench] {args.workload}: n={sc.n} {cam.width}x{cam.height} C={sc.c} K={K} {dtype}", file=sys.stderr,
+          flush=True)
+
+    head = Form(psm, t, cam, K, "ellipse", "topk", gout, device)
+    ms_step, stages, st = timed(head, True, args.steps, args.warmup)
+    print(f"[bench] topk+ellipse fwd+bwd {ms_step:.3f} ms", file=sys.stderr, flush=True)
+    ms_fwd, stages_fwd, _ = timed(head, False, args.steps, args.warmup)
+    print(f"[bench] topk+ellipse fwd {ms_fwd:.3f} ms", file=sys.stderr, flush=True)
+    del head
+    base = Form(psm, t, cam, K, "aabb", "full", gout, device)
+    ms_base_step, stages_base, st_base = timed(base, True, max(3, args.steps // 2), 2)
+    ms_base_fwd, _, _ = timed(base, False, max(3, args.steps // 2), 2)
+    print(f"[bench] full+aabb fwd+bwd {ms_base_step:.3f} ms, fwd {ms_base_fwd:.3f} ms", file=sys.stderr, flush=True)
+    del base
+
+    ablation = {}
+    if not args.no_ablation:
+        rows = {"baseline (sphere, dense)": ("sphere", "full"), "w/ precise tile (ellipse, dense)": ("ellipse", "full"),
+                "w/ top-k (sphere, top-k)": ("sphere", "topk"), "full method (ellipse, top-k)": ("ellipse", "topk")}
+        for label, (tm, bl) in rows.items():
+            f = Form(psm, t, cam, K, tm, bl, gout, device)
+            ms, _, s2 = timed(f, False, max(3, args.steps // 2), 2)
+            ablation[label] = {"fwd_ms": ms, "fps": 1000.0 / ms, "pairs": int(s2.pairs),
+                               "pairs_per_tile": s2.pairs / s2.tiles}
+            del f
+            print(f"[bench] ablation {label}: {ms:.3f} ms", file=sys.stderr, flush=True)
+
+    torch.cuda.empty_cache()
+    line = {
+        "metric": METRIC,
+        "value": 1000.0 / ms_step,
+        "unit": "it/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if dtype == "f32" else dtype,
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: planes7 scene, {sc.n} surfels, {cam.width}x{cam.height}, "
+                               f"{sc.c}-d {dtype} features, K={K}, exact-ellipse tiles, Top-K blend",
+                   "surfels": sc.n, "width": cam.width, "height": cam.height, "feat_dim": sc.c, "k": K,
+                   "tile_mode": "ellipse", "blend": "topk", "parallelism": "single-gpu"},
+        "fwd_fps": 1000.0 / ms_fwd,
+        "fwd_ms": ms_fwd,
+        "dense_aabb_form": {"fwd_fps": 1000.0 / ms_base_fwd, "fwd_bwd_its": 1000.0 / ms_base_step,
+                            "fwd_ms": ms_base_fwd, "fwd_bwd_ms": ms_base_step, "pairs": int(st_base.pairs),
+                            "stages_ms": stages_base},
+        "speedup_vs_dense_aabb": {"fwd": ms_base_fwd / ms_fwd, "fwd_bwd": ms_base_step / ms_step},
+        "pairs": int(st.pairs), "pairs_walked": int(st.pairs_walked), "contributors": int(st.contributors),
+        "visible": int(st.visible),
+        "stages_ms": stages,
+        "roofline": roofline(stages, st, K, sc.c, S, True),
+        "ablation_fwd": ablation,
+    }
+    if not args.no_cpu_baseline:
+        feat64 = t["feat"].float().cpu().numpy().astype(np.float64)
+        line["cpu_baseline"] = cpu_baseline(sc, cam, K, feat64, args.cpu_tiles)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * psm.h -- C ABI of the MI355X (gfx950) rasterizer for Psi-Map panoptic
+ * surfel maps (arXiv 2604.10982).
+ *
+ * The library renders 2D Gaussian surfels (Sec. 3.1 of the paper: tangent
+ * plane disks with kernel exp(-(u^2+v^2)/2) and alpha = o * kernel) by
+ * tile-based front-to-back alpha blending (eq. (1)), with the two
+ * optimisations of Sec. 5: Precise Tile Intersection (surfel->tile pairs from
+ * the exact projected ellipse, eq. (17) and its exact-ellipse refinement) and
+ * Top-K Hard Selection (eq. (18): only the K largest blend weights of a pixel
+ * accumulate the feature channels).  A hand-written backward returns the
+ * gradients of a loss with respect to every surfel parameter.
+ *
+ * Conventions
+ *   - All pointers passed to psm_forward/psm_backward/psm_read_* are DEVICE
+ *     pointers on the context's device unless stated otherwise; all work is
+ *     enqueued asynchronously on `stream` (a hipStream_t passed as void*;
+ *     NULL = the default stream).  The caller owns every buffer: inputs,
+ *     outputs, gradients and the workspace.
+ *   - Camera: OpenCV axes (x right, y down, z forward), world->camera
+ *     rotation R (row-major) and translation t; pinhole intrinsics; pixel
+ *     (i, j) samples the image point (i + 0.5, j + 0.5).
+ *   - Surfel parameters are *activated* values: opacity in (0, 1], scales > 0;
+ *     quaternions are (w, x, y, z) and are normalised inside.
+ *   - Images are row-major: rgb/normal [H][W][3], depth/alpha [H][W],
+ *     feat [H][W][C], all FP32.
+ *   - Errors: every entry point returns a psm_status; negative values are
+ *     errors and psm_last_error() returns a thread-local message.  No entry
+ *     point aborts or throws.  NaN/Inf inputs are not checked; they propagate.
+ */
+#ifndef PSM_H
+#define PSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PSM_OK = 0,
+  PSM_ERR_INVALID_ARG = -1,  /* null pointer, bad size, bad enum value */
+  PSM_ERR_UNSUPPORTED = -2,  /* valid but not implemented (e.g. C % 8 != 0) */
+  PSM_ERR_CAPACITY = -3,     /* workspace pair capacity too small; see stats.pairs_required */
+  PSM_ERR_HIP = -4           /* a HIP runtime call failed; message in psm_last_error() */
+} psm_status;
+
+typedef enum { PSM_F32 = 0, PSM_F16 = 1, PSM_BF16 = 2 } psm_dtype;
+
+/* Footprint used to build surfel->tile pairs (Sec. 5, "Precise Tile
+ * Intersection").  SPHERE is the isotropic bound the paper improves on, AABB
+ * is eq. (17), ELLIPSE is the exact projected-ellipse/tile test.  All three
+ * are conservative for the per-pixel cutoff, so images do not depend on it. */
+typedef enum { PSM_TILE_SPHERE = 0, PSM_TILE_AABB = 1, PSM_TILE_ELLIPSE = 2 } psm_tile_mode;
+
+/* Feature blending: FULL = eq. (1) with c_i = f_i over every contributor;
+ * TOPK = eq. (18), the K largest weights only.  RGB, depth, normal and alpha
+ * always use the dense blend. */
+typedef enum { PSM_BLEND_FULL = 0, PSM_BLEND_TOPK = 1 } psm_blend_mode;
+
+typedef struct {
+  int64_t n;            /* number of surfels, >= 0 */
+  const float* means;   /* [n][3] world-space centres */
+  const float* scales;  /* [n][2] tangent-plane scales (s_u, s_v) > 0 */
+  const float* quats;   /* [n][4] (w, x, y, z) */
+  const float* opacity; /* [n] in (0, 1] */
+  const float* rgb;     /* [n][3] */
+  const void* feat;     /* [n][c] row-major in feat_dtype, 16-byte aligned */
+  int32_t c;            /* feature channels: 8 <= c <= 1024, c % 8 == 0 */
+  int32_t feat_dtype;   /* psm_dtype */
+} psm_surfels;
+
+typedef struct {
+  float R[9];         /* world -> camera rotation, row-major */
+  float t[3];         /* world -> camera translation */
+  float fx, fy, cx, cy;
+  float near_plane;   /* > 0; surfels whose cutoff disk reaches it are culled */
+  int32_t width, height; /* 1..16384 */
+} psm_camera;
+
+typedef struct {
+  int32_t k;          /* Top-K size, 1..32 (also sizes the saved selection) */
+  int32_t tile_mode;  /* psm_tile_mode */
+  int32_t blend;      /* psm_blend_mode */
+  int32_t flags;      /* PSM_FLAG_* */
+} psm_config;
+
+/* Skip the end-of-call status read-back (graph-safe; the caller checks
+ * psm_read_stats later). */
+#define PSM_FLAG_NO_SYNC 1
+/* Record a HIP event pair around every stage on the call's stream; read the
+ * accumulated stage times with psm_profile_read. */
+#define PSM_FLAG_PROFILE 2
+
+typedef struct { float *rgb, *depth, *normal, *alpha, *feat; } psm_images;
+typedef struct { const float *rgb, *depth, *normal, *alpha, *feat; } psm_image_grads;
+/* Gradients, FP32, shapes of the inputs (feat: [n][c] FP32 for every storage
+ * dtype).  psm_backward overwrites them (no accumulation). */
+typedef struct { float *means, *scales, *quats, *opacity, *rgb, *feat; } psm_grads;
+
+typedef struct {
+  int64_t n;              /* surfels */
+  int64_t visible;        /* surfels surviving the cull */
+  int64_t culled[5];      /* by code: 0 unused, 1 zero quaternion, 2 centre behind near,
+                             3 disk reaches near plane, 4 degenerate projection */
+  int64_t pairs;          /* surfel->tile pairs emitted (the sorted list length) */
+  int64_t pairs_required; /* pairs the footprint asked for (> capacity on PSM_ERR_CAPACITY) */
+  int64_t pair_capacity;  /* capacity the workspace was laid out for */
+  int64_t tiles;          /* number of 16x16 tiles */
+  int64_t pairs_walked;   /* pixel x list-entry evaluations of the forward walk */
+  int64_t contributors;   /* (pixel, surfel) pairs blended by the forward walk */
+} psm_stats;
+
+typedef struct psm_ctx psm_ctx;
+
+/* Create a context bound to HIP device `device` (host memory; holds device
+ * properties and the last error).  Returns PSM_ERR_HIP if the device is not
+ * usable. */
+psm_status psm_create(psm_ctx** ctx_out, int device);
+void psm_destroy(psm_ctx* ctx);
+
+/* Size in bytes of the workspace for n surfels, this camera and config,
+ * c feature channels and room for `pair_capacity` surfel->tile pairs.  The
+ * workspace holds the per-surfel records, the pair lists and sort scratch,
+ * the tile ranges and the per-pixel state saved for the backward (last
+ * contributor, final transmittance, Top-K positions and weights).  Pure host
+ * computation; ctx may be NULL. */
+psm_status psm_workspace_size(int64_t n, const psm_camera* cam, const psm_config* cfg, int32_t c,
+                              int64_t pair_capacity, size_t* bytes_out);
+
+/* Forward render (Sec. 3.1 eq. (1); Sec. 5 eqs. (17), (18)).
+ * workspace: device buffer of at least psm_workspace_size(...) bytes, 256-byte
+ * aligned, that must stay untouched until the matching psm_backward.
+ * out: device pointers; any member may be NULL to skip that map (feat must be
+ * non-NULL when c > 0 and blend is used).  Unless PSM_FLAG_NO_SYNC is set the
+ * call synchronises `stream` once at the end to read the pair count and
+ * returns PSM_ERR_CAPACITY when the pairs did not fit (images are then
+ * invalid; re-run with a larger capacity). */
+psm_status psm_forward(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cam,
+                       const psm_config* cfg, void* workspace, size_t workspace_bytes,
+                       int64_t pair_capacity, psm_images* out, void* stream);
+
+/* Backward of L = sum over all maps of <grad_out, image>: writes dL/d(every
+ * surfel parameter) into `grads` (all members required, FP32 device arrays).
+ * Uses the workspace state of the last psm_forward with the same inputs,
+ * camera and config; grad_out members may be NULL (treated as zero).
+ * Gradients hold the Top-K set, the contributor set and the alpha clamp
+ * fixed (their a.e. derivative). */
+psm_status psm_backward(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cam,
+                        const psm_config* cfg, void* workspace, size_t workspace_bytes,
+                        int64_t pair_capacity, const psm_image_grads* grad_out, psm_grads* grads,
+                        void* stream);
+
+/* Synchronises `stream` and reads the counters of the last psm_forward in
+ * this workspace into *out (host memory). */
+psm_status psm_read_stats(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cam,
+                          const psm_config* cfg, int32_t c, int64_t pair_capacity, psm_stats* out,
+                          void* stream);
+
+/* Inspection of the key stage, for testing: copies (device to device, on
+ * `stream`) the sorted pair list -- tile ids and surfel ids, `cap` entries at
+ * most -- and per surfel the cull code, the FP32 depth-key bits and the pair
+ * count.  Any output may be NULL.  *pairs_out (host) receives the list
+ * length (this call synchronises `stream`). */
+psm_status psm_read_pairs(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cam,
+                          const psm_config* cfg, int32_t c, int64_t pair_capacity,
+                          int32_t* tile_out, int32_t* id_out, int64_t cap, int32_t* cull_out,
+                          uint32_t* depth_bits_out, int32_t* count_out, int64_t* pairs_out,
+                          void* stream);
+
+/* Inspection of the Top-K selection saved by the last forward: for every
+ * pixel (row-major), K surfel ids in front-to-back order (-1 padded) and
+ * their blend weights, plus the number of list entries walked and T_final.
+ * Device outputs, any may be NULL. */
+psm_status psm_read_selection(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cam,
+                              const psm_config* cfg, int32_t c, int64_t pair_capacity,
+                              int32_t* sel_id_out, float* sel_w_out, int32_t* n_last_out,
+                              float* t_final_out, void* stream);
+
+/* Stage timing (PSM_FLAG_PROFILE).  Stages are numbered 0 .. PSM_NUM_STAGES-1
+ * (preprocess, depth_sort, count_scan, emit, pair_sort, ranges, walk,
+ * feature_blend, bwd_feature, bwd_walk, bwd_preprocess, fill).  psm_profile_read
+ * synchronises the recorded events and returns, for `stage`, its name (static
+ * string), the summed duration in ms and the number of recorded calls since
+ * the last psm_profile_reset.  Events are recorded on the stream each call was
+ * given. */
+#define PSM_NUM_STAGES 12
+psm_status psm_profile_read(psm_ctx* ctx, int32_t stage, const char** name_out, double* total_ms_out,
+                            int64_t* calls_out);
+psm_status psm_profile_reset(psm_ctx* ctx);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* psm_last_error(void);
+
+/* Library version string (host memory, static). */
+const char* psm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSM_H */

@@ -1,0 +1,410 @@
+// C ABI of the rasterizer (include/psm.h): argument validation, workspace
+// layout and the ordered enqueue of the kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/psm.h"
+#include "internal.h"
+
+using namespace psm;
+
+namespace {
+
+const char* const kStageNames[kNumStages] = {"preprocess", "depth_sort", "count_scan", "emit",
+                                             "pair_sort",  "ranges",     "walk",       "feature_blend",
+                                             "bwd_feature", "bwd_walk",  "bwd_preprocess", "fill"};
+
+// HIP-event stage timer: an event pair per stage and call, on the call's stream.
+struct Profiler {
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kNumStages];
+  hipEvent_t open[kNumStages] = {};
+  double total_ms[kNumStages] = {};
+  int64_t calls[kNumStages] = {};
+
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  static void mark(void* self, int stage, int is_end, hipStream_t st) {
+    Profiler* p = static_cast<Profiler*>(self);
+    hipEvent_t e = p->take();
+    (void)hipEventRecord(e, st);
+    if (!is_end) p->open[stage] = e;
+    else p->pending[stage].push_back({p->open[stage], e});
+  }
+  bool collect() {
+    bool ok = true;
+    for (int s = 0; s < kNumStages; ++s) {
+      for (auto& pr : pending[s]) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(pr.second) != hipSuccess || hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess)
+          ok = false;
+        total_ms[s] += ms;
+        calls[s] += 1;
+        pool.push_back(pr.first);
+        pool.push_back(pr.second);
+      }
+      pending[s].clear();
+    }
+    return ok;
+  }
+  ~Profiler() {
+    for (auto& v : pending)
+      for (auto& pr : v) pool.push_back(pr.first), pool.push_back(pr.second);
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+}  // namespace
+
+struct psm_ctx {
+  int device;
+  int cu_count;
+  Profiler prof;
+};
+
+namespace {
+
+ProfHook hook_for(psm_ctx* ctx, const psm_config* cfg) {
+  ProfHook h;
+  if (cfg->flags & PSM_FLAG_PROFILE) {
+    h.self = &ctx->prof;
+    h.mark = &Profiler::mark;
+  }
+  return h;
+}
+
+thread_local std::string g_err;
+
+psm_status fail(psm_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+// Keeps the caller's current device and restores it on exit.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+psm_status check_hip(const char* where) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(PSM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+  return PSM_OK;
+}
+
+psm_status validate_common(const psm_camera* cam, const psm_config* cfg, int64_t n, int32_t c,
+                           int64_t pair_capacity) {
+  if (!cam || !cfg) return fail(PSM_ERR_INVALID_ARG, "camera and config are required");
+  if (n < 0 || n > 0x7FFFFFFFLL) return fail(PSM_ERR_INVALID_ARG, "n must be in [0, 2^31)");
+  if (cam->width < 1 || cam->height < 1 || cam->width > 16384 || cam->height > 16384)
+    return fail(PSM_ERR_INVALID_ARG, "image size must be in [1, 16384]");
+  if (!(cam->near_plane > 0.0f) || !std::isfinite(cam->near_plane))
+    return fail(PSM_ERR_INVALID_ARG, "near_plane must be finite and > 0");
+  if (!std::isfinite(cam->fx) || !std::isfinite(cam->fy) || cam->fx == 0.0f || cam->fy == 0.0f)
+    return fail(PSM_ERR_INVALID_ARG, "focal lengths must be finite and non-zero");
+  if (cfg->k < 1 || cfg->k > kMaxK) return fail(PSM_ERR_INVALID_ARG, "k must be in [1, 32]");
+  if (cfg->tile_mode < 0 || cfg->tile_mode > 2) return fail(PSM_ERR_INVALID_ARG, "bad tile_mode");
+  if (cfg->blend < 0 || cfg->blend > 1) return fail(PSM_ERR_INVALID_ARG, "bad blend mode");
+  if (c < 0 || c > 1024) return fail(PSM_ERR_INVALID_ARG, "c must be in [0, 1024]");
+  if (c % 8 != 0) return fail(PSM_ERR_UNSUPPORTED, "c must be a multiple of 8");
+  if (pair_capacity < 0 || pair_capacity > 0x7FFFFFFFLL)
+    return fail(PSM_ERR_INVALID_ARG, "pair_capacity must be in [0, 2^31)");
+  return PSM_OK;
+}
+
+psm_status validate_surfels(const psm_surfels* s) {
+  if (!s) return fail(PSM_ERR_INVALID_ARG, "surfels are required");
+  if (s->feat_dtype < 0 || s->feat_dtype > 2) return fail(PSM_ERR_INVALID_ARG, "bad feat_dtype");
+  if (s->n > 0 && (!s->means || !s->scales || !s->quats || !s->opacity || !s->rgb))
+    return fail(PSM_ERR_INVALID_ARG, "null surfel parameter array");
+  if (s->n > 0 && s->c > 0) {
+    if (!s->feat) return fail(PSM_ERR_INVALID_ARG, "null feature array");
+    if (reinterpret_cast<uintptr_t>(s->feat) % 16 != 0)
+      return fail(PSM_ERR_INVALID_ARG, "feature array must be 16-byte aligned");
+  }
+  return PSM_OK;
+}
+
+Layout layout_for(int64_t n, const psm_camera* cam, const psm_config* cfg, int32_t c, int64_t cap) {
+  return make_layout(n, cam->width, cam->height, cfg->k, c, cap);
+}
+
+CamArgs cam_args(const psm_camera* cam) {
+  CamArgs a;
+  std::memcpy(a.R, cam->R, sizeof(a.R));
+  std::memcpy(a.t, cam->t, sizeof(a.t));
+  a.fx = cam->fx; a.fy = cam->fy; a.cx = cam->cx; a.cy = cam->cy; a.near_plane = cam->near_plane;
+  a.W = cam->width; a.H = cam->height;
+  return a;
+}
+
+SurfelArgs surfel_args(const psm_surfels* s) {
+  return SurfelArgs{s->n, s->means, s->scales, s->quats, s->opacity, s->rgb, s->feat, s->c, s->feat_dtype};
+}
+
+int bits_for(int64_t tiles) {
+  int b = 0;
+  while ((1LL << b) < tiles) ++b;
+  return b;
+}
+
+psm_status check_workspace(const Layout& L, const void* ws, size_t bytes) {
+  if (!ws) return fail(PSM_ERR_INVALID_ARG, "workspace is required");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(PSM_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (bytes < L.total)
+    return fail(PSM_ERR_INVALID_ARG, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  return PSM_OK;
+}
+
+psm_status read_status(const Layout& L, const void* ws, uint32_t* st_host, hipStream_t st) {
+  if (hipMemcpyAsync(st_host, (const char*)ws + L.status, kStWords * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(PSM_ERR_HIP, std::string("status read-back: ") + hipGetErrorString(hipGetLastError()));
+  return PSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* psm_last_error(void) { return g_err.c_str(); }
+
+const char* psm_version(void) { return "psm 0.1 (gfx950)"; }
+
+psm_status psm_create(psm_ctx** ctx_out, int device) {
+  if (!ctx_out) return fail(PSM_ERR_INVALID_ARG, "ctx_out is null");
+  *ctx_out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return fail(PSM_ERR_HIP, "no usable HIP device " + std::to_string(device));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(PSM_ERR_HIP, "hipGetDeviceProperties failed");
+  psm_ctx* c = new psm_ctx;
+  c->device = device;
+  c->cu_count = prop.multiProcessorCount;
+  *ctx_out = c;
+  g_err.clear();
+  return PSM_OK;
+}
+
+void psm_destroy(psm_ctx* ctx) { delete ctx; }
+
+psm_status psm_workspace_size(int64_t n, const psm_camera* cam, const psm_config* cfg, int32_t c,
+                              int64_t pair_capacity, size_t* bytes_out) {
+  if (!bytes_out) return fail(PSM_ERR_INVALID_ARG, "bytes_out is null");
+  psm_status s = validate_common(cam, cfg, n, c, pair_capacity);
+  if (s != PSM_OK) return s;
+  *bytes_out = layout_for(n, cam, cfg, c, pair_capacity).total;
+  return PSM_OK;
+}
+
+psm_status psm_forward(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cam, const psm_config* cfg,
+                       void* workspace, size_t workspace_bytes, int64_t pair_capacity, psm_images* out,
+                       void* stream) {
+  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+  if (!out) return fail(PSM_ERR_INVALID_ARG, "out is null");
+  psm_status r = validate_surfels(s);
+  if (r != PSM_OK) return r;
+  r = validate_common(cam, cfg, s->n, s->c, pair_capacity);
+  if (r != PSM_OK) return r;
+  const Layout L = layout_for(s->n, cam, cfg, s->c, pair_capacity);
+  r = check_workspace(L, workspace, workspace_bytes);
+  if (r != PSM_OK) return r;
+  if (s->c > 0 && !out->feat) return fail(PSM_ERR_INVALID_ARG, "out->feat is required when c > 0");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const CamArgs ca = cam_args(cam);
+  const SurfelArgs sa = surfel_args(s);
+  const int64_t nb_max = cdiv(std::max<int64_t>(std::max<int64_t>(L.n, L.cap), 1), kSortTile);
+  uint32_t* status = (uint32_t*)(ws + L.status);
+  uint32_t* hist = (uint32_t*)(ws + L.hist);
+
+  const ProfHook prof = hook_for(ctx, cfg);
+
+  prof.begin(kStageFill, st);
+  launch_init_status(status, s->n, st);
+  launch_fill_u32(ws + L.ranges, 0u, L.tiles * 2, st);
+  prof.end(kStageFill, st);
+  prof.begin(kStagePreprocess, st);
+  launch_preprocess(sa, ca, cfg->tile_mode, L, ws, st);
+  prof.end(kStagePreprocess, st);
+  prof.begin(kStageDepthSort, st);
+  radix_sort_pairs((uint32_t*)(ws + L.key0), (uint32_t*)(ws + L.id0), (uint32_t*)(ws + L.key1),
+                   (uint32_t*)(ws + L.id1), status + kStN, L.n, 32, hist, nb_max, st);
+  prof.end(kStageDepthSort, st);
+  prof.begin(kStageScan, st);
+  launch_scan_counts(L, ws, st);
+  prof.end(kStageScan, st);
+  prof.begin(kStageEmit, st);
+  launch_emit(ca, cfg->tile_mode, L, ws, st);
+  prof.end(kStageEmit, st);
+  prof.begin(kStagePairSort, st);
+  radix_sort_pairs((uint32_t*)(ws + L.ptile0), (uint32_t*)(ws + L.pid0), (uint32_t*)(ws + L.ptile1),
+                   (uint32_t*)(ws + L.pid1), status + kStP, L.cap, bits_for(L.tiles), hist, nb_max, st);
+  prof.end(kStagePairSort, st);
+  prof.begin(kStageRanges, st);
+  launch_ranges(L, ws, st);
+  prof.end(kStageRanges, st);
+  ImageArgs ia{out->rgb, out->depth, out->normal, out->alpha, out->feat};
+  prof.begin(kStageWalk, st);
+  launch_walk(L, ca, cfg->blend, ia, ws, st);
+  prof.end(kStageWalk, st);
+  prof.begin(kStageBlend, st);
+  launch_feature_blend(sa, L, ca, cfg->blend, out->feat, ws, st);
+  prof.end(kStageBlend, st);
+  r = check_hip("psm_forward launch");
+  if (r != PSM_OK) return r;
+  if (!(cfg->flags & PSM_FLAG_NO_SYNC)) {
+    uint32_t h[kStWords];
+    r = read_status(L, ws, h, st);
+    if (r != PSM_OK) return r;
+    if (h[kStOverflow]) {
+      const uint64_t req = (uint64_t)h[kStReqLo] | ((uint64_t)h[kStReqHi] << 32);
+      return fail(PSM_ERR_CAPACITY, "pair capacity " + std::to_string(L.cap) + " < required " + std::to_string(req));
+    }
+  }
+  g_err.clear();
+  return PSM_OK;
+}
+
+psm_status psm_backward(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cam, const psm_config* cfg,
+                        void* workspace, size_t workspace_bytes, int64_t pair_capacity,
+                        const psm_image_grads* grad_out, psm_grads* grads, void* stream) {
+  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+  if (!grad_out || !grads) return fail(PSM_ERR_INVALID_ARG, "grad_out and grads are required");
+  psm_status r = validate_surfels(s);
+  if (r != PSM_OK) return r;
+  r = validate_common(cam, cfg, s->n, s->c, pair_capacity);
+  if (r != PSM_OK) return r;
+  if (s->n > 0 && (!grads->means || !grads->scales || !grads->quats || !grads->opacity || !grads->rgb ||
+                   (s->c > 0 && !grads->feat)))
+    return fail(PSM_ERR_INVALID_ARG, "every gradient array is required");
+  const Layout L = layout_for(s->n, cam, cfg, s->c, pair_capacity);
+  r = check_workspace(L, workspace, workspace_bytes);
+  if (r != PSM_OK) return r;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
+  hipStream_t st = (hipStream_t)stream;
+  ImageGradArgs g{grad_out->rgb, grad_out->depth, grad_out->normal, grad_out->alpha, grad_out->feat};
+  GradArgs ga{grads->means, grads->scales, grads->quats, grads->opacity, grads->rgb, grads->feat};
+  launch_backward(surfel_args(s), cam_args(cam), cfg->blend, L, g, ga, (char*)workspace, st, hook_for(ctx, cfg));
+  r = check_hip("psm_backward launch");
+  if (r != PSM_OK) return r;
+  g_err.clear();
+  return PSM_OK;
+}
+
+psm_status psm_read_stats(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cam,
+                          const psm_config* cfg, int32_t c, int64_t pair_capacity, psm_stats* out, void* stream) {
+  if (!ctx || !out) return fail(PSM_ERR_INVALID_ARG, "ctx and out are required");
+  psm_status r = validate_common(cam, cfg, n, c, pair_capacity);
+  if (r != PSM_OK) return r;
+  const Layout L = layout_for(n, cam, cfg, c, pair_capacity);
+  if (!workspace) return fail(PSM_ERR_INVALID_ARG, "workspace is required");
+  DeviceGuard dg(ctx->device);
+  uint32_t h[kStWords];
+  r = read_status(L, workspace, h, (hipStream_t)stream);
+  if (r != PSM_OK) return r;
+  std::memset(out, 0, sizeof(*out));
+  out->n = n;
+  out->visible = h[kStVisible];
+  for (int i = 0; i < 5; ++i) out->culled[i] = i == 0 ? 0 : h[kStCull + i];
+  out->pairs = h[kStP];
+  out->pairs_required = (int64_t)((uint64_t)h[kStReqLo] | ((uint64_t)h[kStReqHi] << 32));
+  out->pair_capacity = pair_capacity;
+  out->tiles = L.tiles;
+  out->pairs_walked = (int64_t)((uint64_t)h[kStWalked] | ((uint64_t)h[kStWalked + 1] << 32));
+  out->contributors = (int64_t)((uint64_t)h[kStBlended] | ((uint64_t)h[kStBlended + 1] << 32));
+  return PSM_OK;
+}
+
+psm_status psm_profile_read(psm_ctx* ctx, int32_t stage, const char** name_out, double* total_ms_out,
+                            int64_t* calls_out) {
+  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+  if (stage < 0 || stage >= kNumStages) return fail(PSM_ERR_INVALID_ARG, "stage out of range");
+  DeviceGuard dg(ctx->device);
+  if (!ctx->prof.collect()) return fail(PSM_ERR_HIP, "profile events could not be read");
+  if (name_out) *name_out = kStageNames[stage];
+  if (total_ms_out) *total_ms_out = ctx->prof.total_ms[stage];
+  if (calls_out) *calls_out = ctx->prof.calls[stage];
+  return PSM_OK;
+}
+
+psm_status psm_profile_reset(psm_ctx* ctx) {
+  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+  DeviceGuard dg(ctx->device);
+  const bool ok = ctx->prof.collect();
+  for (int s = 0; s < kNumStages; ++s) {
+    ctx->prof.total_ms[s] = 0.0;
+    ctx->prof.calls[s] = 0;
+  }
+  return ok ? PSM_OK : fail(PSM_ERR_HIP, "profile events could not be read");
+}
+
+psm_status psm_read_pairs(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cam,
+                          const psm_config* cfg, int32_t c, int64_t pair_capacity, int32_t* tile_out,
+                          int32_t* id_out, int64_t cap, int32_t* cull_out, uint32_t* depth_bits_out,
+                          int32_t* count_out, int64_t* pairs_out, void* stream) {
+  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+  psm_status r = validate_common(cam, cfg, n, c, pair_capacity);
+  if (r != PSM_OK) return r;
+  if (!workspace) return fail(PSM_ERR_INVALID_ARG, "workspace is required");
+  const Layout L = layout_for(n, cam, cfg, c, pair_capacity);
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = (hipStream_t)stream;
+  const char* ws = (const char*)workspace;
+  uint32_t h[kStWords];
+  r = read_status(L, workspace, h, st);
+  if (r != PSM_OK) return r;
+  const int64_t P = h[kStP];
+  if (pairs_out) *pairs_out = P;
+  const int64_t m = std::min<int64_t>(P, cap);
+  if (m > 0 && tile_out) (void)hipMemcpyAsync(tile_out, ws + L.ptile0, m * 4, hipMemcpyDeviceToDevice, st);
+  if (m > 0 && id_out) (void)hipMemcpyAsync(id_out, ws + L.pid0, m * 4, hipMemcpyDeviceToDevice, st);
+  launch_export_keys(L, (char*)workspace, cull_out, depth_bits_out, count_out, st);
+  r = check_hip("psm_read_pairs");
+  if (r != PSM_OK) return r;
+  if (hipStreamSynchronize(st) != hipSuccess) return fail(PSM_ERR_HIP, "psm_read_pairs sync");
+  return PSM_OK;
+}
+
+psm_status psm_read_selection(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cam,
+                              const psm_config* cfg, int32_t c, int64_t pair_capacity, int32_t* sel_id_out,
+                              float* sel_w_out, int32_t* n_last_out, float* t_final_out, void* stream) {
+  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+  psm_status r = validate_common(cam, cfg, n, c, pair_capacity);
+  if (r != PSM_OK) return r;
+  if (!workspace) return fail(PSM_ERR_INVALID_ARG, "workspace is required");
+  const Layout L = layout_for(n, cam, cfg, c, pair_capacity);
+  DeviceGuard dg(ctx->device);
+  launch_export_selection(L, cam_args(cam), (char*)workspace, cfg->blend == PSM_BLEND_TOPK ? sel_id_out : nullptr,
+                          cfg->blend == PSM_BLEND_TOPK ? sel_w_out : nullptr, n_last_out, t_final_out,
+                          (hipStream_t)stream);
+  return check_hip("psm_read_selection");
+}
+
+}  // extern "C"

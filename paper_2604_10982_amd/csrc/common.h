@@ -1,0 +1,261 @@
+// Shared definitions of the gfx950 rasterizer: constants, workspace layout,
+// the per-surfel walk record and the per-pixel ray/surfel evaluation used by
+// both the forward and the backward walk (so both take identical decisions).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psm {
+
+// ----------------------------------------------------------------- constants
+// Cutoff r = 3 in tangent units ("3 sigma", Sec. 5), applied per pixel.
+constexpr float kCut2 = 9.0f;
+constexpr float kCut = 3.0f;
+// Footprint radius^2 = 9 (1 + 2^-10): a superset of the FP32 per-pixel test.
+constexpr float kFoot2 = 9.0087890625f;
+// Thresholds the paper leaves to the 3DGS conventions.
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+
+constexpr int kTile = 16;               // 16x16 pixel tiles
+constexpr int kTilePix = kTile * kTile; // one pixel per thread, 4 waves
+constexpr int kMaxK = 32;
+constexpr int kRecWords = 6;             // 16-byte words per surfel walk record
+
+enum : int { kSphere = 0, kAabb = 1, kEllipse = 2 };
+enum : int { kFull = 0, kTopK = 1 };
+enum : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
+
+// Status words kept in the workspace (uint32 each).
+enum : int {
+  kStP = 0,        // pairs emitted (min(required, capacity))
+  kStOverflow = 1, // 1 if required > capacity
+  kStN = 2,        // number of surfels
+  kStVisible = 3,
+  kStCull = 4,     // 4 .. 8: cull codes 0..4
+  kStReqLo = 10,   // required pairs, 64-bit
+  kStReqHi = 11,
+  kStWalked = 12,  // 64-bit: pixel x list-entry evaluations of the forward walk
+  kStBlended = 14, // 64-bit: blended (pixel, surfel) pairs
+  kStWords = 16
+};
+
+// Radix sort tiling.
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+// Count-scan tiling.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------- workspace layout
+struct Layout {
+  int64_t n, cap, ntx, nty, tiles, spix;  // spix = tiles * 256 (tile-major pixels)
+  int k, c;
+  size_t rec, fp, key0, key1, id0, id1, count, offs, cull, ptile0, ptile1, pid0, pid1, ranges,
+      nlast, tfinal, selpos, selw, seldot, gacc, hist, bsum, status, total;
+};
+
+inline Layout make_layout(int64_t n, int width, int height, int k, int c, int64_t cap) {
+  Layout L{};
+  L.n = n;
+  L.cap = cap;
+  L.k = k;
+  L.c = c;
+  L.ntx = cdiv(width, kTile);
+  L.nty = cdiv(height, kTile);
+  L.tiles = L.ntx * L.nty;
+  L.spix = L.tiles * kTilePix;
+  const int64_t n1 = n > 0 ? n : 1, cap1 = cap > 0 ? cap : 1;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  L.rec = take(n1 * 16 * kRecWords);  // walk record
+  L.fp = take(n1 * 48);           // footprint floats, 12
+  L.key0 = take(n1 * 4);          // depth keys (sort ping-pong)
+  L.key1 = take(n1 * 4);
+  L.id0 = take(n1 * 4);           // surfel ids (sort ping-pong)
+  L.id1 = take(n1 * 4);
+  L.count = take(n1 * 4);         // pairs per surfel
+  L.offs = take((n1 + 1) * 4);    // exclusive scan of counts in depth order
+  L.cull = take(n1 * 4);
+  L.ptile0 = take(cap1 * 4);      // pair tile ids (sort ping-pong)
+  L.ptile1 = take(cap1 * 4);
+  L.pid0 = take(cap1 * 4);        // pair surfel ids
+  L.pid1 = take(cap1 * 4);
+  L.ranges = take(L.tiles * 8);   // [start, end) per tile
+  L.nlast = take(L.spix * 4);
+  L.tfinal = take(L.spix * 4);
+  L.selpos = take(L.spix * (size_t)k * 4);
+  L.selw = take(L.spix * (size_t)k * 4);
+  L.seldot = take(L.spix * (size_t)k * 4);
+  L.gacc = take(n1 * 64);         // per-surfel gradient accumulators, 16 floats
+  const int64_t nb = cdiv(n1 > cap1 ? n1 : cap1, kSortTile);
+  L.hist = take((256 * nb + 256) * 4);
+  L.bsum = take((cdiv(n1, kScanTile) + 1) * 8);
+  L.status = take(kStWords * 4);
+  L.total = o;
+  return L;
+}
+
+// ------------------------------------------------------------ walk record
+// Per surfel (global, 6 x 16 bytes), computed in FP64 from the FP32 inputs:
+//   d0 = (Ai00, Ai01), d1 = (Ai10, Ai11)   FP64: inverse of A, the centred,
+//                                          depth-normalised homography [[A,0],[p q 1]]
+//   d2 = (e0, e1)                          FP64: e = (p, q) A^-1
+//   d3 = (xc, yc)                          FP64: projected surfel centre
+//   f0 = (mz, o, r, g), f1 = (b, n0, n1, n2)  FP32
+// For a pixel offset d = (x - xc, y - yc):  u' = A^-1 d, w' = 1 - e.d,
+// (u, v) = u'/w', intersection depth z = mz / w'.
+//
+// The solve is FP64: for a surfel seen at a grazing angle A is ill-conditioned
+// and an FP32 evaluation of u' loses eps * cond(A) relative accuracy (1e-4 in
+// rho at cond(A) ~ 100), far beyond the 1e-5 image tolerance; FP32 pixel
+// coordinates near 10^3 would also carry 6e-5 px of rounding.
+
+struct __align__(16) WalkRec {
+  double2 d0, d1, d2, d3;
+  float4 f0, f1;
+};
+static_assert(sizeof(WalkRec) == 16 * kRecWords, "walk record layout");
+
+// Tile-local copy staged in LDS: the tile origin's offset (ox, oy) from the
+// centre, so a pixel's offset is d = (lx + ox, ly + oy) for its tile-local
+// centre (lx, ly).
+struct LRec {
+  double a00, a01, a10, a11, e0, e1, ox, oy;
+  float mz, o, r, g, b, n0, n1, n2;
+};
+
+// LDS staging of a batch of tile-local records (structure of arrays, so a
+// batch is written with consecutive addresses and read by broadcast).
+template <int B>
+struct Staged {
+  double2 a0[B], a1[B], e[B], o[B];
+  float4 f0[B], f1[B];
+
+  __device__ __forceinline__ void put(int slot, const WalkRec& r, float tx0, float ty0) {
+    a0[slot] = r.d0;
+    a1[slot] = r.d1;
+    e[slot] = r.d2;
+    o[slot] = make_double2((double)tx0 - r.d3.x, (double)ty0 - r.d3.y);
+    f0[slot] = r.f0;
+    f1[slot] = r.f1;
+  }
+  __device__ __forceinline__ LRec get(int k) const {
+    LRec s;
+    const double2 x0 = a0[k], x1 = a1[k], x2 = e[k], x3 = o[k];
+    const float4 y0 = f0[k], y1 = f1[k];
+    s.a00 = x0.x; s.a01 = x0.y; s.a10 = x1.x; s.a11 = x1.y;
+    s.e0 = x2.x; s.e1 = x2.y; s.ox = x3.x; s.oy = x3.y;
+    s.mz = y0.x; s.o = y0.y; s.r = y0.z; s.g = y0.w;
+    s.b = y1.x; s.n0 = y1.y; s.n1 = y1.z; s.n2 = y1.w;
+    return s;
+  }
+};
+
+// Per-pixel evaluation of one surfel (Sec. 3.1): the intersection (u, v) of
+// the pixel ray with the surfel plane, rho = u^2 + v^2, hit iff rho <= 9,
+// alpha = min(0.99, o exp(-rho/2)).  Returns true for a contributor
+// (hit and alpha >= 1/255).  The hit decision is taken in FP64; rho, alpha
+// and the values handed on are FP32.
+struct PixEval {
+  float dx, dy, u, v, iw, G, alpha;
+  bool clamped;
+};
+
+__device__ __forceinline__ bool eval_pixel(const LRec& s, float lx, float ly, PixEval& e) {
+  const double dx = (double)lx + s.ox, dy = (double)ly + s.oy;
+  const double u1 = fma(s.a00, dx, s.a01 * dy);
+  const double v1 = fma(s.a10, dx, s.a11 * dy);
+  const double w1 = 1.0 - fma(s.e0, dx, s.e1 * dy);
+  const double num = fma(u1, u1, v1 * v1);
+  if (!(w1 > 0.0) || !(num <= 9.0 * (w1 * w1))) return false;
+  e.dx = (float)dx;
+  e.dy = (float)dy;
+  const float wf = (float)w1;
+  e.iw = __builtin_amdgcn_rcpf(wf);
+  e.u = (float)u1 * e.iw;
+  e.v = (float)v1 * e.iw;
+  const float rho = fmaf(e.u, e.u, e.v * e.v);
+  e.G = __builtin_amdgcn_exp2f(rho * -0.72134752044448170f);  // exp(-rho/2)
+  const float oG = s.o * e.G;
+  e.clamped = oG > kAlphaMax;
+  e.alpha = e.clamped ? kAlphaMax : oG;
+  return e.alpha >= kAlphaMin;
+}
+
+// Tile index of a block: consecutive block ids are dispatched round-robin
+// over the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring
+// tiles share surfels, and each XCD has its own L2).
+__device__ inline int xcd_tile(int bid, int tiles) {
+  const int per = (tiles + 7) >> 3;
+  return (bid & 7) * per + (bid >> 3);
+}
+inline int xcd_grid(int64_t tiles) { return (int)(((tiles + 7) >> 3) << 3); }
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------ feature loads (to float)
+// Storage types: float, __half, and uint16_t holding bf16 bits.
+template <typename FT>
+struct VecN {
+  static constexpr int N = 16 / sizeof(FT);  // elements per 16-byte load
+};
+
+template <typename FT>
+__device__ __forceinline__ void load_vec(const FT* p, float* v);
+template <>
+__device__ __forceinline__ void load_vec<float>(const float* p, float* v) {
+  const float4 x = *reinterpret_cast<const float4*>(p);
+  v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+}
+template <>
+__device__ __forceinline__ void load_vec<__half>(const __half* p, float* v) {
+  const uint4 x = *reinterpret_cast<const uint4*>(p);
+  const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[2 * i] = __half2float(__ushort_as_half((unsigned short)(w[i] & 0xFFFF)));
+    v[2 * i + 1] = __half2float(__ushort_as_half((unsigned short)(w[i] >> 16)));
+  }
+}
+template <>
+__device__ __forceinline__ void load_vec<uint16_t>(const uint16_t* p, float* v) {
+  const uint4 x = *reinterpret_cast<const uint4*>(p);
+  const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[2 * i] = __uint_as_float(w[i] << 16);
+    v[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);
+  }
+}
+template <typename FT>
+__device__ __forceinline__ float load_one(const FT* p);
+template <>
+__device__ __forceinline__ float load_one<float>(const float* p) { return *p; }
+template <>
+__device__ __forceinline__ float load_one<__half>(const __half* p) { return __half2float(*p); }
+template <>
+__device__ __forceinline__ float load_one<uint16_t>(const uint16_t* p) {
+  return __uint_as_float(((uint32_t)*p) << 16);
+}
+
+__device__ __forceinline__ int pow2_ge(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+}  // namespace psm

@@ -1,0 +1,430 @@
+// Key stage of the rasterizer (Sec. 5, Precise Tile Intersection):
+//   preprocess  -- per surfel: rotation, camera space, culling, the projected
+//                  cutoff ellipse, its footprint count, the walk record;
+//   count scan  -- exclusive prefix of the counts in depth order;
+//   emission    -- (tile id, surfel id) pairs, written in depth order;
+//   tile ranges -- [start, end) of every tile in the tile-sorted pair list.
+//
+// Every floating-point decision here (cull, depth key, footprint) follows one
+// prescribed sequence of IEEE FP32 operations: this translation unit is built
+// with -ffp-contract=off and correctly rounded division and square root.
+#include "common.h"
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace psm {
+
+struct Cam {
+  float R[9], t[3], fx, fy, cx, cy, near_plane;
+  int W, H;
+};
+
+// Projected cutoff ellipse of a visible surfel.
+struct Foot {
+  float ecx, ecy, S00, S01, S11, ex, ey, gam, kk;
+};
+
+// Quantities of the prescribed FP32 key stage for one surfel.
+struct Key {
+  int cull;
+  int flip;
+  float mc2, p, q, xc, yc, A00, A01, A10, A11, dA;
+  float nc[3];
+  Foot f;
+};
+
+__device__ __noinline__ Key key_stage(const float* mu, const float* sc, const float* qq, const Cam& k) {
+  Key r;
+  r.cull = 0;
+  r.flip = 0;
+  const float nq = ((qq[0] * qq[0] + qq[1] * qq[1]) + qq[2] * qq[2]) + qq[3] * qq[3];
+  if (!(nq > 0.0f)) { r.cull = 1; return r; }
+  const float rn = 1.0f / sqrtf(nq);
+  const float w = qq[0] * rn, x = qq[1] * rn, y = qq[2] * rn, z = qq[3] * rn;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  const float xy = x * y, xz = x * z, yz = y * z;
+  const float wx = w * x, wy = w * y, wz = w * z;
+  const float tu0 = 1.0f - 2.0f * (yy + zz), tu1 = 2.0f * (xy + wz), tu2 = 2.0f * (xz - wy);
+  const float tv0 = 2.0f * (xy - wz), tv1 = 1.0f - 2.0f * (xx + zz), tv2 = 2.0f * (yz + wx);
+  const float nn0 = 2.0f * (xz + wy), nn1 = 2.0f * (yz - wx), nn2 = 1.0f - 2.0f * (xx + yy);
+  float mc[3], a[3], b[3], rnv[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float R0 = k.R[3 * i], R1 = k.R[3 * i + 1], R2 = k.R[3 * i + 2];
+    mc[i] = ((R0 * mu[0] + R1 * mu[1]) + R2 * mu[2]) + k.t[i];
+    const float ra = (R0 * tu0 + R1 * tu1) + R2 * tu2;
+    const float rb = (R0 * tv0 + R1 * tv1) + R2 * tv2;
+    rnv[i] = (R0 * nn0 + R1 * nn1) + R2 * nn2;
+    a[i] = sc[0] * ra;
+    b[i] = sc[1] * rb;
+  }
+  const float dn = (rnv[0] * mc[0] + rnv[1] * mc[1]) + rnv[2] * mc[2];
+  r.flip = dn > 0.0f ? 1 : 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) r.nc[i] = r.flip ? -rnv[i] : rnv[i];
+  if (!(mc[2] > k.near_plane)) { r.cull = 2; return r; }
+  const float zmin = mc[2] - kCut * sqrtf(a[2] * a[2] + b[2] * b[2]);
+  if (!(zmin > k.near_plane)) { r.cull = 3; return r; }
+  const float iz = 1.0f / mc[2];
+  const float p = a[2] * iz, q = b[2] * iz;
+  const float g2 = p * p + q * q;
+  const float gam = 1.0f - kFoot2 * g2;
+  if (!(gam > 0.0f)) { r.cull = 3; return r; }
+  const float mx = mc[0] * iz, my = mc[1] * iz;
+  const float xc = k.fx * mx + k.cx, yc = k.fy * my + k.cy;
+  const float A00 = k.fx * ((a[0] - mx * a[2]) * iz);
+  const float A01 = k.fx * ((b[0] - mx * b[2]) * iz);
+  const float A10 = k.fy * ((a[1] - my * a[2]) * iz);
+  const float A11 = k.fy * ((b[1] - my * b[2]) * iz);
+  const float dA = A00 * A11 - A01 * A10;
+  if (!(fabsf(dA) > 0.0f)) { r.cull = 4; return r; }
+  const float cc = kFoot2 / gam;
+  const float w0 = A00 * p + A01 * q, w1 = A10 * p + A11 * q;
+  const float S00 = cc * ((A00 * A00 + A01 * A01) + cc * (w0 * w0));
+  const float S01 = cc * ((A00 * A10 + A01 * A11) + cc * (w0 * w1));
+  const float S11 = cc * ((A10 * A10 + A11 * A11) + cc * (w1 * w1));
+  if (!(S00 > 0.0f && S11 > 0.0f && S00 < 1e24f && S11 < 1e24f)) { r.cull = 4; return r; }
+  r.mc2 = mc[2]; r.p = p; r.q = q; r.xc = xc; r.yc = yc;
+  r.A00 = A00; r.A01 = A01; r.A10 = A10; r.A11 = A11; r.dA = dA;
+  r.f.ecx = xc - cc * w0;
+  r.f.ecy = yc - cc * w1;
+  r.f.S00 = S00; r.f.S01 = S01; r.f.S11 = S11;
+  r.f.ex = sqrtf(S00);
+  r.f.ey = sqrtf(S11);
+  r.f.gam = gam;
+  r.f.kk = fabsf(cc * dA);
+  return r;
+}
+
+// Walk record of a visible surfel (not part of any decision): the centred,
+// depth-normalised homography's A^-1, e = (p, q) A^-1 and the projected centre,
+// evaluated and kept in FP64 (the per-pixel solve is FP64 as well).
+__device__ __noinline__ void walk_record(const float* mu_f, const float* sc, const float* qf, float o,
+                                         const float* rgb, const float* nc, const Cam& k, WalkRec* out) {
+  const double q0 = qf[0], q1 = qf[1], q2 = qf[2], q3 = qf[3];
+  const double rn = 1.0 / sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+  const double w = q0 * rn, x = q1 * rn, y = q2 * rn, z = q3 * rn;
+  const double tu[3] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y + w * z), 2.0 * (x * z - w * y)};
+  const double tv[3] = {2.0 * (x * y - w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z + w * x)};
+  double mc[3], a[3], b[3];
+  for (int i = 0; i < 3; ++i) {
+    const double R0 = k.R[3 * i], R1 = k.R[3 * i + 1], R2 = k.R[3 * i + 2];
+    mc[i] = R0 * mu_f[0] + R1 * mu_f[1] + R2 * mu_f[2] + (double)k.t[i];
+    a[i] = sc[0] * (R0 * tu[0] + R1 * tu[1] + R2 * tu[2]);
+    b[i] = sc[1] * (R0 * tv[0] + R1 * tv[1] + R2 * tv[2]);
+  }
+  const double iz = 1.0 / mc[2];
+  const double p = a[2] * iz, q = b[2] * iz, mx = mc[0] * iz, my = mc[1] * iz;
+  const double xc = (double)k.fx * mx + (double)k.cx, yc = (double)k.fy * my + (double)k.cy;
+  const double A00 = k.fx * (a[0] - mx * a[2]) * iz, A01 = k.fx * (b[0] - mx * b[2]) * iz;
+  const double A10 = k.fy * (a[1] - my * a[2]) * iz, A11 = k.fy * (b[1] - my * b[2]) * iz;
+  const double idA = 1.0 / (A00 * A11 - A01 * A10);
+  const double i00 = A11 * idA, i01 = -A01 * idA, i10 = -A10 * idA, i11 = A00 * idA;
+  const double e0 = p * i00 + q * i10, e1 = p * i01 + q * i11;
+  WalkRec r;
+  r.d0 = make_double2(i00, i01);
+  r.d1 = make_double2(i10, i11);
+  r.d2 = make_double2(e0, e1);
+  r.d3 = make_double2(xc, yc);
+  r.f0 = make_float4((float)mc[2], o, rgb[0], rgb[1]);
+  r.f1 = make_float4(rgb[2], nc[0], nc[1], nc[2]);
+  *out = r;
+}
+
+// Tiles whose pixel-centre hull [t*T + 0.5, min(t*T + T - 0.5, npix - 0.5)]
+// meets [lo, hi] along one axis.
+__device__ __forceinline__ bool tile_span(float lo, float hi, int npix, int nt, int& t0, int& t1) {
+  if (!(hi >= 0.5f) || !(lo <= (float)npix - 0.5f)) return false;
+  float f0 = ceilf((lo - ((float)kTile - 0.5f)) / (float)kTile);
+  float f1 = floorf((hi - 0.5f) / (float)kTile);
+  f0 = fmaxf(f0, 0.0f);
+  f1 = fminf(f1, (float)(nt - 1));
+  if (!(f0 <= f1)) return false;
+  t0 = (int)f0;
+  t1 = (int)f1;
+  return true;
+}
+
+// Calls fn(ty, tx0, tx1) for each tile row of the footprint of mode `mode`.
+template <class F>
+__device__ __forceinline__ void for_each_row(const Foot& f, int mode, int W, int H, int ntx, int nty, F&& fn) {
+  int ax0, ax1, ay0, ay1;
+  if (mode == kSphere) {
+    const float hs = 0.5f * (f.S00 + f.S11);
+    const float hd = 0.5f * (f.S00 - f.S11);
+    const float lmax = hs + sqrtf(hd * hd + f.S01 * f.S01);
+    const float rr = fmaxf(sqrtf(lmax), fmaxf(f.ex, f.ey));
+    if (!tile_span(f.ecx - rr, f.ecx + rr, W, ntx, ax0, ax1)) return;
+    if (!tile_span(f.ecy - rr, f.ecy + rr, H, nty, ay0, ay1)) return;
+    for (int ty = ay0; ty <= ay1; ++ty) fn(ty, ax0, ax1);
+    return;
+  }
+  if (!tile_span(f.ecx - f.ex, f.ecx + f.ex, W, ntx, ax0, ax1)) return;
+  if (!tile_span(f.ecy - f.ey, f.ecy + f.ey, H, nty, ay0, ay1)) return;
+  if (mode == kAabb) {
+    for (int ty = ay0; ty <= ay1; ++ty) fn(ty, ax0, ax1);
+    return;
+  }
+  // exact ellipse: x-extent of the ellipse inside each tile row's band
+  const float yr = f.S01 / f.ex;
+  for (int ty = ay0; ty <= ay1; ++ty) {
+    const float ylo = ((float)(ty * kTile) + 0.5f) - f.ecy;
+    const float yhi = fminf((float)(ty * kTile) + ((float)kTile - 0.5f), (float)H - 0.5f) - f.ecy;
+    const float lo = fmaxf(ylo, -f.ey), hi = fminf(yhi, f.ey);
+    if (!(lo <= hi)) continue;
+    const float dR = fminf(fmaxf(yr, lo), hi);
+    const float dL = fminf(fmaxf(-yr, lo), hi);
+    const float hR = sqrtf(fmaxf(0.0f, (f.S11 - dR * dR) / f.gam)) * f.kk;
+    const float hL = sqrtf(fmaxf(0.0f, (f.S11 - dL * dL) / f.gam)) * f.kk;
+    const float xR = (f.S01 * dR + hR) / f.S11;
+    const float xL = (f.S01 * dL - hL) / f.S11;
+    int x0, x1;
+    if (!tile_span(f.ecx + xL, f.ecx + xR, W, ntx, x0, x1)) continue;
+    x0 = max(x0, ax0);
+    x1 = min(x1, ax1);
+    if (x0 <= x1) fn(ty, x0, x1);
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = i; j < count; j += stride) p[j] = v;
+}
+
+__global__ void k_init_status(uint32_t* __restrict__ st, uint32_t n) {
+  const int i = threadIdx.x;
+  if (i < kStWords) st[i] = (i == kStN) ? n : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_preprocess(
+    int64_t n, const float* __restrict__ means, const float* __restrict__ scales,
+    const float* __restrict__ quats, const float* __restrict__ opacity, const float* __restrict__ rgb,
+    Cam cam, int mode, int ntx, int nty, WalkRec* __restrict__ rec, float4* __restrict__ fp,
+    uint32_t* __restrict__ key, uint32_t* __restrict__ ids, uint32_t* __restrict__ count,
+    int32_t* __restrict__ cull, uint32_t* __restrict__ status) {
+  __shared__ uint32_t s_cnt[5];
+  if (threadIdx.x < 5) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const Key kk = key_stage(means + 3 * i, scales + 2 * i, quats + 4 * i, cam);
+    ids[i] = (uint32_t)i;
+    cull[i] = kk.cull | (kk.flip << 8);  // bit 8: normal flipped toward the camera
+    atomicAdd(&s_cnt[kk.cull], 1u);
+    if (kk.cull != 0) {
+      key[i] = 0xFFFFFFFFu;
+      count[i] = 0;
+    } else {
+      key[i] = __float_as_uint(kk.mc2);
+      uint32_t c = 0;
+      for_each_row(kk.f, mode, cam.W, cam.H, ntx, nty, [&](int, int x0, int x1) { c += (uint32_t)(x1 - x0 + 1); });
+      count[i] = c;
+      fp[3 * i + 0] = make_float4(kk.f.ecx, kk.f.ecy, kk.f.S00, kk.f.S01);
+      fp[3 * i + 1] = make_float4(kk.f.S11, kk.f.ex, kk.f.ey, kk.f.gam);
+      fp[3 * i + 2] = make_float4(kk.f.kk, 0.0f, 0.0f, 0.0f);
+      walk_record(means + 3 * i, scales + 2 * i, quats + 4 * i, opacity[i], rgb + 3 * i, kk.nc, cam,
+                  rec + i);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 5 && s_cnt[threadIdx.x]) atomicAdd(&status[kStCull + threadIdx.x], s_cnt[threadIdx.x]);
+  if (threadIdx.x == 0 && s_cnt[0]) atomicAdd(&status[kStVisible], s_cnt[0]);
+}
+
+// ---- exclusive scan of the pair counts, gathered in depth order ------------
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(int64_t n, const uint32_t* __restrict__ order,
+                                                             const uint32_t* __restrict__ count,
+                                                             uint64_t* __restrict__ bsum) {
+  __shared__ uint64_t s[kScanThreads];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  uint64_t acc = 0;
+#pragma unroll 4
+  for (int j = 0; j < kScanItems; ++j) {
+    const int64_t r = base + (int64_t)j * kScanThreads + threadIdx.x;
+    if (r < n) acc += count[order[r]];
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = kScanThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = s[0];
+}
+
+// One block: exclusive scan of the block sums, total -> status.
+__global__ __launch_bounds__(1024) void k_scan_top(int64_t nb, uint64_t* __restrict__ bsum, int64_t cap,
+                                                   uint32_t* __restrict__ status) {
+  __shared__ uint64_t s[1024];
+  const int t = threadIdx.x;
+  const int64_t per = cdiv(nb, 1024);
+  const int64_t b0 = t * per, b1 = min<int64_t>(nb, b0 + per);
+  uint64_t acc = 0;
+  for (int64_t b = b0; b < b1; ++b) acc += bsum[b];
+  s[t] = acc;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    uint64_t v = t >= o ? s[t - o] : 0;
+    __syncthreads();
+    s[t] += v;
+    __syncthreads();
+  }
+  uint64_t run = s[t] - acc;
+  for (int64_t b = b0; b < b1; ++b) {
+    const uint64_t v = bsum[b];
+    bsum[b] = run;
+    run += v;
+  }
+  if (t == 1023) {
+    const uint64_t total = s[1023];
+    status[kStReqLo] = (uint32_t)total;
+    status[kStReqHi] = (uint32_t)(total >> 32);
+    status[kStP] = (uint32_t)(total < (uint64_t)cap ? total : (uint64_t)cap);
+    status[kStOverflow] = total > (uint64_t)cap ? 1u : 0u;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(int64_t n, const uint32_t* __restrict__ order,
+                                                           const uint32_t* __restrict__ count,
+                                                           const uint64_t* __restrict__ bsum,
+                                                           uint32_t* __restrict__ offs) {
+  __shared__ uint64_t s[kScanThreads];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint64_t acc = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    const int64_t r = base + j;
+    v[j] = r < n ? count[order[r]] : 0u;
+    acc += v[j];
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 1; o < kScanThreads; o <<= 1) {
+    uint64_t x = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+    __syncthreads();
+    s[threadIdx.x] += x;
+    __syncthreads();
+  }
+  uint64_t run = bsum[blockIdx.x] + s[threadIdx.x] - acc;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    const int64_t r = base + j;
+    if (r < n) offs[r] = (uint32_t)run;
+    run += v[j];
+  }
+}
+
+// ---- pair emission in depth order --------------------------------------------
+__global__ __launch_bounds__(256) void k_emit(int64_t n, const uint32_t* __restrict__ order,
+                                              const uint32_t* __restrict__ count,
+                                              const uint32_t* __restrict__ offs, const float4* __restrict__ fp,
+                                              int mode, int W, int H, int ntx, int nty, int64_t cap,
+                                              uint32_t* __restrict__ ptile, uint32_t* __restrict__ pid) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const uint32_t i = order[r];
+  if (count[i] == 0) return;
+  const float4 f0 = fp[3 * i], f1 = fp[3 * i + 1], f2 = fp[3 * i + 2];
+  const Foot f{f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w, f2.x};
+  int64_t o = offs[r];
+  for_each_row(f, mode, W, H, ntx, nty, [&](int ty, int x0, int x1) {
+    for (int tx = x0; tx <= x1; ++tx, ++o) {
+      if (o < cap) {
+        ptile[o] = (uint32_t)(ty * ntx + tx);
+        pid[o] = i;
+      }
+    }
+  });
+}
+
+// Per-surfel key-stage results in surfel order (inspection / tests).
+__global__ __launch_bounds__(256) void k_export_keys(int64_t n, const int32_t* __restrict__ cull,
+                                                     const uint32_t* __restrict__ skey,
+                                                     const uint32_t* __restrict__ sid,
+                                                     const uint32_t* __restrict__ count, int32_t* __restrict__ o_cull,
+                                                     uint32_t* __restrict__ o_depth, int32_t* __restrict__ o_count) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  if (o_cull) o_cull[r] = cull[r] & 0xFF;
+  if (o_count) o_count[r] = (int32_t)count[r];
+  if (o_depth) {
+    const uint32_t i = sid[r];  // depth-sorted rank r holds surfel i
+    o_depth[i] = cull[i] & 0xFF ? 0u : skey[r];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ ptile, const uint32_t* __restrict__ status,
+                                                uint2* __restrict__ ranges) {
+  const uint32_t P = status[kStP];
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= P) return;
+  const uint32_t t = ptile[j];
+  if (j == 0 || ptile[j - 1] != t) ranges[t].x = j;
+  if (j == P - 1 || ptile[j + 1] != t) ranges[t].y = j + 1;
+}
+
+// ------------------------------------------------------------- host wrappers
+static Cam to_cam(const CamArgs& c) {
+  Cam k;
+  for (int i = 0; i < 9; ++i) k.R[i] = c.R[i];
+  for (int i = 0; i < 3; ++i) k.t[i] = c.t[i];
+  k.fx = c.fx; k.fy = c.fy; k.cx = c.cx; k.cy = c.cy; k.near_plane = c.near_plane;
+  k.W = c.W; k.H = c.H;
+  return k;
+}
+
+void launch_fill_u32(void* p, uint32_t v, int64_t count, hipStream_t st) {
+  if (count <= 0) return;
+  const int64_t blocks = std::min<int64_t>(cdiv(count, 256), 4096);
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t*)p, v, count);
+}
+
+void launch_init_status(uint32_t* status, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, st, status, (uint32_t)n);
+}
+
+void launch_preprocess(const SurfelArgs& s, const CamArgs& c, int mode, const Layout& L, char* ws, hipStream_t st) {
+  if (s.n == 0) return;
+  hipLaunchKernelGGL(k_preprocess, dim3((unsigned)cdiv(s.n, 256)), dim3(256), 0, st, s.n, s.means, s.scales,
+                     s.quats, s.opacity, s.rgb, to_cam(c), mode, (int)L.ntx, (int)L.nty,
+                     (WalkRec*)(ws + L.rec), (float4*)(ws + L.fp), (uint32_t*)(ws + L.key0),
+                     (uint32_t*)(ws + L.id0), (uint32_t*)(ws + L.count), (int32_t*)(ws + L.cull),
+                     (uint32_t*)(ws + L.status));
+}
+
+void launch_scan_counts(const Layout& L, char* ws, hipStream_t st) {
+  const int64_t nb = std::max<int64_t>(1, cdiv(L.n, kScanTile));
+  const uint32_t* order = (const uint32_t*)(ws + L.id0);
+  const uint32_t* count = (const uint32_t*)(ws + L.count);
+  uint64_t* bsum = (uint64_t*)(ws + L.bsum);
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, L.n, order, count, bsum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, nb, bsum, L.cap, (uint32_t*)(ws + L.status));
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, st, L.n, order, count,
+                     (const uint64_t*)bsum, (uint32_t*)(ws + L.offs));
+}
+
+void launch_emit(const CamArgs& c, int mode, const Layout& L, char* ws, hipStream_t st) {
+  if (L.n == 0) return;
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)cdiv(L.n, 256)), dim3(256), 0, st, L.n,
+                     (const uint32_t*)(ws + L.id0), (const uint32_t*)(ws + L.count),
+                     (const uint32_t*)(ws + L.offs), (const float4*)(ws + L.fp), mode, c.W, c.H, (int)L.ntx,
+                     (int)L.nty, L.cap, (uint32_t*)(ws + L.ptile0), (uint32_t*)(ws + L.pid0));
+}
+
+void launch_export_keys(const Layout& L, char* ws, int32_t* cull, uint32_t* depth, int32_t* count, hipStream_t st) {
+  if (L.n == 0 || (!cull && !depth && !count)) return;
+  hipLaunchKernelGGL(k_export_keys, dim3((unsigned)cdiv(L.n, 256)), dim3(256), 0, st, L.n,
+                     (const int32_t*)(ws + L.cull), (const uint32_t*)(ws + L.key0), (const uint32_t*)(ws + L.id0),
+                     (const uint32_t*)(ws + L.count), cull, depth, count);
+}
+
+void launch_ranges(const Layout& L, char* ws, hipStream_t st) {
+  if (L.cap == 0) return;
+  hipLaunchKernelGGL(k_ranges, dim3((unsigned)cdiv(L.cap, 256)), dim3(256), 0, st,
+                     (const uint32_t*)(ws + L.ptile0), (const uint32_t*)(ws + L.status), (uint2*)(ws + L.ranges));
+}
+
+}  // namespace psm

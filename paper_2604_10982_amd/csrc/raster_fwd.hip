@@ -1,0 +1,377 @@
+// Forward compositing (Sec. 3.1 eq. (1); Sec. 5 eq. (18)).
+//
+// k_walk: one 16x16 tile per 256-thread block (4 wave64), one pixel per lane.
+//   Surfel records of the tile's depth-sorted list are staged in LDS in
+//   batches of 256 and read by broadcast.  Each lane walks front to back:
+//   ray/surfel intersection, alpha, transmittance, dense RGB/depth/normal/
+//   alpha blend, stop before T would fall below 1e-4, and (Top-K mode) a
+//   per-pixel register heap of the K largest weights with their list
+//   positions.  A block stops when all of its pixels are done.
+// k_blend_topk: eq. (18) gather-blend of the selected feature rows, lane per
+//   channel group (coalesced 16-byte loads), accumulated front to back.
+// k_full_feat: the dense feature blend of eq. (1) (the baseline the paper
+//   accelerates), channel-chunked re-walks with feature rows staged in LDS.
+#include "common.h"
+#include "internal.h"
+
+namespace psm {
+
+constexpr int kWalkBatch = 256;
+
+template <int N>
+__device__ __forceinline__ void sort_by_position(int (&p)[N], float (&w)[N]) {
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool up = (i & k) == 0;
+          const bool sw = up ? (p[i] > p[l]) : (p[i] < p[l]);
+          const int tp = p[i];
+          const float tw = w[i];
+          p[i] = sw ? p[l] : p[i];
+          w[i] = sw ? w[l] : w[i];
+          p[l] = sw ? tp : p[l];
+          w[l] = sw ? tw : w[l];
+        }
+      }
+    }
+  }
+}
+
+template <int KMAX, bool TOPK>
+__global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, const uint32_t* __restrict__ pid,
+                                              const uint2* __restrict__ ranges, int W, int H, int ntx, int tiles,
+                                              int K, float* __restrict__ o_rgb, float* __restrict__ o_depth,
+                                              float* __restrict__ o_normal, float* __restrict__ o_alpha,
+                                              uint32_t* __restrict__ nlast, float* __restrict__ tfinal,
+                                              int32_t* __restrict__ selpos, float* __restrict__ selw,
+                                              uint32_t* __restrict__ status) {
+  __shared__ Staged<kWalkBatch> s_r;
+  const int tile = xcd_tile(blockIdx.x, tiles);
+  if (tile >= tiles) return;
+  const int tid = threadIdx.x;
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
+  const bool inside = px < W && py < H;
+  const float lx = (float)(tid & 15) + 0.5f, ly = (float)(tid >> 4) + 0.5f;
+  const uint2 rg = ranges[tile];
+  const int L = (int)(rg.y - rg.x);
+
+  float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f, nx = 0.f, ny = 0.f, nz = 0.f;
+  int last = 0, walked = 0, blended = 0;
+  bool done = !inside;
+  float hw[KMAX];
+  int hp[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    hw[q] = q < K ? -1.0f : INFINITY;
+    hp[q] = -1;
+  }
+  float hmin = -1.0f;
+  int imin = 0, pmin = -1;
+
+  for (int base = 0; base < L; base += kWalkBatch) {
+    if (__syncthreads_count(done) == kTilePix) break;
+    const int j = base + tid;
+    if (j < L) s_r.put(tid, rec[pid[rg.x + j]], (float)(tx * kTile), (float)(ty * kTile));
+    __syncthreads();
+    const int nb = min(kWalkBatch, L - base);
+    for (int k = 0; k < nb; ++k) {
+      if (__all(done)) break;
+      if (done) continue;
+      ++walked;
+      const LRec s = s_r.get(k);
+      PixEval e;
+      if (!eval_pixel(s, lx, ly, e)) continue;
+      const float Tn = T * (1.0f - e.alpha);
+      if (Tn < kTMin) {
+        done = true;
+        continue;
+      }
+      const float w = e.alpha * T;
+      cr = fmaf(w, s.r, cr);
+      cg = fmaf(w, s.g, cg);
+      cb = fmaf(w, s.b, cb);
+      dep = fmaf(w, s.mz * e.iw, dep);
+      nx = fmaf(w, s.n0, nx);
+      ny = fmaf(w, s.n1, ny);
+      nz = fmaf(w, s.n2, nz);
+      T = Tn;
+      ++blended;
+      const int pos = base + k;
+      last = pos + 1;
+      if (TOPK && w > hmin) {
+        // replace the current minimum, then find the new minimum under the
+        // order (weight descending, position ascending)
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) {
+          const bool hit = q == imin;
+          hw[q] = hit ? w : hw[q];
+          hp[q] = hit ? pos : hp[q];
+        }
+        hmin = hw[0];
+        pmin = hp[0];
+        imin = 0;
+#pragma unroll
+        for (int q = 1; q < KMAX; ++q) {
+          const bool lt = hw[q] < hmin || (hw[q] == hmin && hp[q] > pmin);
+          hmin = lt ? hw[q] : hmin;
+          pmin = lt ? hp[q] : pmin;
+          imin = lt ? q : imin;
+        }
+      }
+    }
+  }
+
+  const int sp = tile * kTilePix + tid;
+  nlast[sp] = (uint32_t)last;
+  tfinal[sp] = T;
+  {
+    int wsum = walked, bsum = blended;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      wsum += __shfl_xor(wsum, o, 64);
+      bsum += __shfl_xor(bsum, o, 64);
+    }
+    if ((tid & 63) == 0) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(status + kStWalked), (unsigned long long)wsum);
+      atomicAdd(reinterpret_cast<unsigned long long*>(status + kStBlended), (unsigned long long)bsum);
+    }
+  }
+  if (inside) {
+    const int64_t pix = (int64_t)py * W + px;
+    if (o_rgb) {
+      o_rgb[3 * pix] = cr;
+      o_rgb[3 * pix + 1] = cg;
+      o_rgb[3 * pix + 2] = cb;
+    }
+    if (o_depth) o_depth[pix] = dep;
+    if (o_normal) {
+      o_normal[3 * pix] = nx;
+      o_normal[3 * pix + 1] = ny;
+      o_normal[3 * pix + 2] = nz;
+    }
+    if (o_alpha) o_alpha[pix] = 1.0f - T;
+  }
+  if (TOPK) {
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+      if (!(hw[q] >= 0.0f) || q >= K) hp[q] = 0x7FFFFFFF;
+    sort_by_position<KMAX>(hp, hw);
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+      if (q < K) {
+        const size_t o = ((size_t)tile * K + q) * kTilePix + tid;
+        const bool ok = hp[q] != 0x7FFFFFFF;
+        selpos[o] = ok ? hp[q] : -1;
+        selw[o] = ok ? hw[q] : 0.0f;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- features
+template <typename FT>
+__global__ __launch_bounds__(256) void k_blend_topk(const uint32_t* __restrict__ pid, const uint2* __restrict__ ranges,
+                                                    const int32_t* __restrict__ selpos,
+                                                    const float* __restrict__ selw, const FT* __restrict__ feat,
+                                                    int C, int K, int W, int H, int ntx, int tiles,
+                                                    float* __restrict__ o_feat) {
+  extern __shared__ char smem[];
+  int32_t* s_id = reinterpret_cast<int32_t*>(smem);
+  float* s_w = reinterpret_cast<float*>(smem + (size_t)K * kTilePix * 4);
+  const int tile = xcd_tile(blockIdx.x, tiles);
+  if (tile >= tiles) return;
+  const int tid = threadIdx.x;
+  const uint32_t start = ranges[tile].x;
+  for (int q = 0; q < K; ++q) {
+    const size_t o = ((size_t)tile * K + q) * kTilePix + tid;
+    const int pos = selpos[o];
+    s_id[q * kTilePix + tid] = pos >= 0 ? (int)pid[start + pos] : -1;
+    s_w[q * kTilePix + tid] = selw[o];
+  }
+  __syncthreads();
+  constexpr int V = VecN<FT>::N;
+  const int lpp = C / V;  // lanes needed per pixel
+  const int lpp2 = lpp >= 64 ? 64 : pow2_ge(lpp);
+  const int ppw = 64 / lpp2;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int sub = lane / lpp2, cl = lane % lpp2;
+  const int tx = tile % ntx, ty = tile / ntx;
+  for (int p0 = 0; p0 < 64; p0 += ppw) {
+    const int p = wave * 64 + p0 + sub;
+    const int px = tx * kTile + (p & 15), py = ty * kTile + (p >> 4);
+    if (px >= W || py >= H) continue;
+    float* out = o_feat + ((int64_t)py * W + px) * C;
+    for (int cgp = cl; cgp < lpp; cgp += lpp2) {
+      float acc[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[v] = 0.0f;
+      for (int q = 0; q < K; ++q) {
+        const int id = s_id[q * kTilePix + p];
+        if (id < 0) break;
+        const float w = s_w[q * kTilePix + p];
+        float f[V];
+        load_vec<FT>(feat + (size_t)id * C + cgp * V, f);
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = fmaf(w, f[v], acc[v]);
+      }
+#pragma unroll
+      for (int v = 0; v < V; v += 4)
+        *reinterpret_cast<float4*>(out + cgp * V + v) = make_float4(acc[v], acc[v + 1], acc[v + 2], acc[v + 3]);
+    }
+  }
+}
+
+constexpr int kFullBatch = 64;
+
+template <typename FT, int CH>
+__global__ __launch_bounds__(256) void k_full_feat(const WalkRec* __restrict__ rec, const uint32_t* __restrict__ pid,
+                                                   const uint2* __restrict__ ranges, const FT* __restrict__ feat,
+                                                   int C, int W, int H, int ntx, int tiles,
+                                                   const uint32_t* __restrict__ nlast, float* __restrict__ o_feat) {
+  __shared__ Staged<kFullBatch> s_r;
+  __shared__ float s_f[kFullBatch][CH];
+  __shared__ uint32_t s_id[kFullBatch];
+  __shared__ int s_lmax;
+  const int tile = xcd_tile(blockIdx.x, tiles);
+  if (tile >= tiles) return;
+  const int tid = threadIdx.x;
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
+  const bool inside = px < W && py < H;
+  const float lx = (float)(tid & 15) + 0.5f, ly = (float)(tid >> 4) + 0.5f;
+  const uint32_t start = ranges[tile].x;
+  const int my_last = (int)nlast[tile * kTilePix + tid];
+  if (tid == 0) s_lmax = 0;
+  __syncthreads();
+  atomicMax(&s_lmax, my_last);
+  __syncthreads();
+  const int Lw = s_lmax;
+  for (int c0 = 0; c0 < C; c0 += CH) {
+    float acc[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) acc[c] = 0.0f;
+    float T = 1.0f;
+    for (int base = 0; base < Lw; base += kFullBatch) {
+      const int nb = min(kFullBatch, Lw - base);
+      __syncthreads();
+      if (tid < nb) {
+        const uint32_t id = pid[start + base + tid];
+        s_id[tid] = id;
+        s_r.put(tid, rec[id], (float)(tx * kTile), (float)(ty * kTile));
+      }
+      __syncthreads();
+      for (int e = tid; e < nb * CH; e += 256) {
+        const int k = e / CH, c = e % CH;
+        float v = 0.0f;
+        if (c0 + c < C) {
+          v = load_one<FT>(feat + (size_t)s_id[k] * C + c0 + c);
+        }
+        s_f[k][c] = v;
+      }
+      __syncthreads();
+      for (int k = 0; k < nb; ++k) {
+        if (base + k >= my_last) break;
+        const LRec s = s_r.get(k);
+        PixEval ev;
+        if (!eval_pixel(s, lx, ly, ev)) continue;
+        const float w = ev.alpha * T;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) acc[c] = fmaf(w, s_f[k][c], acc[c]);
+        T = T * (1.0f - ev.alpha);
+      }
+    }
+    if (inside) {
+      float* out = o_feat + ((int64_t)py * W + px) * C + c0;
+      const int cn = min(CH, C - c0);
+#pragma unroll
+      for (int c = 0; c < CH; c += 4)
+        if (c < cn) *reinterpret_cast<float4*>(out + c) = make_float4(acc[c], acc[c + 1], acc[c + 2], acc[c + 3]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_export_sel(const uint32_t* __restrict__ pid, const uint2* __restrict__ ranges,
+                                                    const int32_t* __restrict__ selpos,
+                                                    const float* __restrict__ selw,
+                                                    const uint32_t* __restrict__ nlast,
+                                                    const float* __restrict__ tfinal, int K, int W, int H, int ntx,
+                                                    int tiles, int32_t* __restrict__ o_id, float* __restrict__ o_w,
+                                                    int32_t* __restrict__ o_nlast, float* __restrict__ o_tf) {
+  const int tile = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
+  if (px >= W || py >= H) return;
+  const int64_t pix = (int64_t)py * W + px;
+  const uint32_t start = ranges[tile].x;
+  for (int q = 0; q < K; ++q) {
+    const size_t o = ((size_t)tile * K + q) * kTilePix + tid;
+    const int pos = selpos ? selpos[o] : -1;
+    if (o_id) o_id[pix * K + q] = pos >= 0 ? (int32_t)pid[start + pos] : -1;
+    if (o_w) o_w[pix * K + q] = pos >= 0 ? selw[o] : 0.0f;
+  }
+  if (o_nlast) o_nlast[pix] = (int32_t)nlast[tile * kTilePix + tid];
+  if (o_tf) o_tf[pix] = tfinal[tile * kTilePix + tid];
+}
+
+// ------------------------------------------------------------- host wrappers
+template <int KMAX, bool TOPK>
+static void walk_launch(const Layout& L, const CamArgs& c, const ImageArgs& out, char* ws, hipStream_t st) {
+  hipLaunchKernelGGL((k_walk<KMAX, TOPK>), dim3(xcd_grid(L.tiles)), dim3(256), 0, st, (const WalkRec*)(ws + L.rec),
+                     (const uint32_t*)(ws + L.pid0), (const uint2*)(ws + L.ranges), c.W, c.H, (int)L.ntx,
+                     (int)L.tiles, L.k, out.rgb, out.depth, out.normal, out.alpha, (uint32_t*)(ws + L.nlast),
+                     (float*)(ws + L.tfinal), (int32_t*)(ws + L.selpos), (float*)(ws + L.selw),
+                     (uint32_t*)(ws + L.status));
+}
+
+void launch_walk(const Layout& L, const CamArgs& c, int blend, const ImageArgs& out, char* ws, hipStream_t st) {
+  if (blend == kFull) {
+    walk_launch<1, false>(L, c, out, ws, st);
+  } else if (L.k <= 8) {
+    walk_launch<8, true>(L, c, out, ws, st);
+  } else if (L.k <= 16) {
+    walk_launch<16, true>(L, c, out, ws, st);
+  } else {
+    walk_launch<32, true>(L, c, out, ws, st);
+  }
+}
+
+template <typename FT>
+static void blend_launch(const SurfelArgs& s, const Layout& L, const CamArgs& c, int blend, float* out_feat,
+                         char* ws, hipStream_t st) {
+  if (blend == kTopK) {
+    const size_t shm = (size_t)L.k * kTilePix * 8;
+    hipLaunchKernelGGL((k_blend_topk<FT>), dim3(xcd_grid(L.tiles)), dim3(256), shm, st,
+                       (const uint32_t*)(ws + L.pid0), (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos),
+                       (const float*)(ws + L.selw), (const FT*)s.feat, s.c, L.k, c.W, c.H, (int)L.ntx, (int)L.tiles,
+                       out_feat);
+  } else {
+    hipLaunchKernelGGL((k_full_feat<FT, 64>), dim3(xcd_grid(L.tiles)), dim3(256), 0, st, (const WalkRec*)(ws + L.rec),
+                       (const uint32_t*)(ws + L.pid0), (const uint2*)(ws + L.ranges), (const FT*)s.feat, s.c, c.W,
+                       c.H, (int)L.ntx, (int)L.tiles, (const uint32_t*)(ws + L.nlast), out_feat);
+  }
+}
+
+void launch_feature_blend(const SurfelArgs& s, const Layout& L, const CamArgs& c, int blend, float* out_feat,
+                          char* ws, hipStream_t st) {
+  if (!out_feat || s.c <= 0) return;
+  if (s.dtype == kF32) blend_launch<float>(s, L, c, blend, out_feat, ws, st);
+  else if (s.dtype == kF16) blend_launch<__half>(s, L, c, blend, out_feat, ws, st);
+  else blend_launch<uint16_t>(s, L, c, blend, out_feat, ws, st);
+}
+
+void launch_export_selection(const Layout& L, const CamArgs& c, char* ws, int32_t* sel_id, float* sel_w,
+                             int32_t* n_last, float* t_final, hipStream_t st) {
+  hipLaunchKernelGGL(k_export_sel, dim3((unsigned)L.tiles), dim3(256), 0, st, (const uint32_t*)(ws + L.pid0),
+                     (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos), (const float*)(ws + L.selw),
+                     (const uint32_t*)(ws + L.nlast), (const float*)(ws + L.tfinal), L.k, c.W, c.H, (int)L.ntx,
+                     (int)L.tiles, sel_id, sel_w, n_last, t_final);
+}
+
+}  // namespace psm

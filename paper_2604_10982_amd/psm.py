@@ -1,0 +1,342 @@
+"""ctypes binding of libpsm.so (include/psm.h).
+
+Argument marshalling only: torch provides device memory and the stream;
+every step of the render runs in the library's HIP kernels.  There is no
+fallback: if libpsm.so is missing or the device is not usable, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpsm.so")
+
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_CAPACITY, ERR_HIP = 0, -1, -2, -3, -4
+TILE_MODES = {"sphere": 0, "aabb": 1, "ellipse": 2}
+BLENDS = {"full": 0, "topk": 1}
+DTYPES = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2}
+FLAG_NO_SYNC = 1
+FLAG_PROFILE = 2
+NUM_STAGES = 12
+
+# Every symbol include/psm.h declares.
+EXPORTS = ("psm_create", "psm_destroy", "psm_workspace_size", "psm_forward", "psm_backward",
+           "psm_read_stats", "psm_read_pairs", "psm_read_selection", "psm_profile_read", "psm_profile_reset",
+           "psm_last_error", "psm_version")
+
+
+class PsmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"psm error {status}: {msg}")
+        self.status = status
+
+
+class CapacityError(PsmError):
+    pass
+
+
+class Surfels(C.Structure):
+    _fields_ = [("n", C.c_int64), ("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity", C.c_void_p), ("rgb", C.c_void_p), ("feat", C.c_void_p), ("c", C.c_int32),
+                ("feat_dtype", C.c_int32)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("near_plane", C.c_float), ("width", C.c_int32),
+                ("height", C.c_int32)]
+
+
+class Config(C.Structure):
+    _fields_ = [("k", C.c_int32), ("tile_mode", C.c_int32), ("blend", C.c_int32), ("flags", C.c_int32)]
+
+
+class Images(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("rgb", "depth", "normal", "alpha", "feat")]
+
+
+class ImageGrads(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("rgb", "depth", "normal", "alpha", "feat")]
+
+
+class Grads(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("means", "scales", "quats", "opacity", "rgb", "feat")]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("visible", C.c_int64), ("culled", C.c_int64 * 5), ("pairs", C.c_int64),
+                ("pairs_required", C.c_int64), ("pair_capacity", C.c_int64), ("tiles", C.c_int64),
+                ("pairs_walked", C.c_int64), ("contributors", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpsm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_10982_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        L.psm_create.argtypes = [C.POINTER(vp), C.c_int]
+        L.psm_destroy.argtypes = [vp]
+        L.psm_destroy.restype = None
+        L.psm_workspace_size.argtypes = [i64, C.POINTER(Camera), C.POINTER(Config), i32, i64, C.POINTER(C.c_size_t)]
+        L.psm_forward.argtypes = [vp, C.POINTER(Surfels), C.POINTER(Camera), C.POINTER(Config), vp, C.c_size_t,
+                                  i64, C.POINTER(Images), vp]
+        L.psm_backward.argtypes = [vp, C.POINTER(Surfels), C.POINTER(Camera), C.POINTER(Config), vp, C.c_size_t,
+                                   i64, C.POINTER(ImageGrads), C.POINTER(Grads), vp]
+        L.psm_read_stats.argtypes = [vp, vp, i64, C.POINTER(Camera), C.POINTER(Config), i32, i64,
+                                     C.POINTER(Stats), vp]
+        L.psm_read_pairs.argtypes = [vp, vp, i64, C.POINTER(Camera), C.POINTER(Config), i32, i64, vp, vp, i64,
+                                     vp, vp, vp, C.POINTER(i64), vp]
+        L.psm_read_selection.argtypes = [vp, vp, i64, C.POINTER(Camera), C.POINTER(Config), i32, i64, vp, vp,
+                                         vp, vp, vp]
+        L.psm_profile_read.argtypes = [vp, i32, C.POINTER(C.c_char_p), C.POINTER(C.c_double), C.POINTER(i64)]
+        L.psm_profile_reset.argtypes = [vp]
+        L.psm_last_error.restype = C.c_char_p
+        L.psm_version.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("psm_destroy", "psm_last_error", "psm_version"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        msg = lib().psm_last_error().decode()
+        if status == ERR_CAPACITY:
+            raise CapacityError(status, f"{what}: {msg}")
+        raise PsmError(status, f"{what}: {msg}")
+
+
+class Context:
+    """Library context bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        _check(lib().psm_create(C.byref(h), device), "psm_create")
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.psm_destroy(self.handle)
+            self.handle = None
+
+
+_contexts: dict[int, Context] = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _contexts:
+        _contexts[device] = Context(device)
+    return _contexts[device]
+
+
+def camera_struct(cam) -> Camera:
+    """From a scenes.Camera (or anything with R, t, fx, fy, cx, cy, width, height, near)."""
+    c = Camera()
+    R = [float(v) for v in torch.as_tensor(cam.R, dtype=torch.float32).reshape(9).tolist()]
+    t = [float(v) for v in torch.as_tensor(cam.t, dtype=torch.float32).reshape(3).tolist()]
+    c.R[:] = R
+    c.t[:] = t
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.near_plane = float(getattr(cam, "near", 0.2))
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def config_struct(k: int, tile_mode="ellipse", blend="topk", flags: int = 0) -> Config:
+    tm = TILE_MODES[tile_mode] if isinstance(tile_mode, str) else int(tile_mode)
+    bl = BLENDS[blend] if isinstance(blend, str) else int(blend)
+    return Config(int(k), tm, bl, int(flags))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+@dataclass
+class Workspace:
+    """Caller-owned device workspace; also the state saved for the backward."""
+    buf: torch.Tensor
+    capacity: int
+    n: int
+    c: int
+    k: int
+
+    @property
+    def nbytes(self) -> int:
+        return self.buf.numel()
+
+
+def workspace_size(n: int, cam: Camera, cfg: Config, c: int, capacity: int) -> int:
+    out = C.c_size_t()
+    _check(lib().psm_workspace_size(n, C.byref(cam), C.byref(cfg), c, capacity, C.byref(out)), "psm_workspace_size")
+    return int(out.value)
+
+
+def alloc_workspace(n, cam: Camera, cfg: Config, c: int, capacity: int, device) -> Workspace:
+    nbytes = workspace_size(n, cam, cfg, c, capacity)
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return Workspace(buf[off:off + nbytes], capacity, n, c, cfg.k)
+
+
+def _surfels(means, scales, quats, opacity, rgb, feat) -> Surfels:
+    n = means.shape[0]
+    for name, t, w in (("means", means, 3), ("scales", scales, 2), ("quats", quats, 4), ("rgb", rgb, 3)):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (n, w):
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of shape ({n}, {w})")
+    if opacity.dtype != torch.float32 or not opacity.is_cuda or not opacity.is_contiguous() or opacity.numel() != n:
+        raise ValueError("opacity must be a contiguous float32 CUDA tensor of shape (n,)")
+    c, dt, fp = 0, 0, None
+    if feat is not None:
+        if (feat.dtype not in DTYPES or not feat.is_cuda or not feat.is_contiguous() or feat.dim() != 2
+                or feat.shape[0] != n):
+            raise ValueError("feat must be a contiguous (n, C) float32/float16/bfloat16 CUDA tensor")
+        c, dt, fp = int(feat.shape[1]), DTYPES[feat.dtype], feat.data_ptr()
+    return Surfels(n, means.data_ptr(), scales.data_ptr(), quats.data_ptr(), opacity.data_ptr(), rgb.data_ptr(),
+                   fp, c, dt)
+
+
+def alloc_images(cam: Camera, c: int, device) -> dict:
+    H, W = cam.height, cam.width
+    e = lambda *s: torch.empty(*s, dtype=torch.float32, device=device)
+    return {"rgb": e(H, W, 3), "depth": e(H, W), "normal": e(H, W, 3), "alpha": e(H, W),
+            "feat": e(H, W, c) if c > 0 else None}
+
+
+def capacity_guess(n: int, cam: Camera) -> int:
+    tiles = math.ceil(cam.width / 16) * math.ceil(cam.height / 16)
+    return int(min(2**31 - 1, 8 * n + 4 * tiles + 1024))
+
+
+def forward_into(ctx: Context, s: Surfels, cam: Camera, cfg: Config, ws: Workspace, out: dict, stream=None):
+    """Raw forward into preallocated outputs (no allocation, no retry)."""
+    imgs = Images(*(_ptr(out.get(k)) for k in ("rgb", "depth", "normal", "alpha", "feat")))
+    st = stream if stream is not None else _stream(ctx.device)
+    _check(lib().psm_forward(ctx.handle, C.byref(s), C.byref(cam), C.byref(cfg), _ptr(ws.buf), ws.nbytes,
+                             ws.capacity, C.byref(imgs), st), "psm_forward")
+
+
+def backward_into(ctx: Context, s: Surfels, cam: Camera, cfg: Config, ws: Workspace, gout: dict, grads: dict,
+                  stream=None):
+    g = ImageGrads(*(_ptr(gout.get(k)) for k in ("rgb", "depth", "normal", "alpha", "feat")))
+    gr = Grads(*(_ptr(grads.get(k)) for k in ("means", "scales", "quats", "opacity", "rgb", "feat")))
+    st = stream if stream is not None else _stream(ctx.device)
+    _check(lib().psm_backward(ctx.handle, C.byref(s), C.byref(cam), C.byref(cfg), _ptr(ws.buf), ws.nbytes,
+                              ws.capacity, C.byref(g), C.byref(gr), st), "psm_backward")
+
+
+def forward(means, scales, quats, opacity, rgb, feat, camera, k=16, tile_mode="ellipse", blend="topk",
+            capacity: int | None = None, ws: Workspace | None = None):
+    """Render; returns (images dict, workspace).  The workspace holds the
+    state the backward needs.  Re-allocates once if the pairs do not fit."""
+    device = means.device
+    ctx = context(device.index or 0)
+    s = _surfels(means, scales, quats, opacity, rgb, feat)
+    cam = camera if isinstance(camera, Camera) else camera_struct(camera)
+    cfg = config_struct(k, tile_mode, blend)
+    out = alloc_images(cam, s.c, device)
+    cap = capacity if capacity is not None else (ws.capacity if ws is not None else capacity_guess(s.n, cam))
+    for attempt in range(3):
+        if ws is None or ws.capacity < cap or ws.n != s.n or ws.c != s.c or ws.k != cfg.k:
+            ws = alloc_workspace(s.n, cam, cfg, s.c, cap, device)
+        try:
+            forward_into(ctx, s, cam, cfg, ws, out)
+            return out, ws
+        except CapacityError:
+            st = read_stats(ws, s.n, cam, cfg, s.c, ws.capacity, device)
+            cap = int(min(2**31 - 1, st.pairs_required * 1.15 + 1024))
+            ws = None
+    raise RuntimeError("pair capacity could not be satisfied")
+
+
+def backward(means, scales, quats, opacity, rgb, feat, camera, ws: Workspace, gout: dict, k=16,
+             tile_mode="ellipse", blend="topk") -> dict:
+    device = means.device
+    ctx = context(device.index or 0)
+    s = _surfels(means, scales, quats, opacity, rgb, feat)
+    cam = camera if isinstance(camera, Camera) else camera_struct(camera)
+    cfg = config_struct(k, tile_mode, blend)
+    n = s.n
+    z = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=device)
+    grads = {"means": z(n, 3), "scales": z(n, 2), "quats": z(n, 4), "opacity": z(n), "rgb": z(n, 3),
+             "feat": z(n, s.c) if s.c > 0 else None}
+    gout = {kk: (None if v is None else v.contiguous().float()) for kk, v in gout.items()}
+    backward_into(ctx, s, cam, cfg, ws, gout, grads)
+    return grads
+
+
+def read_stats(ws: Workspace, n, cam: Camera, cfg: Config, c, capacity, device=None) -> Stats:
+    ctx = context(ws.buf.device.index or 0)
+    st = Stats()
+    _check(lib().psm_read_stats(ctx.handle, _ptr(ws.buf), n, C.byref(cam), C.byref(cfg), c, capacity, C.byref(st),
+                                _stream(ctx.device)), "psm_read_stats")
+    return st
+
+
+def read_pairs(ws: Workspace, cam: Camera, cfg: Config) -> dict:
+    """Sorted pair list and per-surfel key-stage results, as CPU tensors."""
+    ctx = context(ws.buf.device.index or 0)
+    dev = ws.buf.device
+    st = read_stats(ws, ws.n, cam, cfg, ws.c, ws.capacity)
+    P = int(st.pairs)
+    tile = torch.empty(max(P, 1), dtype=torch.int32, device=dev)
+    ids = torch.empty(max(P, 1), dtype=torch.int32, device=dev)
+    n = max(ws.n, 1)
+    cull = torch.empty(n, dtype=torch.int32, device=dev)
+    depth = torch.empty(n, dtype=torch.int32, device=dev)
+    count = torch.empty(n, dtype=torch.int32, device=dev)
+    got = C.c_int64()
+    _check(lib().psm_read_pairs(ctx.handle, _ptr(ws.buf), ws.n, C.byref(cam), C.byref(cfg), ws.c, ws.capacity,
+                                _ptr(tile), _ptr(ids), P, _ptr(cull), _ptr(depth), _ptr(count), C.byref(got),
+                                _stream(ctx.device)), "psm_read_pairs")
+    return {"P": int(got.value), "tile": tile[:P].cpu(), "id": ids[:P].cpu(), "cull": cull[:ws.n].cpu(),
+            "depth_bits": depth[:ws.n].cpu().view(torch.int32), "count": count[:ws.n].cpu(), "stats": st}
+
+
+def read_selection(ws: Workspace, cam: Camera, cfg: Config) -> dict:
+    ctx = context(ws.buf.device.index or 0)
+    dev = ws.buf.device
+    H, W, K = cam.height, cam.width, cfg.k
+    sid = torch.empty(H, W, K, dtype=torch.int32, device=dev)
+    sw = torch.empty(H, W, K, dtype=torch.float32, device=dev)
+    nl = torch.empty(H, W, dtype=torch.int32, device=dev)
+    tf = torch.empty(H, W, dtype=torch.float32, device=dev)
+    _check(lib().psm_read_selection(ctx.handle, _ptr(ws.buf), ws.n, C.byref(cam), C.byref(cfg), ws.c, ws.capacity,
+                                    _ptr(sid), _ptr(sw), _ptr(nl), _ptr(tf), _stream(ctx.device)),
+           "psm_read_selection")
+    return {"sel_id": sid, "sel_w": sw, "n_last": nl, "T_final": tf}
+
+
+def profile_read(ctx: Context) -> dict:
+    """{stage name: (total ms, calls)} accumulated since the last reset."""
+    out = {}
+    for i in range(NUM_STAGES):
+        name, ms, calls = C.c_char_p(), C.c_double(), C.c_int64()
+        _check(lib().psm_profile_read(ctx.handle, i, C.byref(name), C.byref(ms), C.byref(calls)), "psm_profile_read")
+        out[name.value.decode()] = (float(ms.value), int(calls.value))
+    return out
+
+
+def profile_reset(ctx: Context):
+    _check(lib().psm_profile_reset(ctx.handle), "psm_profile_reset")
+
+
+def version() -> str:
+    return lib().psm_version().decode()

@@ -1,0 +1,79 @@
+"""The C-ABI library loads on a host without a GPU, exports every symbol
+include/psm.h declares, and rejects bad arguments on the host."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "psm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(psm_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def psm():
+    from paper_2604_10982_amd import psm as P
+    P.lib()
+    return P
+
+
+def test_exports_every_declared_symbol(psm):
+    names = declared_functions()
+    assert len(names) >= 10
+    assert set(names) == set(psm.EXPORTS)
+    L = psm.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert psm.version().startswith("psm")
+
+
+def _cam(psm, w=64, h=48):
+    c = psm.Camera()
+    c.R[:] = [1, 0, 0, 0, 1, 0, 0, 0, 1]
+    c.t[:] = [0, 0, 0]
+    c.fx = c.fy = 50.0
+    c.cx, c.cy = w / 2, h / 2
+    c.near_plane = 0.2
+    c.width, c.height = w, h
+    return c
+
+
+def test_host_validation(psm):
+    L = psm.lib()
+    cam = _cam(psm)
+    out = C.c_size_t()
+    ok = psm.config_struct(16)
+    assert L.psm_workspace_size(100, C.byref(cam), C.byref(ok), 16, 1000, C.byref(out)) == 0
+    assert out.value > 0
+    for k in (0, 33):
+        assert L.psm_workspace_size(100, C.byref(cam), C.byref(psm.config_struct(k)), 16, 1000,
+                                    C.byref(out)) == psm.ERR_INVALID_ARG
+    assert L.psm_workspace_size(100, C.byref(cam), C.byref(ok), 12, 1000, C.byref(out)) == psm.ERR_UNSUPPORTED
+    assert L.psm_workspace_size(-1, C.byref(cam), C.byref(ok), 16, 1000, C.byref(out)) == psm.ERR_INVALID_ARG
+    assert L.psm_workspace_size(100, C.byref(cam), C.byref(ok), 16, -5, C.byref(out)) == psm.ERR_INVALID_ARG
+    bad = _cam(psm)
+    bad.near_plane = 0.0
+    assert L.psm_workspace_size(100, C.byref(bad), C.byref(ok), 16, 1000, C.byref(out)) == psm.ERR_INVALID_ARG
+    bad = _cam(psm, w=0)
+    assert L.psm_workspace_size(100, C.byref(bad), C.byref(ok), 16, 1000, C.byref(out)) == psm.ERR_INVALID_ARG
+    assert "must" in L.psm_last_error().decode()
+    # null context / arguments are rejected before any device work
+    s = psm.Surfels()
+    imgs = psm.Images()
+    assert L.psm_forward(None, C.byref(s), C.byref(cam), C.byref(ok), None, 0, 0, C.byref(imgs), None) == \
+        psm.ERR_INVALID_ARG
+    assert L.psm_backward(None, C.byref(s), C.byref(cam), C.byref(ok), None, 0, 0, None, None, None) == \
+        psm.ERR_INVALID_ARG
+
+
+def test_workspace_grows_with_capacity(psm):
+    cam = _cam(psm)
+    cfg = psm.config_struct(16)
+    a = psm.workspace_size(1000, cam, cfg, 32, 10_000)
+    b = psm.workspace_size(1000, cam, cfg, 32, 20_000)
+    assert b - a >= 4 * 4 * 10_000

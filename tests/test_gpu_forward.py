@@ -1,0 +1,82 @@
+"""Forward parity of the HIP path with the FP64 oracle (Sec. 3.1 eq. (1),
+Sec. 5 eq. (18)): images within 1e-5 of sum_j w_j |x_j| per channel for FP32
+features, the Top-K selection itself, tile-mode invariance and Top-K = dense
+blend when K covers the depth complexity (bit-identical)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import OUTPUTS, image_errors, np_out, render, require_gpu, stored_feat, to_dev
+from paper_2604_10982_amd import psm, scenes
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = 1e-4   # pixels whose closest decision is within this relative margin are excluded (and counted)
+
+
+def _ref(orc, sc, cam, K, blend, feat):
+    ref = orc.render(sc, cam, K, orc.TOPK if blend == "topk" else orc.FULL, feat=feat)
+    absf = orc.render(sc, cam, K, orc.TOPK if blend == "topk" else orc.FULL, feat=np.abs(feat))["feat"]
+    return ref, absf
+
+
+CASES = {
+    "c1_box2k": lambda: scenes.config("c1_box2k")[:3],
+    "planes20k_ragged": lambda: (scenes.planes7(20_000, 16, seed=5), scenes.pinhole(328, 200), 16),
+    "room30k": lambda: (scenes.room6(30_000, 24, seed=6), scenes.pinhole(256, 192), 4),
+}
+
+
+@pytest.mark.parametrize("blend", ["topk", "full"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_images_match_oracle(orc, case, blend):
+    require_gpu()
+    sc, cam, K = CASES[case]()
+    t = to_dev(sc)
+    out, ws = render(t, cam, K, "ellipse", blend)
+    ref, absf = _ref(orc, sc, cam, K, blend, stored_feat(t))
+    ok = ref["margin"] > MARGIN
+    assert (~ok).mean() < 1e-3, f"{(~ok).sum()} pixels within the decision margin"
+    worst = image_errors(np_out(out), ref, absf, ok, 1e-5)
+    assert max(worst.values()) <= 1.0, worst
+    if blend == "topk":
+        sel = psm.read_selection(ws, psm.camera_struct(cam), psm.config_struct(K, "ellipse", "topk"))
+        np.testing.assert_array_equal(sel["sel_id"].cpu().numpy()[ok], ref["sel_id"][ok])
+
+
+def test_tile_modes_give_identical_images(orc):
+    require_gpu()
+    sc, cam, K = CASES["planes20k_ragged"]()
+    t = to_dev(sc)
+    outs = {m: np_out(render(t, cam, K, m, "topk")[0]) for m in ("sphere", "aabb", "ellipse")}
+    pairs = {}
+    for m in outs:
+        pairs[m] = orc.keystage(sc, cam, m, pairs=False)["P"]
+        for k in OUTPUTS:
+            np.testing.assert_array_equal(outs[m][k], outs["ellipse"][k], err_msg=f"{m} {k}")
+    assert pairs["ellipse"] < pairs["aabb"] < pairs["sphere"]
+
+
+def test_topk_equals_full_bitwise_when_k_covers_depth(orc):
+    require_gpu()
+    sc, cam, _ = CASES["c1_box2k"]()
+    t = to_dev(sc)
+    full, ws = render(t, cam, 8, "ellipse", "full")
+    ref = orc.render(sc, cam, 8, orc.FULL)
+    kmax = int(ref["ncontrib"].max())
+    assert kmax <= 32
+    topk, _ = render(t, cam, kmax, "ellipse", "topk")
+    for k in OUTPUTS:
+        assert torch.equal(topk[k], full[k]), k
+
+
+@pytest.mark.parametrize("K", [1, 3, 32])
+def test_small_and_large_k(orc, K):
+    require_gpu()
+    sc, cam, _ = CASES["c1_box2k"]()
+    t = to_dev(sc)
+    out, ws = render(t, cam, K, "ellipse", "topk")
+    ref, absf = _ref(orc, sc, cam, K, "topk", stored_feat(t))
+    ok = ref["margin"] > MARGIN
+    worst = image_errors(np_out(out), ref, absf, ok, 1e-5)
+    assert max(worst.values()) <= 1.0, worst

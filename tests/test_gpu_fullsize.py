@@ -1,0 +1,93 @@
+"""Parity at the full benchmark sizes, in the launch configuration the
+benchmark times: the key stage bit-exact on the whole frame, images on
+sampled pixels and gradients on sampled surfels (the oracle computes only
+those)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import DEV, image_errors, np_out, render, require_gpu, stored_feat, to_dev
+from paper_2604_10982_amd import psm, scenes
+from test_gpu_backward import grad_errors
+
+pytestmark = pytest.mark.gpu
+
+CONFIGS = ["c2_planes200k", "c3_planes500k", "planes1m_1080p", "c4_street1m"]
+
+
+def _sample_pixels(cam, rng, n=3000, tiles=3):
+    S = cam.width * cam.height
+    pix = set(rng.choice(S, n, replace=False).tolist())
+    ntx, nty = (cam.width + 15) // 16, (cam.height + 15) // 16
+    for t in rng.choice(ntx * nty, tiles, replace=False):
+        ty, tx = divmod(int(t), ntx)
+        for y in range(ty * 16, min(ty * 16 + 16, cam.height)):
+            for x in range(tx * 16, min(tx * 16 + 16, cam.width)):
+                pix.add(y * cam.width + x)
+    return np.array(sorted(pix), np.int64)
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_fullsize_keys_and_sampled_images(orc, name):
+    require_gpu()
+    sc, cam, K, dtype = scenes.config(name)
+    print(f"[fullsize] {name}: n={sc.n} {cam.width}x{cam.height} C={sc.c} K={K} {dtype}", flush=True)
+    t = to_dev(sc, dtype)
+    out, ws = render(t, cam, K, "ellipse", "topk")
+    got = psm.read_pairs(ws, psm.camera_struct(cam), psm.config_struct(K))
+    ref_k = orc.keystage(sc, cam, "ellipse")
+    assert got["P"] == ref_k["P"]
+    np.testing.assert_array_equal(got["cull"].numpy(), ref_k["cull"])
+    np.testing.assert_array_equal(got["tile"].numpy(), ref_k["tile"])
+    np.testing.assert_array_equal(got["id"].numpy(), ref_k["id"])
+    del got, ref_k
+    rng = np.random.default_rng(0)
+    pix = _sample_pixels(cam, rng)
+    feat = stored_feat(t)
+    ref = orc.render(sc, cam, K, orc.TOPK, feat=feat, pix=pix)
+    absf = orc.render(sc, cam, K, orc.TOPK, feat=np.abs(feat), pix=pix)["feat"]
+    g = np_out(out)
+    flat = {k: v.reshape(cam.width * cam.height, -1)[pix] for k, v in g.items()}
+    ok = ref["margin"] > 1e-4
+    assert (~ok).mean() < 1e-3
+    worst = image_errors(flat, ref, absf, ok, 1e-5 if dtype == "f32" else 1e-5)
+    assert max(worst.values()) <= 1.0, worst
+    sel = psm.read_selection(ws, psm.camera_struct(cam), psm.config_struct(K))
+    sid = sel["sel_id"].reshape(-1, K).cpu().numpy()[pix]
+    np.testing.assert_array_equal(sid[ok], ref["sel_id"][ok])
+
+
+def test_fullsize_sampled_gradients(orc):
+    require_gpu()
+    sc, cam, K, dtype = scenes.config("c3_planes500k")
+    t = to_dev(sc, dtype)
+    out, ws = render(t, cam, K, "ellipse", "topk")
+    ks = orc.keystage(sc, cam, "ellipse")
+    rng = np.random.default_rng(2)
+    cand = np.nonzero((ks["count"] > 0) & (ks["count"] <= 6))[0]
+    pick = rng.choice(cand, 48, replace=False)
+    mask = np.zeros(sc.n, np.uint8)
+    mask[pick] = 1
+    ntx = (cam.width + 15) // 16
+    tiles = np.unique(ks["tile"][mask[ks["id"]] == 1])
+    pix = []
+    for tt in tiles:
+        ty, tx = divmod(int(tt), ntx)
+        ys, xs = np.mgrid[ty * 16:min(ty * 16 + 16, cam.height), tx * 16:min(tx * 16 + 16, cam.width)]
+        pix.append((ys * cam.width + xs).ravel())
+    pix = np.unique(np.concatenate(pix)).astype(np.int64)
+    feat = stored_feat(t)
+    r = orc.render(sc, cam, K, orc.TOPK, feat=feat, pix=pix)
+    g = scenes.upstream(cam.height, cam.width, sc.c, seed=1)
+    bad = pix[r["margin"] <= 1e-4]
+    for k in g:
+        flat = g[k].reshape(cam.width * cam.height, -1)
+        flat[bad] = 0.0
+    gsub = {k: v.reshape(cam.width * cam.height, -1)[pix] for k, v in g.items()}
+    ref = orc.backward(sc, cam, gsub, K=K, blend=orc.TOPK, feat=feat, pix=pix, mask=mask)
+    gt = {k: torch.tensor(v, device=DEV) for k, v in g.items()}
+    got = psm.backward(t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"], cam, ws, gt, K)
+    got = {k: v.cpu().numpy().astype(np.float64)[pick] for k, v in got.items()}
+    ref = {k: v[pick] for k, v in ref.items()}
+    worst = grad_errors(got, ref)
+    assert max(worst.values()) <= 1e-3, worst

@@ -18,7 +18,7 @@ from paper_2604_10982_amd.scenes import Scene, pinhole
 R_FOOT2 = 9.0 * (1.0 + 2.0 ** -10)
 
 
-def varied_scene(n=300, seed=7, c=4):
+def varied_scene(n=300, seed=7, c=8):
     """Mixed sizes and orientations, some surfels close to edge-on."""
     rng = np.random.default_rng(seed)
     means = np.c_[rng.uniform(-1.6, 1.6, n), rng.uniform(-1.2, 1.2, n), rng.uniform(1.0, 8.0, n)]

@@ -146,7 +146,7 @@ def roofline(stages, st, K, C, S, bwd):
         "pair_sort": P * 8 * 2,
         "emit": P * 8 + st.visible * 56,
         "count_scan": N * 8,
-        "bwd_preprocess": N * (64 + 40 + 52),
+        "bwd_reduce": N * (64 + 40 + 52) + st.pairs * 80,
         "ranges": P * 4,
         "fill": N * 4 * (16 + C),
     }

@@ -180,7 +180,7 @@ psm_status psm_read_selection(psm_ctx* ctx, const void* workspace, int64_t n, co
 
 /* Stage timing (PSM_FLAG_PROFILE).  Stages are numbered 0 .. PSM_NUM_STAGES-1
  * (preprocess, depth_sort, count_scan, emit, pair_sort, ranges, walk,
- * feature_blend, bwd_feature, bwd_walk, bwd_preprocess, fill).  psm_profile_read
+ * feature_blend, bwd_feature, bwd_walk, bwd_reduce, fill).  psm_profile_read
  * synchronises the recorded events and returns, for `stage`, its name (static
  * string), the summed duration in ms and the number of recorded calls since
  * the last psm_profile_reset.  Events are recorded on the stream each call was

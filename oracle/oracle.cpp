@@ -396,26 +396,32 @@ struct Contrib {
   bool clamped;
 };
 
+// Relative distance of the pixel's decisions from their thresholds, by kind:
+// [0] rho vs r^2 (hit), [1] alpha vs 1/255 and vs the 0.99 clamp,
+// [2] T' vs 1e-4 (stop), [3] Top-K gap between the K-th and (K+1)-th weight.
+struct Margins {
+  double m[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+};
+
 // Front-to-back walk of one pixel (eq. (1)): skip non-hits and alpha < 1/255,
-// stop before a surfel that would take T below 1e-4.  Also returns the
-// smallest relative distance of any decision from its threshold.
+// stop before a surfel that would take T below 1e-4.
 void walk_pixel(const Scene& sc, const Prepared& P, const Cam& k, int px, int py,
-                std::vector<Contrib>& out, double& T_final, double& margin) {
+                std::vector<Contrib>& out, double& T_final, Margins& margin) {
   out.clear();
-  margin = INFINITY;
+  margin = Margins();
   const double x = px + 0.5, y = py + 0.5;
   const auto& bin = P.bins[(size_t)(py / P.th) * P.ntx + (px / P.tw)];
   double T = 1.0;
   for (int64_t id : bin) {
     Eval e = eval_pixel(P.geo[id], sc.opacity[id], x, y);
-    if (std::isfinite(e.rho)) margin = std::min(margin, std::fabs(e.rho - kCut2) / kCut2);
+    if (std::isfinite(e.rho)) margin.m[0] = std::min(margin.m[0], std::fabs(e.rho - kCut2) / kCut2);
     if (!e.hit) continue;
     double a_raw = sc.opacity[id] * e.G;
-    margin = std::min(margin, std::fabs(a_raw / kAlphaMax - 1.0));
-    margin = std::min(margin, std::fabs(e.alpha / kAlphaMin - 1.0));
+    margin.m[1] = std::min(margin.m[1], std::fabs(a_raw / kAlphaMax - 1.0));
+    margin.m[1] = std::min(margin.m[1], std::fabs(e.alpha / kAlphaMin - 1.0));
     if (e.alpha < kAlphaMin) continue;
     double Tn = T * (1.0 - e.alpha);
-    margin = std::min(margin, std::fabs(Tn / kTMin - 1.0));
+    margin.m[2] = std::min(margin.m[2], std::fabs(Tn / kTMin - 1.0));
     if (Tn < kTMin) break;
     out.push_back({id, e.alpha, T, e.alpha * T, e.z, e.clamped});
     T = Tn;
@@ -532,7 +538,7 @@ void orc_eval_points(int64_t n, const float* means, const float* scales, const f
 // pix == null).  Per entry: rgb[3] depth normal[3] alpha feat[C], the number
 // of blended surfels, T_final, the id of the last blended surfel, the
 // selected ids in front-to-back order with their weights (K slots, -1 pad)
-// and the decision margin (min over thresholds and the Top-K gap).
+// and the four decision margins (see Margins).
 void orc_render(int64_t n, const float* means, const float* scales, const float* quats,
                 const float* opacity, const float* rgb, const double* feat, int C,
                 const float* cam, int tw, int th, int K, int blend,
@@ -554,7 +560,8 @@ void orc_render(int64_t n, const float* means, const float* scales, const float*
     for (int64_t e = 0; e < cnt; ++e) {
       const int64_t p = pix ? pix[e] : e;
       const int px = (int)(p % k.W), py = (int)(p / k.W);
-      double T_final, margin, gap;
+      double T_final, gap;
+      Margins margin;
       walk_pixel(sc, P, k, px, py, cs, T_final, margin);
       double col[3] = {0, 0, 0}, nor[3] = {0, 0, 0}, dep = 0;
       for (const Contrib& c : cs) {
@@ -567,7 +574,7 @@ void orc_render(int64_t n, const float* means, const float* scales, const float*
       }
       if (blend == 1) select_topk(cs, K, sel, gap);
       else { sel.assign(cs.size(), 1); gap = INFINITY; }
-      if (blend == 1) margin = std::min(margin, gap);
+      if (blend == 1) margin.m[3] = gap;
       if (feat_out) {
         double* F = feat_out + e * C;
         for (int j = 0; j < C; ++j) F[j] = 0;
@@ -584,7 +591,8 @@ void orc_render(int64_t n, const float* means, const float* scales, const float*
       if (ncontrib_out) ncontrib_out[e] = (int32_t)cs.size();
       if (tfinal_out) tfinal_out[e] = T_final;
       if (last_out) last_out[e] = cs.empty() ? -1 : cs.back().id;
-      if (margin_out) margin_out[e] = margin;
+      if (margin_out)
+        for (int j = 0; j < 4; ++j) margin_out[4 * e + j] = margin.m[j];
       if (sel_id_out || sel_w_out) {
         int s = 0;
         for (size_t i = 0; i < cs.size() && s < K; ++i) {
@@ -630,7 +638,8 @@ void orc_backward(int64_t n, const float* means, const float* scales, const floa
     for (int64_t e = 0; e < cnt; ++e) {
       const int64_t p = pix ? pix[e] : e;
       const int px = (int)(p % k.W), py = (int)(p / k.W);
-      double T_final, margin, gap;
+      double T_final, gap;
+      Margins margin;
       walk_pixel(sc, P, k, px, py, cs, T_final, margin);
       const int m = (int)cs.size();
       if (m == 0) continue;
@@ -718,7 +727,8 @@ void orc_decisions(int64_t n, const float* means, const float* scales, const flo
 #pragma omp for schedule(dynamic, 64)
     for (int64_t e = 0; e < npix; ++e) {
       const int64_t p = pix[e];
-      double T_final, margin, gap;
+      double T_final, gap;
+      Margins margin;
       walk_pixel(sc, P, k, (int)(p % k.W), (int)(p / k.W), cs, T_final, margin);
       if (blend == 1) select_topk(cs, K, sel, gap);
       else sel.assign(cs.size(), 1);

@@ -130,17 +130,18 @@ def render(scene, cam, K=16, blend=TOPK, feat=None, pix=None, tile=16) -> dict:
         "rgb": np.zeros((cnt, 3)), "depth": np.zeros(cnt), "normal": np.zeros((cnt, 3)),
         "alpha": np.zeros(cnt), "feat": np.zeros((cnt, Cn)), "ncontrib": np.zeros(cnt, np.int32),
         "T_final": np.zeros(cnt), "last": np.zeros(cnt, np.int64),
-        "sel_id": np.zeros((cnt, K), np.int64), "sel_w": np.zeros((cnt, K)), "margin": np.zeros(cnt),
+        "sel_id": np.zeros((cnt, K), np.int64), "sel_w": np.zeros((cnt, K)), "margins": np.zeros((cnt, 4)),
     }
     lib().orc_render(n, _vp(mu), _vp(sc), _vp(q), _vp(_c32(scene.opacity)), _vp(_c32(scene.rgb)),
                      _vp(f64), Cn, _vp(cam.as_array()), tile, tile, K, int(blend),
                      0 if pix is None else pix.size, _vp(pix),
                      _vp(o["rgb"]), _vp(o["depth"]), _vp(o["normal"]), _vp(o["alpha"]), _vp(o["feat"]),
                      _vp(o["ncontrib"]), _vp(o["T_final"]), _vp(o["last"]), _vp(o["sel_id"]),
-                     _vp(o["sel_w"]), _vp(o["margin"]))
+                     _vp(o["sel_w"]), _vp(o["margins"]))
+    o["margin"] = o["margins"].min(-1)
     if pix is None:
         H, W = cam.height, cam.width
-        for key in ("rgb", "normal", "feat", "sel_id", "sel_w"):
+        for key in ("rgb", "normal", "feat", "sel_id", "sel_w", "margins"):
             o[key] = o[key].reshape(H, W, -1)
         for key in ("depth", "alpha", "ncontrib", "T_final", "last", "margin"):
             o[key] = o[key].reshape(H, W)

@@ -18,7 +18,7 @@ namespace {
 
 const char* const kStageNames[kNumStages] = {"preprocess", "depth_sort", "count_scan", "emit",
                                              "pair_sort",  "ranges",     "walk",       "feature_blend",
-                                             "bwd_feature", "bwd_walk",  "bwd_preprocess", "fill"};
+                                             "bwd_feature", "bwd_walk",  "bwd_reduce", "fill"};
 
 // HIP-event stage timer: an event pair per stage and call, on the call's stream.
 struct Profiler {
@@ -263,8 +263,8 @@ psm_status psm_forward(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cam
   launch_emit(ca, cfg->tile_mode, L, ws, st);
   prof.end(kStageEmit, st);
   prof.begin(kStagePairSort, st);
-  radix_sort_pairs((uint32_t*)(ws + L.ptile0), (uint32_t*)(ws + L.pid0), (uint32_t*)(ws + L.ptile1),
-                   (uint32_t*)(ws + L.pid1), status + kStP, L.cap, bits_for(L.tiles), hist, nb_max, st);
+  radix_sort_pairs((uint32_t*)(ws + L.ptile0), (uint32_t*)(ws + L.eid0), (uint32_t*)(ws + L.ptile1),
+                   (uint32_t*)(ws + L.eid1), status + kStP, L.cap, bits_for(L.tiles), hist, nb_max, st);
   prof.end(kStagePairSort, st);
   prof.begin(kStageRanges, st);
   launch_ranges(L, ws, st);
@@ -384,7 +384,7 @@ psm_status psm_read_pairs(psm_ctx* ctx, const void* workspace, int64_t n, const 
   if (pairs_out) *pairs_out = P;
   const int64_t m = std::min<int64_t>(P, cap);
   if (m > 0 && tile_out) (void)hipMemcpyAsync(tile_out, ws + L.ptile0, m * 4, hipMemcpyDeviceToDevice, st);
-  if (m > 0 && id_out) (void)hipMemcpyAsync(id_out, ws + L.pid0, m * 4, hipMemcpyDeviceToDevice, st);
+  if (m > 0 && id_out) (void)hipMemcpyAsync(id_out, ws + L.pid, m * 4, hipMemcpyDeviceToDevice, st);
   launch_export_keys(L, (char*)workspace, cull_out, depth_bits_out, count_out, st);
   r = check_hip("psm_read_pairs");
   if (r != PSM_OK) return r;

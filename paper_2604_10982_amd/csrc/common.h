@@ -59,8 +59,8 @@ __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size
 struct Layout {
   int64_t n, cap, ntx, nty, tiles, spix;  // spix = tiles * 256 (tile-major pixels)
   int k, c;
-  size_t rec, fp, key0, key1, id0, id1, count, offs, cull, ptile0, ptile1, pid0, pid1, ranges,
-      nlast, tfinal, selpos, selw, seldot, gacc, hist, bsum, status, total;
+  size_t rec, fp, key0, key1, id0, id1, count, offs, cull, ptile0, ptile1, eid0, eid1, sid_emit, pid, inv, ranges,
+      nlast, tfinal, selpos, selw, seldot, gflag, fflag, gpart, fpart, hist, bsum, status, total;
 };
 
 inline Layout make_layout(int64_t n, int width, int height, int k, int c, int64_t cap) {
@@ -85,17 +85,24 @@ inline Layout make_layout(int64_t n, int width, int height, int k, int c, int64_
   L.count = take(n1 * 4);         // pairs per surfel
   L.offs = take((n1 + 1) * 4);    // exclusive scan of counts in depth order
   L.cull = take(n1 * 4);
-  L.ptile0 = take(cap1 * 4);      // pair tile ids (sort ping-pong)
+  L.ptile0 = take(cap1 * 4);      // pair tile ids (sort keys, ping-pong)
   L.ptile1 = take(cap1 * 4);
-  L.pid0 = take(cap1 * 4);        // pair surfel ids
-  L.pid1 = take(cap1 * 4);
+  L.eid0 = take(cap1 * 4);        // pair emission index (sort values, ping-pong)
+  L.eid1 = take(cap1 * 4);
+  L.sid_emit = take(cap1 * 4);    // surfel id of each emitted pair
+  L.pid = take(cap1 * 4);         // surfel id of each sorted pair
+  L.inv = take(cap1 * 4);         // sorted position of each emitted pair
   L.ranges = take(L.tiles * 8);   // [start, end) per tile
   L.nlast = take(L.spix * 4);
   L.tfinal = take(L.spix * 4);
   L.selpos = take(L.spix * (size_t)k * 4);
   L.selw = take(L.spix * (size_t)k * 4);
   L.seldot = take(L.spix * (size_t)k * 4);
-  L.gacc = take(n1 * 64);         // per-surfel gradient accumulators, 16 floats
+  // backward partial sums per (tile, surfel) pair, at the pair's sorted index
+  L.gflag = take(cap1);
+  L.fflag = take(cap1);
+  L.gpart = take(cap1 * 64);      // 16 floats: geometric and colour terms
+  L.fpart = take(cap1 * (size_t)(c > 0 ? c : 1) * 4);  // feature gradient rows
   const int64_t nb = cdiv(n1 > cap1 ? n1 : cap1, kSortTile);
   L.hist = take((256 * nb + 256) * 4);
   L.bsum = take((cdiv(n1, kScanTile) + 1) * 8);
@@ -205,6 +212,25 @@ __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// Sums 16 per-lane values over the wave with 17 exchanges instead of 96:
+// each step halves the number of values a lane carries.  Lane l returns the
+// wave total of value index (l >> 2) & 15.
+__device__ __forceinline__ float wave_reduce16(const float (&v)[16]) {
+  const int lane = threadIdx.x & 63;
+  float a[8], b[4], c[2];
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) a[i] = (b5 ? v[8 + i] : v[i]) + __shfl_xor(b5 ? v[i] : v[8 + i], 32, 64);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) b[i] = (b4 ? a[4 + i] : a[i]) + __shfl_xor(b4 ? a[i] : a[4 + i], 16, 64);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) c[i] = (b3 ? b[2 + i] : b[i]) + __shfl_xor(b3 ? b[i] : b[2 + i], 8, 64);
+  float d = (b2 ? c[1] : c[0]) + __shfl_xor(b2 ? c[0] : c[1], 4, 64);
+  d += __shfl_xor(d, 2, 64);
+  d += __shfl_xor(d, 1, 64);
+  return d;
 }
 
 // ------------------------------------------------ feature loads (to float)

@@ -322,7 +322,8 @@ __global__ __launch_bounds__(256) void k_emit(int64_t n, const uint32_t* __restr
                                               const uint32_t* __restrict__ count,
                                               const uint32_t* __restrict__ offs, const float4* __restrict__ fp,
                                               int mode, int W, int H, int ntx, int nty, int64_t cap,
-                                              uint32_t* __restrict__ ptile, uint32_t* __restrict__ pid) {
+                                              uint32_t* __restrict__ ptile, uint32_t* __restrict__ eid,
+                                              uint32_t* __restrict__ sid_emit) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const uint32_t i = order[r];
@@ -334,7 +335,8 @@ __global__ __launch_bounds__(256) void k_emit(int64_t n, const uint32_t* __restr
     for (int tx = x0; tx <= x1; ++tx, ++o) {
       if (o < cap) {
         ptile[o] = (uint32_t)(ty * ntx + tx);
-        pid[o] = i;
+        eid[o] = (uint32_t)o;
+        sid_emit[o] = i;
       }
     }
   });
@@ -356,11 +358,19 @@ __global__ __launch_bounds__(256) void k_export_keys(int64_t n, const int32_t* _
   }
 }
 
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ ptile, const uint32_t* __restrict__ status,
-                                                uint2* __restrict__ ranges) {
+// After the tile sort: surfel id of each sorted pair, the sorted position of
+// each emitted pair (so a surfel can find its own pairs again), tile ranges.
+__global__ __launch_bounds__(256) void k_finalize_pairs(const uint32_t* __restrict__ ptile,
+                                                        const uint32_t* __restrict__ eid,
+                                                        const uint32_t* __restrict__ sid_emit,
+                                                        const uint32_t* __restrict__ status, uint32_t* __restrict__ pid,
+                                                        uint32_t* __restrict__ inv, uint2* __restrict__ ranges) {
   const uint32_t P = status[kStP];
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= P) return;
+  const uint32_t e = eid[j];
+  pid[j] = sid_emit[e];
+  inv[e] = j;
   const uint32_t t = ptile[j];
   if (j == 0 || ptile[j - 1] != t) ranges[t].x = j;
   if (j == P - 1 || ptile[j + 1] != t) ranges[t].y = j + 1;
@@ -411,7 +421,8 @@ void launch_emit(const CamArgs& c, int mode, const Layout& L, char* ws, hipStrea
   hipLaunchKernelGGL(k_emit, dim3((unsigned)cdiv(L.n, 256)), dim3(256), 0, st, L.n,
                      (const uint32_t*)(ws + L.id0), (const uint32_t*)(ws + L.count),
                      (const uint32_t*)(ws + L.offs), (const float4*)(ws + L.fp), mode, c.W, c.H, (int)L.ntx,
-                     (int)L.nty, L.cap, (uint32_t*)(ws + L.ptile0), (uint32_t*)(ws + L.pid0));
+                     (int)L.nty, L.cap, (uint32_t*)(ws + L.ptile0), (uint32_t*)(ws + L.eid0),
+                     (uint32_t*)(ws + L.sid_emit));
 }
 
 void launch_export_keys(const Layout& L, char* ws, int32_t* cull, uint32_t* depth, int32_t* count, hipStream_t st) {
@@ -423,8 +434,10 @@ void launch_export_keys(const Layout& L, char* ws, int32_t* cull, uint32_t* dept
 
 void launch_ranges(const Layout& L, char* ws, hipStream_t st) {
   if (L.cap == 0) return;
-  hipLaunchKernelGGL(k_ranges, dim3((unsigned)cdiv(L.cap, 256)), dim3(256), 0, st,
-                     (const uint32_t*)(ws + L.ptile0), (const uint32_t*)(ws + L.status), (uint2*)(ws + L.ranges));
+  hipLaunchKernelGGL(k_finalize_pairs, dim3((unsigned)cdiv(L.cap, 256)), dim3(256), 0, st,
+                     (const uint32_t*)(ws + L.ptile0), (const uint32_t*)(ws + L.eid0),
+                     (const uint32_t*)(ws + L.sid_emit), (const uint32_t*)(ws + L.status), (uint32_t*)(ws + L.pid),
+                     (uint32_t*)(ws + L.inv), (uint2*)(ws + L.ranges));
 }
 
 }  // namespace psm

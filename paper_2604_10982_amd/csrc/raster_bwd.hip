@@ -2,18 +2,24 @@
 // to every surfel parameter.  The selection (eq. (18)), the contributor set,
 // the stop point and the alpha clamp are held fixed.
 //
+// Deterministic and free of floating-point atomics: every (tile, surfel) pair
+// of the sorted list owns a slot at its sorted index for its partial sums,
+// and a per-surfel pass later adds its own slots in a fixed order (the pair
+// sort recorded where each surfel's pairs went).
+//
 // k_feat_bwd_topk: per tile, for every (pixel, selected surfel): the dot
 //   product of the pixel's feature gradient with the surfel's feature row
-//   (needed by the alpha adjoint), and dL/df accumulated first in LDS per
-//   distinct selected surfel of the tile, then with one global atomic per
-//   (surfel, channel).
+//   (needed by the alpha adjoint); and, per distinct selected surfel of the
+//   tile, the row sum_p w_p g_F(p) over the pixels that selected it, in pixel
+//   order (per-slot pixel masks give each entry its rank without atomics on
+//   floats).
 // k_walk_bwd: per tile, back to front from each pixel's last contributor,
-//   recovering T_i = T_{i+1} / (1 - alpha_i).  Per surfel the per-pixel
-//   terms are reduced over the wave, then over the 4 waves through LDS, and
-//   added to 16 per-surfel accumulators with global atomics.  In dense-blend
-//   mode each batch also computes the feature dot products (batch x C x
-//   pixels) and the feature gradients (pixels x batch x C) tile-wide.
-// k_preprocess_bwd: chain rule from the accumulators to mu, s, q, o, rgb.
+//   recovering T_i = T_{i+1} / (1 - alpha_i).  Per surfel the per-pixel terms
+//   are reduced over the wave, then over the 4 waves through LDS, and written
+//   as the pair's 16 partial sums.  In dense-blend mode each batch also forms
+//   the feature dot products and feature-gradient rows tile-wide.
+// k_reduce_geo / k_reduce_feat: per surfel, sum of its pairs' partials, then
+//   the chain rule to mu, s, q (FP64, as the forward's walk record).
 #include "common.h"
 #include "internal.h"
 
@@ -24,16 +30,33 @@ constexpr int kNV = 17;          // per-pixel values reduced per surfel
 constexpr int kWinWords = 1024;  // selected-position window: 32768 positions
 
 // ------------------------------------------------------------ Top-K feature
+constexpr int kSlotChunk = 256;  // distinct selected surfels handled per pass
+
+// Position (within the window) of the s-th set bit of the window bitmap.
+__device__ __forceinline__ int slot_position(const uint32_t* bits, const uint32_t* pref, int s) {
+  int lo = 0, hi = kWinWords - 1;  // largest word w with pref[w] <= s
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((int)pref[mid] <= s) lo = mid;
+    else hi = mid - 1;
+  }
+  uint32_t w = bits[lo];
+  for (int r = s - (int)pref[lo]; r > 0; --r) w &= w - 1u;
+  return lo * 32 + (__ffs(w) - 1);
+}
+
 template <typename FT>
 __global__ __launch_bounds__(256) void k_feat_bwd_topk(
     const uint32_t* __restrict__ pid, const uint2* __restrict__ ranges, const int32_t* __restrict__ selpos,
     const float* __restrict__ selw, const FT* __restrict__ feat, const float* __restrict__ gfeat, int C, int K,
-    int W, int H, int ntx, int tiles, int sch, float* __restrict__ seldot, float* __restrict__ dfeat) {
+    int W, int H, int ntx, int tiles, float* __restrict__ seldot, float* __restrict__ fpart,
+    uint8_t* __restrict__ fflag) {
   extern __shared__ char smem[];
-  uint32_t* s_bits = reinterpret_cast<uint32_t*>(smem);
-  uint32_t* s_pref = s_bits + kWinWords;
-  uint32_t* s_sid = s_pref + kWinWords;            // slot -> surfel id (256*K)
-  float* s_acc = reinterpret_cast<float*>(s_sid + kTilePix * K);  // [sch][C]
+  uint32_t* s_bits = reinterpret_cast<uint32_t*>(smem);  // selected positions of the window
+  uint32_t* s_pref = s_bits + kWinWords;                   // exclusive popcount prefix per word
+  uint32_t* s_mask = s_pref + kWinWords;                   // [kSlotChunk][8] pixels selecting a slot
+  uint32_t* s_off = s_mask + kSlotChunk * 8;               // [kSlotChunk + 1] entry offsets
+  uint32_t* s_list = s_off + kSlotChunk + 1;               // [256 K] entries (pixel | k << 8)
   __shared__ int s_maxpos;
   __shared__ uint32_t s_wsum[256];
 
@@ -61,23 +84,24 @@ __global__ __launch_bounds__(256) void k_feat_bwd_topk(
       if (pos >= 0) {
         const uint32_t id = pid[start + pos];
         for (int cg = cl; cg < lpp; cg += lpp2) {
-          float f[V], g[V];
+          float f[V];
           load_vec<FT>(feat + (size_t)id * C + cg * V, f);
 #pragma unroll
           for (int v = 0; v < V; v += 4) {
             const float4 x = *reinterpret_cast<const float4*>(grow + cg * V + v);
-            g[v] = x.x; g[v + 1] = x.y; g[v + 2] = x.z; g[v + 3] = x.w;
+            part = fmaf(x.x, f[v], part);
+            part = fmaf(x.y, f[v + 1], part);
+            part = fmaf(x.z, f[v + 2], part);
+            part = fmaf(x.w, f[v + 3], part);
           }
-#pragma unroll
-          for (int v = 0; v < V; ++v) part = fmaf(g[v], f[v], part);
         }
       }
       for (int o = lpp2 >> 1; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-      if (cl == 0 && p < kTilePix) seldot[tbase + (size_t)q * kTilePix + p] = pos >= 0 ? part : 0.0f;
+      if (cl == 0) seldot[tbase + (size_t)q * kTilePix + p] = pos >= 0 ? part : 0.0f;
     }
   }
 
-  // --- dL/df: distinct selected positions of the tile -> LDS slots
+  // --- dL/df rows, one per distinct selected (tile, surfel) pair
   if (tid == 0) s_maxpos = -1;
   __syncthreads();
   int mymax = -1;
@@ -93,7 +117,6 @@ __global__ __launch_bounds__(256) void k_feat_bwd_topk(
       if (pos >= 0 && pos < kWinWords * 32) atomicOr(&s_bits[pos >> 5], 1u << (pos & 31));
     }
     __syncthreads();
-    // exclusive scan of the popcounts (4 words per thread)
     uint32_t c4 = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) c4 += __popc(s_bits[tid * 4 + i]);
@@ -113,47 +136,77 @@ __global__ __launch_bounds__(256) void k_feat_bwd_topk(
     }
     const int U = (int)s_wsum[255];
     __syncthreads();
-    for (int q = 0; q < K; ++q) {
-      const int pos = selpos[tbase + (size_t)q * kTilePix + tid] - w0;
-      if (pos >= 0 && pos < kWinWords * 32) {
-        const uint32_t wd = s_bits[pos >> 5];
-        const int slot = (int)(s_pref[pos >> 5] + __popc(wd & ((1u << (pos & 31)) - 1u)));
-        s_sid[slot] = pid[start + w0 + pos];
-      }
-    }
-    for (int c0 = 0; c0 < U; c0 += sch) {
-      for (int i = tid; i < sch * C; i += 256) s_acc[i] = 0.0f;
+    for (int c0 = 0; c0 < U; c0 += kSlotChunk) {
+      const int ns = min(kSlotChunk, U - c0);
+      for (int i = tid; i < ns * 8; i += 256) s_mask[i] = 0u;
       __syncthreads();
-      for (int p0 = 0; p0 < 64; p0 += ppw) {
-        const int p = wave * 64 + p0 + sub;
-        const int px = tx * kTile + (p & 15), py = ty * kTile + (p >> 4);
-        if (px >= W || py >= H) continue;
-        const float* grow = gfeat + ((int64_t)py * W + px) * C;
-        for (int q = 0; q < K; ++q) {
-          const size_t o = tbase + (size_t)q * kTilePix + p;
-          const int pos = selpos[o] - w0;
-          if (pos < 0 || pos >= kWinWords * 32) continue;
-          const int slot = (int)(s_pref[pos >> 5] + __popc(s_bits[pos >> 5] & ((1u << (pos & 31)) - 1u))) - c0;
-          if (slot < 0 || slot >= sch) continue;
-          const float w = selw[o];
+      // which pixels selected each slot of this chunk
+      for (int q = 0; q < K; ++q) {
+        const int pos = selpos[tbase + (size_t)q * kTilePix + tid] - w0;
+        if (pos < 0 || pos >= kWinWords * 32) continue;
+        const int slot = (int)(s_pref[pos >> 5] + __popc(s_bits[pos >> 5] & ((1u << (pos & 31)) - 1u))) - c0;
+        if (slot >= 0 && slot < ns) atomicOr(&s_mask[slot * 8 + (tid >> 5)], 1u << (tid & 31));
+      }
+      __syncthreads();
+      // entry offsets: exclusive scan of the slot populations
+      uint32_t cnt = 0;
+      if (tid < ns)
+        for (int w = 0; w < 8; ++w) cnt += __popc(s_mask[tid * 8 + w]);
+      s_wsum[tid] = cnt;
+      __syncthreads();
+      for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t v = tid >= o ? s_wsum[tid - o] : 0u;
+        __syncthreads();
+        s_wsum[tid] += v;
+        __syncthreads();
+      }
+      if (tid < ns) s_off[tid] = s_wsum[tid] - cnt;
+      if (tid == 0) s_off[ns] = s_wsum[ns - 1];
+      __syncthreads();
+      // entries in pixel order within each slot
+      for (int q = 0; q < K; ++q) {
+        const int pos = selpos[tbase + (size_t)q * kTilePix + tid] - w0;
+        if (pos < 0 || pos >= kWinWords * 32) continue;
+        const int slot = (int)(s_pref[pos >> 5] + __popc(s_bits[pos >> 5] & ((1u << (pos & 31)) - 1u))) - c0;
+        if (slot < 0 || slot >= ns) continue;
+        const uint32_t* m = s_mask + slot * 8;
+        uint32_t rank = __popc(m[tid >> 5] & ((1u << (tid & 31)) - 1u));
+        for (int w = 0; w < (tid >> 5); ++w) rank += __popc(m[w]);
+        s_list[s_off[slot] + rank] = (uint32_t)tid | ((uint32_t)q << 8);
+      }
+      __syncthreads();
+      // one lane group per slot: sum_p w_p g_F(p)
+      for (int sb = wave * ppw; sb < ns; sb += 4 * ppw) {
+        const int sl = sb + sub;
+        if (sl < ns) {
+          const int pos = w0 + slot_position(s_bits, s_pref, c0 + sl);
+          const uint32_t e0 = s_off[sl], e1 = s_off[sl + 1];
+          float* out = fpart + ((size_t)start + pos) * C;
           for (int cg = cl; cg < lpp; cg += lpp2) {
+            float acc[V];
 #pragma unroll
-            for (int v = 0; v < V; v += 4) {
-              const float4 x = *reinterpret_cast<const float4*>(grow + cg * V + v);
-              float* a = s_acc + (size_t)slot * C + cg * V + v;
-              atomicAdd(a + 0, w * x.x);
-              atomicAdd(a + 1, w * x.y);
-              atomicAdd(a + 2, w * x.z);
-              atomicAdd(a + 3, w * x.w);
+            for (int v = 0; v < V; ++v) acc[v] = 0.0f;
+            for (uint32_t e = e0; e < e1; ++e) {
+              const uint32_t ent = s_list[e];
+              const int p = (int)(ent & 255u), q = (int)(ent >> 8);
+              const float w = selw[tbase + (size_t)q * kTilePix + p];
+              const int px = tx * kTile + (p & 15), py = ty * kTile + (p >> 4);
+              const float* grow = gfeat + ((int64_t)py * W + px) * C + cg * V;
+#pragma unroll
+              for (int v = 0; v < V; v += 4) {
+                const float4 x = *reinterpret_cast<const float4*>(grow + v);
+                acc[v] = fmaf(w, x.x, acc[v]);
+                acc[v + 1] = fmaf(w, x.y, acc[v + 1]);
+                acc[v + 2] = fmaf(w, x.z, acc[v + 2]);
+                acc[v + 3] = fmaf(w, x.w, acc[v + 3]);
+              }
             }
+#pragma unroll
+            for (int v = 0; v < V; v += 4)
+              *reinterpret_cast<float4*>(out + cg * V + v) = make_float4(acc[v], acc[v + 1], acc[v + 2], acc[v + 3]);
           }
+          if (cl == 0) fflag[start + pos] = 1;
         }
-      }
-      __syncthreads();
-      const int ns = min(sch, U - c0);
-      for (int i = tid; i < ns * C; i += 256) {
-        const float v = s_acc[i];
-        if (v != 0.0f) atomicAdd(dfeat + (size_t)s_sid[c0 + i / C] * C + (i % C), v);
       }
       __syncthreads();
     }
@@ -168,8 +221,8 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
     int H, int ntx, int tiles, int K, const uint32_t* __restrict__ nlast, const float* __restrict__ tfinal,
     const int32_t* __restrict__ selpos, const float* __restrict__ seldot, const float* __restrict__ g_rgb,
     const float* __restrict__ g_depth, const float* __restrict__ g_normal, const float* __restrict__ g_alpha,
-    const float* __restrict__ g_feat, const FT* __restrict__ feat, int C, float* __restrict__ dfeat,
-    float* __restrict__ gacc) {
+    const float* __restrict__ g_feat, const FT* __restrict__ feat, int C, float* __restrict__ gpart,
+    uint8_t* __restrict__ gflag, float* __restrict__ fpart, uint8_t* __restrict__ fflag) {
   __shared__ Staged<kBB> s_r;
   __shared__ uint32_t s_id[kBB];
   __shared__ float s_part[4][kBB][kNV];
@@ -311,12 +364,13 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
       if constexpr (MODE == kFull) s_om[k][tid] = wgt;
       const bool any = __any(contrib);
       if (any) {
+        float v16[16];
 #pragma unroll
-        for (int i = 0; i < kNV; ++i) v[i] = wave_sum(v[i]);
-        if (lane == 0) {
-#pragma unroll
-          for (int i = 0; i < kNV; ++i) s_part[wave][k][i] = v[i];
-        }
+        for (int i = 0; i < 16; ++i) v16[i] = v[i];
+        const float tot = wave_reduce16(v16);
+        const float last = wave_sum(v[16]);
+        if ((lane & 3) == 0) s_part[wave][k][(lane >> 2) & 15] = tot;
+        if (lane == 0) s_part[wave][k][16] = last;
       }
       if (lane == 0) s_has[wave][k] = any ? 1u : 0u;
     }
@@ -338,25 +392,16 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
         const WalkRec& rr = rec[id];
         const float a00 = (float)rr.d0.x, a01 = (float)rr.d0.y, a10 = (float)rr.d1.x, a11 = (float)rr.d1.y;
         const float e0 = (float)rr.d2.x, e1 = (float)rr.d2.y;
-        float* g = gacc + (size_t)id * 16;
-        // u' = A^-1 d, w' = 1 - e.d with d = pixel - centre
-        atomicAdd(g + 0, t[0]);
-        atomicAdd(g + 1, t[1]);
-        atomicAdd(g + 2, t[3]);
-        atomicAdd(g + 3, t[4]);
-        atomicAdd(g + 4, -t[6]);
-        atomicAdd(g + 5, -t[7]);
-        // d depends on the centre with slope -1
-        atomicAdd(g + 6, -(a00 * t[2] + a10 * t[5] - e0 * t[8]));
-        atomicAdd(g + 7, -(a01 * t[2] + a11 * t[5] - e1 * t[8]));
-        atomicAdd(g + 8, t[9]);
-        atomicAdd(g + 9, t[10]);
-        atomicAdd(g + 10, t[11]);
-        atomicAdd(g + 11, t[12]);
-        atomicAdd(g + 12, t[13]);
-        atomicAdd(g + 13, t[14]);
-        atomicAdd(g + 14, t[15]);
-        atomicAdd(g + 15, t[16]);
+        const size_t slot = (size_t)start + lo + k;
+        float4* g = reinterpret_cast<float4*>(gpart + slot * 16);
+        // u' = A^-1 d, w' = 1 - e.d with d = pixel - centre; d depends on the
+        // centre with slope -1
+        g[0] = make_float4(t[0], t[1], t[3], t[4]);
+        g[1] = make_float4(-t[6], -t[7], -(a00 * t[2] + a10 * t[5] - e0 * t[8]),
+                           -(a01 * t[2] + a11 * t[5] - e1 * t[8]));
+        g[2] = make_float4(t[9], t[10], t[11], t[12]);
+        g[3] = make_float4(t[13], t[14], t[15], t[16]);
+        gflag[slot] = 1;
       }
     }
 
@@ -382,7 +427,11 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
 #pragma unroll
             for (int j = 0; j < PER; ++j) {
               const int k = kg * PER + j;
-              if (k < nb && acc[j] != 0.0f) atomicAdd(dfeat + (size_t)s_id[k] * C + c, acc[j]);
+              if (k < nb) {
+                const size_t slot = (size_t)start + lo + k;
+                fpart[slot * C + c] = acc[j];
+                if (c == 0) fflag[slot] = 1;
+              }
             }
           }
         }
@@ -391,20 +440,27 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
   }
 }
 
-// ------------------------------------------------------- preprocess backward
+// ------------------------------------------------------- per-surfel reduction
 struct CamB {
   float R[9], t[3], fx, fy, cx, cy;
 };
 
-__global__ __launch_bounds__(256) void k_preprocess_bwd(int64_t n, const float* __restrict__ means,
-                                                        const float* __restrict__ scales,
-                                                        const float* __restrict__ quats,
-                                                        const int32_t* __restrict__ cull, CamB k,
-                                                        const float* __restrict__ gacc, float* __restrict__ d_means,
-                                                        float* __restrict__ d_scales, float* __restrict__ d_quats,
-                                                        float* __restrict__ d_opacity, float* __restrict__ d_rgb) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// Thread per surfel, visited in depth order so its pairs are the emitted
+// range [offs[r], offs[r] + count): their sorted slots come from `inv`.
+__global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, const uint32_t* __restrict__ order,
+                                                    const uint32_t* __restrict__ count,
+                                                    const uint32_t* __restrict__ offs,
+                                                    const uint32_t* __restrict__ inv, int64_t cap,
+                                                    const float* __restrict__ gpart,
+                                                    const uint8_t* __restrict__ gflag,
+                                                    const float* __restrict__ means, const float* __restrict__ scales,
+                                                    const float* __restrict__ quats, const int32_t* __restrict__ cull,
+                                                    CamB k, float* __restrict__ d_means, float* __restrict__ d_scales,
+                                                    float* __restrict__ d_quats, float* __restrict__ d_opacity,
+                                                    float* __restrict__ d_rgb) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const uint32_t i = order[r];
   if ((cull[i] & 0xFF) != 0) {
     for (int j = 0; j < 3; ++j) { d_means[3 * i + j] = 0.f; d_rgb[3 * i + j] = 0.f; }
     d_scales[2 * i] = d_scales[2 * i + 1] = 0.f;
@@ -412,11 +468,22 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(int64_t n, const float* 
     d_opacity[i] = 0.f;
     return;
   }
-  // The walk record was evaluated in FP64 from the FP32 inputs; its chain
-  // rule is evaluated the same way.
   double G[16];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) G[j] = gacc[16 * i + j];
+  for (int j = 0; j < 16; ++j) G[j] = 0.0;
+  const int64_t base = offs[r], cnt = count[i];
+  for (int64_t j = 0; j < cnt && base + j < cap; ++j) {
+    const uint32_t slot = inv[base + j];
+    if (!gflag[slot]) continue;
+    const float4* g = reinterpret_cast<const float4*>(gpart + (size_t)slot * 16);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 v = g[q];
+      G[4 * q] += v.x; G[4 * q + 1] += v.y; G[4 * q + 2] += v.z; G[4 * q + 3] += v.w;
+    }
+  }
+  // The walk record was evaluated in FP64 from the FP32 inputs; its chain
+  // rule is evaluated the same way.
   const double mu[3] = {means[3 * i], means[3 * i + 1], means[3 * i + 2]};
   const double su = scales[2 * i], sv = scales[2 * i + 1];
   const double q0 = quats[4 * i], q1 = quats[4 * i + 1], q2 = quats[4 * i + 2], q3 = quats[4 * i + 3];
@@ -512,26 +579,55 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(int64_t n, const float* 
   d_rgb[3 * i + 2] = (float)G[12];
 }
 
+// Lane group per surfel (in depth order): dL/df = sum of its pairs' rows.
+__global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, const uint32_t* __restrict__ order,
+                                                     const uint32_t* __restrict__ count,
+                                                     const uint32_t* __restrict__ offs,
+                                                     const uint32_t* __restrict__ inv, int64_t cap,
+                                                     const float* __restrict__ fpart,
+                                                     const uint8_t* __restrict__ fflag, int C,
+                                                     float* __restrict__ dfeat) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lpp = C / 4;
+  const int lpp2 = lpp >= 64 ? 64 : pow2_ge(lpp);
+  const int spw = 64 / lpp2;
+  const int sub = lane / lpp2, cl = lane % lpp2;
+  const int64_t r = ((int64_t)blockIdx.x * 4 + wave) * spw + sub;
+  if (r >= n) return;
+  const uint32_t i = order[r];
+  const int64_t base = offs[r], cnt = count[i];
+  for (int cg = cl; cg < lpp; cg += lpp2) {
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t j = 0; j < cnt && base + j < cap; ++j) {
+      const uint32_t slot = inv[base + j];
+      if (!fflag[slot]) continue;
+      const float4 v = *reinterpret_cast<const float4*>(fpart + (size_t)slot * C + cg * 4);
+      acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+    }
+    *reinterpret_cast<float4*>(dfeat + (size_t)i * C + cg * 4) = acc;
+  }
+}
+
 // ------------------------------------------------------------- host wrappers
 template <typename FT>
 static void backward_typed(const SurfelArgs& s, const CamArgs& c, int blend, const Layout& L, const ImageGradArgs& g,
                            const GradArgs& gr, char* ws, hipStream_t st, const ProfHook& prof) {
   const WalkRec* rec = (const WalkRec*)(ws + L.rec);
-  const uint32_t* pid = (const uint32_t*)(ws + L.pid0);
+  const uint32_t* pid = (const uint32_t*)(ws + L.pid);
   const uint2* ranges = (const uint2*)(ws + L.ranges);
-  float* gacc = (float*)(ws + L.gacc);
+  float* gpart = (float*)(ws + L.gpart);
+  float* fpart = (float*)(ws + L.fpart);
+  uint8_t* gflag = (uint8_t*)(ws + L.gflag);
+  uint8_t* fflag = (uint8_t*)(ws + L.fflag);
   const dim3 grid(xcd_grid(L.tiles));
+  const bool want_f = g.feat != nullptr && s.c > 0;
   if (blend == kTopK) {
     prof.begin(kStageBwdFeature, st);
-    if (g.feat && s.c > 0) {
-      const size_t fixed = (size_t)(2 * kWinWords + kTilePix * L.k) * 4;
-      const size_t budget = 60 * 1024;  // dynamic part; about 1 KB of static LDS comes on top
-      int sch = (int)((budget - fixed) / ((size_t)s.c * 4));
-      sch = std::max(1, std::min(sch, kTilePix * L.k));
-      const size_t shm = fixed + (size_t)sch * s.c * 4;
+    if (want_f) {
+      const size_t shm = (size_t)(2 * kWinWords + kSlotChunk * 8 + kSlotChunk + 1 + kTilePix * L.k) * 4;
       hipLaunchKernelGGL((k_feat_bwd_topk<FT>), grid, dim3(256), shm, st, pid, ranges,
                          (const int32_t*)(ws + L.selpos), (const float*)(ws + L.selw), (const FT*)s.feat, g.feat, s.c,
-                         L.k, c.W, c.H, (int)L.ntx, (int)L.tiles, sch, (float*)(ws + L.seldot), gr.feat);
+                         L.k, c.W, c.H, (int)L.ntx, (int)L.tiles, (float*)(ws + L.seldot), fpart, fflag);
     } else {
       launch_fill_u32(ws + L.seldot, 0u, L.spix * (int64_t)L.k, st);
     }
@@ -540,14 +636,14 @@ static void backward_typed(const SurfelArgs& s, const CamArgs& c, int blend, con
     hipLaunchKernelGGL((k_walk_bwd<kTopK, FT>), grid, dim3(256), 0, st, rec, pid, ranges, c.W, c.H, (int)L.ntx,
                        (int)L.tiles, L.k, (const uint32_t*)(ws + L.nlast), (const float*)(ws + L.tfinal),
                        (const int32_t*)(ws + L.selpos), (const float*)(ws + L.seldot), g.rgb, g.depth, g.normal,
-                       g.alpha, g.feat, (const FT*)s.feat, s.c, gr.feat, gacc);
+                       g.alpha, g.feat, (const FT*)s.feat, s.c, gpart, gflag, fpart, fflag);
     prof.end(kStageBwdWalk, st);
   } else {
     prof.begin(kStageBwdWalk, st);
     hipLaunchKernelGGL((k_walk_bwd<kFull, FT>), grid, dim3(256), 0, st, rec, pid, ranges, c.W, c.H, (int)L.ntx,
                        (int)L.tiles, L.k, (const uint32_t*)(ws + L.nlast), (const float*)(ws + L.tfinal),
                        (const int32_t*)(ws + L.selpos), (const float*)(ws + L.seldot), g.rgb, g.depth, g.normal,
-                       g.alpha, (s.c > 0 ? g.feat : nullptr), (const FT*)s.feat, s.c, gr.feat, gacc);
+                       g.alpha, want_f ? g.feat : nullptr, (const FT*)s.feat, s.c, gpart, gflag, fpart, fflag);
     prof.end(kStageBwdWalk, st);
   }
   CamB cb;
@@ -555,18 +651,31 @@ static void backward_typed(const SurfelArgs& s, const CamArgs& c, int blend, con
   for (int i = 0; i < 3; ++i) cb.t[i] = c.t[i];
   cb.fx = c.fx; cb.fy = c.fy; cb.cx = c.cx; cb.cy = c.cy;
   prof.begin(kStageBwdPreprocess, st);
-  if (s.n > 0)
-    hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)cdiv(s.n, 256)), dim3(256), 0, st, s.n, s.means, s.scales,
-                       s.quats, (const int32_t*)(ws + L.cull), cb, (const float*)gacc, gr.means, gr.scales, gr.quats,
-                       gr.opacity, gr.rgb);
+  const uint32_t* order = (const uint32_t*)(ws + L.id0);
+  const uint32_t* count = (const uint32_t*)(ws + L.count);
+  const uint32_t* offs = (const uint32_t*)(ws + L.offs);
+  const uint32_t* inv = (const uint32_t*)(ws + L.inv);
+  if (s.n > 0) {
+    hipLaunchKernelGGL(k_reduce_geo, dim3((unsigned)cdiv(s.n, 256)), dim3(256), 0, st, s.n, order, count, offs, inv,
+                       L.cap, (const float*)gpart, (const uint8_t*)gflag, s.means, s.scales, s.quats,
+                       (const int32_t*)(ws + L.cull), cb, gr.means, gr.scales, gr.quats, gr.opacity, gr.rgb);
+    if (s.c > 0 && gr.feat) {
+      const int lpp = s.c / 4;
+      int lpp2 = 1;
+      while (lpp2 < lpp && lpp2 < 64) lpp2 <<= 1;
+      const int per_block = 4 * (64 / lpp2);
+      hipLaunchKernelGGL(k_reduce_feat, dim3((unsigned)cdiv(s.n, per_block)), dim3(256), 0, st, s.n, order, count,
+                         offs, inv, L.cap, (const float*)fpart, (const uint8_t*)fflag, s.c, gr.feat);
+    }
+  }
   prof.end(kStageBwdPreprocess, st);
 }
 
 void launch_backward(const SurfelArgs& s, const CamArgs& c, int blend, const Layout& L, const ImageGradArgs& g,
                      const GradArgs& grads, char* ws, hipStream_t st, const ProfHook& prof) {
   prof.begin(kStageFill, st);
-  launch_fill_u32(ws + L.gacc, 0u, L.n * 16, st);
-  if (grads.feat && s.c > 0) launch_fill_u32(grads.feat, 0u, L.n * (int64_t)s.c, st);
+  launch_fill_u32(ws + L.gflag, 0u, cdiv(std::max<int64_t>(L.cap, 1), 4), st);
+  launch_fill_u32(ws + L.fflag, 0u, cdiv(std::max<int64_t>(L.cap, 1), 4), st);
   prof.end(kStageFill, st);
   if (s.dtype == kF32) backward_typed<float>(s, c, blend, L, g, grads, ws, st, prof);
   else if (s.dtype == kF16) backward_typed<__half>(s, c, blend, L, g, grads, ws, st, prof);

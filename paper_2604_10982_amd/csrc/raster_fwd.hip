@@ -42,6 +42,24 @@ __device__ __forceinline__ void sort_by_position(int (&p)[N], float (&w)[N]) {
   }
 }
 
+// Tile-local record from a surfel record held in scalar registers: every lane
+// of a wave evaluates the same surfel, so the record is wave-uniform.
+__device__ __forceinline__ LRec fold_uniform(const WalkRec& r, double tx0, double ty0) {
+  LRec s;
+  s.a00 = r.d0.x; s.a01 = r.d0.y; s.a10 = r.d1.x; s.a11 = r.d1.y;
+  s.e0 = r.d2.x; s.e1 = r.d2.y;
+  s.ox = tx0 - r.d3.x;
+  s.oy = ty0 - r.d3.y;
+  s.mz = r.f0.x; s.o = r.f0.y; s.r = r.f0.z; s.g = r.f0.w;
+  s.b = r.f1.x; s.n0 = r.f1.y; s.n1 = r.f1.z; s.n2 = r.f1.w;
+  return s;
+}
+
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Each wave walks its 64 pixels independently (no LDS, no barriers): the
+// tile's surfel ids and records are wave-uniform and come through the scalar
+// cache into SGPRs, one record ahead of the evaluation.
 template <int KMAX, bool TOPK>
 __global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, const uint32_t* __restrict__ pid,
                                               const uint2* __restrict__ ranges, int W, int H, int ntx, int tiles,
@@ -50,7 +68,6 @@ __global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, c
                                               uint32_t* __restrict__ nlast, float* __restrict__ tfinal,
                                               int32_t* __restrict__ selpos, float* __restrict__ selw,
                                               uint32_t* __restrict__ status) {
-  __shared__ Staged<kWalkBatch> s_r;
   const int tile = xcd_tile(blockIdx.x, tiles);
   if (tile >= tiles) return;
   const int tid = threadIdx.x;
@@ -58,8 +75,10 @@ __global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, c
   const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
   const bool inside = px < W && py < H;
   const float lx = (float)(tid & 15) + 0.5f, ly = (float)(tid >> 4) + 0.5f;
+  const double tx0 = (double)(tx * kTile), ty0 = (double)(ty * kTile);
   const uint2 rg = ranges[tile];
   const int L = (int)(rg.y - rg.x);
+  const uint32_t* ids = pid + rg.x;
 
   float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f, nx = 0.f, ny = 0.f, nz = 0.f;
   int last = 0, walked = 0, blended = 0;
@@ -74,55 +93,54 @@ __global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, c
   float hmin = -1.0f;
   int imin = 0, pmin = -1;
 
-  for (int base = 0; base < L; base += kWalkBatch) {
-    if (__syncthreads_count(done) == kTilePix) break;
-    const int j = base + tid;
-    if (j < L) s_r.put(tid, rec[pid[rg.x + j]], (float)(tx * kTile), (float)(ty * kTile));
-    __syncthreads();
-    const int nb = min(kWalkBatch, L - base);
-    for (int k = 0; k < nb; ++k) {
-      if (__all(done)) break;
-      if (done) continue;
-      ++walked;
-      const LRec s = s_r.get(k);
-      PixEval e;
-      if (!eval_pixel(s, lx, ly, e)) continue;
-      const float Tn = T * (1.0f - e.alpha);
-      if (Tn < kTMin) {
-        done = true;
-        continue;
+  uint32_t id_next = L > 1 ? uniform_u32(ids[1]) : 0u;
+  WalkRec r_next;
+  if (L > 0) r_next = rec[uniform_u32(ids[0])];
+  for (int j = 0; j < L; ++j) {
+    if (__all(done)) break;
+    const WalkRec r = r_next;
+    const uint32_t id_after = j + 2 < L ? uniform_u32(ids[j + 2]) : 0u;
+    if (j + 1 < L) r_next = rec[id_next];
+    id_next = id_after;
+    if (done) continue;
+    ++walked;
+    const LRec s = fold_uniform(r, tx0, ty0);
+    PixEval e;
+    if (!eval_pixel(s, lx, ly, e)) continue;
+    const float Tn = T * (1.0f - e.alpha);
+    if (Tn < kTMin) {
+      done = true;
+      continue;
+    }
+    const float w = e.alpha * T;
+    cr = fmaf(w, s.r, cr);
+    cg = fmaf(w, s.g, cg);
+    cb = fmaf(w, s.b, cb);
+    dep = fmaf(w, s.mz * e.iw, dep);
+    nx = fmaf(w, s.n0, nx);
+    ny = fmaf(w, s.n1, ny);
+    nz = fmaf(w, s.n2, nz);
+    T = Tn;
+    ++blended;
+    last = j + 1;
+    if (TOPK && w > hmin) {
+      // replace the current minimum, then find the new minimum under the
+      // order (weight descending, position ascending)
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q) {
+        const bool hit = q == imin;
+        hw[q] = hit ? w : hw[q];
+        hp[q] = hit ? j : hp[q];
       }
-      const float w = e.alpha * T;
-      cr = fmaf(w, s.r, cr);
-      cg = fmaf(w, s.g, cg);
-      cb = fmaf(w, s.b, cb);
-      dep = fmaf(w, s.mz * e.iw, dep);
-      nx = fmaf(w, s.n0, nx);
-      ny = fmaf(w, s.n1, ny);
-      nz = fmaf(w, s.n2, nz);
-      T = Tn;
-      ++blended;
-      const int pos = base + k;
-      last = pos + 1;
-      if (TOPK && w > hmin) {
-        // replace the current minimum, then find the new minimum under the
-        // order (weight descending, position ascending)
+      hmin = hw[0];
+      pmin = hp[0];
+      imin = 0;
 #pragma unroll
-        for (int q = 0; q < KMAX; ++q) {
-          const bool hit = q == imin;
-          hw[q] = hit ? w : hw[q];
-          hp[q] = hit ? pos : hp[q];
-        }
-        hmin = hw[0];
-        pmin = hp[0];
-        imin = 0;
-#pragma unroll
-        for (int q = 1; q < KMAX; ++q) {
-          const bool lt = hw[q] < hmin || (hw[q] == hmin && hp[q] > pmin);
-          hmin = lt ? hw[q] : hmin;
-          pmin = lt ? hp[q] : pmin;
-          imin = lt ? q : imin;
-        }
+      for (int q = 1; q < KMAX; ++q) {
+        const bool lt = hw[q] < hmin || (hw[q] == hmin && hp[q] > pmin);
+        hmin = lt ? hw[q] : hmin;
+        pmin = lt ? hp[q] : pmin;
+        imin = lt ? q : imin;
       }
     }
   }
@@ -324,7 +342,7 @@ __global__ __launch_bounds__(256) void k_export_sel(const uint32_t* __restrict__
 template <int KMAX, bool TOPK>
 static void walk_launch(const Layout& L, const CamArgs& c, const ImageArgs& out, char* ws, hipStream_t st) {
   hipLaunchKernelGGL((k_walk<KMAX, TOPK>), dim3(xcd_grid(L.tiles)), dim3(256), 0, st, (const WalkRec*)(ws + L.rec),
-                     (const uint32_t*)(ws + L.pid0), (const uint2*)(ws + L.ranges), c.W, c.H, (int)L.ntx,
+                     (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), c.W, c.H, (int)L.ntx,
                      (int)L.tiles, L.k, out.rgb, out.depth, out.normal, out.alpha, (uint32_t*)(ws + L.nlast),
                      (float*)(ws + L.tfinal), (int32_t*)(ws + L.selpos), (float*)(ws + L.selw),
                      (uint32_t*)(ws + L.status));
@@ -348,12 +366,12 @@ static void blend_launch(const SurfelArgs& s, const Layout& L, const CamArgs& c,
   if (blend == kTopK) {
     const size_t shm = (size_t)L.k * kTilePix * 8;
     hipLaunchKernelGGL((k_blend_topk<FT>), dim3(xcd_grid(L.tiles)), dim3(256), shm, st,
-                       (const uint32_t*)(ws + L.pid0), (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos),
+                       (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos),
                        (const float*)(ws + L.selw), (const FT*)s.feat, s.c, L.k, c.W, c.H, (int)L.ntx, (int)L.tiles,
                        out_feat);
   } else {
     hipLaunchKernelGGL((k_full_feat<FT, 64>), dim3(xcd_grid(L.tiles)), dim3(256), 0, st, (const WalkRec*)(ws + L.rec),
-                       (const uint32_t*)(ws + L.pid0), (const uint2*)(ws + L.ranges), (const FT*)s.feat, s.c, c.W,
+                       (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), (const FT*)s.feat, s.c, c.W,
                        c.H, (int)L.ntx, (int)L.tiles, (const uint32_t*)(ws + L.nlast), out_feat);
   }
 }
@@ -368,7 +386,7 @@ void launch_feature_blend(const SurfelArgs& s, const Layout& L, const CamArgs& c
 
 void launch_export_selection(const Layout& L, const CamArgs& c, char* ws, int32_t* sel_id, float* sel_w,
                              int32_t* n_last, float* t_final, hipStream_t st) {
-  hipLaunchKernelGGL(k_export_sel, dim3((unsigned)L.tiles), dim3(256), 0, st, (const uint32_t*)(ws + L.pid0),
+  hipLaunchKernelGGL(k_export_sel, dim3((unsigned)L.tiles), dim3(256), 0, st, (const uint32_t*)(ws + L.pid),
                      (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos), (const float*)(ws + L.selw),
                      (const uint32_t*)(ws + L.nlast), (const float*)(ws + L.tfinal), L.k, c.W, c.H, (int)L.ntx,
                      (int)L.tiles, sel_id, sel_w, n_last, t_final);

@@ -10,6 +10,19 @@ TORCH_DTYPES = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat
 OUTPUTS = ("rgb", "depth", "normal", "alpha", "feat")
 
 
+# Relative decision margins below which the HIP path and the FP64 oracle may
+# legitimately decide differently ("several results correct"): the hit test is
+# FP64 on both sides; alpha, transmittance and the blend weights are FP32 on
+# the GPU (the transmittance product accumulates about n * 6e-8 relative).
+# Order: rho vs 9, alpha vs 1/255 and 0.99, T' vs 1e-4, Top-K gap.
+MARGIN_TOL = (1e-9, 1e-5, 5e-5, 5e-5)
+
+
+def decided(ref, tol=MARGIN_TOL):
+    """Pixels whose every decision is farther than `tol` from its threshold."""
+    return np.all(ref["margins"] > np.asarray(tol), axis=-1)
+
+
 def require_gpu():
     assert torch.cuda.is_available(), "GPU parity tests need a HIP device"
 

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import DEV, OUTPUTS, image_errors, np_out, render, require_gpu, stored_feat, to_dev
+from gpu_helpers import decided, DEV, OUTPUTS, image_errors, np_out, render, require_gpu, stored_feat, to_dev
 from paper_2604_10982_amd import psm, scenes
 from paper_2604_10982_amd.scenes import Scene
 
@@ -55,7 +55,7 @@ def test_single_pixel_and_single_tile_images(orc):
         out, _ = render(t, cam, 4)
         ref = orc.render(sc, cam, 4, orc.TOPK)
         absf = orc.render(sc, cam, 4, orc.TOPK, feat=np.abs(sc.feat.astype(np.float64)))["feat"]
-        ok = ref["margin"] > 1e-4
+        ok = decided(ref)
         worst = image_errors(np_out(out), ref, absf, ok, 1e-5)
         assert max(worst.values()) <= 1.0, (w, h, worst)
 
@@ -113,6 +113,6 @@ def test_near_plane_straddling_and_degenerate_surfels(orc):
     np.testing.assert_array_equal(got["id"].numpy(), ref["id"])
     r = orc.render(sc, cam, 8, orc.TOPK)
     absf = orc.render(sc, cam, 8, orc.TOPK, feat=np.abs(sc.feat.astype(np.float64)))["feat"]
-    ok = r["margin"] > 1e-4
+    ok = decided(r)
     worst = image_errors(np_out(out), r, absf, ok, 1e-5)
     assert max(worst.values()) <= 1.0, worst

@@ -6,12 +6,11 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import OUTPUTS, image_errors, np_out, render, require_gpu, stored_feat, to_dev
+from gpu_helpers import decided, OUTPUTS, image_errors, np_out, render, require_gpu, stored_feat, to_dev
 from paper_2604_10982_amd import psm, scenes
 
 pytestmark = pytest.mark.gpu
 
-MARGIN = 1e-4   # pixels whose closest decision is within this relative margin are excluded (and counted)
 
 
 def _ref(orc, sc, cam, K, blend, feat):
@@ -35,7 +34,7 @@ def test_images_match_oracle(orc, case, blend):
     t = to_dev(sc)
     out, ws = render(t, cam, K, "ellipse", blend)
     ref, absf = _ref(orc, sc, cam, K, blend, stored_feat(t))
-    ok = ref["margin"] > MARGIN
+    ok = decided(ref)
     assert (~ok).mean() < 1e-3, f"{(~ok).sum()} pixels within the decision margin"
     worst = image_errors(np_out(out), ref, absf, ok, 1e-5)
     assert max(worst.values()) <= 1.0, worst
@@ -77,6 +76,6 @@ def test_small_and_large_k(orc, K):
     t = to_dev(sc)
     out, ws = render(t, cam, K, "ellipse", "topk")
     ref, absf = _ref(orc, sc, cam, K, "topk", stored_feat(t))
-    ok = ref["margin"] > MARGIN
+    ok = decided(ref)
     worst = image_errors(np_out(out), ref, absf, ok, 1e-5)
     assert max(worst.values()) <= 1.0, worst

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import DEV, image_errors, np_out, render, require_gpu, stored_feat, to_dev
+from gpu_helpers import decided, DEV, image_errors, np_out, render, require_gpu, stored_feat, to_dev
 from paper_2604_10982_amd import psm, scenes
 from test_gpu_backward import grad_errors
 
@@ -48,7 +48,7 @@ def test_fullsize_keys_and_sampled_images(orc, name):
     absf = orc.render(sc, cam, K, orc.TOPK, feat=np.abs(feat), pix=pix)["feat"]
     g = np_out(out)
     flat = {k: v.reshape(cam.width * cam.height, -1)[pix] for k, v in g.items()}
-    ok = ref["margin"] > 1e-4
+    ok = decided(ref)
     assert (~ok).mean() < 1e-3
     worst = image_errors(flat, ref, absf, ok, 1e-5 if dtype == "f32" else 1e-5)
     assert max(worst.values()) <= 1.0, worst
@@ -79,7 +79,7 @@ def test_fullsize_sampled_gradients(orc):
     feat = stored_feat(t)
     r = orc.render(sc, cam, K, orc.TOPK, feat=feat, pix=pix)
     g = scenes.upstream(cam.height, cam.width, sc.c, seed=1)
-    bad = pix[r["margin"] <= 1e-4]
+    bad = pix[~decided(r)]
     for k in g:
         flat = g[k].reshape(cam.width * cam.height, -1)
         flat[bad] = 0.0

@@ -59,7 +59,7 @@ __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size
 struct Layout {
   int64_t n, cap, ntx, nty, tiles, spix;  // spix = tiles * 256 (tile-major pixels)
   int k, c;
-  size_t rec, fp, key0, key1, id0, id1, count, offs, cull, ptile0, ptile1, eid0, eid1, sid_emit, pid, inv, ranges,
+  size_t rec, fp, key0, key1, id0, id1, count, offs, cull, ptile0, ptile1, eid0, eid1, sid_emit, pid, ranges,
       nlast, tfinal, selpos, selw, seldot, gflag, fflag, gpart, fpart, hist, bsum, status, total;
 };
 
@@ -91,14 +91,13 @@ inline Layout make_layout(int64_t n, int width, int height, int k, int c, int64_
   L.eid1 = take(cap1 * 4);
   L.sid_emit = take(cap1 * 4);    // surfel id of each emitted pair
   L.pid = take(cap1 * 4);         // surfel id of each sorted pair
-  L.inv = take(cap1 * 4);         // sorted position of each emitted pair
   L.ranges = take(L.tiles * 8);   // [start, end) per tile
   L.nlast = take(L.spix * 4);
   L.tfinal = take(L.spix * 4);
   L.selpos = take(L.spix * (size_t)k * 4);
   L.selw = take(L.spix * (size_t)k * 4);
   L.seldot = take(L.spix * (size_t)k * 4);
-  // backward partial sums per (tile, surfel) pair, at the pair's sorted index
+  // backward partial sums per (tile, surfel) pair, at the pair's emission index
   L.gflag = take(cap1);
   L.fflag = take(cap1);
   L.gpart = take(cap1 * 64);      // 16 floats: geometric and colour terms

@@ -358,19 +358,18 @@ __global__ __launch_bounds__(256) void k_export_keys(int64_t n, const int32_t* _
   }
 }
 
-// After the tile sort: surfel id of each sorted pair, the sorted position of
-// each emitted pair (so a surfel can find its own pairs again), tile ranges.
+// After the tile sort: surfel id of each sorted pair and the tile ranges.  The
+// sorted values keep each pair's emission index, where the backward writes the
+// pair's partial sums.
 __global__ __launch_bounds__(256) void k_finalize_pairs(const uint32_t* __restrict__ ptile,
                                                         const uint32_t* __restrict__ eid,
                                                         const uint32_t* __restrict__ sid_emit,
                                                         const uint32_t* __restrict__ status, uint32_t* __restrict__ pid,
-                                                        uint32_t* __restrict__ inv, uint2* __restrict__ ranges) {
+                                                        uint2* __restrict__ ranges) {
   const uint32_t P = status[kStP];
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= P) return;
-  const uint32_t e = eid[j];
-  pid[j] = sid_emit[e];
-  inv[e] = j;
+  pid[j] = sid_emit[eid[j]];
   const uint32_t t = ptile[j];
   if (j == 0 || ptile[j - 1] != t) ranges[t].x = j;
   if (j == P - 1 || ptile[j + 1] != t) ranges[t].y = j + 1;
@@ -437,7 +436,7 @@ void launch_ranges(const Layout& L, char* ws, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize_pairs, dim3((unsigned)cdiv(L.cap, 256)), dim3(256), 0, st,
                      (const uint32_t*)(ws + L.ptile0), (const uint32_t*)(ws + L.eid0),
                      (const uint32_t*)(ws + L.sid_emit), (const uint32_t*)(ws + L.status), (uint32_t*)(ws + L.pid),
-                     (uint32_t*)(ws + L.inv), (uint2*)(ws + L.ranges));
+                     (uint2*)(ws + L.ranges));
 }
 
 }  // namespace psm

@@ -3,16 +3,15 @@
 // the stop point and the alpha clamp are held fixed.
 //
 // Deterministic and free of floating-point atomics: every (tile, surfel) pair
-// of the sorted list owns a slot at its sorted index for its partial sums,
-// and a per-surfel pass later adds its own slots in a fixed order (the pair
-// sort recorded where each surfel's pairs went).
+// owns a slot for its partial sums at the index where the key stage emitted
+// it, so a surfel's pairs are contiguous and a per-surfel pass adds them in
+// a fixed order (emission order).
 //
 // k_feat_bwd_topk: per tile, for every (pixel, selected surfel): the dot
 //   product of the pixel's feature gradient with the surfel's feature row
 //   (needed by the alpha adjoint); and, per distinct selected surfel of the
 //   tile, the row sum_p w_p g_F(p) over the pixels that selected it, in pixel
-//   order (per-slot pixel masks give each entry its rank without atomics on
-//   floats).
+//   order.
 // k_walk_bwd: per tile, back to front from each pixel's last contributor,
 //   recovering T_i = T_{i+1} / (1 - alpha_i).  Per surfel the per-pixel terms
 //   are reduced over the wave, then over the 4 waves through LDS, and written
@@ -22,202 +21,186 @@
 //   the chain rule to mu, s, q (FP64, as the forward's walk record).
 #include "common.h"
 #include "internal.h"
+#include "select.h"
 
 namespace psm {
 
 constexpr int kBB = 32;          // surfels per backward batch
 constexpr int kNV = 17;          // per-pixel values reduced per surfel
-constexpr int kWinWords = 1024;  // selected-position window: 32768 positions
 
 // ------------------------------------------------------------ Top-K feature
-constexpr int kSlotChunk = 256;  // distinct selected surfels handled per pass
+constexpr int kGC = 16;         // feature channels per backward pass
+constexpr int kGRow = kGC + 4;  // LDS row stride (floats)
 
-// Position (within the window) of the s-th set bit of the window bitmap.
-__device__ __forceinline__ int slot_position(const uint32_t* bits, const uint32_t* pref, int s) {
-  int lo = 0, hi = kWinWords - 1;  // largest word w with pref[w] <= s
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if ((int)pref[mid] <= s) lo = mid;
-    else hi = mid - 1;
-  }
-  uint32_t w = bits[lo];
-  for (int r = s - (int)pref[lo]; r > 0; --r) w &= w - 1u;
-  return lo * 32 + (__ffs(w) - 1);
-}
-
-template <typename FT>
+// Per tile: the tile's distinct selected surfels get slots (list order); each
+// slot gets the list of (pixel, weight) entries that selected it, in pixel
+// order.  Per pass of 16 channels the pixels' feature gradients and the
+// slots' feature rows are staged in LDS, then
+//   thread = pixel:             dot[q] += g_F(p) . f_slot(q)    (registers)
+//   thread = (slot, 4 channels): row = sum over the slot's entries of w g_F(p)
+// and each row is written at the emitted index of its (tile, surfel) pair.
+template <typename FT, int KMAX>
 __global__ __launch_bounds__(256) void k_feat_bwd_topk(
-    const uint32_t* __restrict__ pid, const uint2* __restrict__ ranges, const int32_t* __restrict__ selpos,
-    const float* __restrict__ selw, const FT* __restrict__ feat, const float* __restrict__ gfeat, int C, int K,
-    int W, int H, int ntx, int tiles, float* __restrict__ seldot, float* __restrict__ fpart,
-    uint8_t* __restrict__ fflag) {
-  extern __shared__ char smem[];
-  uint32_t* s_bits = reinterpret_cast<uint32_t*>(smem);  // selected positions of the window
-  uint32_t* s_pref = s_bits + kWinWords;                   // exclusive popcount prefix per word
-  uint32_t* s_mask = s_pref + kWinWords;                   // [kSlotChunk][8] pixels selecting a slot
-  uint32_t* s_off = s_mask + kSlotChunk * 8;               // [kSlotChunk + 1] entry offsets
-  uint32_t* s_list = s_off + kSlotChunk + 1;               // [256 K] entries (pixel | k << 8)
-  __shared__ int s_maxpos;
-  __shared__ uint32_t s_wsum[256];
+    const uint32_t* __restrict__ pid, const uint32_t* __restrict__ eid, const uint2* __restrict__ ranges,
+    const int32_t* __restrict__ selpos, const float* __restrict__ selw, const FT* __restrict__ feat,
+    const float* __restrict__ gfeat, int C, int K, int W, int H, int ntx, int tiles, float* __restrict__ seldot,
+    float* __restrict__ fpart, uint8_t* __restrict__ fflag) {
+  __shared__ SelShared S;
+  __shared__ __align__(16) float s_G[kTilePix * kGRow];
+  __shared__ __align__(16) float s_F[kSlotChunk * kGRow];
+  __shared__ uint32_t s_mask[kSlotChunk * 8];  // pixels selecting each slot
+  __shared__ uint32_t s_off[kSlotChunk + 1];   // entry offsets per slot
+  __shared__ uint32_t s_fe[kSlotChunk];        // emitted pair index per slot
+  extern __shared__ __align__(16) char smem[];
+  float* s_lw = reinterpret_cast<float*>(smem);                    // [256 K] entry weights
+  uint8_t* s_lp = reinterpret_cast<uint8_t*>(s_lw + kTilePix * K);  // [256 K] entry pixels
 
   const int tile = xcd_tile(blockIdx.x, tiles);
   if (tile >= tiles) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   const int tx = tile % ntx, ty = tile / ntx;
+  const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
+  const bool inside = px < W && py < H;
   const uint32_t start = ranges[tile].x;
-  constexpr int V = VecN<FT>::N;
-  const int lpp = C / V;
-  const int lpp2 = lpp >= 64 ? 64 : pow2_ge(lpp);
-  const int ppw = 64 / lpp2;
-  const int sub = lane / lpp2, cl = lane % lpp2;
   const size_t tbase = (size_t)tile * K * kTilePix;
+  const float* grow = gfeat + ((int64_t)py * W + px) * C;
 
-  // --- dot products g_F(p) . f_j for the selected j (front-to-back slots)
-  for (int p0 = 0; p0 < 64; p0 += ppw) {
-    const int p = wave * 64 + p0 + sub;
-    const int px = tx * kTile + (p & 15), py = ty * kTile + (p >> 4);
-    const bool in = px < W && py < H;
-    const float* grow = gfeat + ((int64_t)py * W + px) * C;
-    for (int q = 0; q < K; ++q) {
-      const int pos = in ? selpos[tbase + (size_t)q * kTilePix + p] : -1;
-      float part = 0.0f;
-      if (pos >= 0) {
-        const uint32_t id = pid[start + pos];
-        for (int cg = cl; cg < lpp; cg += lpp2) {
-          float f[V];
-          load_vec<FT>(feat + (size_t)id * C + cg * V, f);
-#pragma unroll
-          for (int v = 0; v < V; v += 4) {
-            const float4 x = *reinterpret_cast<const float4*>(grow + cg * V + v);
-            part = fmaf(x.x, f[v], part);
-            part = fmaf(x.y, f[v + 1], part);
-            part = fmaf(x.z, f[v + 2], part);
-            part = fmaf(x.w, f[v + 3], part);
-          }
-        }
-      }
-      for (int o = lpp2 >> 1; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-      if (cl == 0) seldot[tbase + (size_t)q * kTilePix + p] = pos >= 0 ? part : 0.0f;
-    }
-  }
-
-  // --- dL/df rows, one per distinct selected (tile, surfel) pair
-  if (tid == 0) s_maxpos = -1;
-  __syncthreads();
+  int pos[KMAX];
+  float w[KMAX], dot[KMAX];
   int mymax = -1;
-  for (int q = 0; q < K; ++q) mymax = max(mymax, selpos[tbase + (size_t)q * kTilePix + tid]);
-  atomicMax(&s_maxpos, mymax);
-  __syncthreads();
-  const int maxpos = s_maxpos;
-  for (int w0 = 0; w0 <= maxpos; w0 += kWinWords * 32) {
-    for (int i = tid; i < kWinWords; i += 256) s_bits[i] = 0u;
-    __syncthreads();
-    for (int q = 0; q < K; ++q) {
-      const int pos = selpos[tbase + (size_t)q * kTilePix + tid] - w0;
-      if (pos >= 0 && pos < kWinWords * 32) atomicOr(&s_bits[pos >> 5], 1u << (pos & 31));
-    }
-    __syncthreads();
-    uint32_t c4 = 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) c4 += __popc(s_bits[tid * 4 + i]);
-    s_wsum[tid] = c4;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-      const uint32_t v = tid >= o ? s_wsum[tid - o] : 0u;
-      __syncthreads();
-      s_wsum[tid] += v;
-      __syncthreads();
-    }
-    uint32_t run = s_wsum[tid] - c4;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      s_pref[tid * 4 + i] = run;
-      run += __popc(s_bits[tid * 4 + i]);
-    }
-    const int U = (int)s_wsum[255];
-    __syncthreads();
-    for (int c0 = 0; c0 < U; c0 += kSlotChunk) {
-      const int ns = min(kSlotChunk, U - c0);
+  for (int q = 0; q < KMAX; ++q) {
+    pos[q] = q < K ? selpos[tbase + (size_t)q * kTilePix + tid] : -1;
+    w[q] = q < K ? selw[tbase + (size_t)q * kTilePix + tid] : 0.0f;
+    dot[q] = 0.0f;
+    mymax = max(mymax, pos[q]);
+  }
+  const int maxpos = block_max(mymax, S.red);
+
+  for (int w0 = 0; w0 <= maxpos; w0 += kWinPos) {
+    const int nw = window_words(maxpos, w0);
+    const int Uw = build_window(S, pos, K, w0, nw);
+    for (int c0 = 0; c0 < Uw; c0 += kSlotChunk) {
+      const int ns = min(kSlotChunk, Uw - c0);
       for (int i = tid; i < ns * 8; i += 256) s_mask[i] = 0u;
       __syncthreads();
-      // which pixels selected each slot of this chunk
-      for (int q = 0; q < K; ++q) {
-        const int pos = selpos[tbase + (size_t)q * kTilePix + tid] - w0;
-        if (pos < 0 || pos >= kWinWords * 32) continue;
-        const int slot = (int)(s_pref[pos >> 5] + __popc(s_bits[pos >> 5] & ((1u << (pos & 31)) - 1u))) - c0;
-        if (slot >= 0 && slot < ns) atomicOr(&s_mask[slot * 8 + (tid >> 5)], 1u << (tid & 31));
-      }
-      __syncthreads();
-      // entry offsets: exclusive scan of the slot populations
-      uint32_t cnt = 0;
-      if (tid < ns)
-        for (int w = 0; w < 8; ++w) cnt += __popc(s_mask[tid * 8 + w]);
-      s_wsum[tid] = cnt;
-      __syncthreads();
-      for (int o = 1; o < 256; o <<= 1) {
-        const uint32_t v = tid >= o ? s_wsum[tid - o] : 0u;
-        __syncthreads();
-        s_wsum[tid] += v;
-        __syncthreads();
-      }
-      if (tid < ns) s_off[tid] = s_wsum[tid] - cnt;
-      if (tid == 0) s_off[ns] = s_wsum[ns - 1];
-      __syncthreads();
-      // entries in pixel order within each slot
-      for (int q = 0; q < K; ++q) {
-        const int pos = selpos[tbase + (size_t)q * kTilePix + tid] - w0;
-        if (pos < 0 || pos >= kWinWords * 32) continue;
-        const int slot = (int)(s_pref[pos >> 5] + __popc(s_bits[pos >> 5] & ((1u << (pos & 31)) - 1u))) - c0;
-        if (slot < 0 || slot >= ns) continue;
-        const uint32_t* m = s_mask + slot * 8;
-        uint32_t rank = __popc(m[tid >> 5] & ((1u << (tid & 31)) - 1u));
-        for (int w = 0; w < (tid >> 5); ++w) rank += __popc(m[w]);
-        s_list[s_off[slot] + rank] = (uint32_t)tid | ((uint32_t)q << 8);
-      }
-      __syncthreads();
-      // one lane group per slot: sum_p w_p g_F(p)
-      for (int sb = wave * ppw; sb < ns; sb += 4 * ppw) {
-        const int sl = sb + sub;
-        if (sl < ns) {
-          const int pos = w0 + slot_position(s_bits, s_pref, c0 + sl);
-          const uint32_t e0 = s_off[sl], e1 = s_off[sl + 1];
-          float* out = fpart + ((size_t)start + pos) * C;
-          for (int cg = cl; cg < lpp; cg += lpp2) {
-            float acc[V];
+      int sl[KMAX];
 #pragma unroll
-            for (int v = 0; v < V; ++v) acc[v] = 0.0f;
-            for (uint32_t e = e0; e < e1; ++e) {
-              const uint32_t ent = s_list[e];
-              const int p = (int)(ent & 255u), q = (int)(ent >> 8);
-              const float w = selw[tbase + (size_t)q * kTilePix + p];
-              const int px = tx * kTile + (p & 15), py = ty * kTile + (p >> 4);
-              const float* grow = gfeat + ((int64_t)py * W + px) * C + cg * V;
-#pragma unroll
-              for (int v = 0; v < V; v += 4) {
-                const float4 x = *reinterpret_cast<const float4*>(grow + v);
-                acc[v] = fmaf(w, x.x, acc[v]);
-                acc[v + 1] = fmaf(w, x.y, acc[v + 1]);
-                acc[v + 2] = fmaf(w, x.z, acc[v + 2]);
-                acc[v + 3] = fmaf(w, x.w, acc[v + 3]);
-              }
-            }
-#pragma unroll
-            for (int v = 0; v < V; v += 4)
-              *reinterpret_cast<float4*>(out + cg * V + v) = make_float4(acc[v], acc[v + 1], acc[v + 2], acc[v + 3]);
-          }
-          if (cl == 0) fflag[start + pos] = 1;
+      for (int q = 0; q < KMAX; ++q) {
+        const int s = q < K ? slot_of(S, pos[q], w0, nw) : -1;
+        sl[q] = (s >= c0 && s < c0 + ns) ? s - c0 : -1;
+        if (sl[q] >= 0) {
+          atomicOr(&s_mask[sl[q] * 8 + (tid >> 5)], 1u << (tid & 31));
+          S.fid[sl[q]] = pid[start + pos[q]];
+          S.lpos[sl[q]] = (uint32_t)pos[q];
         }
       }
       __syncthreads();
+      uint32_t cnt = 0;
+      if (tid < ns)
+        for (int wd = 0; wd < 8; ++wd) cnt += (uint32_t)__popc(s_mask[tid * 8 + wd]);
+      uint32_t tot;
+      const uint32_t off = block_scan_excl(cnt, S.red, tot);
+      if (tid < ns) {
+        s_off[tid] = off;
+        s_fe[tid] = eid[start + S.lpos[tid]];
+      }
+      if (tid == 0) s_off[ns] = tot;
+      __syncthreads();
+      // entries of each slot in pixel order: rank = selecting pixels before this one
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q) {
+        if (sl[q] >= 0) {
+          const uint32_t* m = s_mask + sl[q] * 8;
+          uint32_t rank = (uint32_t)__popc(m[tid >> 5] & ((1u << (tid & 31)) - 1u));
+          for (int wd = 0; wd < (tid >> 5); ++wd) rank += (uint32_t)__popc(m[wd]);
+          const uint32_t e = s_off[sl[q]] + rank;
+          s_lw[e] = w[q];
+          s_lp[e] = (uint8_t)tid;
+        }
+      }
+      __syncthreads();
+
+      for (int cc = 0; cc < C; cc += kGC) {
+        float4 g[kGC / 4];
+#pragma unroll
+        for (int j = 0; j < kGC / 4; ++j) {
+          const int c = cc + 4 * j;
+          g[j] = inside && c < C ? *reinterpret_cast<const float4*>(grow + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+          *reinterpret_cast<float4*>(s_G + tid * kGRow + 4 * j) = g[j];
+        }
+        for (int item = tid; item < ns * (kGC / 4); item += 256) {
+          const int s = item / (kGC / 4), j = item % (kGC / 4), c = cc + 4 * j;
+          const float4 f = c < C ? load4<FT>(feat + (size_t)S.fid[s] * C + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+          *reinterpret_cast<float4*>(s_F + s * kGRow + 4 * j) = f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) {
+          if (sl[q] >= 0) {
+            const float* fr = s_F + sl[q] * kGRow;
+            float d = dot[q];
+#pragma unroll
+            for (int j = 0; j < kGC / 4; ++j) {
+              const float4 f = *reinterpret_cast<const float4*>(fr + 4 * j);
+              d = fmaf(g[j].x, f.x, d);
+              d = fmaf(g[j].y, f.y, d);
+              d = fmaf(g[j].z, f.z, d);
+              d = fmaf(g[j].w, f.w, d);
+            }
+            dot[q] = d;
+          }
+        }
+        for (int item = tid; item < ns * (kGC / 4); item += 256) {
+          const int s = item / (kGC / 4), j = item % (kGC / 4), c = cc + 4 * j;
+          const int e1 = (int)s_off[s + 1];
+          int e = (int)s_off[s];
+          float4 a[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) a[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+          for (; e + 4 <= e1; e += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const float wt = s_lw[e + u];
+              const float4 x = *reinterpret_cast<const float4*>(s_G + (int)s_lp[e + u] * kGRow + 4 * j);
+              a[u].x = fmaf(wt, x.x, a[u].x);
+              a[u].y = fmaf(wt, x.y, a[u].y);
+              a[u].z = fmaf(wt, x.z, a[u].z);
+              a[u].w = fmaf(wt, x.w, a[u].w);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 3; ++u) {
+            if (e + u < e1) {
+              const float wt = s_lw[e + u];
+              const float4 x = *reinterpret_cast<const float4*>(s_G + (int)s_lp[e + u] * kGRow + 4 * j);
+              a[u].x = fmaf(wt, x.x, a[u].x);
+              a[u].y = fmaf(wt, x.y, a[u].y);
+              a[u].z = fmaf(wt, x.z, a[u].z);
+              a[u].w = fmaf(wt, x.w, a[u].w);
+            }
+          }
+          if (c < C) {
+            const float4 r = make_float4((a[0].x + a[1].x) + (a[2].x + a[3].x), (a[0].y + a[1].y) + (a[2].y + a[3].y),
+                                         (a[0].z + a[1].z) + (a[2].z + a[3].z), (a[0].w + a[1].w) + (a[2].w + a[3].w));
+            *reinterpret_cast<float4*>(fpart + (size_t)s_fe[s] * C + c) = r;
+          }
+        }
+        __syncthreads();
+      }
+      if (tid < ns) fflag[s_fe[tid]] = 1;
     }
-    __syncthreads();  // the next window rewrites the bitmap
   }
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q)
+    if (q < K) seldot[tbase + (size_t)q * kTilePix + tid] = pos[q] >= 0 ? dot[q] : 0.0f;
 }
 
 // ------------------------------------------------------------- walk backward
 template <int MODE, typename FT>
 __global__ __launch_bounds__(256) void k_walk_bwd(
-    const WalkRec* __restrict__ rec, const uint32_t* __restrict__ pid, const uint2* __restrict__ ranges, int W,
+    const WalkRec* __restrict__ rec, const uint32_t* __restrict__ pid, const uint32_t* __restrict__ eid,
+    const uint2* __restrict__ ranges, int W,
     int H, int ntx, int tiles, int K, const uint32_t* __restrict__ nlast, const float* __restrict__ tfinal,
     const int32_t* __restrict__ selpos, const float* __restrict__ seldot, const float* __restrict__ g_rgb,
     const float* __restrict__ g_depth, const float* __restrict__ g_normal, const float* __restrict__ g_alpha,
@@ -392,7 +375,7 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
         const WalkRec& rr = rec[id];
         const float a00 = (float)rr.d0.x, a01 = (float)rr.d0.y, a10 = (float)rr.d1.x, a11 = (float)rr.d1.y;
         const float e0 = (float)rr.d2.x, e1 = (float)rr.d2.y;
-        const size_t slot = (size_t)start + lo + k;
+        const size_t slot = eid[start + lo + k];
         float4* g = reinterpret_cast<float4*>(gpart + slot * 16);
         // u' = A^-1 d, w' = 1 - e.d with d = pixel - centre; d depends on the
         // centre with slope -1
@@ -428,7 +411,7 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
             for (int j = 0; j < PER; ++j) {
               const int k = kg * PER + j;
               if (k < nb) {
-                const size_t slot = (size_t)start + lo + k;
+                const size_t slot = eid[start + lo + k];
                 fpart[slot * C + c] = acc[j];
                 if (c == 0) fflag[slot] = 1;
               }
@@ -446,11 +429,10 @@ struct CamB {
 };
 
 // Thread per surfel, visited in depth order so its pairs are the emitted
-// range [offs[r], offs[r] + count): their sorted slots come from `inv`.
+// range [offs[r], offs[r] + count).
 __global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, const uint32_t* __restrict__ order,
                                                     const uint32_t* __restrict__ count,
-                                                    const uint32_t* __restrict__ offs,
-                                                    const uint32_t* __restrict__ inv, int64_t cap,
+                                                    const uint32_t* __restrict__ offs, int64_t cap,
                                                     const float* __restrict__ gpart,
                                                     const uint8_t* __restrict__ gflag,
                                                     const float* __restrict__ means, const float* __restrict__ scales,
@@ -472,8 +454,8 @@ __global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, const uint32_t* _
 #pragma unroll
   for (int j = 0; j < 16; ++j) G[j] = 0.0;
   const int64_t base = offs[r], cnt = count[i];
-  for (int64_t j = 0; j < cnt && base + j < cap; ++j) {
-    const uint32_t slot = inv[base + j];
+  const int64_t end = min(base + cnt, cap);
+  for (int64_t slot = base; slot < end; ++slot) {
     if (!gflag[slot]) continue;
     const float4* g = reinterpret_cast<const float4*>(gpart + (size_t)slot * 16);
 #pragma unroll
@@ -582,8 +564,7 @@ __global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, const uint32_t* _
 // Lane group per surfel (in depth order): dL/df = sum of its pairs' rows.
 __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, const uint32_t* __restrict__ order,
                                                      const uint32_t* __restrict__ count,
-                                                     const uint32_t* __restrict__ offs,
-                                                     const uint32_t* __restrict__ inv, int64_t cap,
+                                                     const uint32_t* __restrict__ offs, int64_t cap,
                                                      const float* __restrict__ fpart,
                                                      const uint8_t* __restrict__ fflag, int C,
                                                      float* __restrict__ dfeat) {
@@ -598,8 +579,8 @@ __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, const uint32_t* 
   const int64_t base = offs[r], cnt = count[i];
   for (int cg = cl; cg < lpp; cg += lpp2) {
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int64_t j = 0; j < cnt && base + j < cap; ++j) {
-      const uint32_t slot = inv[base + j];
+    const int64_t end = min(base + cnt, cap);
+    for (int64_t slot = base; slot < end; ++slot) {
       if (!fflag[slot]) continue;
       const float4 v = *reinterpret_cast<const float4*>(fpart + (size_t)slot * C + cg * 4);
       acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
@@ -609,11 +590,23 @@ __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, const uint32_t* 
 }
 
 // ------------------------------------------------------------- host wrappers
+template <typename FT, int KMAX>
+static void feat_bwd_launch(const SurfelArgs& s, const Layout& L, const CamArgs& c, const ImageGradArgs& g, char* ws,
+                            hipStream_t st) {
+  const size_t shm = (size_t)kTilePix * L.k * 5;  // entry weights + entry pixels
+  hipLaunchKernelGGL((k_feat_bwd_topk<FT, KMAX>), dim3(xcd_grid(L.tiles)), dim3(256), shm, st,
+                     (const uint32_t*)(ws + L.pid), (const uint32_t*)(ws + L.eid0), (const uint2*)(ws + L.ranges),
+                     (const int32_t*)(ws + L.selpos), (const float*)(ws + L.selw), (const FT*)s.feat, g.feat, s.c, L.k,
+                     c.W, c.H, (int)L.ntx, (int)L.tiles, (float*)(ws + L.seldot), (float*)(ws + L.fpart),
+                     (uint8_t*)(ws + L.fflag));
+}
+
 template <typename FT>
 static void backward_typed(const SurfelArgs& s, const CamArgs& c, int blend, const Layout& L, const ImageGradArgs& g,
                            const GradArgs& gr, char* ws, hipStream_t st, const ProfHook& prof) {
   const WalkRec* rec = (const WalkRec*)(ws + L.rec);
   const uint32_t* pid = (const uint32_t*)(ws + L.pid);
+  const uint32_t* eid = (const uint32_t*)(ws + L.eid0);
   const uint2* ranges = (const uint2*)(ws + L.ranges);
   float* gpart = (float*)(ws + L.gpart);
   float* fpart = (float*)(ws + L.fpart);
@@ -624,23 +617,22 @@ static void backward_typed(const SurfelArgs& s, const CamArgs& c, int blend, con
   if (blend == kTopK) {
     prof.begin(kStageBwdFeature, st);
     if (want_f) {
-      const size_t shm = (size_t)(2 * kWinWords + kSlotChunk * 8 + kSlotChunk + 1 + kTilePix * L.k) * 4;
-      hipLaunchKernelGGL((k_feat_bwd_topk<FT>), grid, dim3(256), shm, st, pid, ranges,
-                         (const int32_t*)(ws + L.selpos), (const float*)(ws + L.selw), (const FT*)s.feat, g.feat, s.c,
-                         L.k, c.W, c.H, (int)L.ntx, (int)L.tiles, (float*)(ws + L.seldot), fpart, fflag);
+      if (L.k <= 8) feat_bwd_launch<FT, 8>(s, L, c, g, ws, st);
+      else if (L.k <= 16) feat_bwd_launch<FT, 16>(s, L, c, g, ws, st);
+      else feat_bwd_launch<FT, 32>(s, L, c, g, ws, st);
     } else {
       launch_fill_u32(ws + L.seldot, 0u, L.spix * (int64_t)L.k, st);
     }
     prof.end(kStageBwdFeature, st);
     prof.begin(kStageBwdWalk, st);
-    hipLaunchKernelGGL((k_walk_bwd<kTopK, FT>), grid, dim3(256), 0, st, rec, pid, ranges, c.W, c.H, (int)L.ntx,
+    hipLaunchKernelGGL((k_walk_bwd<kTopK, FT>), grid, dim3(256), 0, st, rec, pid, eid, ranges, c.W, c.H, (int)L.ntx,
                        (int)L.tiles, L.k, (const uint32_t*)(ws + L.nlast), (const float*)(ws + L.tfinal),
                        (const int32_t*)(ws + L.selpos), (const float*)(ws + L.seldot), g.rgb, g.depth, g.normal,
                        g.alpha, g.feat, (const FT*)s.feat, s.c, gpart, gflag, fpart, fflag);
     prof.end(kStageBwdWalk, st);
   } else {
     prof.begin(kStageBwdWalk, st);
-    hipLaunchKernelGGL((k_walk_bwd<kFull, FT>), grid, dim3(256), 0, st, rec, pid, ranges, c.W, c.H, (int)L.ntx,
+    hipLaunchKernelGGL((k_walk_bwd<kFull, FT>), grid, dim3(256), 0, st, rec, pid, eid, ranges, c.W, c.H, (int)L.ntx,
                        (int)L.tiles, L.k, (const uint32_t*)(ws + L.nlast), (const float*)(ws + L.tfinal),
                        (const int32_t*)(ws + L.selpos), (const float*)(ws + L.seldot), g.rgb, g.depth, g.normal,
                        g.alpha, want_f ? g.feat : nullptr, (const FT*)s.feat, s.c, gpart, gflag, fpart, fflag);
@@ -654,9 +646,8 @@ static void backward_typed(const SurfelArgs& s, const CamArgs& c, int blend, con
   const uint32_t* order = (const uint32_t*)(ws + L.id0);
   const uint32_t* count = (const uint32_t*)(ws + L.count);
   const uint32_t* offs = (const uint32_t*)(ws + L.offs);
-  const uint32_t* inv = (const uint32_t*)(ws + L.inv);
   if (s.n > 0) {
-    hipLaunchKernelGGL(k_reduce_geo, dim3((unsigned)cdiv(s.n, 256)), dim3(256), 0, st, s.n, order, count, offs, inv,
+    hipLaunchKernelGGL(k_reduce_geo, dim3((unsigned)cdiv(s.n, 256)), dim3(256), 0, st, s.n, order, count, offs,
                        L.cap, (const float*)gpart, (const uint8_t*)gflag, s.means, s.scales, s.quats,
                        (const int32_t*)(ws + L.cull), cb, gr.means, gr.scales, gr.quats, gr.opacity, gr.rgb);
     if (s.c > 0 && gr.feat) {
@@ -665,7 +656,7 @@ static void backward_typed(const SurfelArgs& s, const CamArgs& c, int blend, con
       while (lpp2 < lpp && lpp2 < 64) lpp2 <<= 1;
       const int per_block = 4 * (64 / lpp2);
       hipLaunchKernelGGL(k_reduce_feat, dim3((unsigned)cdiv(s.n, per_block)), dim3(256), 0, st, s.n, order, count,
-                         offs, inv, L.cap, (const float*)fpart, (const uint8_t*)fflag, s.c, gr.feat);
+                         offs, L.cap, (const float*)fpart, (const uint8_t*)fflag, s.c, gr.feat);
     }
   }
   prof.end(kStageBwdPreprocess, st);

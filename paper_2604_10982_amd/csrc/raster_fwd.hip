@@ -7,12 +7,15 @@
 //   alpha blend, stop before T would fall below 1e-4, and (Top-K mode) a
 //   per-pixel register heap of the K largest weights with their list
 //   positions.  A block stops when all of its pixels are done.
-// k_blend_topk: eq. (18) gather-blend of the selected feature rows, lane per
-//   channel group (coalesced 16-byte loads), accumulated front to back.
+// k_blend_topk: eq. (18) blend of the selected feature rows, thread per pixel.
+//   The tile's distinct selected rows are staged in LDS per pass of 32
+//   channels and read by slot; each pixel accumulates in ascending list
+//   position (front to back).
 // k_full_feat: the dense feature blend of eq. (1) (the baseline the paper
 //   accelerates), channel-chunked re-walks with feature rows staged in LDS.
 #include "common.h"
 #include "internal.h"
+#include "select.h"
 
 namespace psm {
 
@@ -193,54 +196,124 @@ __global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, c
 }
 
 // ---------------------------------------------------------------- features
+constexpr int kBC = 32;           // feature channels per blend pass
+constexpr int kBRow = kBC + 4;    // LDS row stride (floats)
+
+// Stages channels [cc, cc + kBC) of the chunk's ns slot rows into s_F.
 template <typename FT>
+__device__ __forceinline__ void stage_rows(float* s_F, const uint32_t* fid, int ns, const FT* __restrict__ feat,
+                                           int C, int cc) {
+  for (int item = threadIdx.x; item < ns * (kBC / 4); item += 256) {
+    const int s = item / (kBC / 4), j = item % (kBC / 4), c = cc + 4 * j;
+    const float4 f = c < C ? load4<FT>(feat + (size_t)fid[s] * C + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+    *reinterpret_cast<float4*>(s_F + s * kBRow + 4 * j) = f;
+  }
+}
+
+// Adds the selections of this thread's pixel that fall in the staged chunk
+// (sl[q] = chunk slot or -1), in ascending list position.
+template <int KMAX>
+__device__ __forceinline__ void blend_chunk(const float* s_F, const int (&sl)[KMAX], const float (&w)[KMAX], int K,
+                                            float (&acc)[kBC]) {
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    if (q < K && sl[q] >= 0) {
+      const float* fr = s_F + sl[q] * kBRow;
+#pragma unroll
+      for (int c = 0; c < kBC; c += 4) {
+        const float4 f = *reinterpret_cast<const float4*>(fr + c);
+        acc[c] = fmaf(w[q], f.x, acc[c]);
+        acc[c + 1] = fmaf(w[q], f.y, acc[c + 1]);
+        acc[c + 2] = fmaf(w[q], f.z, acc[c + 2]);
+        acc[c + 3] = fmaf(w[q], f.w, acc[c + 3]);
+      }
+    }
+  }
+}
+
+// Thread per pixel; the tile's distinct selected rows are staged in LDS once
+// per channel pass and read by slot.
+template <typename FT, int KMAX>
 __global__ __launch_bounds__(256) void k_blend_topk(const uint32_t* __restrict__ pid, const uint2* __restrict__ ranges,
                                                     const int32_t* __restrict__ selpos,
                                                     const float* __restrict__ selw, const FT* __restrict__ feat,
                                                     int C, int K, int W, int H, int ntx, int tiles,
                                                     float* __restrict__ o_feat) {
-  extern __shared__ char smem[];
-  int32_t* s_id = reinterpret_cast<int32_t*>(smem);
-  float* s_w = reinterpret_cast<float*>(smem + (size_t)K * kTilePix * 4);
+  __shared__ SelShared S;
+  __shared__ __align__(16) float s_F[kSlotChunk * kBRow];
   const int tile = xcd_tile(blockIdx.x, tiles);
   if (tile >= tiles) return;
   const int tid = threadIdx.x;
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
+  const bool inside = px < W && py < H;
   const uint32_t start = ranges[tile].x;
-  for (int q = 0; q < K; ++q) {
-    const size_t o = ((size_t)tile * K + q) * kTilePix + tid;
-    const int pos = selpos[o];
-    s_id[q * kTilePix + tid] = pos >= 0 ? (int)pid[start + pos] : -1;
-    s_w[q * kTilePix + tid] = selw[o];
+  const size_t tbase = (size_t)tile * K * kTilePix;
+  float* out = o_feat + ((int64_t)py * W + px) * C;
+
+  int pos[KMAX];
+  float w[KMAX];
+  int mymax = -1;
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    pos[q] = q < K ? selpos[tbase + (size_t)q * kTilePix + tid] : -1;
+    w[q] = q < K ? selw[tbase + (size_t)q * kTilePix + tid] : 0.0f;
+    mymax = max(mymax, pos[q]);
+  }
+  const int maxpos = block_max(mymax, S.red);
+
+  // One window whose slots fit one chunk: rank once, stage per channel pass.
+  int sl[KMAX];
+  int U = 0;
+  const bool one_window = maxpos < kWinPos;
+  if (maxpos >= 0 && one_window) {
+    U = build_window(S, pos, K, 0, window_words(maxpos, 0));
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) sl[q] = q < K ? slot_of(S, pos[q], 0, window_words(maxpos, 0)) : -1;
+  }
+  const bool cached = maxpos >= 0 && one_window && U <= kSlotChunk;
+  if (cached) {
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+      if (sl[q] >= 0) S.fid[sl[q]] = pid[start + pos[q]];
   }
   __syncthreads();
-  constexpr int V = VecN<FT>::N;
-  const int lpp = C / V;  // lanes needed per pixel
-  const int lpp2 = lpp >= 64 ? 64 : pow2_ge(lpp);
-  const int ppw = 64 / lpp2;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int sub = lane / lpp2, cl = lane % lpp2;
-  const int tx = tile % ntx, ty = tile / ntx;
-  for (int p0 = 0; p0 < 64; p0 += ppw) {
-    const int p = wave * 64 + p0 + sub;
-    const int px = tx * kTile + (p & 15), py = ty * kTile + (p >> 4);
-    if (px >= W || py >= H) continue;
-    float* out = o_feat + ((int64_t)py * W + px) * C;
-    for (int cgp = cl; cgp < lpp; cgp += lpp2) {
-      float acc[V];
+
+  for (int cc = 0; cc < C; cc += kBC) {
+    float acc[kBC];
 #pragma unroll
-      for (int v = 0; v < V; ++v) acc[v] = 0.0f;
-      for (int q = 0; q < K; ++q) {
-        const int id = s_id[q * kTilePix + p];
-        if (id < 0) break;
-        const float w = s_w[q * kTilePix + p];
-        float f[V];
-        load_vec<FT>(feat + (size_t)id * C + cgp * V, f);
+    for (int c = 0; c < kBC; ++c) acc[c] = 0.0f;
+    if (cached) {
+      stage_rows<FT>(s_F, S.fid, U, feat, C, cc);
+      __syncthreads();
+      blend_chunk<KMAX>(s_F, sl, w, K, acc);
+      __syncthreads();
+    } else {
+      for (int w0 = 0; w0 <= maxpos; w0 += kWinPos) {
+        const int nw = window_words(maxpos, w0);
+        const int Uw = build_window(S, pos, K, w0, nw);
+        for (int c0 = 0; c0 < Uw; c0 += kSlotChunk) {
+          const int ns = min(kSlotChunk, Uw - c0);
+          int sq[KMAX];
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc[v] = fmaf(w, f[v], acc[v]);
+          for (int q = 0; q < KMAX; ++q) {
+            const int s = q < K ? slot_of(S, pos[q], w0, nw) : -1;
+            sq[q] = (s >= c0 && s < c0 + ns) ? s - c0 : -1;
+            if (sq[q] >= 0) S.fid[sq[q]] = pid[start + pos[q]];
+          }
+          __syncthreads();
+          stage_rows<FT>(s_F, S.fid, ns, feat, C, cc);
+          __syncthreads();
+          blend_chunk<KMAX>(s_F, sq, w, K, acc);
+          __syncthreads();
+        }
       }
+    }
+    if (inside) {
 #pragma unroll
-      for (int v = 0; v < V; v += 4)
-        *reinterpret_cast<float4*>(out + cgp * V + v) = make_float4(acc[v], acc[v + 1], acc[v + 2], acc[v + 3]);
+      for (int c = 0; c < kBC; c += 4)
+        if (cc + c < C)
+          *reinterpret_cast<float4*>(out + cc + c) = make_float4(acc[c], acc[c + 1], acc[c + 2], acc[c + 3]);
     }
   }
 }
@@ -360,15 +433,22 @@ void launch_walk(const Layout& L, const CamArgs& c, int blend, const ImageArgs& 
   }
 }
 
+template <typename FT, int KMAX>
+static void blend_topk_launch(const SurfelArgs& s, const Layout& L, const CamArgs& c, float* out_feat, char* ws,
+                              hipStream_t st) {
+  hipLaunchKernelGGL((k_blend_topk<FT, KMAX>), dim3(xcd_grid(L.tiles)), dim3(256), 0, st,
+                     (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos),
+                     (const float*)(ws + L.selw), (const FT*)s.feat, s.c, L.k, c.W, c.H, (int)L.ntx, (int)L.tiles,
+                     out_feat);
+}
+
 template <typename FT>
 static void blend_launch(const SurfelArgs& s, const Layout& L, const CamArgs& c, int blend, float* out_feat,
                          char* ws, hipStream_t st) {
   if (blend == kTopK) {
-    const size_t shm = (size_t)L.k * kTilePix * 8;
-    hipLaunchKernelGGL((k_blend_topk<FT>), dim3(xcd_grid(L.tiles)), dim3(256), shm, st,
-                       (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos),
-                       (const float*)(ws + L.selw), (const FT*)s.feat, s.c, L.k, c.W, c.H, (int)L.ntx, (int)L.tiles,
-                       out_feat);
+    if (L.k <= 8) blend_topk_launch<FT, 8>(s, L, c, out_feat, ws, st);
+    else if (L.k <= 16) blend_topk_launch<FT, 16>(s, L, c, out_feat, ws, st);
+    else blend_topk_launch<FT, 32>(s, L, c, out_feat, ws, st);
   } else {
     hipLaunchKernelGGL((k_full_feat<FT, 64>), dim3(xcd_grid(L.tiles)), dim3(256), 0, st, (const WalkRec*)(ws + L.rec),
                        (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), (const FT*)s.feat, s.c, c.W,

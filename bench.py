@@ -49,7 +49,8 @@ def parse():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
-    ap.add_argument("--cpu-tiles", type=int, default=96)
+    ap.add_argument("--cpu-tiles", type=int, default=1200)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 8-camera batched workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -120,21 +121,56 @@ def timed(form, bwd, steps, warmup):
     return el * 1000.0 / steps, per_stage, st
 
 
-def roofline(stages, st, K, C, S, bwd):
+def kernel_source_hash() -> str:
+    """SHA-256 over the kernel sources (csrc/*.hip, csrc/*.h), in name order."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_10982_amd", "csrc", "*.h")) +
+                    glob.glob(os.path.join(ROOT, "paper_2604_10982_amd", "csrc", "*.hip"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage: str, workload: str):
+    """HBM bytes per launch (read + written) of a stage's kernel from the
+    committed rocprofv3 counter summary, or None when there is none or the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{stage}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel sources sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["bytes per launch (read + write)"])
+    except (KeyError, ValueError):
+        return None
+
+
+def roofline(stages, st, K, C, S, bwd, workload=WORKLOAD):
     """Roofline object for the dominant stage of the step."""
     name = max(stages, key=stages.get)
     ms = stages[name]
+    traffic = measured_traffic(name, workload)
     if name == "walk":
         flops = FLOP_PER_EVAL * st.pairs_walked + FLOP_PER_CONTRIB * st.contributors
         a = flops / (ms * 1e-3) / 1e12
         return {"kernel": name, "bound": "alu", "achieved": a, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": a / FP32_VALU_PEAK_TFLOPS, "traffic": None, "ms": ms,
+                "frac": a / FP32_VALU_PEAK_TFLOPS, "traffic": traffic, "ms": ms,
                 "work": {"pairs_walked": st.pairs_walked, "contributors": st.contributors}}
     if name == "bwd_walk":
         flops = BWD_FLOP_PER_EVAL * st.pairs_walked + BWD_FLOP_PER_CONTRIB * st.contributors
         a = flops / (ms * 1e-3) / 1e12
         return {"kernel": name, "bound": "alu", "achieved": a, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": a / FP32_VALU_PEAK_TFLOPS, "traffic": None, "ms": ms,
+                "frac": a / FP32_VALU_PEAK_TFLOPS, "traffic": traffic, "ms": ms,
                 "work": {"pairs_walked": st.pairs_walked, "contributors": st.contributors}}
     # streaming stages: algorithmic bytes
     P, N = st.pairs, st.n
@@ -153,7 +189,88 @@ def roofline(stages, st, K, C, S, bwd):
     b = bytes_by.get(name, 0)
     a = b / (ms * 1e-3) / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": a / HBM_PEAK_GBS, "traffic": None, "ms": ms}
+            "frac": a / HBM_PEAK_GBS, "traffic": traffic, "ms": ms}
+
+
+def batch_workload(psm, scenes, steps, warmup):
+    """The batched workload: a shared 2M-surfel street scene with 128-d FP16
+    features seen by 8 cameras of uneven resolution, fwd+bwd in one call per
+    stage.  Launch choices come from the library's autotuner; the step is
+    also captured in a HIP graph and replayed."""
+    import numpy as np
+    import torch
+    device = torch.device("cuda:0")
+    sc, cams, K, dtype = scenes.batch_config()
+    t = {k: torch.tensor(getattr(sc, k), device=device) for k in ("means", "scales", "quats", "opacity", "rgb")}
+    t["feat"] = torch.tensor(sc.feat, device=device).to(torch.float16).contiguous()
+    args = (t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"])
+    carr = psm.camera_array(cams)
+    _, ws0, _ = psm.forward_batch(*args, carr, K)
+    need = psm.read_stats_batch(ws0, carr, psm.config_struct(K)).pairs_required
+    del ws0
+    cfg = psm.config_struct(K, "ellipse", "topk", psm.FLAG_NO_SYNC | psm.FLAG_PROFILE)
+    ws = psm.alloc_workspace_batch(sc.n, carr, cfg, sc.c, int(need * 1.05) + 4096, device)
+    out = psm.alloc_images_batch(carr, sc.c, device)
+    P = psm.total_pixels(carr)
+    g = torch.Generator(device=device).manual_seed(1)
+    gout = {"rgb": torch.randn(P, 3, device=device, generator=g), "depth": torch.randn(P, device=device, generator=g),
+            "normal": torch.randn(P, 3, device=device, generator=g), "alpha": torch.randn(P, device=device, generator=g),
+            "feat": torch.randn(P, sc.c, device=device, generator=g)}
+    n = sc.n
+    z = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=device)
+    grads = {"means": z(n, 3), "scales": z(n, 2), "quats": z(n, 4), "opacity": z(n), "rgb": z(n, 3),
+             "feat": z(n, sc.c)}
+    s = psm._surfels(*args)
+    ctx = psm.context(0)
+    tune_cfg = psm.config_struct(K, "ellipse", "topk")
+    tuned_ms = psm.autotune(ctx, s, carr, tune_cfg, ws, out, gout, grads, reps=3, cache=False)
+    cfg.schedule, cfg.blend_pass, cfg.bwd_pass = tune_cfg.schedule, tune_cfg.blend_pass, tune_cfg.bwd_pass
+
+    def step(c):
+        psm.forward_batch_into(ctx, s, carr, c, ws, out)
+        psm.backward_batch_into(ctx, s, carr, c, ws, gout, grads)
+
+    for _ in range(warmup):
+        step(cfg)
+    torch.cuda.synchronize()
+    psm.profile_reset(ctx)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(cfg)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / steps
+    prof = psm.profile_read(ctx)
+    stages = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1] > 0}
+    st = psm.read_stats_batch(ws, carr, cfg)
+    if st.pairs_required > st.pair_capacity:
+        raise RuntimeError("pair capacity exceeded in the batched workload")
+    # the same step captured once and replayed
+    gcfg = psm.config_struct(K, "ellipse", "topk", psm.FLAG_NO_SYNC, tune_cfg.schedule, tune_cfg.blend_pass,
+                             tune_cfg.bwd_pass)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step(gcfg)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step(gcfg)
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    gms = (time.perf_counter() - t0) * 1000.0 / steps
+    return {"workload": f"street40 scene, {n} surfels, 128-d f16 features, K={K}, 8 cameras "
+                        + ", ".join(f"{c.width}x{c.height}" for c in cams),
+            "pixels": P, "fwd_bwd_ms": ms, "fwd_bwd_its": 1000.0 / ms, "graph_replay_ms": gms,
+            "graph_replay_its": 1000.0 / gms, "autotuned": {"schedule": ["grid", "persistent"][tune_cfg.schedule],
+                                                           "blend_pass": tune_cfg.blend_pass,
+                                                           "bwd_pass": tune_cfg.bwd_pass, "tuned_ms": tuned_ms},
+            "pairs": int(st.pairs), "stages_ms": stages}
 
 
 def cpu_baseline(sc, cam, K, feat64, tiles):
@@ -274,12 +391,19 @@ def main():
         "pairs": int(st.pairs), "pairs_walked": int(st.pairs_walked), "contributors": int(st.contributors),
         "visible": int(st.visible),
         "stages_ms": stages,
-        "roofline": roofline(stages, st, K, sc.c, S, True),
+        "roofline": roofline(stages, st, K, sc.c, S, True, args.workload),
         "ablation_fwd": ablation,
     }
     if not args.no_cpu_baseline:
         feat64 = t["feat"].float().cpu().numpy().astype(np.float64)
         line["cpu_baseline"] = cpu_baseline(sc, cam, K, feat64, args.cpu_tiles)
+        print(f"[bench] cpu baseline {line['cpu_baseline']['value']:.4f} it/s", file=sys.stderr, flush=True)
+    if not args.no_batch:
+        del t, gout
+        torch.cuda.empty_cache()
+        line["batch_8cam"] = batch_workload(psm, scenes, max(3, args.steps // 2), 2)
+        print(f"[bench] batch 8 cameras fwd+bwd {line['batch_8cam']['fwd_bwd_ms']:.3f} ms, graph "
+              f"{line['batch_8cam']['graph_replay_ms']:.3f} ms", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 

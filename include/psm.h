@@ -84,7 +84,19 @@ typedef struct {
   int32_t tile_mode;  /* psm_tile_mode */
   int32_t blend;      /* psm_blend_mode */
   int32_t flags;      /* PSM_FLAG_* */
+  /* Launch choices (results do not depend on them; psm_autotune picks them).
+   * A backward must use the values of its forward. */
+  int32_t schedule;   /* psm_schedule */
+  int32_t blend_pass; /* feature channels per Top-K blend pass: 0 (= 32), 16 or 32 */
+  int32_t bwd_pass;   /* feature channels per feature-backward pass: 0 (= 16), 8 or 16 */
+  int32_t reserved;   /* must be 0 */
 } psm_config;
+
+/* Tile scheduling of the per-tile kernels.  GRID: one workgroup per 16x16
+ * tile, tiles of neighbouring ids kept on one XCD.  PERSISTENT: a grid that
+ * fills the device once takes tiles from a work queue sorted longest list
+ * first (the forward sorts the tiles by list length). */
+typedef enum { PSM_SCHED_GRID = 0, PSM_SCHED_PERSISTENT = 1 } psm_schedule;
 
 /* Skip the end-of-call status read-back (graph-safe; the caller checks
  * psm_read_stats later). */
@@ -101,13 +113,13 @@ typedef struct { float *means, *scales, *quats, *opacity, *rgb, *feat; } psm_gra
 
 typedef struct {
   int64_t n;              /* surfels */
-  int64_t visible;        /* surfels surviving the cull */
+  int64_t visible;        /* surfels surviving the cull (summed over cameras) */
   int64_t culled[5];      /* by code: 0 unused, 1 zero quaternion, 2 centre behind near,
                              3 disk reaches near plane, 4 degenerate projection */
   int64_t pairs;          /* surfel->tile pairs emitted (the sorted list length) */
   int64_t pairs_required; /* pairs the footprint asked for (> capacity on PSM_ERR_CAPACITY) */
   int64_t pair_capacity;  /* capacity the workspace was laid out for */
-  int64_t tiles;          /* number of 16x16 tiles */
+  int64_t tiles;          /* number of 16x16 tiles (all cameras) */
   int64_t pairs_walked;   /* pixel x list-entry evaluations of the forward walk */
   int64_t contributors;   /* (pixel, surfel) pairs blended by the forward walk */
 } psm_stats;
@@ -189,6 +201,55 @@ psm_status psm_read_selection(psm_ctx* ctx, const void* workspace, int64_t n, co
 psm_status psm_profile_read(psm_ctx* ctx, int32_t stage, const char** name_out, double* total_ms_out,
                             int64_t* calls_out);
 psm_status psm_profile_reset(psm_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Several cameras in one call (one launch per stage for all of them).
+ * Surfel i seen by camera b is the virtual surfel v = b * n + i; every
+ * camera gets its own tiles and images, and the gradients are summed over
+ * the cameras (in camera order, deterministically).  Output and upstream
+ * maps are the cameras' maps concatenated in camera order: camera b's map
+ * starts at pixel sum_{b' < b} width_b' * height_b' (times the map's
+ * channels).  1 <= n_cams <= PSM_MAX_CAMERAS and n * n_cams < 2^31.
+ * Rendering camera b alone gives bit-identical images.  psm_read_pairs_batch
+ * reports global tile ids (camera b's tiles follow those of the cameras
+ * before it) and virtual surfel ids; its per-surfel outputs have n_cams * n
+ * entries.  The single-camera entry points above are the n_cams = 1 case.
+ * ------------------------------------------------------------------------ */
+#define PSM_MAX_CAMERAS 8
+
+psm_status psm_workspace_size_batch(int64_t n, const psm_camera* cams, int32_t n_cams, const psm_config* cfg,
+                                    int32_t c, int64_t pair_capacity, size_t* bytes_out);
+psm_status psm_forward_batch(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cams, int32_t n_cams,
+                             const psm_config* cfg, void* workspace, size_t workspace_bytes,
+                             int64_t pair_capacity, psm_images* out, void* stream);
+psm_status psm_backward_batch(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cams, int32_t n_cams,
+                              const psm_config* cfg, void* workspace, size_t workspace_bytes,
+                              int64_t pair_capacity, const psm_image_grads* grad_out, psm_grads* grads,
+                              void* stream);
+psm_status psm_read_stats_batch(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cams,
+                                int32_t n_cams, const psm_config* cfg, int32_t c, int64_t pair_capacity,
+                                psm_stats* out, void* stream);
+psm_status psm_read_pairs_batch(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cams,
+                                int32_t n_cams, const psm_config* cfg, int32_t c, int64_t pair_capacity,
+                                int32_t* tile_out, int32_t* id_out, int64_t cap, int32_t* cull_out,
+                                uint32_t* depth_bits_out, int32_t* count_out, int64_t* pairs_out, void* stream);
+psm_status psm_read_selection_batch(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cams,
+                                    int32_t n_cams, const psm_config* cfg, int32_t c, int64_t pair_capacity,
+                                    int32_t* sel_id_out, float* sel_w_out, int32_t* n_last_out,
+                                    float* t_final_out, void* stream);
+
+/* Autotuner: times every candidate launch choice (schedule, blend_pass,
+ * bwd_pass) on these inputs -- forward, plus backward when grads is non-NULL
+ * -- `reps` times each after one warm-up, and writes the fastest into *cfg
+ * (and its median time in ms into *best_ms_out when non-NULL).  The choice is
+ * cached in the context per (cameras' sizes, n, c, k, dtype, modes, backward)
+ * and returned without timing on later calls.  Overwrites the outputs, the
+ * gradients and the workspace; synchronises `stream` (not for use under
+ * stream capture).  Returns PSM_ERR_CAPACITY if the pairs do not fit. */
+psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cams, int32_t n_cams,
+                        psm_config* cfg, void* workspace, size_t workspace_bytes, int64_t pair_capacity,
+                        psm_images* out, const psm_image_grads* grad_out, psm_grads* grads, int32_t reps,
+                        double* best_ms_out, void* stream);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* psm_last_error(void);

@@ -2,6 +2,7 @@
 // layout and the ordered enqueue of the kernels on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -70,11 +71,34 @@ struct Profiler {
 
 }  // namespace
 
+struct TuneKey {
+  std::string key;
+  psm::Tuning tu;
+  double ms;
+};
+
 struct psm_ctx {
   int device;
   int cu_count;
   Profiler prof;
+  std::vector<TuneKey> tuned;
 };
+
+namespace psm {
+
+// Persistent grids: as many blocks as fit on the device at once.
+int tile_grid(const Layout& L, const Tuning& tu, const void* kernel, size_t dyn_lds) {
+  if (tu.sched != kSchedPersistent) return xcd_grid(L.tiles);
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, dyn_lds) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  const int64_t g = (int64_t)cus * per_cu;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, L.tiles));
+}
+
+}  // namespace psm
 
 namespace {
 
@@ -114,19 +138,37 @@ psm_status check_hip(const char* where) {
   return PSM_OK;
 }
 
-psm_status validate_common(const psm_camera* cam, const psm_config* cfg, int64_t n, int32_t c,
-                           int64_t pair_capacity) {
-  if (!cam || !cfg) return fail(PSM_ERR_INVALID_ARG, "camera and config are required");
-  if (n < 0 || n > 0x7FFFFFFFLL) return fail(PSM_ERR_INVALID_ARG, "n must be in [0, 2^31)");
+psm_status validate_camera(const psm_camera* cam) {
   if (cam->width < 1 || cam->height < 1 || cam->width > 16384 || cam->height > 16384)
     return fail(PSM_ERR_INVALID_ARG, "image size must be in [1, 16384]");
   if (!(cam->near_plane > 0.0f) || !std::isfinite(cam->near_plane))
     return fail(PSM_ERR_INVALID_ARG, "near_plane must be finite and > 0");
   if (!std::isfinite(cam->fx) || !std::isfinite(cam->fy) || cam->fx == 0.0f || cam->fy == 0.0f)
     return fail(PSM_ERR_INVALID_ARG, "focal lengths must be finite and non-zero");
+  return PSM_OK;
+}
+
+psm_status validate_common(const psm_camera* cams, int32_t n_cams, const psm_config* cfg, int64_t n, int32_t c,
+                           int64_t pair_capacity) {
+  if (!cams || !cfg) return fail(PSM_ERR_INVALID_ARG, "camera and config are required");
+  if (n_cams < 1 || n_cams > kMaxCams) return fail(PSM_ERR_INVALID_ARG, "n_cams must be in [1, 8]");
+  if (n < 0 || n * n_cams > 0x7FFFFFFFLL) return fail(PSM_ERR_INVALID_ARG, "n * n_cams must be in [0, 2^31)");
+  int64_t tiles = 0;
+  for (int b = 0; b < n_cams; ++b) {
+    psm_status r = validate_camera(cams + b);
+    if (r != PSM_OK) return r;
+    tiles += cdiv(cams[b].width, kTile) * cdiv(cams[b].height, kTile);
+  }
+  if (tiles * kTilePix > 0x7FFFFFFFLL) return fail(PSM_ERR_INVALID_ARG, "too many pixels in one call");
   if (cfg->k < 1 || cfg->k > kMaxK) return fail(PSM_ERR_INVALID_ARG, "k must be in [1, 32]");
   if (cfg->tile_mode < 0 || cfg->tile_mode > 2) return fail(PSM_ERR_INVALID_ARG, "bad tile_mode");
   if (cfg->blend < 0 || cfg->blend > 1) return fail(PSM_ERR_INVALID_ARG, "bad blend mode");
+  if (cfg->schedule < 0 || cfg->schedule > 1) return fail(PSM_ERR_INVALID_ARG, "bad schedule");
+  if (cfg->blend_pass != 0 && cfg->blend_pass != 16 && cfg->blend_pass != 32)
+    return fail(PSM_ERR_INVALID_ARG, "blend_pass must be 0, 16 or 32");
+  if (cfg->bwd_pass != 0 && cfg->bwd_pass != 8 && cfg->bwd_pass != 16)
+    return fail(PSM_ERR_INVALID_ARG, "bwd_pass must be 0, 8 or 16");
+  if (cfg->reserved != 0) return fail(PSM_ERR_INVALID_ARG, "reserved must be 0");
   if (c < 0 || c > 1024) return fail(PSM_ERR_INVALID_ARG, "c must be in [0, 1024]");
   if (c % 8 != 0) return fail(PSM_ERR_UNSUPPORTED, "c must be a multiple of 8");
   if (pair_capacity < 0 || pair_capacity > 0x7FFFFFFFLL)
@@ -147,17 +189,41 @@ psm_status validate_surfels(const psm_surfels* s) {
   return PSM_OK;
 }
 
-Layout layout_for(int64_t n, const psm_camera* cam, const psm_config* cfg, int32_t c, int64_t cap) {
-  return make_layout(n, cam->width, cam->height, cfg->k, c, cap);
+CamTable cam_table(const psm_camera* cams, int32_t n_cams, int64_t n) {
+  CamTable t;
+  std::memset(&t, 0, sizeof(t));
+  t.n = n_cams;
+  t.nsurf = n;
+  int tile = 0;
+  int64_t pix = 0;
+  for (int b = 0; b < n_cams; ++b) {
+    const psm_camera* cam = cams + b;
+    CamArgs& a = t.cam[b];
+    std::memcpy(a.R, cam->R, sizeof(a.R));
+    std::memcpy(a.t, cam->t, sizeof(a.t));
+    a.fx = cam->fx; a.fy = cam->fy; a.cx = cam->cx; a.cy = cam->cy; a.near_plane = cam->near_plane;
+    a.W = cam->width; a.H = cam->height;
+    t.ntx[b] = (int)cdiv(cam->width, kTile);
+    t.nty[b] = (int)cdiv(cam->height, kTile);
+    t.tile0[b] = tile;
+    t.pix0[b] = pix;
+    tile += t.ntx[b] * t.nty[b];
+    pix += (int64_t)cam->width * cam->height;
+  }
+  for (int b = n_cams; b <= kMaxCams; ++b) {
+    t.tile0[b] = tile;
+    t.pix0[b] = pix;
+  }
+  for (int b = n_cams; b < kMaxCams; ++b) t.ntx[b] = t.nty[b] = 1;
+  return t;
 }
 
-CamArgs cam_args(const psm_camera* cam) {
-  CamArgs a;
-  std::memcpy(a.R, cam->R, sizeof(a.R));
-  std::memcpy(a.t, cam->t, sizeof(a.t));
-  a.fx = cam->fx; a.fy = cam->fy; a.cx = cam->cx; a.cy = cam->cy; a.near_plane = cam->near_plane;
-  a.W = cam->width; a.H = cam->height;
-  return a;
+Tuning tuning_of(const psm_config* cfg) {
+  Tuning t;
+  t.sched = cfg->schedule;
+  t.blend_pass = cfg->blend_pass == 0 ? 32 : cfg->blend_pass;
+  t.bwd_pass = cfg->bwd_pass == 0 ? 16 : cfg->bwd_pass;
+  return t;
 }
 
 SurfelArgs surfel_args(const psm_surfels* s) {
@@ -185,13 +251,200 @@ psm_status read_status(const Layout& L, const void* ws, uint32_t* st_host, hipSt
   return PSM_OK;
 }
 
+psm_status capacity_error(const Layout& L, const uint32_t* h) {
+  const uint64_t req = (uint64_t)h[kStReqLo] | ((uint64_t)h[kStReqHi] << 32);
+  return fail(PSM_ERR_CAPACITY, "pair capacity " + std::to_string(L.cap) + " < required " + std::to_string(req));
+}
+
+// Enqueues the forward on `st` (no host synchronisation).
+void enqueue_forward(const SurfelArgs& sa, const CamTable& ct, const psm_config* cfg, const Layout& L, char* ws,
+                     const psm_images* out, hipStream_t st, const ProfHook& prof) {
+  const Tuning tu = tuning_of(cfg);
+  int64_t big = std::max<int64_t>(std::max<int64_t>(L.n, L.cap), L.tiles);
+  const int64_t nb_max = cdiv(std::max<int64_t>(big, 1), kSortTile);
+  uint32_t* status = (uint32_t*)(ws + L.status);
+  uint32_t* hist = (uint32_t*)(ws + L.hist);
+  prof.begin(kStageFill, st);
+  launch_init_status(status, L.n, L.tiles, st);
+  launch_fill_u32(ws + L.ranges, 0u, L.tiles * 2, st);
+  prof.end(kStageFill, st);
+  prof.begin(kStagePreprocess, st);
+  launch_preprocess(sa, ct, cfg->tile_mode, L, ws, st);
+  prof.end(kStagePreprocess, st);
+  prof.begin(kStageDepthSort, st);
+  radix_sort_pairs((uint32_t*)(ws + L.key0), (uint32_t*)(ws + L.id0), (uint32_t*)(ws + L.key1),
+                   (uint32_t*)(ws + L.id1), status + kStN, L.n, 32, hist, nb_max, st);
+  prof.end(kStageDepthSort, st);
+  prof.begin(kStageScan, st);
+  launch_scan_counts(L, ws, st);
+  prof.end(kStageScan, st);
+  prof.begin(kStageEmit, st);
+  launch_emit(ct, cfg->tile_mode, L, ws, st);
+  prof.end(kStageEmit, st);
+  prof.begin(kStagePairSort, st);
+  radix_sort_pairs((uint32_t*)(ws + L.ptile0), (uint32_t*)(ws + L.eid0), (uint32_t*)(ws + L.ptile1),
+                   (uint32_t*)(ws + L.eid1), status + kStP, L.cap, bits_for(L.tiles), hist, nb_max, st);
+  prof.end(kStagePairSort, st);
+  prof.begin(kStageRanges, st);
+  launch_ranges(L, ws, st);
+  if (tu.sched == kSchedPersistent) {
+    launch_tile_keys(L, ws, st);
+    radix_sort_pairs((uint32_t*)(ws + L.tkey0), (uint32_t*)(ws + L.torder0), (uint32_t*)(ws + L.tkey1),
+                     (uint32_t*)(ws + L.torder1), status + kStTiles, L.tiles, 32, hist, nb_max, st);
+  }
+  prof.end(kStageRanges, st);
+  ImageArgs ia{out->rgb, out->depth, out->normal, out->alpha, out->feat};
+  prof.begin(kStageWalk, st);
+  launch_walk(L, ct, cfg->blend, tu, ia, ws, st);
+  prof.end(kStageWalk, st);
+  prof.begin(kStageBlend, st);
+  launch_feature_blend(sa, L, ct, cfg->blend, tu, out->feat, ws, st);
+  prof.end(kStageBlend, st);
+}
+
+psm_status forward_impl(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cams, int32_t n_cams,
+                        const psm_config* cfg, void* workspace, size_t workspace_bytes, int64_t pair_capacity,
+                        psm_images* out, void* stream) {
+  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+  if (!out) return fail(PSM_ERR_INVALID_ARG, "out is null");
+  psm_status r = validate_surfels(s);
+  if (r != PSM_OK) return r;
+  r = validate_common(cams, n_cams, cfg, s->n, s->c, pair_capacity);
+  if (r != PSM_OK) return r;
+  const CamTable ct = cam_table(cams, n_cams, s->n);
+  const Layout L = make_layout(ct, cfg->k, s->c, pair_capacity);
+  r = check_workspace(L, workspace, workspace_bytes);
+  if (r != PSM_OK) return r;
+  if (s->c > 0 && !out->feat) return fail(PSM_ERR_INVALID_ARG, "out->feat is required when c > 0");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
+  hipStream_t st = (hipStream_t)stream;
+  enqueue_forward(surfel_args(s), ct, cfg, L, (char*)workspace, out, st, hook_for(ctx, cfg));
+  r = check_hip("psm_forward launch");
+  if (r != PSM_OK) return r;
+  if (!(cfg->flags & PSM_FLAG_NO_SYNC)) {
+    uint32_t h[kStWords];
+    r = read_status(L, workspace, h, st);
+    if (r != PSM_OK) return r;
+    if (h[kStOverflow]) return capacity_error(L, h);
+  }
+  g_err.clear();
+  return PSM_OK;
+}
+
+psm_status backward_impl(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cams, int32_t n_cams,
+                         const psm_config* cfg, void* workspace, size_t workspace_bytes, int64_t pair_capacity,
+                         const psm_image_grads* grad_out, psm_grads* grads, void* stream) {
+  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+  if (!grad_out || !grads) return fail(PSM_ERR_INVALID_ARG, "grad_out and grads are required");
+  psm_status r = validate_surfels(s);
+  if (r != PSM_OK) return r;
+  r = validate_common(cams, n_cams, cfg, s->n, s->c, pair_capacity);
+  if (r != PSM_OK) return r;
+  if (s->n > 0 && (!grads->means || !grads->scales || !grads->quats || !grads->opacity || !grads->rgb ||
+                   (s->c > 0 && !grads->feat)))
+    return fail(PSM_ERR_INVALID_ARG, "every gradient array is required");
+  const CamTable ct = cam_table(cams, n_cams, s->n);
+  const Layout L = make_layout(ct, cfg->k, s->c, pair_capacity);
+  r = check_workspace(L, workspace, workspace_bytes);
+  if (r != PSM_OK) return r;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
+  hipStream_t st = (hipStream_t)stream;
+  ImageGradArgs g{grad_out->rgb, grad_out->depth, grad_out->normal, grad_out->alpha, grad_out->feat};
+  GradArgs ga{grads->means, grads->scales, grads->quats, grads->opacity, grads->rgb, grads->feat};
+  launch_backward(surfel_args(s), ct, cfg->blend, tuning_of(cfg), L, g, ga, (char*)workspace, st,
+                  hook_for(ctx, cfg));
+  r = check_hip("psm_backward launch");
+  if (r != PSM_OK) return r;
+  g_err.clear();
+  return PSM_OK;
+}
+
+psm_status read_stats_impl(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cams, int32_t n_cams,
+                           const psm_config* cfg, int32_t c, int64_t pair_capacity, psm_stats* out, void* stream) {
+  if (!ctx || !out) return fail(PSM_ERR_INVALID_ARG, "ctx and out are required");
+  psm_status r = validate_common(cams, n_cams, cfg, n, c, pair_capacity);
+  if (r != PSM_OK) return r;
+  const Layout L = make_layout(cam_table(cams, n_cams, n), cfg->k, c, pair_capacity);
+  if (!workspace) return fail(PSM_ERR_INVALID_ARG, "workspace is required");
+  DeviceGuard dg(ctx->device);
+  uint32_t h[kStWords];
+  r = read_status(L, workspace, h, (hipStream_t)stream);
+  if (r != PSM_OK) return r;
+  std::memset(out, 0, sizeof(*out));
+  out->n = n;
+  out->visible = h[kStVisible];
+  for (int i = 0; i < 5; ++i) out->culled[i] = i == 0 ? 0 : h[kStCull + i];
+  out->pairs = h[kStP];
+  out->pairs_required = (int64_t)((uint64_t)h[kStReqLo] | ((uint64_t)h[kStReqHi] << 32));
+  out->pair_capacity = pair_capacity;
+  out->tiles = L.tiles;
+  out->pairs_walked = (int64_t)((uint64_t)h[kStWalked] | ((uint64_t)h[kStWalked + 1] << 32));
+  out->contributors = (int64_t)((uint64_t)h[kStBlended] | ((uint64_t)h[kStBlended + 1] << 32));
+  return PSM_OK;
+}
+
+psm_status read_pairs_impl(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cams, int32_t n_cams,
+                           const psm_config* cfg, int32_t c, int64_t pair_capacity, int32_t* tile_out,
+                           int32_t* id_out, int64_t cap, int32_t* cull_out, uint32_t* depth_bits_out,
+                           int32_t* count_out, int64_t* pairs_out, void* stream) {
+  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+  psm_status r = validate_common(cams, n_cams, cfg, n, c, pair_capacity);
+  if (r != PSM_OK) return r;
+  if (!workspace) return fail(PSM_ERR_INVALID_ARG, "workspace is required");
+  const Layout L = make_layout(cam_table(cams, n_cams, n), cfg->k, c, pair_capacity);
+  DeviceGuard dg(ctx->device);
+  hipStream_t st = (hipStream_t)stream;
+  const char* ws = (const char*)workspace;
+  uint32_t h[kStWords];
+  r = read_status(L, workspace, h, st);
+  if (r != PSM_OK) return r;
+  const int64_t P = h[kStP];
+  if (pairs_out) *pairs_out = P;
+  const int64_t m = std::min<int64_t>(P, cap);
+  if (m > 0 && tile_out) (void)hipMemcpyAsync(tile_out, ws + L.ptile0, m * 4, hipMemcpyDeviceToDevice, st);
+  if (m > 0 && id_out) (void)hipMemcpyAsync(id_out, ws + L.pid, m * 4, hipMemcpyDeviceToDevice, st);
+  launch_export_keys(L, (char*)workspace, cull_out, depth_bits_out, count_out, st);
+  r = check_hip("psm_read_pairs");
+  if (r != PSM_OK) return r;
+  if (hipStreamSynchronize(st) != hipSuccess) return fail(PSM_ERR_HIP, "psm_read_pairs sync");
+  return PSM_OK;
+}
+
+psm_status read_selection_impl(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cams,
+                               int32_t n_cams, const psm_config* cfg, int32_t c, int64_t pair_capacity,
+                               int32_t* sel_id_out, float* sel_w_out, int32_t* n_last_out, float* t_final_out,
+                               void* stream) {
+  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+  psm_status r = validate_common(cams, n_cams, cfg, n, c, pair_capacity);
+  if (r != PSM_OK) return r;
+  if (!workspace) return fail(PSM_ERR_INVALID_ARG, "workspace is required");
+  const CamTable ct = cam_table(cams, n_cams, n);
+  const Layout L = make_layout(ct, cfg->k, c, pair_capacity);
+  DeviceGuard dg(ctx->device);
+  launch_export_selection(L, ct, (char*)workspace, cfg->blend == PSM_BLEND_TOPK ? sel_id_out : nullptr,
+                          cfg->blend == PSM_BLEND_TOPK ? sel_w_out : nullptr, n_last_out, t_final_out,
+                          (hipStream_t)stream);
+  return check_hip("psm_read_selection");
+}
+
+std::string tune_key(const psm_surfels* s, const psm_camera* cams, int32_t n_cams, const psm_config* cfg,
+                     bool bwd) {
+  std::string k = std::to_string(s->n) + "|" + std::to_string(s->c) + "|" + std::to_string(s->feat_dtype) + "|" +
+                  std::to_string(cfg->k) + "|" + std::to_string(cfg->tile_mode) + "|" + std::to_string(cfg->blend) +
+                  "|" + (bwd ? "b" : "f");
+  for (int b = 0; b < n_cams; ++b) k += "|" + std::to_string(cams[b].width) + "x" + std::to_string(cams[b].height);
+  return k;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* psm_last_error(void) { return g_err.c_str(); }
 
-const char* psm_version(void) { return "psm 0.1 (gfx950)"; }
+const char* psm_version(void) { return "psm 0.2 (gfx950)"; }
 
 psm_status psm_create(psm_ctx** ctx_out, int device) {
   if (!ctx_out) return fail(PSM_ERR_INVALID_ARG, "ctx_out is null");
@@ -211,134 +464,169 @@ psm_status psm_create(psm_ctx** ctx_out, int device) {
 
 void psm_destroy(psm_ctx* ctx) { delete ctx; }
 
+psm_status psm_workspace_size_batch(int64_t n, const psm_camera* cams, int32_t n_cams, const psm_config* cfg,
+                                    int32_t c, int64_t pair_capacity, size_t* bytes_out) {
+  if (!bytes_out) return fail(PSM_ERR_INVALID_ARG, "bytes_out is null");
+  psm_status s = validate_common(cams, n_cams, cfg, n, c, pair_capacity);
+  if (s != PSM_OK) return s;
+  *bytes_out = make_layout(cam_table(cams, n_cams, n), cfg->k, c, pair_capacity).total;
+  return PSM_OK;
+}
+
 psm_status psm_workspace_size(int64_t n, const psm_camera* cam, const psm_config* cfg, int32_t c,
                               int64_t pair_capacity, size_t* bytes_out) {
-  if (!bytes_out) return fail(PSM_ERR_INVALID_ARG, "bytes_out is null");
-  psm_status s = validate_common(cam, cfg, n, c, pair_capacity);
-  if (s != PSM_OK) return s;
-  *bytes_out = layout_for(n, cam, cfg, c, pair_capacity).total;
-  return PSM_OK;
+  return psm_workspace_size_batch(n, cam, 1, cfg, c, pair_capacity, bytes_out);
+}
+
+psm_status psm_forward_batch(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cams, int32_t n_cams,
+                             const psm_config* cfg, void* workspace, size_t workspace_bytes, int64_t pair_capacity,
+                             psm_images* out, void* stream) {
+  return forward_impl(ctx, s, cams, n_cams, cfg, workspace, workspace_bytes, pair_capacity, out, stream);
 }
 
 psm_status psm_forward(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cam, const psm_config* cfg,
                        void* workspace, size_t workspace_bytes, int64_t pair_capacity, psm_images* out,
                        void* stream) {
-  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
-  if (!out) return fail(PSM_ERR_INVALID_ARG, "out is null");
-  psm_status r = validate_surfels(s);
-  if (r != PSM_OK) return r;
-  r = validate_common(cam, cfg, s->n, s->c, pair_capacity);
-  if (r != PSM_OK) return r;
-  const Layout L = layout_for(s->n, cam, cfg, s->c, pair_capacity);
-  r = check_workspace(L, workspace, workspace_bytes);
-  if (r != PSM_OK) return r;
-  if (s->c > 0 && !out->feat) return fail(PSM_ERR_INVALID_ARG, "out->feat is required when c > 0");
-  DeviceGuard dg(ctx->device);
-  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
-  hipStream_t st = (hipStream_t)stream;
-  char* ws = (char*)workspace;
-  const CamArgs ca = cam_args(cam);
-  const SurfelArgs sa = surfel_args(s);
-  const int64_t nb_max = cdiv(std::max<int64_t>(std::max<int64_t>(L.n, L.cap), 1), kSortTile);
-  uint32_t* status = (uint32_t*)(ws + L.status);
-  uint32_t* hist = (uint32_t*)(ws + L.hist);
+  return forward_impl(ctx, s, cam, 1, cfg, workspace, workspace_bytes, pair_capacity, out, stream);
+}
 
-  const ProfHook prof = hook_for(ctx, cfg);
-
-  prof.begin(kStageFill, st);
-  launch_init_status(status, s->n, st);
-  launch_fill_u32(ws + L.ranges, 0u, L.tiles * 2, st);
-  prof.end(kStageFill, st);
-  prof.begin(kStagePreprocess, st);
-  launch_preprocess(sa, ca, cfg->tile_mode, L, ws, st);
-  prof.end(kStagePreprocess, st);
-  prof.begin(kStageDepthSort, st);
-  radix_sort_pairs((uint32_t*)(ws + L.key0), (uint32_t*)(ws + L.id0), (uint32_t*)(ws + L.key1),
-                   (uint32_t*)(ws + L.id1), status + kStN, L.n, 32, hist, nb_max, st);
-  prof.end(kStageDepthSort, st);
-  prof.begin(kStageScan, st);
-  launch_scan_counts(L, ws, st);
-  prof.end(kStageScan, st);
-  prof.begin(kStageEmit, st);
-  launch_emit(ca, cfg->tile_mode, L, ws, st);
-  prof.end(kStageEmit, st);
-  prof.begin(kStagePairSort, st);
-  radix_sort_pairs((uint32_t*)(ws + L.ptile0), (uint32_t*)(ws + L.eid0), (uint32_t*)(ws + L.ptile1),
-                   (uint32_t*)(ws + L.eid1), status + kStP, L.cap, bits_for(L.tiles), hist, nb_max, st);
-  prof.end(kStagePairSort, st);
-  prof.begin(kStageRanges, st);
-  launch_ranges(L, ws, st);
-  prof.end(kStageRanges, st);
-  ImageArgs ia{out->rgb, out->depth, out->normal, out->alpha, out->feat};
-  prof.begin(kStageWalk, st);
-  launch_walk(L, ca, cfg->blend, ia, ws, st);
-  prof.end(kStageWalk, st);
-  prof.begin(kStageBlend, st);
-  launch_feature_blend(sa, L, ca, cfg->blend, out->feat, ws, st);
-  prof.end(kStageBlend, st);
-  r = check_hip("psm_forward launch");
-  if (r != PSM_OK) return r;
-  if (!(cfg->flags & PSM_FLAG_NO_SYNC)) {
-    uint32_t h[kStWords];
-    r = read_status(L, ws, h, st);
-    if (r != PSM_OK) return r;
-    if (h[kStOverflow]) {
-      const uint64_t req = (uint64_t)h[kStReqLo] | ((uint64_t)h[kStReqHi] << 32);
-      return fail(PSM_ERR_CAPACITY, "pair capacity " + std::to_string(L.cap) + " < required " + std::to_string(req));
-    }
-  }
-  g_err.clear();
-  return PSM_OK;
+psm_status psm_backward_batch(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cams, int32_t n_cams,
+                              const psm_config* cfg, void* workspace, size_t workspace_bytes, int64_t pair_capacity,
+                              const psm_image_grads* grad_out, psm_grads* grads, void* stream) {
+  return backward_impl(ctx, s, cams, n_cams, cfg, workspace, workspace_bytes, pair_capacity, grad_out, grads,
+                       stream);
 }
 
 psm_status psm_backward(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cam, const psm_config* cfg,
                         void* workspace, size_t workspace_bytes, int64_t pair_capacity,
                         const psm_image_grads* grad_out, psm_grads* grads, void* stream) {
-  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
-  if (!grad_out || !grads) return fail(PSM_ERR_INVALID_ARG, "grad_out and grads are required");
-  psm_status r = validate_surfels(s);
-  if (r != PSM_OK) return r;
-  r = validate_common(cam, cfg, s->n, s->c, pair_capacity);
-  if (r != PSM_OK) return r;
-  if (s->n > 0 && (!grads->means || !grads->scales || !grads->quats || !grads->opacity || !grads->rgb ||
-                   (s->c > 0 && !grads->feat)))
-    return fail(PSM_ERR_INVALID_ARG, "every gradient array is required");
-  const Layout L = layout_for(s->n, cam, cfg, s->c, pair_capacity);
-  r = check_workspace(L, workspace, workspace_bytes);
-  if (r != PSM_OK) return r;
-  DeviceGuard dg(ctx->device);
-  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
-  hipStream_t st = (hipStream_t)stream;
-  ImageGradArgs g{grad_out->rgb, grad_out->depth, grad_out->normal, grad_out->alpha, grad_out->feat};
-  GradArgs ga{grads->means, grads->scales, grads->quats, grads->opacity, grads->rgb, grads->feat};
-  launch_backward(surfel_args(s), cam_args(cam), cfg->blend, L, g, ga, (char*)workspace, st, hook_for(ctx, cfg));
-  r = check_hip("psm_backward launch");
-  if (r != PSM_OK) return r;
-  g_err.clear();
-  return PSM_OK;
+  return backward_impl(ctx, s, cam, 1, cfg, workspace, workspace_bytes, pair_capacity, grad_out, grads, stream);
+}
+
+psm_status psm_read_stats_batch(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cams,
+                                int32_t n_cams, const psm_config* cfg, int32_t c, int64_t pair_capacity,
+                                psm_stats* out, void* stream) {
+  return read_stats_impl(ctx, workspace, n, cams, n_cams, cfg, c, pair_capacity, out, stream);
 }
 
 psm_status psm_read_stats(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cam,
                           const psm_config* cfg, int32_t c, int64_t pair_capacity, psm_stats* out, void* stream) {
-  if (!ctx || !out) return fail(PSM_ERR_INVALID_ARG, "ctx and out are required");
-  psm_status r = validate_common(cam, cfg, n, c, pair_capacity);
+  return read_stats_impl(ctx, workspace, n, cam, 1, cfg, c, pair_capacity, out, stream);
+}
+
+psm_status psm_read_pairs_batch(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cams,
+                                int32_t n_cams, const psm_config* cfg, int32_t c, int64_t pair_capacity,
+                                int32_t* tile_out, int32_t* id_out, int64_t cap, int32_t* cull_out,
+                                uint32_t* depth_bits_out, int32_t* count_out, int64_t* pairs_out, void* stream) {
+  return read_pairs_impl(ctx, workspace, n, cams, n_cams, cfg, c, pair_capacity, tile_out, id_out, cap, cull_out,
+                         depth_bits_out, count_out, pairs_out, stream);
+}
+
+psm_status psm_read_pairs(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cam,
+                          const psm_config* cfg, int32_t c, int64_t pair_capacity, int32_t* tile_out,
+                          int32_t* id_out, int64_t cap, int32_t* cull_out, uint32_t* depth_bits_out,
+                          int32_t* count_out, int64_t* pairs_out, void* stream) {
+  return read_pairs_impl(ctx, workspace, n, cam, 1, cfg, c, pair_capacity, tile_out, id_out, cap, cull_out,
+                         depth_bits_out, count_out, pairs_out, stream);
+}
+
+psm_status psm_read_selection_batch(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cams,
+                                    int32_t n_cams, const psm_config* cfg, int32_t c, int64_t pair_capacity,
+                                    int32_t* sel_id_out, float* sel_w_out, int32_t* n_last_out, float* t_final_out,
+                                    void* stream) {
+  return read_selection_impl(ctx, workspace, n, cams, n_cams, cfg, c, pair_capacity, sel_id_out, sel_w_out,
+                             n_last_out, t_final_out, stream);
+}
+
+psm_status psm_read_selection(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cam,
+                              const psm_config* cfg, int32_t c, int64_t pair_capacity, int32_t* sel_id_out,
+                              float* sel_w_out, int32_t* n_last_out, float* t_final_out, void* stream) {
+  return read_selection_impl(ctx, workspace, n, cam, 1, cfg, c, pair_capacity, sel_id_out, sel_w_out, n_last_out,
+                             t_final_out, stream);
+}
+
+psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cams, int32_t n_cams,
+                        psm_config* cfg, void* workspace, size_t workspace_bytes, int64_t pair_capacity,
+                        psm_images* out, const psm_image_grads* grad_out, psm_grads* grads, int32_t reps,
+                        double* best_ms_out, void* stream) {
+  if (!ctx || !cfg || !out) return fail(PSM_ERR_INVALID_ARG, "ctx, cfg and out are required");
+  if (reps < 1 || reps > 1000) return fail(PSM_ERR_INVALID_ARG, "reps must be in [1, 1000]");
+  psm_status r = validate_surfels(s);
   if (r != PSM_OK) return r;
-  const Layout L = layout_for(n, cam, cfg, c, pair_capacity);
-  if (!workspace) return fail(PSM_ERR_INVALID_ARG, "workspace is required");
+  r = validate_common(cams, n_cams, cfg, s->n, s->c, pair_capacity);
+  if (r != PSM_OK) return r;
+  const bool bwd = grads != nullptr;
+  if (bwd && !grad_out) return fail(PSM_ERR_INVALID_ARG, "grad_out is required with grads");
+  const std::string key = tune_key(s, cams, n_cams, cfg, bwd);
+  for (const TuneKey& t : ctx->tuned) {
+    if (t.key == key) {
+      cfg->schedule = t.tu.sched;
+      cfg->blend_pass = t.tu.blend_pass;
+      cfg->bwd_pass = t.tu.bwd_pass;
+      if (best_ms_out) *best_ms_out = t.ms;
+      return PSM_OK;
+    }
+  }
   DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<Tuning> cands;
+  const bool feat = s->c > 0 && cfg->blend == PSM_BLEND_TOPK;
+  for (int sched = 0; sched < 2; ++sched)
+    for (int bp : {16, 32})
+      for (int gp : {8, 16}) {
+        if (!feat && (bp != 32 || gp != 16)) continue;
+        if (feat && !bwd && gp != 16) continue;
+        cands.push_back(Tuning{sched, bp, gp});
+      }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(PSM_ERR_HIP, "hipEventCreate failed");
+  Tuning best{};
+  double best_ms = 1e300;
+  psm_status res = PSM_OK;
+  for (const Tuning& tu : cands) {
+    psm_config c2 = *cfg;
+    c2.schedule = tu.sched;
+    c2.blend_pass = tu.blend_pass;
+    c2.bwd_pass = tu.bwd_pass;
+    c2.flags = (cfg->flags | PSM_FLAG_NO_SYNC) & ~PSM_FLAG_PROFILE;
+    std::vector<double> ts;
+    for (int it = 0; it <= reps && res == PSM_OK; ++it) {
+      (void)hipEventRecord(e0, st);
+      res = forward_impl(ctx, s, cams, n_cams, &c2, workspace, workspace_bytes, pair_capacity, out, stream);
+      if (res == PSM_OK && bwd)
+        res = backward_impl(ctx, s, cams, n_cams, &c2, workspace, workspace_bytes, pair_capacity, grad_out, grads,
+                            stream);
+      (void)hipEventRecord(e1, st);
+      float ms = 0.0f;
+      if (res == PSM_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        res = fail(PSM_ERR_HIP, "autotune timing failed");
+      if (it > 0) ts.push_back(ms);
+    }
+    if (res != PSM_OK) break;
+    std::sort(ts.begin(), ts.end());
+    const double med = ts[ts.size() / 2];
+    if (med < best_ms) {
+      best_ms = med;
+      best = tu;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (res != PSM_OK) return res;
+  const CamTable ct = cam_table(cams, n_cams, s->n);
+  const Layout L = make_layout(ct, cfg->k, s->c, pair_capacity);
   uint32_t h[kStWords];
-  r = read_status(L, workspace, h, (hipStream_t)stream);
+  r = read_status(L, workspace, h, st);
   if (r != PSM_OK) return r;
-  std::memset(out, 0, sizeof(*out));
-  out->n = n;
-  out->visible = h[kStVisible];
-  for (int i = 0; i < 5; ++i) out->culled[i] = i == 0 ? 0 : h[kStCull + i];
-  out->pairs = h[kStP];
-  out->pairs_required = (int64_t)((uint64_t)h[kStReqLo] | ((uint64_t)h[kStReqHi] << 32));
-  out->pair_capacity = pair_capacity;
-  out->tiles = L.tiles;
-  out->pairs_walked = (int64_t)((uint64_t)h[kStWalked] | ((uint64_t)h[kStWalked + 1] << 32));
-  out->contributors = (int64_t)((uint64_t)h[kStBlended] | ((uint64_t)h[kStBlended + 1] << 32));
+  if (h[kStOverflow]) return capacity_error(L, h);
+  ctx->tuned.push_back(TuneKey{key, best, best_ms});
+  cfg->schedule = best.sched;
+  cfg->blend_pass = best.blend_pass;
+  cfg->bwd_pass = best.bwd_pass;
+  if (best_ms_out) *best_ms_out = best_ms;
+  g_err.clear();
   return PSM_OK;
 }
 
@@ -363,48 +651,6 @@ psm_status psm_profile_reset(psm_ctx* ctx) {
     ctx->prof.calls[s] = 0;
   }
   return ok ? PSM_OK : fail(PSM_ERR_HIP, "profile events could not be read");
-}
-
-psm_status psm_read_pairs(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cam,
-                          const psm_config* cfg, int32_t c, int64_t pair_capacity, int32_t* tile_out,
-                          int32_t* id_out, int64_t cap, int32_t* cull_out, uint32_t* depth_bits_out,
-                          int32_t* count_out, int64_t* pairs_out, void* stream) {
-  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
-  psm_status r = validate_common(cam, cfg, n, c, pair_capacity);
-  if (r != PSM_OK) return r;
-  if (!workspace) return fail(PSM_ERR_INVALID_ARG, "workspace is required");
-  const Layout L = layout_for(n, cam, cfg, c, pair_capacity);
-  DeviceGuard dg(ctx->device);
-  hipStream_t st = (hipStream_t)stream;
-  const char* ws = (const char*)workspace;
-  uint32_t h[kStWords];
-  r = read_status(L, workspace, h, st);
-  if (r != PSM_OK) return r;
-  const int64_t P = h[kStP];
-  if (pairs_out) *pairs_out = P;
-  const int64_t m = std::min<int64_t>(P, cap);
-  if (m > 0 && tile_out) (void)hipMemcpyAsync(tile_out, ws + L.ptile0, m * 4, hipMemcpyDeviceToDevice, st);
-  if (m > 0 && id_out) (void)hipMemcpyAsync(id_out, ws + L.pid, m * 4, hipMemcpyDeviceToDevice, st);
-  launch_export_keys(L, (char*)workspace, cull_out, depth_bits_out, count_out, st);
-  r = check_hip("psm_read_pairs");
-  if (r != PSM_OK) return r;
-  if (hipStreamSynchronize(st) != hipSuccess) return fail(PSM_ERR_HIP, "psm_read_pairs sync");
-  return PSM_OK;
-}
-
-psm_status psm_read_selection(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cam,
-                              const psm_config* cfg, int32_t c, int64_t pair_capacity, int32_t* sel_id_out,
-                              float* sel_w_out, int32_t* n_last_out, float* t_final_out, void* stream) {
-  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
-  psm_status r = validate_common(cam, cfg, n, c, pair_capacity);
-  if (r != PSM_OK) return r;
-  if (!workspace) return fail(PSM_ERR_INVALID_ARG, "workspace is required");
-  const Layout L = layout_for(n, cam, cfg, c, pair_capacity);
-  DeviceGuard dg(ctx->device);
-  launch_export_selection(L, cam_args(cam), (char*)workspace, cfg->blend == PSM_BLEND_TOPK ? sel_id_out : nullptr,
-                          cfg->blend == PSM_BLEND_TOPK ? sel_w_out : nullptr, n_last_out, t_final_out,
-                          (hipStream_t)stream);
-  return check_hip("psm_read_selection");
 }
 
 }  // extern "C"

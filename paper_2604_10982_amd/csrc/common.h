@@ -33,16 +33,18 @@ enum : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
 enum : int {
   kStP = 0,        // pairs emitted (min(required, capacity))
   kStOverflow = 1, // 1 if required > capacity
-  kStN = 2,        // number of surfels
+  kStN = 2,        // number of virtual surfels
   kStVisible = 3,
   kStCull = 4,     // 4 .. 8: cull codes 0..4
+  kStTiles = 9,    // number of tiles (length of the tile work order)
   kStReqLo = 10,   // required pairs, 64-bit
   kStReqHi = 11,
   kStWalked = 12,  // 64-bit: pixel x list-entry evaluations of the forward walk
   kStBlended = 14, // 64-bit: blended (pixel, surfel) pairs
-  kStWords = 16
+  kStQueue = 16,   // 16 .. 19: work-queue heads of the persistent tile kernels
+  kStWords = 20
 };
-
+enum : int { kQWalk = 0, kQBlend = 1, kQFeatBwd = 2, kQWalkBwd = 3 };
 // Radix sort tiling.
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
@@ -55,43 +57,102 @@ constexpr int kScanTile = kScanThreads * kScanItems;
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// ---------------------------------------------------------- workspace layout
-struct Layout {
-  int64_t n, cap, ntx, nty, tiles, spix;  // spix = tiles * 256 (tile-major pixels)
-  int k, c;
-  size_t rec, fp, key0, key1, id0, id1, count, offs, cull, ptile0, ptile1, eid0, eid1, sid_emit, pid, ranges,
-      nlast, tfinal, selpos, selw, seldot, gflag, fflag, gpart, fpart, hist, bsum, status, total;
+// ----------------------------------------------------------------- cameras
+constexpr int kMaxCams = 8;
+
+struct CamArgs {
+  float R[9], t[3], fx, fy, cx, cy, near_plane;
+  int W, H;
 };
 
-inline Layout make_layout(int64_t n, int width, int height, int k, int c, int64_t cap) {
+// The cameras of one call, passed to kernels by value.  Surfel i seen by
+// camera b is the virtual surfel v = b * N + i; camera b's tiles are the
+// global tiles [tile0[b], tile0[b + 1]) and its images start at pixel
+// pix0[b] of the concatenated output maps.
+struct CamTable {
+  int n;
+  int64_t nsurf;
+  CamArgs cam[kMaxCams];
+  int ntx[kMaxCams], nty[kMaxCams];
+  int tile0[kMaxCams + 1];
+  int64_t pix0[kMaxCams + 1];
+};
+
+// Where global tile g lies: its camera, tile coordinates and image.
+struct TileLoc {
+  int b, tx, ty, W, H;
+  int64_t pix0;  // first pixel of the camera's images
+  int64_t v0;    // first virtual surfel of the camera
+};
+
+// Camera of virtual surfel v (no 64-bit division).
+__host__ __device__ inline int camera_of(const CamTable& ct, int64_t v) {
+  int b = 0;
+#pragma unroll
+  for (int k = 1; k < kMaxCams; ++k) b += (k < ct.n && v >= (int64_t)k * ct.nsurf) ? 1 : 0;
+  return b;
+}
+
+__host__ __device__ inline TileLoc locate(const CamTable& ct, int g) {
+  int b = 0;
+#pragma unroll
+  for (int k = 1; k < kMaxCams; ++k) b += (k < ct.n && g >= ct.tile0[k]) ? 1 : 0;
+  const int lt = g - ct.tile0[b];
+  TileLoc t;
+  t.b = b;
+  t.tx = lt % ct.ntx[b];
+  t.ty = lt / ct.ntx[b];
+  t.W = ct.cam[b].W;
+  t.H = ct.cam[b].H;
+  t.pix0 = ct.pix0[b];
+  t.v0 = (int64_t)b * ct.nsurf;
+  return t;
+}
+
+// ---------------------------------------------------------- workspace layout
+struct Layout {
+  int64_t n, nreal, cap, tiles, spix;  // n = virtual surfels; spix = tiles * 256 (tile-major pixels)
+  int k, c, ncam;
+  size_t rec, fp, ext, key0, key1, id0, id1, vbase, count, offs, cull, ptile0, ptile1, eid0, eid1, sid_emit, pid, ranges,
+      tkey0, tkey1, torder0, torder1, nlast, tfinal, selpos, selw, seldot, gflag, fflag, gpart, fpart, hist, bsum,
+      status, total;
+};
+
+inline Layout make_layout(const CamTable& ct, int k, int c, int64_t cap) {
   Layout L{};
-  L.n = n;
+  L.nreal = ct.nsurf;
+  L.ncam = ct.n;
+  L.n = ct.nsurf * ct.n;
   L.cap = cap;
   L.k = k;
   L.c = c;
-  L.ntx = cdiv(width, kTile);
-  L.nty = cdiv(height, kTile);
-  L.tiles = L.ntx * L.nty;
+  L.tiles = ct.tile0[ct.n];
   L.spix = L.tiles * kTilePix;
-  const int64_t n1 = n > 0 ? n : 1, cap1 = cap > 0 ? cap : 1;
+  const int64_t n1 = L.n > 0 ? L.n : 1, cap1 = cap > 0 ? cap : 1, t1 = L.tiles > 0 ? L.tiles : 1;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
   L.rec = take(n1 * 16 * kRecWords);  // walk record
   L.fp = take(n1 * 48);           // footprint floats, 12
+  L.ext = take(n1 * 16);          // ellipse centre and half-extents (x, y), for band culling
   L.key0 = take(n1 * 4);          // depth keys (sort ping-pong)
   L.key1 = take(n1 * 4);
-  L.id0 = take(n1 * 4);           // surfel ids (sort ping-pong)
+  L.id0 = take(n1 * 4);           // virtual surfel ids (sort ping-pong)
   L.id1 = take(n1 * 4);
-  L.count = take(n1 * 4);         // pairs per surfel
+  L.vbase = take(n1 * 4);         // first emitted pair of each virtual surfel
+  L.count = take(n1 * 4);         // pairs per virtual surfel
   L.offs = take((n1 + 1) * 4);    // exclusive scan of counts in depth order
   L.cull = take(n1 * 4);
   L.ptile0 = take(cap1 * 4);      // pair tile ids (sort keys, ping-pong)
   L.ptile1 = take(cap1 * 4);
   L.eid0 = take(cap1 * 4);        // pair emission index (sort values, ping-pong)
   L.eid1 = take(cap1 * 4);
-  L.sid_emit = take(cap1 * 4);    // surfel id of each emitted pair
-  L.pid = take(cap1 * 4);         // surfel id of each sorted pair
-  L.ranges = take(L.tiles * 8);   // [start, end) per tile
+  L.sid_emit = take(cap1 * 4);    // virtual surfel id of each emitted pair
+  L.pid = take(cap1 * 4);         // virtual surfel id of each sorted pair
+  L.ranges = take(t1 * 8);        // [start, end) per tile
+  L.tkey0 = take(t1 * 4);         // tile work order (longest list first), sort ping-pong
+  L.tkey1 = take(t1 * 4);
+  L.torder0 = take(t1 * 4);
+  L.torder1 = take(t1 * 4);
   L.nlast = take(L.spix * 4);
   L.tfinal = take(L.spix * 4);
   L.selpos = take(L.spix * (size_t)k * 4);
@@ -102,7 +163,9 @@ inline Layout make_layout(int64_t n, int width, int height, int k, int c, int64_
   L.fflag = take(cap1);
   L.gpart = take(cap1 * 64);      // 16 floats: geometric and colour terms
   L.fpart = take(cap1 * (size_t)(c > 0 ? c : 1) * 4);  // feature gradient rows
-  const int64_t nb = cdiv(n1 > cap1 ? n1 : cap1, kSortTile);
+  int64_t big = n1 > cap1 ? n1 : cap1;
+  big = big > t1 ? big : t1;
+  const int64_t nb = cdiv(big, kSortTile);
   L.hist = take((256 * nb + 256) * 4);
   L.bsum = take((cdiv(n1, kScanTile) + 1) * 8);
   L.status = take(kStWords * 4);
@@ -197,6 +260,17 @@ __device__ __forceinline__ bool eval_pixel(const LRec& s, float lx, float ly, Pi
   return e.alpha >= kAlphaMin;
 }
 
+// Band culling of the walks: a wave owns 4 rows of its tile and skips a
+// surfel whose footprint ellipse's y-extent (centre ecy, half-extent ey, the
+// key stage's FP32 values) misses the rows' pixel centres.  The footprint
+// contains every pixel the per-pixel test can hit; the slack covers the FP32
+// rounding of the band edges (ulp(16384) = 2^-9 px).
+constexpr float kBandSlack = 0.015625f;
+
+__device__ __forceinline__ bool band_meets(float ecy, float ey, float yb0, float yb1) {
+  return (ecy + ey) + kBandSlack >= yb0 && (ecy - ey) - kBandSlack <= yb1;
+}
+
 // Tile index of a block: consecutive block ids are dispatched round-robin
 // over the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring
 // tiles share surfels, and each XCD has its own L2).
@@ -205,6 +279,34 @@ __device__ inline int xcd_tile(int bid, int tiles) {
   return (bid & 7) * per + (bid >> 3);
 }
 inline int xcd_grid(int64_t tiles) { return (int)(((tiles + 7) >> 3) << 3); }
+
+// Tile scheduling of the per-tile kernels.  Grid mode (order == null): one
+// block per tile, XCD-aware.  Persistent mode: a grid that fills the device
+// once takes tiles from a work queue ordered longest list first, so long
+// tiles start early and blocks that finish keep taking work.  Every block
+// leaves the loop once the queue is drained.
+struct TileQueue {
+  const uint32_t* order;  // tile ids, longest list first; null: grid mode
+  uint32_t* head;         // queue head, zero before the launch
+  int tiles;
+};
+
+template <bool PERSIST, class F>
+__device__ __forceinline__ void for_tiles(const TileQueue& q, int* s_item, F&& body) {
+  if constexpr (!PERSIST) {
+    const int tile = xcd_tile(blockIdx.x, q.tiles);
+    if (tile < q.tiles) body(tile);
+  } else {
+    for (;;) {
+      __syncthreads();  // the previous tile is finished by every thread
+      if (threadIdx.x == 0) *s_item = (int)atomicAdd(q.head, 1u);
+      __syncthreads();
+      const int it = *s_item;
+      if (it >= q.tiles) break;
+      body((int)q.order[it]);
+    }
+  }
+}
 
 // ------------------------------------------------------------ wave helpers
 __device__ __forceinline__ float wave_sum(float v) {

@@ -18,11 +18,6 @@ struct SurfelArgs {
   int c, dtype;
 };
 
-struct CamArgs {
-  float R[9], t[3], fx, fy, cx, cy, near_plane;
-  int W, H;
-};
-
 struct ImageArgs {
   float *rgb, *depth, *normal, *alpha, *feat;
 };
@@ -47,13 +42,23 @@ struct ProfHook {
   void end(int s, hipStream_t st) const { if (mark) mark(self, s, 1, st); }
 };
 
+// Launch choices the autotuner searches (all give identical results).
+struct Tuning {
+  int sched;       // kSchedGrid or kSchedPersistent
+  int blend_pass;  // feature channels per Top-K blend pass: 16 or 32
+  int bwd_pass;    // feature channels per feature-backward pass: 8 or 16
+};
+enum : int { kSchedGrid = 0, kSchedPersistent = 1 };
+
 // keystage.hip
 void launch_fill_u32(void* p, uint32_t v, int64_t count, hipStream_t st);
-void launch_init_status(uint32_t* status, int64_t n, hipStream_t st);
-void launch_preprocess(const SurfelArgs& s, const CamArgs& c, int mode, const Layout& L, char* ws, hipStream_t st);
+void launch_init_status(uint32_t* status, int64_t n, int64_t tiles, hipStream_t st);
+void launch_preprocess(const SurfelArgs& s, const CamTable& ct, int mode, const Layout& L, char* ws,
+                       hipStream_t st);
 void launch_scan_counts(const Layout& L, char* ws, hipStream_t st);
-void launch_emit(const CamArgs& c, int mode, const Layout& L, char* ws, hipStream_t st);
+void launch_emit(const CamTable& ct, int mode, const Layout& L, char* ws, hipStream_t st);
 void launch_ranges(const Layout& L, char* ws, hipStream_t st);
+void launch_tile_keys(const Layout& L, char* ws, hipStream_t st);
 void launch_export_keys(const Layout& L, char* ws, int32_t* cull, uint32_t* depth, int32_t* count, hipStream_t st);
 
 // sort.hip: stable LSD radix sort of (key, value) pairs on bits [0, bits) of
@@ -62,15 +67,30 @@ void launch_export_keys(const Layout& L, char* ws, int32_t* cull, uint32_t* dept
 void radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev,
                       int64_t cap_n, int bits, uint32_t* hist, int64_t nb_max, hipStream_t st);
 
+// Grid of a per-tile kernel: one block per tile, or (persistent) enough
+// blocks to fill the device once.
+int tile_grid(const Layout& L, const Tuning& tu, const void* kernel, size_t dyn_lds);
+
+// Work queue of a per-tile kernel (work order sorted by the forward; queue
+// heads zeroed before each use).
+inline TileQueue tile_queue(const Layout& L, const Tuning& tu, char* ws, int q) {
+  TileQueue t;
+  t.tiles = (int)L.tiles;
+  t.order = tu.sched == kSchedPersistent ? (const uint32_t*)(ws + L.torder0) : nullptr;
+  t.head = (uint32_t*)(ws + L.status) + kStQueue + q;
+  return t;
+}
+
 // raster_fwd.hip
-void launch_walk(const Layout& L, const CamArgs& c, int blend, const ImageArgs& out, char* ws, hipStream_t st);
-void launch_feature_blend(const SurfelArgs& s, const Layout& L, const CamArgs& c, int blend, float* out_feat,
-                          char* ws, hipStream_t st);
-void launch_export_selection(const Layout& L, const CamArgs& c, char* ws, int32_t* sel_id, float* sel_w,
+void launch_walk(const Layout& L, const CamTable& ct, int blend, const Tuning& tu, const ImageArgs& out, char* ws,
+                 hipStream_t st);
+void launch_feature_blend(const SurfelArgs& s, const Layout& L, const CamTable& ct, int blend, const Tuning& tu,
+                          float* out_feat, char* ws, hipStream_t st);
+void launch_export_selection(const Layout& L, const CamTable& ct, char* ws, int32_t* sel_id, float* sel_w,
                              int32_t* n_last, float* t_final, hipStream_t st);
 
 // raster_bwd.hip
-void launch_backward(const SurfelArgs& s, const CamArgs& c, int blend, const Layout& L, const ImageGradArgs& g,
-                     const GradArgs& grads, char* ws, hipStream_t st, const ProfHook& prof);
+void launch_backward(const SurfelArgs& s, const CamTable& ct, int blend, const Tuning& tu, const Layout& L,
+                     const ImageGradArgs& g, const GradArgs& grads, char* ws, hipStream_t st, const ProfHook& prof);
 
 }  // namespace psm

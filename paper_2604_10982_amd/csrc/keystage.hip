@@ -15,10 +15,7 @@
 
 namespace psm {
 
-struct Cam {
-  float R[9], t[3], fx, fy, cx, cy, near_plane;
-  int W, H;
-};
+using Cam = CamArgs;
 
 // Projected cutoff ellipse of a visible surfel.
 struct Foot {
@@ -193,39 +190,49 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t count) 
   for (int64_t j = i; j < count; j += stride) p[j] = v;
 }
 
-__global__ void k_init_status(uint32_t* __restrict__ st, uint32_t n) {
+__global__ void k_init_status(uint32_t* __restrict__ st, uint32_t n, uint32_t tiles) {
   const int i = threadIdx.x;
-  if (i < kStWords) st[i] = (i == kStN) ? n : 0u;
+  if (i < kStWords) st[i] = (i == kStN) ? n : (i == kStTiles) ? tiles : 0u;
 }
 
+// Thread per virtual surfel v = b * N + i (surfel i seen by camera b).
 __global__ __launch_bounds__(256) void k_preprocess(
-    int64_t n, const float* __restrict__ means, const float* __restrict__ scales,
+    int64_t nv, const float* __restrict__ means, const float* __restrict__ scales,
     const float* __restrict__ quats, const float* __restrict__ opacity, const float* __restrict__ rgb,
-    Cam cam, int mode, int ntx, int nty, WalkRec* __restrict__ rec, float4* __restrict__ fp,
+    CamTable ct, int mode, WalkRec* __restrict__ rec, float4* __restrict__ fp, float4* __restrict__ ext,
     uint32_t* __restrict__ key, uint32_t* __restrict__ ids, uint32_t* __restrict__ count,
     int32_t* __restrict__ cull, uint32_t* __restrict__ status) {
   __shared__ uint32_t s_cnt[5];
+  __shared__ Cam s_cam[kMaxCams];  // cameras by constant index (no private copy of the table)
   if (threadIdx.x < 5) s_cnt[threadIdx.x] = 0;
+#pragma unroll
+  for (int b = 0; b < kMaxCams; ++b)
+    if (threadIdx.x == b && b < ct.n) s_cam[b] = ct.cam[b];
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < nv) {
+    const int b = camera_of(ct, v);
+    const int64_t i = v - (int64_t)b * ct.nsurf;
+    const Cam& cam = s_cam[b];
     const Key kk = key_stage(means + 3 * i, scales + 2 * i, quats + 4 * i, cam);
-    ids[i] = (uint32_t)i;
-    cull[i] = kk.cull | (kk.flip << 8);  // bit 8: normal flipped toward the camera
+    ids[v] = (uint32_t)v;
+    cull[v] = kk.cull | (kk.flip << 8);  // bit 8: normal flipped toward the camera
     atomicAdd(&s_cnt[kk.cull], 1u);
     if (kk.cull != 0) {
-      key[i] = 0xFFFFFFFFu;
-      count[i] = 0;
+      key[v] = 0xFFFFFFFFu;
+      count[v] = 0;
     } else {
-      key[i] = __float_as_uint(kk.mc2);
+      key[v] = __float_as_uint(kk.mc2);
       uint32_t c = 0;
-      for_each_row(kk.f, mode, cam.W, cam.H, ntx, nty, [&](int, int x0, int x1) { c += (uint32_t)(x1 - x0 + 1); });
-      count[i] = c;
-      fp[3 * i + 0] = make_float4(kk.f.ecx, kk.f.ecy, kk.f.S00, kk.f.S01);
-      fp[3 * i + 1] = make_float4(kk.f.S11, kk.f.ex, kk.f.ey, kk.f.gam);
-      fp[3 * i + 2] = make_float4(kk.f.kk, 0.0f, 0.0f, 0.0f);
+      for_each_row(kk.f, mode, cam.W, cam.H, ct.ntx[b], ct.nty[b],
+                   [&](int, int x0, int x1) { c += (uint32_t)(x1 - x0 + 1); });
+      count[v] = c;
+      fp[3 * v + 0] = make_float4(kk.f.ecx, kk.f.ecy, kk.f.S00, kk.f.S01);
+      fp[3 * v + 1] = make_float4(kk.f.S11, kk.f.ex, kk.f.ey, kk.f.gam);
+      fp[3 * v + 2] = make_float4(kk.f.kk, 0.0f, 0.0f, 0.0f);
+      ext[v] = make_float4(kk.f.ecx, kk.f.ecy, kk.f.ex, kk.f.ey);
       walk_record(means + 3 * i, scales + 2 * i, quats + 4 * i, opacity[i], rgb + 3 * i, kk.nc, cam,
-                  rec + i);
+                  rec + v);
     }
   }
   __syncthreads();
@@ -318,25 +325,30 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(int64_t n, const uin
 }
 
 // ---- pair emission in depth order --------------------------------------------
-__global__ __launch_bounds__(256) void k_emit(int64_t n, const uint32_t* __restrict__ order,
+// Thread per depth rank r: the pairs of virtual surfel v = order[r] go to
+// [offs[r], offs[r] + count[v]), tile rows in order; vbase[v] = offs[r].
+__global__ __launch_bounds__(256) void k_emit(int64_t nv, const uint32_t* __restrict__ order,
                                               const uint32_t* __restrict__ count,
                                               const uint32_t* __restrict__ offs, const float4* __restrict__ fp,
-                                              int mode, int W, int H, int ntx, int nty, int64_t cap,
+                                              CamTable ct, int mode, int64_t cap, uint32_t* __restrict__ vbase,
                                               uint32_t* __restrict__ ptile, uint32_t* __restrict__ eid,
                                               uint32_t* __restrict__ sid_emit) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const uint32_t i = order[r];
-  if (count[i] == 0) return;
-  const float4 f0 = fp[3 * i], f1 = fp[3 * i + 1], f2 = fp[3 * i + 2];
+  if (r >= nv) return;
+  const uint32_t v = order[r];
+  vbase[v] = offs[r];
+  if (count[v] == 0) return;
+  const int b = camera_of(ct, v);
+  const int ntx = ct.ntx[b], t0 = ct.tile0[b];
+  const float4 f0 = fp[3 * (size_t)v], f1 = fp[3 * (size_t)v + 1], f2 = fp[3 * (size_t)v + 2];
   const Foot f{f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w, f2.x};
   int64_t o = offs[r];
-  for_each_row(f, mode, W, H, ntx, nty, [&](int ty, int x0, int x1) {
+  for_each_row(f, mode, ct.cam[b].W, ct.cam[b].H, ntx, ct.nty[b], [&](int ty, int x0, int x1) {
     for (int tx = x0; tx <= x1; ++tx, ++o) {
       if (o < cap) {
-        ptile[o] = (uint32_t)(ty * ntx + tx);
+        ptile[o] = (uint32_t)(t0 + ty * ntx + tx);
         eid[o] = (uint32_t)o;
-        sid_emit[o] = i;
+        sid_emit[o] = v;
       }
     }
   });
@@ -375,37 +387,39 @@ __global__ __launch_bounds__(256) void k_finalize_pairs(const uint32_t* __restri
   if (j == P - 1 || ptile[j + 1] != t) ranges[t].y = j + 1;
 }
 
-// ------------------------------------------------------------- host wrappers
-static Cam to_cam(const CamArgs& c) {
-  Cam k;
-  for (int i = 0; i < 9; ++i) k.R[i] = c.R[i];
-  for (int i = 0; i < 3; ++i) k.t[i] = c.t[i];
-  k.fx = c.fx; k.fy = c.fy; k.cx = c.cx; k.cy = c.cy; k.near_plane = c.near_plane;
-  k.W = c.W; k.H = c.H;
-  return k;
+// Sort keys of the tile work order: longest list first (ties by tile id).
+__global__ __launch_bounds__(256) void k_tile_keys(int64_t tiles, const uint2* __restrict__ ranges,
+                                                   uint32_t* __restrict__ key, uint32_t* __restrict__ order) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tiles) return;
+  const uint2 r = ranges[t];
+  key[t] = ~(r.y - r.x);
+  order[t] = (uint32_t)t;
 }
 
+// ------------------------------------------------------------- host wrappers
 void launch_fill_u32(void* p, uint32_t v, int64_t count, hipStream_t st) {
   if (count <= 0) return;
   const int64_t blocks = std::min<int64_t>(cdiv(count, 256), 4096);
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t*)p, v, count);
 }
 
-void launch_init_status(uint32_t* status, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, st, status, (uint32_t)n);
+void launch_init_status(uint32_t* status, int64_t n, int64_t tiles, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, st, status, (uint32_t)n, (uint32_t)tiles);
 }
 
-void launch_preprocess(const SurfelArgs& s, const CamArgs& c, int mode, const Layout& L, char* ws, hipStream_t st) {
-  if (s.n == 0) return;
-  hipLaunchKernelGGL(k_preprocess, dim3((unsigned)cdiv(s.n, 256)), dim3(256), 0, st, s.n, s.means, s.scales,
-                     s.quats, s.opacity, s.rgb, to_cam(c), mode, (int)L.ntx, (int)L.nty,
-                     (WalkRec*)(ws + L.rec), (float4*)(ws + L.fp), (uint32_t*)(ws + L.key0),
-                     (uint32_t*)(ws + L.id0), (uint32_t*)(ws + L.count), (int32_t*)(ws + L.cull),
-                     (uint32_t*)(ws + L.status));
+void launch_preprocess(const SurfelArgs& s, const CamTable& ct, int mode, const Layout& L, char* ws,
+                       hipStream_t st) {
+  if (L.n == 0) return;
+  hipLaunchKernelGGL(k_preprocess, dim3((unsigned)cdiv(L.n, 256)), dim3(256), 0, st, L.n, s.means, s.scales,
+                     s.quats, s.opacity, s.rgb, ct, mode, (WalkRec*)(ws + L.rec), (float4*)(ws + L.fp),
+                     (float4*)(ws + L.ext),
+                     (uint32_t*)(ws + L.key0), (uint32_t*)(ws + L.id0), (uint32_t*)(ws + L.count),
+                     (int32_t*)(ws + L.cull), (uint32_t*)(ws + L.status));
 }
 
 void launch_scan_counts(const Layout& L, char* ws, hipStream_t st) {
-  const int64_t nb = std::max<int64_t>(1, cdiv(L.n, kScanTile));
+  const int64_t nb = std::max<int64_t>(cdiv(L.n, kScanTile), 1);
   const uint32_t* order = (const uint32_t*)(ws + L.id0);
   const uint32_t* count = (const uint32_t*)(ws + L.count);
   uint64_t* bsum = (uint64_t*)(ws + L.bsum);
@@ -415,12 +429,12 @@ void launch_scan_counts(const Layout& L, char* ws, hipStream_t st) {
                      (const uint64_t*)bsum, (uint32_t*)(ws + L.offs));
 }
 
-void launch_emit(const CamArgs& c, int mode, const Layout& L, char* ws, hipStream_t st) {
+void launch_emit(const CamTable& ct, int mode, const Layout& L, char* ws, hipStream_t st) {
   if (L.n == 0) return;
   hipLaunchKernelGGL(k_emit, dim3((unsigned)cdiv(L.n, 256)), dim3(256), 0, st, L.n,
                      (const uint32_t*)(ws + L.id0), (const uint32_t*)(ws + L.count),
-                     (const uint32_t*)(ws + L.offs), (const float4*)(ws + L.fp), mode, c.W, c.H, (int)L.ntx,
-                     (int)L.nty, L.cap, (uint32_t*)(ws + L.ptile0), (uint32_t*)(ws + L.eid0),
+                     (const uint32_t*)(ws + L.offs), (const float4*)(ws + L.fp), ct, mode, L.cap,
+                     (uint32_t*)(ws + L.vbase), (uint32_t*)(ws + L.ptile0), (uint32_t*)(ws + L.eid0),
                      (uint32_t*)(ws + L.sid_emit));
 }
 
@@ -437,6 +451,12 @@ void launch_ranges(const Layout& L, char* ws, hipStream_t st) {
                      (const uint32_t*)(ws + L.ptile0), (const uint32_t*)(ws + L.eid0),
                      (const uint32_t*)(ws + L.sid_emit), (const uint32_t*)(ws + L.status), (uint32_t*)(ws + L.pid),
                      (uint2*)(ws + L.ranges));
+}
+
+void launch_tile_keys(const Layout& L, char* ws, hipStream_t st) {
+  if (L.tiles == 0) return;
+  hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)cdiv(L.tiles, 256)), dim3(256), 0, st, L.tiles,
+                     (const uint2*)(ws + L.ranges), (uint32_t*)(ws + L.tkey0), (uint32_t*)(ws + L.torder0));
 }
 
 }  // namespace psm

@@ -29,22 +29,20 @@ constexpr int kBB = 32;          // surfels per backward batch
 constexpr int kNV = 17;          // per-pixel values reduced per surfel
 
 // ------------------------------------------------------------ Top-K feature
-constexpr int kGC = 16;         // feature channels per backward pass
-constexpr int kGRow = kGC + 4;  // LDS row stride (floats)
-
 // Per tile: the tile's distinct selected surfels get slots (list order); each
 // slot gets the list of (pixel, weight) entries that selected it, in pixel
-// order.  Per pass of 16 channels the pixels' feature gradients and the
+// order.  Per pass of GC channels the pixels' feature gradients and the
 // slots' feature rows are staged in LDS, then
 //   thread = pixel:             dot[q] += g_F(p) . f_slot(q)    (registers)
 //   thread = (slot, 4 channels): row = sum over the slot's entries of w g_F(p)
 // and each row is written at the emitted index of its (tile, surfel) pair.
-template <typename FT, int KMAX>
+template <typename FT, int KMAX, int GC, bool PERSIST>
 __global__ __launch_bounds__(256) void k_feat_bwd_topk(
     const uint32_t* __restrict__ pid, const uint32_t* __restrict__ eid, const uint2* __restrict__ ranges,
     const int32_t* __restrict__ selpos, const float* __restrict__ selw, const FT* __restrict__ feat,
-    const float* __restrict__ gfeat, int C, int K, int W, int H, int ntx, int tiles, float* __restrict__ seldot,
+    const float* __restrict__ gfeat, int C, int K, CamTable ct, TileQueue tq, float* __restrict__ seldot,
     float* __restrict__ fpart, uint8_t* __restrict__ fflag) {
+  constexpr int kGC = GC, kGRow = GC + 4;  // channels per pass, LDS row stride
   __shared__ SelShared S;
   __shared__ __align__(16) float s_G[kTilePix * kGRow];
   __shared__ __align__(16) float s_F[kSlotChunk * kGRow];
@@ -54,16 +52,16 @@ __global__ __launch_bounds__(256) void k_feat_bwd_topk(
   extern __shared__ __align__(16) char smem[];
   float* s_lw = reinterpret_cast<float*>(smem);                    // [256 K] entry weights
   uint8_t* s_lp = reinterpret_cast<uint8_t*>(s_lw + kTilePix * K);  // [256 K] entry pixels
+  __shared__ int s_item;
 
-  const int tile = xcd_tile(blockIdx.x, tiles);
-  if (tile >= tiles) return;
+  for_tiles<PERSIST>(tq, &s_item, [&](const int tile) {
+  const TileLoc tl = locate(ct, tile);
   const int tid = threadIdx.x;
-  const int tx = tile % ntx, ty = tile / ntx;
-  const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
-  const bool inside = px < W && py < H;
+  const int px = tl.tx * kTile + (tid & 15), py = tl.ty * kTile + (tid >> 4);
+  const bool inside = px < tl.W && py < tl.H;
   const uint32_t start = ranges[tile].x;
   const size_t tbase = (size_t)tile * K * kTilePix;
-  const float* grow = gfeat + ((int64_t)py * W + px) * C;
+  const float* grow = gfeat + (tl.pix0 + (int64_t)py * tl.W + px) * C;
 
   int pos[KMAX];
   float w[KMAX], dot[KMAX];
@@ -91,7 +89,7 @@ __global__ __launch_bounds__(256) void k_feat_bwd_topk(
         sl[q] = (s >= c0 && s < c0 + ns) ? s - c0 : -1;
         if (sl[q] >= 0) {
           atomicOr(&s_mask[sl[q] * 8 + (tid >> 5)], 1u << (tid & 31));
-          S.fid[sl[q]] = pid[start + pos[q]];
+          S.fid[sl[q]] = (uint32_t)(pid[start + pos[q]] - tl.v0);
           S.lpos[sl[q]] = (uint32_t)pos[q];
         }
       }
@@ -194,41 +192,45 @@ __global__ __launch_bounds__(256) void k_feat_bwd_topk(
 #pragma unroll
   for (int q = 0; q < KMAX; ++q)
     if (q < K) seldot[tbase + (size_t)q * kTilePix + tid] = pos[q] >= 0 ? dot[q] : 0.0f;
+  });
 }
 
 // ------------------------------------------------------------- walk backward
-template <int MODE, typename FT>
+template <int MODE, typename FT, bool PERSIST>
 __global__ __launch_bounds__(256) void k_walk_bwd(
-    const WalkRec* __restrict__ rec, const uint32_t* __restrict__ pid, const uint32_t* __restrict__ eid,
-    const uint2* __restrict__ ranges, int W,
-    int H, int ntx, int tiles, int K, const uint32_t* __restrict__ nlast, const float* __restrict__ tfinal,
+    const WalkRec* __restrict__ rec, const float4* __restrict__ ext, const uint32_t* __restrict__ pid, const uint32_t* __restrict__ eid,
+    const uint2* __restrict__ ranges, CamTable ct, TileQueue tq, int K, const uint32_t* __restrict__ nlast,
+    const float* __restrict__ tfinal,
     const int32_t* __restrict__ selpos, const float* __restrict__ seldot, const float* __restrict__ g_rgb,
     const float* __restrict__ g_depth, const float* __restrict__ g_normal, const float* __restrict__ g_alpha,
     const float* __restrict__ g_feat, const FT* __restrict__ feat, int C, float* __restrict__ gpart,
     uint8_t* __restrict__ gflag, float* __restrict__ fpart, uint8_t* __restrict__ fflag) {
   __shared__ Staged<kBB> s_r;
+  __shared__ float2 s_band[kBB];  // (ecy, ey) of the batch, for band culling
   __shared__ uint32_t s_id[kBB];
   __shared__ float s_part[4][kBB][kNV];
   __shared__ uint32_t s_has[4][kBB];
   __shared__ int s_lmax;
   // dense-blend mode only: feature chunk of the batch and the batch weights
   __shared__ float s_fc[MODE == kFull ? kBB : 1][64];
-  __shared__ float s_om[MODE == kFull ? kBB : 1][kTilePix];
+  __shared__ __align__(16) float s_om[MODE == kFull ? kBB : 1][kTilePix];
+  __shared__ int s_item;
 
-  const int tile = xcd_tile(blockIdx.x, tiles);
-  if (tile >= tiles) return;
+  for_tiles<PERSIST>(tq, &s_item, [&](const int tile) {
+  const TileLoc tl = locate(ct, tile);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tx = tile % ntx, ty = tile / ntx;
+  const int tx = tl.tx, ty = tl.ty, W = tl.W, H = tl.H;
   const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
   const bool inside = px < W && py < H;
   const float lx = (float)(tid & 15) + 0.5f, ly = (float)(tid >> 4) + 0.5f;
   const float tx0 = (float)(tx * kTile), ty0 = (float)(ty * kTile);
+  const float yb0 = ty0 + (float)(4 * wave) + 0.5f, yb1 = yb0 + 3.0f;  // this wave's rows
   const uint32_t start = ranges[tile].x;
   const int sp = tile * kTilePix + tid;
   const int my_last = (int)nlast[sp];
   float T = tfinal[sp];
   const float Tfin = T;
-  const int64_t pix = (int64_t)py * W + px;
+  const int64_t pix = tl.pix0 + (int64_t)py * W + px;
   float gC0 = 0.f, gC1 = 0.f, gC2 = 0.f, gD = 0.f, gN0 = 0.f, gN1 = 0.f, gN2 = 0.f, gA = 0.f;
   if (inside) {
     if (g_rgb) { gC0 = g_rgb[3 * pix]; gC1 = g_rgb[3 * pix + 1]; gC2 = g_rgb[3 * pix + 2]; }
@@ -251,6 +253,7 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
   const bool has_gf = MODE == kFull && g_feat != nullptr && inside;
   const float* grow = g_feat + pix * C;
 
+  __syncthreads();
   if (tid == 0) s_lmax = 0;
   __syncthreads();
   atomicMax(&s_lmax, my_last);
@@ -263,8 +266,10 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
     __syncthreads();
     if (tid < nb) {
       const uint32_t id = pid[start + lo + tid];
-      s_id[tid] = id;
+      s_id[tid] = id;  // virtual surfel id
       s_r.put(tid, rec[id], tx0, ty0);
+      const float4 x = ext[id];
+      s_band[tid] = make_float2(x.y, x.w);
     }
     __syncthreads();
 
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
         for (int c0 = 0; c0 < C; c0 += 64) {
           for (int e = tid; e < nb * 64; e += 256) {
             const int k = e >> 6, c = e & 63;
-            s_fc[k][c] = (c0 + c < C) ? load_one<FT>(feat + (size_t)s_id[k] * C + c0 + c) : 0.0f;
+            s_fc[k][c] = (c0 + c < C) ? load_one<FT>(feat + (size_t)(s_id[k] - tl.v0) * C + c0 + c) : 0.0f;
           }
           __syncthreads();
           if (has_gf) {
@@ -294,6 +299,9 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
       }
     }
 
+    // surfels of the batch whose footprint meets this wave's 4 rows
+    const uint64_t band = __ballot(lane < nb && band_meets(s_band[lane < kBB ? lane : 0].x,
+                                                           s_band[lane < kBB ? lane : 0].y, yb0, yb1));
 #pragma unroll 1
     for (int k = nb - 1; k >= 0; --k) {
       const int pos = lo + k;
@@ -302,7 +310,7 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
       for (int i = 0; i < kNV; ++i) v[i] = 0.0f;
       bool contrib = false;
       float wgt = 0.0f;
-      if (pos < my_last) {
+      if (pos < my_last && ((band >> k) & 1u)) {
         const LRec s = s_r.get(k);
         PixEval e;
         if (eval_pixel(s, lx, ly, e)) {
@@ -400,12 +408,31 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
 #pragma unroll
           for (int j = 0; j < PER; ++j) acc[j] = 0.0f;
           if (c < C) {
-            for (int p = 0; p < kTilePix; ++p) {
-              const int qx = tx * kTile + (p & 15), qy = ty * kTile + (p >> 4);
-              if (qx >= W || qy >= H) continue;
-              const float g = g_feat[((int64_t)qy * W + qx) * C + c];
+            // 8 pixels per step: 8 independent upstream loads in flight (pixels
+            // outside the image have zero weight and read as zero)
+            for (int p0 = 0; p0 < kTilePix; p0 += 8) {
+              float g[8];
 #pragma unroll
-              for (int j = 0; j < PER; ++j) acc[j] = fmaf(s_om[kg * PER + j][p], g, acc[j]);
+              for (int u = 0; u < 8; ++u) {
+                const int p = p0 + u;
+                const int qx = tx * kTile + (p & 15), qy = ty * kTile + (p >> 4);
+                g[u] = (qx < W && qy < H) ? g_feat[(tl.pix0 + (int64_t)qy * W + qx) * C + c] : 0.0f;
+              }
+#pragma unroll
+              for (int j = 0; j < PER; ++j) {
+                const float4 w0 = *reinterpret_cast<const float4*>(&s_om[kg * PER + j][p0]);
+                const float4 w1 = *reinterpret_cast<const float4*>(&s_om[kg * PER + j][p0 + 4]);
+                float a = acc[j];
+                a = fmaf(w0.x, g[0], a);
+                a = fmaf(w0.y, g[1], a);
+                a = fmaf(w0.z, g[2], a);
+                a = fmaf(w0.w, g[3], a);
+                a = fmaf(w1.x, g[4], a);
+                a = fmaf(w1.y, g[5], a);
+                a = fmaf(w1.z, g[6], a);
+                a = fmaf(w1.w, g[7], a);
+                acc[j] = a;
+              }
             }
 #pragma unroll
             for (int j = 0; j < PER; ++j) {
@@ -421,59 +448,22 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
       }
     }
   }
+  });
 }
 
 // ------------------------------------------------------- per-surfel reduction
-struct CamB {
-  float R[9], t[3], fx, fy, cx, cy;
+// Chain rule of one camera's view of a surfel: from the 16 pair sums G (dL/d
+// of A^-1 (4), e (2), projected centre (2), centre depth, o, c (3), n_c (3))
+// to the surfel parameters.  The walk record was evaluated in FP64 from the
+// FP32 inputs; its chain rule is evaluated the same way.
+struct SurfelGrad {
+  double mu[3], su, sv, q[4], o, rgb[3];
 };
 
-// Thread per surfel, visited in depth order so its pairs are the emitted
-// range [offs[r], offs[r] + count).
-__global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, const uint32_t* __restrict__ order,
-                                                    const uint32_t* __restrict__ count,
-                                                    const uint32_t* __restrict__ offs, int64_t cap,
-                                                    const float* __restrict__ gpart,
-                                                    const uint8_t* __restrict__ gflag,
-                                                    const float* __restrict__ means, const float* __restrict__ scales,
-                                                    const float* __restrict__ quats, const int32_t* __restrict__ cull,
-                                                    CamB k, float* __restrict__ d_means, float* __restrict__ d_scales,
-                                                    float* __restrict__ d_quats, float* __restrict__ d_opacity,
-                                                    float* __restrict__ d_rgb) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const uint32_t i = order[r];
-  if ((cull[i] & 0xFF) != 0) {
-    for (int j = 0; j < 3; ++j) { d_means[3 * i + j] = 0.f; d_rgb[3 * i + j] = 0.f; }
-    d_scales[2 * i] = d_scales[2 * i + 1] = 0.f;
-    for (int j = 0; j < 4; ++j) d_quats[4 * i + j] = 0.f;
-    d_opacity[i] = 0.f;
-    return;
-  }
-  double G[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) G[j] = 0.0;
-  const int64_t base = offs[r], cnt = count[i];
-  const int64_t end = min(base + cnt, cap);
-  for (int64_t slot = base; slot < end; ++slot) {
-    if (!gflag[slot]) continue;
-    const float4* g = reinterpret_cast<const float4*>(gpart + (size_t)slot * 16);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float4 v = g[q];
-      G[4 * q] += v.x; G[4 * q + 1] += v.y; G[4 * q + 2] += v.z; G[4 * q + 3] += v.w;
-    }
-  }
-  // The walk record was evaluated in FP64 from the FP32 inputs; its chain
-  // rule is evaluated the same way.
-  const double mu[3] = {means[3 * i], means[3 * i + 1], means[3 * i + 2]};
-  const double su = scales[2 * i], sv = scales[2 * i + 1];
-  const double q0 = quats[4 * i], q1 = quats[4 * i + 1], q2 = quats[4 * i + 2], q3 = quats[4 * i + 3];
-  const double rn = 1.0 / sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-  const double w = q0 * rn, x = q1 * rn, y = q2 * rn, z = q3 * rn;
-  const double Rq[3][3] = {{1. - 2. * (y * y + z * z), 2. * (x * y - w * z), 2. * (x * z + w * y)},
-                           {2. * (x * y + w * z), 1. - 2. * (x * x + z * z), 2. * (y * z - w * x)},
-                           {2. * (x * z - w * y), 2. * (y * z + w * x), 1. - 2. * (x * x + y * y)}};
+__device__ __forceinline__ void chain_rule(const double (&G)[16], const CamArgs& k, bool flip, const double (&mu)[3],
+                                           double su, double sv, const double (&qn)[4], const double (&Rq)[3][3],
+                                           SurfelGrad& acc) {
+  const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
   double mc[3], ra[3], rb[3], a[3], b[3];
   for (int r = 0; r < 3; ++r) {
     const float* Rr = k.R + 3 * r;
@@ -483,7 +473,7 @@ __global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, const uint32_t* _
     a[r] = su * ra[r];
     b[r] = sv * rb[r];
   }
-  const double sgn = (cull[i] >> 8) & 1 ? -1.0 : 1.0;  // orientation chosen by the key stage
+  const double sgn = flip ? -1.0 : 1.0;  // orientation chosen by the key stage
   const double fx = k.fx, fy = k.fy;
   const double iz = 1.0 / mc[2];
   const double p = a[2] * iz, q = b[2] * iz;
@@ -493,7 +483,6 @@ __global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, const uint32_t* _
   const double A00 = B00 * iz, A01 = B01 * iz, A10 = B10 * iz, A11 = B11 * iz;
   const double idA = 1.0 / (A00 * A11 - A01 * A10);
   const double Ai[2][2] = {{A11 * idA, -A01 * idA}, {-A10 * idA, A00 * idA}};
-  // accumulators: d/dA^-1 (4), d/de (2), d/dxc, d/dyc, d/dz_centre, d/do, d/dc (3), d/dn_c (3)
   const double dAi[2][2] = {{G[0], G[1]}, {G[2], G[3]}};
   const double de[2] = {G[4], G[5]};
   const double dxc = G[6], dyc = G[7], dmz = G[8];
@@ -527,44 +516,93 @@ __global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, const uint32_t* _
   d_mc[2] = -d_iz * iz * iz + dmz;
   const double dn[3] = {sgn * G[13], sgn * G[14], sgn * G[15]};
   // back through the world -> camera rotation
-  double dtu[3], dtv[3], dnn[3], dmu[3];
+  double dtu[3], dtv[3], dnn[3];
   for (int c = 0; c < 3; ++c) {
     const double R0 = k.R[c], R1 = k.R[3 + c], R2 = k.R[6 + c];
     dtu[c] = su * (R0 * d_a[0] + R1 * d_a[1] + R2 * d_a[2]);
     dtv[c] = sv * (R0 * d_b[0] + R1 * d_b[1] + R2 * d_b[2]);
     dnn[c] = R0 * dn[0] + R1 * dn[1] + R2 * dn[2];
-    dmu[c] = R0 * d_mc[0] + R1 * d_mc[1] + R2 * d_mc[2];
+    acc.mu[c] += R0 * d_mc[0] + R1 * d_mc[1] + R2 * d_mc[2];
   }
-  const double dsu = d_a[0] * ra[0] + d_a[1] * ra[1] + d_a[2] * ra[2];
-  const double dsv = d_b[0] * rb[0] + d_b[1] * rb[1] + d_b[2] * rb[2];
+  acc.su += d_a[0] * ra[0] + d_a[1] * ra[1] + d_a[2] * ra[2];
+  acc.sv += d_b[0] * rb[0] + d_b[1] * rb[1] + d_b[2] * rb[2];
   // Rq columns are t_u, t_v, n;  Gm[r][c] = dL/dRq[r][c]
   const double Gm[3][3] = {{dtu[0], dtv[0], dnn[0]}, {dtu[1], dtv[1], dnn[1]}, {dtu[2], dtv[2], dnn[2]}};
-  const double dw = 2. * (-z * Gm[0][1] + y * Gm[0][2] + z * Gm[1][0] - x * Gm[1][2] - y * Gm[2][0] + x * Gm[2][1]);
-  const double dx = 2. * (y * Gm[0][1] + z * Gm[0][2] + y * Gm[1][0] - 2. * x * Gm[1][1] - w * Gm[1][2] +
-                          z * Gm[2][0] + w * Gm[2][1] - 2. * x * Gm[2][2]);
-  const double dy = 2. * (-2. * y * Gm[0][0] + x * Gm[0][1] + w * Gm[0][2] + x * Gm[1][0] + z * Gm[1][2] -
-                          w * Gm[2][0] + z * Gm[2][1] - 2. * y * Gm[2][2]);
-  const double dz = 2. * (-2. * z * Gm[0][0] - w * Gm[0][1] + x * Gm[0][2] + w * Gm[1][0] - 2. * z * Gm[1][1] +
-                          y * Gm[1][2] + x * Gm[2][0] + y * Gm[2][1]);
-  // unit quaternion: project out the radial component
-  const double dot = w * dw + x * dx + y * dy + z * dz;
-  d_quats[4 * i + 0] = (float)((dw - w * dot) * rn);
-  d_quats[4 * i + 1] = (float)((dx - x * dot) * rn);
-  d_quats[4 * i + 2] = (float)((dy - y * dot) * rn);
-  d_quats[4 * i + 3] = (float)((dz - z * dot) * rn);
-  for (int j = 0; j < 3; ++j) d_means[3 * i + j] = (float)dmu[j];
-  d_scales[2 * i] = (float)dsu;
-  d_scales[2 * i + 1] = (float)dsv;
-  d_opacity[i] = (float)G[9];
-  d_rgb[3 * i] = (float)G[10];
-  d_rgb[3 * i + 1] = (float)G[11];
-  d_rgb[3 * i + 2] = (float)G[12];
+  acc.q[0] += 2. * (-z * Gm[0][1] + y * Gm[0][2] + z * Gm[1][0] - x * Gm[1][2] - y * Gm[2][0] + x * Gm[2][1]);
+  acc.q[1] += 2. * (y * Gm[0][1] + z * Gm[0][2] + y * Gm[1][0] - 2. * x * Gm[1][1] - w * Gm[1][2] + z * Gm[2][0] +
+                    w * Gm[2][1] - 2. * x * Gm[2][2]);
+  acc.q[2] += 2. * (-2. * y * Gm[0][0] + x * Gm[0][1] + w * Gm[0][2] + x * Gm[1][0] + z * Gm[1][2] - w * Gm[2][0] +
+                    z * Gm[2][1] - 2. * y * Gm[2][2]);
+  acc.q[3] += 2. * (-2. * z * Gm[0][0] - w * Gm[0][1] + x * Gm[0][2] + w * Gm[1][0] - 2. * z * Gm[1][1] +
+                    y * Gm[1][2] + x * Gm[2][0] + y * Gm[2][1]);
+  acc.o += G[9];
+  acc.rgb[0] += G[10];
+  acc.rgb[1] += G[11];
+  acc.rgb[2] += G[12];
 }
 
-// Lane group per surfel (in depth order): dL/df = sum of its pairs' rows.
-__global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, const uint32_t* __restrict__ order,
-                                                     const uint32_t* __restrict__ count,
-                                                     const uint32_t* __restrict__ offs, int64_t cap,
+// Thread per surfel: for each camera in order, the sum of its pairs' partials
+// (its emitted range [vbase, vbase + count), in emission order), then that
+// camera's chain rule; the cameras' contributions are added in camera order.
+__global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, CamTable ct, const uint32_t* __restrict__ vbase,
+                                                    const uint32_t* __restrict__ count, int64_t cap,
+                                                    const float* __restrict__ gpart,
+                                                    const uint8_t* __restrict__ gflag,
+                                                    const float* __restrict__ means, const float* __restrict__ scales,
+                                                    const float* __restrict__ quats, const int32_t* __restrict__ cull,
+                                                    float* __restrict__ d_means, float* __restrict__ d_scales,
+                                                    float* __restrict__ d_quats, float* __restrict__ d_opacity,
+                                                    float* __restrict__ d_rgb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  SurfelGrad acc;
+  for (int j = 0; j < 3; ++j) acc.mu[j] = acc.rgb[j] = 0.0;
+  for (int j = 0; j < 4; ++j) acc.q[j] = 0.0;
+  acc.su = acc.sv = acc.o = 0.0;
+  const double mu[3] = {means[3 * i], means[3 * i + 1], means[3 * i + 2]};
+  const double su = scales[2 * i], sv = scales[2 * i + 1];
+  const double q0 = quats[4 * i], q1 = quats[4 * i + 1], q2 = quats[4 * i + 2], q3 = quats[4 * i + 3];
+  const double qq = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
+  const double rn = qq > 0.0 ? 1.0 / sqrt(qq) : 0.0;
+  const double qn[4] = {q0 * rn, q1 * rn, q2 * rn, q3 * rn};
+  const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
+  const double Rq[3][3] = {{1. - 2. * (y * y + z * z), 2. * (x * y - w * z), 2. * (x * z + w * y)},
+                           {2. * (x * y + w * z), 1. - 2. * (x * x + z * z), 2. * (y * z - w * x)},
+                           {2. * (x * z - w * y), 2. * (y * z + w * x), 1. - 2. * (x * x + y * y)}};
+  for (int b = 0; b < ct.n; ++b) {
+    const int64_t v = (int64_t)b * n + i;
+    const int32_t cv = cull[v];
+    if ((cv & 0xFF) != 0) continue;
+    double G[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) G[j] = 0.0;
+    const int64_t base = vbase[v];
+    const int64_t end = min(base + (int64_t)count[v], cap);
+    for (int64_t slot = base; slot < end; ++slot) {
+      if (!gflag[slot]) continue;
+      const float4* g = reinterpret_cast<const float4*>(gpart + (size_t)slot * 16);
+#pragma unroll
+      for (int qd = 0; qd < 4; ++qd) {
+        const float4 t = g[qd];
+        G[4 * qd] += t.x; G[4 * qd + 1] += t.y; G[4 * qd + 2] += t.z; G[4 * qd + 3] += t.w;
+      }
+    }
+    chain_rule(G, ct.cam[b], ((cv >> 8) & 1) != 0, mu, su, sv, qn, Rq, acc);
+  }
+  // unit quaternion: project out the radial component
+  const double dot = w * acc.q[0] + x * acc.q[1] + y * acc.q[2] + z * acc.q[3];
+  for (int j = 0; j < 4; ++j) d_quats[4 * i + j] = (float)((acc.q[j] - qn[j] * dot) * rn);
+  for (int j = 0; j < 3; ++j) d_means[3 * i + j] = (float)acc.mu[j];
+  d_scales[2 * i] = (float)acc.su;
+  d_scales[2 * i + 1] = (float)acc.sv;
+  d_opacity[i] = (float)acc.o;
+  for (int j = 0; j < 3; ++j) d_rgb[3 * i + j] = (float)acc.rgb[j];
+}
+
+// Lane group per surfel: dL/df = sum over cameras (in order) of the sum of its
+// pairs' rows (emission order).
+__global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const uint32_t* __restrict__ vbase,
+                                                     const uint32_t* __restrict__ count, int64_t cap,
                                                      const float* __restrict__ fpart,
                                                      const uint8_t* __restrict__ fflag, int C,
                                                      float* __restrict__ dfeat) {
@@ -573,104 +611,122 @@ __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, const uint32_t* 
   const int lpp2 = lpp >= 64 ? 64 : pow2_ge(lpp);
   const int spw = 64 / lpp2;
   const int sub = lane / lpp2, cl = lane % lpp2;
-  const int64_t r = ((int64_t)blockIdx.x * 4 + wave) * spw + sub;
-  if (r >= n) return;
-  const uint32_t i = order[r];
-  const int64_t base = offs[r], cnt = count[i];
+  const int64_t i = ((int64_t)blockIdx.x * 4 + wave) * spw + sub;
+  if (i >= n) return;
   for (int cg = cl; cg < lpp; cg += lpp2) {
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    const int64_t end = min(base + cnt, cap);
-    for (int64_t slot = base; slot < end; ++slot) {
-      if (!fflag[slot]) continue;
-      const float4 v = *reinterpret_cast<const float4*>(fpart + (size_t)slot * C + cg * 4);
-      acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+    for (int b = 0; b < ncam; ++b) {
+      const int64_t v = (int64_t)b * n + i;
+      const int64_t base = vbase[v];
+      const int64_t end = min(base + (int64_t)count[v], cap);
+      for (int64_t slot = base; slot < end; ++slot) {
+        if (!fflag[slot]) continue;
+        const float4 t = *reinterpret_cast<const float4*>(fpart + (size_t)slot * C + cg * 4);
+        acc.x += t.x; acc.y += t.y; acc.z += t.z; acc.w += t.w;
+      }
     }
     *reinterpret_cast<float4*>(dfeat + (size_t)i * C + cg * 4) = acc;
   }
 }
 
 // ------------------------------------------------------------- host wrappers
-template <typename FT, int KMAX>
-static void feat_bwd_launch(const SurfelArgs& s, const Layout& L, const CamArgs& c, const ImageGradArgs& g, char* ws,
-                            hipStream_t st) {
+template <typename FT, int KMAX, int GC, bool PERSIST>
+static void feat_bwd_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
+                            const ImageGradArgs& g, char* ws, hipStream_t st) {
   const size_t shm = (size_t)kTilePix * L.k * 5;  // entry weights + entry pixels
-  hipLaunchKernelGGL((k_feat_bwd_topk<FT, KMAX>), dim3(xcd_grid(L.tiles)), dim3(256), shm, st,
+  const void* k = reinterpret_cast<const void*>(&k_feat_bwd_topk<FT, KMAX, GC, PERSIST>);
+  hipLaunchKernelGGL((k_feat_bwd_topk<FT, KMAX, GC, PERSIST>), dim3(tile_grid(L, tu, k, shm)), dim3(256), shm, st,
                      (const uint32_t*)(ws + L.pid), (const uint32_t*)(ws + L.eid0), (const uint2*)(ws + L.ranges),
                      (const int32_t*)(ws + L.selpos), (const float*)(ws + L.selw), (const FT*)s.feat, g.feat, s.c, L.k,
-                     c.W, c.H, (int)L.ntx, (int)L.tiles, (float*)(ws + L.seldot), (float*)(ws + L.fpart),
+                     ct, tile_queue(L, tu, ws, kQFeatBwd), (float*)(ws + L.seldot), (float*)(ws + L.fpart),
                      (uint8_t*)(ws + L.fflag));
 }
 
+template <typename FT, int GC>
+static void feat_bwd_k(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
+                       const ImageGradArgs& g, char* ws, hipStream_t st) {
+  const bool p = tu.sched == kSchedPersistent;
+  if (L.k <= 8) (p ? feat_bwd_launch<FT, 8, GC, true> : feat_bwd_launch<FT, 8, GC, false>)(s, L, ct, tu, g, ws, st);
+  else if (L.k <= 16)
+    (p ? feat_bwd_launch<FT, 16, GC, true> : feat_bwd_launch<FT, 16, GC, false>)(s, L, ct, tu, g, ws, st);
+  else (p ? feat_bwd_launch<FT, 32, GC, true> : feat_bwd_launch<FT, 32, GC, false>)(s, L, ct, tu, g, ws, st);
+}
+
+template <int MODE, typename FT, bool PERSIST>
+static void walk_bwd_launch_t(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
+                              const ImageGradArgs& g, bool want_f, char* ws, hipStream_t st) {
+  const void* k = reinterpret_cast<const void*>(&k_walk_bwd<MODE, FT, PERSIST>);
+  hipLaunchKernelGGL((k_walk_bwd<MODE, FT, PERSIST>), dim3(tile_grid(L, tu, k, 0)), dim3(256), 0, st,
+                     (const WalkRec*)(ws + L.rec), (const float4*)(ws + L.ext), (const uint32_t*)(ws + L.pid),
+                     (const uint32_t*)(ws + L.eid0), (const uint2*)(ws + L.ranges), ct,
+                     tile_queue(L, tu, ws, kQWalkBwd), L.k,
+                     (const uint32_t*)(ws + L.nlast), (const float*)(ws + L.tfinal), (const int32_t*)(ws + L.selpos),
+                     (const float*)(ws + L.seldot), g.rgb, g.depth, g.normal, g.alpha, want_f ? g.feat : nullptr,
+                     (const FT*)s.feat, s.c, (float*)(ws + L.gpart), (uint8_t*)(ws + L.gflag), (float*)(ws + L.fpart),
+                     (uint8_t*)(ws + L.fflag));
+}
+
+template <int MODE, typename FT>
+static void walk_bwd_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
+                            const ImageGradArgs& g, bool want_f, char* ws, hipStream_t st) {
+  if (tu.sched == kSchedPersistent) walk_bwd_launch_t<MODE, FT, true>(s, L, ct, tu, g, want_f, ws, st);
+  else walk_bwd_launch_t<MODE, FT, false>(s, L, ct, tu, g, want_f, ws, st);
+}
+
 template <typename FT>
-static void backward_typed(const SurfelArgs& s, const CamArgs& c, int blend, const Layout& L, const ImageGradArgs& g,
-                           const GradArgs& gr, char* ws, hipStream_t st, const ProfHook& prof) {
-  const WalkRec* rec = (const WalkRec*)(ws + L.rec);
-  const uint32_t* pid = (const uint32_t*)(ws + L.pid);
-  const uint32_t* eid = (const uint32_t*)(ws + L.eid0);
-  const uint2* ranges = (const uint2*)(ws + L.ranges);
-  float* gpart = (float*)(ws + L.gpart);
-  float* fpart = (float*)(ws + L.fpart);
-  uint8_t* gflag = (uint8_t*)(ws + L.gflag);
-  uint8_t* fflag = (uint8_t*)(ws + L.fflag);
-  const dim3 grid(xcd_grid(L.tiles));
+static void backward_typed(const SurfelArgs& s, const CamTable& ct, int blend, const Tuning& tu, const Layout& L,
+                           const ImageGradArgs& g, const GradArgs& gr, char* ws, hipStream_t st,
+                           const ProfHook& prof) {
   const bool want_f = g.feat != nullptr && s.c > 0;
-  if (blend == kTopK) {
-    prof.begin(kStageBwdFeature, st);
-    if (want_f) {
-      if (L.k <= 8) feat_bwd_launch<FT, 8>(s, L, c, g, ws, st);
-      else if (L.k <= 16) feat_bwd_launch<FT, 16>(s, L, c, g, ws, st);
-      else feat_bwd_launch<FT, 32>(s, L, c, g, ws, st);
+  if (L.tiles > 0) {
+    if (blend == kTopK) {
+      prof.begin(kStageBwdFeature, st);
+      if (want_f) {
+        if (tu.bwd_pass == 8) feat_bwd_k<FT, 8>(s, L, ct, tu, g, ws, st);
+        else feat_bwd_k<FT, 16>(s, L, ct, tu, g, ws, st);
+      } else {
+        launch_fill_u32(ws + L.seldot, 0u, L.spix * (int64_t)L.k, st);
+      }
+      prof.end(kStageBwdFeature, st);
+      prof.begin(kStageBwdWalk, st);
+      walk_bwd_launch<kTopK, FT>(s, L, ct, tu, g, want_f, ws, st);
+      prof.end(kStageBwdWalk, st);
     } else {
-      launch_fill_u32(ws + L.seldot, 0u, L.spix * (int64_t)L.k, st);
+      prof.begin(kStageBwdWalk, st);
+      walk_bwd_launch<kFull, FT>(s, L, ct, tu, g, want_f, ws, st);
+      prof.end(kStageBwdWalk, st);
     }
-    prof.end(kStageBwdFeature, st);
-    prof.begin(kStageBwdWalk, st);
-    hipLaunchKernelGGL((k_walk_bwd<kTopK, FT>), grid, dim3(256), 0, st, rec, pid, eid, ranges, c.W, c.H, (int)L.ntx,
-                       (int)L.tiles, L.k, (const uint32_t*)(ws + L.nlast), (const float*)(ws + L.tfinal),
-                       (const int32_t*)(ws + L.selpos), (const float*)(ws + L.seldot), g.rgb, g.depth, g.normal,
-                       g.alpha, g.feat, (const FT*)s.feat, s.c, gpart, gflag, fpart, fflag);
-    prof.end(kStageBwdWalk, st);
-  } else {
-    prof.begin(kStageBwdWalk, st);
-    hipLaunchKernelGGL((k_walk_bwd<kFull, FT>), grid, dim3(256), 0, st, rec, pid, eid, ranges, c.W, c.H, (int)L.ntx,
-                       (int)L.tiles, L.k, (const uint32_t*)(ws + L.nlast), (const float*)(ws + L.tfinal),
-                       (const int32_t*)(ws + L.selpos), (const float*)(ws + L.seldot), g.rgb, g.depth, g.normal,
-                       g.alpha, want_f ? g.feat : nullptr, (const FT*)s.feat, s.c, gpart, gflag, fpart, fflag);
-    prof.end(kStageBwdWalk, st);
   }
-  CamB cb;
-  for (int i = 0; i < 9; ++i) cb.R[i] = c.R[i];
-  for (int i = 0; i < 3; ++i) cb.t[i] = c.t[i];
-  cb.fx = c.fx; cb.fy = c.fy; cb.cx = c.cx; cb.cy = c.cy;
   prof.begin(kStageBwdPreprocess, st);
-  const uint32_t* order = (const uint32_t*)(ws + L.id0);
+  const uint32_t* vbase = (const uint32_t*)(ws + L.vbase);
   const uint32_t* count = (const uint32_t*)(ws + L.count);
-  const uint32_t* offs = (const uint32_t*)(ws + L.offs);
   if (s.n > 0) {
-    hipLaunchKernelGGL(k_reduce_geo, dim3((unsigned)cdiv(s.n, 256)), dim3(256), 0, st, s.n, order, count, offs,
-                       L.cap, (const float*)gpart, (const uint8_t*)gflag, s.means, s.scales, s.quats,
-                       (const int32_t*)(ws + L.cull), cb, gr.means, gr.scales, gr.quats, gr.opacity, gr.rgb);
+    hipLaunchKernelGGL(k_reduce_geo, dim3((unsigned)cdiv(s.n, 256)), dim3(256), 0, st, s.n, ct, vbase, count, L.cap,
+                       (const float*)(ws + L.gpart), (const uint8_t*)(ws + L.gflag), s.means, s.scales, s.quats,
+                       (const int32_t*)(ws + L.cull), gr.means, gr.scales, gr.quats, gr.opacity, gr.rgb);
     if (s.c > 0 && gr.feat) {
       const int lpp = s.c / 4;
       int lpp2 = 1;
       while (lpp2 < lpp && lpp2 < 64) lpp2 <<= 1;
       const int per_block = 4 * (64 / lpp2);
-      hipLaunchKernelGGL(k_reduce_feat, dim3((unsigned)cdiv(s.n, per_block)), dim3(256), 0, st, s.n, order, count,
-                         offs, L.cap, (const float*)fpart, (const uint8_t*)fflag, s.c, gr.feat);
+      hipLaunchKernelGGL(k_reduce_feat, dim3((unsigned)cdiv(s.n, per_block)), dim3(256), 0, st, s.n, ct.n, vbase,
+                         count, L.cap, (const float*)(ws + L.fpart), (const uint8_t*)(ws + L.fflag), s.c,
+                         gr.feat);
     }
   }
   prof.end(kStageBwdPreprocess, st);
 }
 
-void launch_backward(const SurfelArgs& s, const CamArgs& c, int blend, const Layout& L, const ImageGradArgs& g,
-                     const GradArgs& grads, char* ws, hipStream_t st, const ProfHook& prof) {
+void launch_backward(const SurfelArgs& s, const CamTable& ct, int blend, const Tuning& tu, const Layout& L,
+                     const ImageGradArgs& g, const GradArgs& grads, char* ws, hipStream_t st, const ProfHook& prof) {
   prof.begin(kStageFill, st);
   launch_fill_u32(ws + L.gflag, 0u, cdiv(std::max<int64_t>(L.cap, 1), 4), st);
   launch_fill_u32(ws + L.fflag, 0u, cdiv(std::max<int64_t>(L.cap, 1), 4), st);
+  launch_fill_u32((uint32_t*)(ws + L.status) + kStQueue + kQFeatBwd, 0u, 2, st);
   prof.end(kStageFill, st);
-  if (s.dtype == kF32) backward_typed<float>(s, c, blend, L, g, grads, ws, st, prof);
-  else if (s.dtype == kF16) backward_typed<__half>(s, c, blend, L, g, grads, ws, st, prof);
-  else backward_typed<uint16_t>(s, c, blend, L, g, grads, ws, st, prof);
+  if (s.dtype == kF32) backward_typed<float>(s, ct, blend, tu, L, g, grads, ws, st, prof);
+  else if (s.dtype == kF16) backward_typed<__half>(s, ct, blend, tu, L, g, grads, ws, st, prof);
+  else backward_typed<uint16_t>(s, ct, blend, tu, L, g, grads, ws, st, prof);
 }
 
 }  // namespace psm

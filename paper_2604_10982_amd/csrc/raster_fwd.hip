@@ -8,7 +8,7 @@
 //   per-pixel register heap of the K largest weights with their list
 //   positions.  A block stops when all of its pixels are done.
 // k_blend_topk: eq. (18) blend of the selected feature rows, thread per pixel.
-//   The tile's distinct selected rows are staged in LDS per pass of 32
+//   The tile's distinct selected rows are staged in LDS per pass of 16 or 32
 //   channels and read by slot; each pixel accumulates in ascending list
 //   position (front to back).
 // k_full_feat: the dense feature blend of eq. (1) (the baseline the paper
@@ -63,22 +63,25 @@ __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_a
 // Each wave walks its 64 pixels independently (no LDS, no barriers): the
 // tile's surfel ids and records are wave-uniform and come through the scalar
 // cache into SGPRs, one record ahead of the evaluation.
-template <int KMAX, bool TOPK>
-__global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, const uint32_t* __restrict__ pid,
-                                              const uint2* __restrict__ ranges, int W, int H, int ntx, int tiles,
+template <int KMAX, bool TOPK, bool PERSIST>
+__global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, const float4* __restrict__ ext,
+                                              const uint32_t* __restrict__ pid,
+                                              const uint2* __restrict__ ranges, CamTable ct, TileQueue tq,
                                               int K, float* __restrict__ o_rgb, float* __restrict__ o_depth,
                                               float* __restrict__ o_normal, float* __restrict__ o_alpha,
                                               uint32_t* __restrict__ nlast, float* __restrict__ tfinal,
                                               int32_t* __restrict__ selpos, float* __restrict__ selw,
                                               uint32_t* __restrict__ status) {
-  const int tile = xcd_tile(blockIdx.x, tiles);
-  if (tile >= tiles) return;
+  __shared__ int s_item;
+  for_tiles<PERSIST>(tq, &s_item, [&](const int tile) {
+  const TileLoc tl = locate(ct, tile);
   const int tid = threadIdx.x;
-  const int tx = tile % ntx, ty = tile / ntx;
+  const int tx = tl.tx, ty = tl.ty, W = tl.W, H = tl.H;
   const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
   const bool inside = px < W && py < H;
   const float lx = (float)(tid & 15) + 0.5f, ly = (float)(tid >> 4) + 0.5f;
   const double tx0 = (double)(tx * kTile), ty0 = (double)(ty * kTile);
+  const float yb0 = (float)(ty * kTile + 4 * (tid >> 6)) + 0.5f, yb1 = yb0 + 3.0f;  // this wave's rows
   const uint2 rg = ranges[tile];
   const int L = (int)(rg.y - rg.x);
   const uint32_t* ids = pid + rg.x;
@@ -98,15 +101,25 @@ __global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, c
 
   uint32_t id_next = L > 1 ? uniform_u32(ids[1]) : 0u;
   WalkRec r_next;
-  if (L > 0) r_next = rec[uniform_u32(ids[0])];
+  float4 x_next;
+  if (L > 0) {
+    const uint32_t id0 = uniform_u32(ids[0]);
+    r_next = rec[id0];
+    x_next = ext[id0];
+  }
   for (int j = 0; j < L; ++j) {
     if (__all(done)) break;
     const WalkRec r = r_next;
+    const float4 x = x_next;
     const uint32_t id_after = j + 2 < L ? uniform_u32(ids[j + 2]) : 0u;
-    if (j + 1 < L) r_next = rec[id_next];
+    if (j + 1 < L) {
+      r_next = rec[id_next];
+      x_next = ext[id_next];
+    }
     id_next = id_after;
     if (done) continue;
     ++walked;
+    if (!band_meets(x.y, x.w, yb0, yb1)) continue;
     const LRec s = fold_uniform(r, tx0, ty0);
     PixEval e;
     if (!eval_pixel(s, lx, ly, e)) continue;
@@ -164,7 +177,7 @@ __global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, c
     }
   }
   if (inside) {
-    const int64_t pix = (int64_t)py * W + px;
+    const int64_t pix = tl.pix0 + (int64_t)py * W + px;
     if (o_rgb) {
       o_rgb[3 * pix] = cr;
       o_rgb[3 * pix + 1] = cg;
@@ -193,34 +206,33 @@ __global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, c
       }
     }
   }
+  });
 }
 
 // ---------------------------------------------------------------- features
-constexpr int kBC = 32;           // feature channels per blend pass
-constexpr int kBRow = kBC + 4;    // LDS row stride (floats)
-
-// Stages channels [cc, cc + kBC) of the chunk's ns slot rows into s_F.
-template <typename FT>
+// Stages channels [cc, cc + BC) of the chunk's ns slot rows into s_F (row
+// stride BC + 4 floats).
+template <typename FT, int BC>
 __device__ __forceinline__ void stage_rows(float* s_F, const uint32_t* fid, int ns, const FT* __restrict__ feat,
                                            int C, int cc) {
-  for (int item = threadIdx.x; item < ns * (kBC / 4); item += 256) {
-    const int s = item / (kBC / 4), j = item % (kBC / 4), c = cc + 4 * j;
+  for (int item = threadIdx.x; item < ns * (BC / 4); item += 256) {
+    const int s = item / (BC / 4), j = item % (BC / 4), c = cc + 4 * j;
     const float4 f = c < C ? load4<FT>(feat + (size_t)fid[s] * C + c) : make_float4(0.f, 0.f, 0.f, 0.f);
-    *reinterpret_cast<float4*>(s_F + s * kBRow + 4 * j) = f;
+    *reinterpret_cast<float4*>(s_F + s * (BC + 4) + 4 * j) = f;
   }
 }
 
 // Adds the selections of this thread's pixel that fall in the staged chunk
 // (sl[q] = chunk slot or -1), in ascending list position.
-template <int KMAX>
+template <int KMAX, int BC>
 __device__ __forceinline__ void blend_chunk(const float* s_F, const int (&sl)[KMAX], const float (&w)[KMAX], int K,
-                                            float (&acc)[kBC]) {
+                                            float (&acc)[BC]) {
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) {
     if (q < K && sl[q] >= 0) {
-      const float* fr = s_F + sl[q] * kBRow;
+      const float* fr = s_F + sl[q] * (BC + 4);
 #pragma unroll
-      for (int c = 0; c < kBC; c += 4) {
+      for (int c = 0; c < BC; c += 4) {
         const float4 f = *reinterpret_cast<const float4*>(fr + c);
         acc[c] = fmaf(w[q], f.x, acc[c]);
         acc[c + 1] = fmaf(w[q], f.y, acc[c + 1]);
@@ -232,24 +244,25 @@ __device__ __forceinline__ void blend_chunk(const float* s_F, const int (&sl)[KM
 }
 
 // Thread per pixel; the tile's distinct selected rows are staged in LDS once
-// per channel pass and read by slot.
-template <typename FT, int KMAX>
+// per pass of BC channels and read by slot.
+template <typename FT, int KMAX, int BC, bool PERSIST>
 __global__ __launch_bounds__(256) void k_blend_topk(const uint32_t* __restrict__ pid, const uint2* __restrict__ ranges,
                                                     const int32_t* __restrict__ selpos,
                                                     const float* __restrict__ selw, const FT* __restrict__ feat,
-                                                    int C, int K, int W, int H, int ntx, int tiles,
+                                                    int C, int K, CamTable ct, TileQueue tq,
                                                     float* __restrict__ o_feat) {
   __shared__ SelShared S;
+  constexpr int kBRow = BC + 4;
   __shared__ __align__(16) float s_F[kSlotChunk * kBRow];
-  const int tile = xcd_tile(blockIdx.x, tiles);
-  if (tile >= tiles) return;
+  __shared__ int s_item;
+  for_tiles<PERSIST>(tq, &s_item, [&](const int tile) {
+  const TileLoc tl = locate(ct, tile);
   const int tid = threadIdx.x;
-  const int tx = tile % ntx, ty = tile / ntx;
-  const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
-  const bool inside = px < W && py < H;
+  const int px = tl.tx * kTile + (tid & 15), py = tl.ty * kTile + (tid >> 4);
+  const bool inside = px < tl.W && py < tl.H;
   const uint32_t start = ranges[tile].x;
   const size_t tbase = (size_t)tile * K * kTilePix;
-  float* out = o_feat + ((int64_t)py * W + px) * C;
+  float* out = o_feat + (tl.pix0 + (int64_t)py * tl.W + px) * C;
 
   int pos[KMAX];
   float w[KMAX];
@@ -275,18 +288,18 @@ __global__ __launch_bounds__(256) void k_blend_topk(const uint32_t* __restrict__
   if (cached) {
 #pragma unroll
     for (int q = 0; q < KMAX; ++q)
-      if (sl[q] >= 0) S.fid[sl[q]] = pid[start + pos[q]];
+      if (sl[q] >= 0) S.fid[sl[q]] = (uint32_t)(pid[start + pos[q]] - tl.v0);
   }
   __syncthreads();
 
-  for (int cc = 0; cc < C; cc += kBC) {
-    float acc[kBC];
+  for (int cc = 0; cc < C; cc += BC) {
+    float acc[BC];
 #pragma unroll
-    for (int c = 0; c < kBC; ++c) acc[c] = 0.0f;
+    for (int c = 0; c < BC; ++c) acc[c] = 0.0f;
     if (cached) {
-      stage_rows<FT>(s_F, S.fid, U, feat, C, cc);
+      stage_rows<FT, BC>(s_F, S.fid, U, feat, C, cc);
       __syncthreads();
-      blend_chunk<KMAX>(s_F, sl, w, K, acc);
+      blend_chunk<KMAX, BC>(s_F, sl, w, K, acc);
       __syncthreads();
     } else {
       for (int w0 = 0; w0 <= maxpos; w0 += kWinPos) {
@@ -299,45 +312,48 @@ __global__ __launch_bounds__(256) void k_blend_topk(const uint32_t* __restrict__
           for (int q = 0; q < KMAX; ++q) {
             const int s = q < K ? slot_of(S, pos[q], w0, nw) : -1;
             sq[q] = (s >= c0 && s < c0 + ns) ? s - c0 : -1;
-            if (sq[q] >= 0) S.fid[sq[q]] = pid[start + pos[q]];
+            if (sq[q] >= 0) S.fid[sq[q]] = (uint32_t)(pid[start + pos[q]] - tl.v0);
           }
           __syncthreads();
-          stage_rows<FT>(s_F, S.fid, ns, feat, C, cc);
+          stage_rows<FT, BC>(s_F, S.fid, ns, feat, C, cc);
           __syncthreads();
-          blend_chunk<KMAX>(s_F, sq, w, K, acc);
+          blend_chunk<KMAX, BC>(s_F, sq, w, K, acc);
           __syncthreads();
         }
       }
     }
     if (inside) {
 #pragma unroll
-      for (int c = 0; c < kBC; c += 4)
+      for (int c = 0; c < BC; c += 4)
         if (cc + c < C)
           *reinterpret_cast<float4*>(out + cc + c) = make_float4(acc[c], acc[c + 1], acc[c + 2], acc[c + 3]);
     }
   }
+  });
 }
 
 constexpr int kFullBatch = 64;
 
-template <typename FT, int CH>
+template <typename FT, int CH, bool PERSIST>
 __global__ __launch_bounds__(256) void k_full_feat(const WalkRec* __restrict__ rec, const uint32_t* __restrict__ pid,
                                                    const uint2* __restrict__ ranges, const FT* __restrict__ feat,
-                                                   int C, int W, int H, int ntx, int tiles,
+                                                   int C, CamTable ct, TileQueue tq,
                                                    const uint32_t* __restrict__ nlast, float* __restrict__ o_feat) {
   __shared__ Staged<kFullBatch> s_r;
   __shared__ float s_f[kFullBatch][CH];
   __shared__ uint32_t s_id[kFullBatch];
   __shared__ int s_lmax;
-  const int tile = xcd_tile(blockIdx.x, tiles);
-  if (tile >= tiles) return;
+  __shared__ int s_item;
+  for_tiles<PERSIST>(tq, &s_item, [&](const int tile) {
+  const TileLoc tl = locate(ct, tile);
   const int tid = threadIdx.x;
-  const int tx = tile % ntx, ty = tile / ntx;
+  const int tx = tl.tx, ty = tl.ty;
   const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
-  const bool inside = px < W && py < H;
+  const bool inside = px < tl.W && py < tl.H;
   const float lx = (float)(tid & 15) + 0.5f, ly = (float)(tid >> 4) + 0.5f;
   const uint32_t start = ranges[tile].x;
   const int my_last = (int)nlast[tile * kTilePix + tid];
+  __syncthreads();
   if (tid == 0) s_lmax = 0;
   __syncthreads();
   atomicMax(&s_lmax, my_last);
@@ -353,7 +369,7 @@ __global__ __launch_bounds__(256) void k_full_feat(const WalkRec* __restrict__ r
       __syncthreads();
       if (tid < nb) {
         const uint32_t id = pid[start + base + tid];
-        s_id[tid] = id;
+        s_id[tid] = (uint32_t)(id - tl.v0);
         s_r.put(tid, rec[id], (float)(tx * kTile), (float)(ty * kTile));
       }
       __syncthreads();
@@ -378,33 +394,34 @@ __global__ __launch_bounds__(256) void k_full_feat(const WalkRec* __restrict__ r
       }
     }
     if (inside) {
-      float* out = o_feat + ((int64_t)py * W + px) * C + c0;
+      float* out = o_feat + (tl.pix0 + (int64_t)py * tl.W + px) * C + c0;
       const int cn = min(CH, C - c0);
 #pragma unroll
       for (int c = 0; c < CH; c += 4)
         if (c < cn) *reinterpret_cast<float4*>(out + c) = make_float4(acc[c], acc[c + 1], acc[c + 2], acc[c + 3]);
     }
   }
+  });
 }
 
 __global__ __launch_bounds__(256) void k_export_sel(const uint32_t* __restrict__ pid, const uint2* __restrict__ ranges,
                                                     const int32_t* __restrict__ selpos,
                                                     const float* __restrict__ selw,
                                                     const uint32_t* __restrict__ nlast,
-                                                    const float* __restrict__ tfinal, int K, int W, int H, int ntx,
-                                                    int tiles, int32_t* __restrict__ o_id, float* __restrict__ o_w,
+                                                    const float* __restrict__ tfinal, int K, CamTable ct,
+                                                    int32_t* __restrict__ o_id, float* __restrict__ o_w,
                                                     int32_t* __restrict__ o_nlast, float* __restrict__ o_tf) {
   const int tile = blockIdx.x;
   const int tid = threadIdx.x;
-  const int tx = tile % ntx, ty = tile / ntx;
-  const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
-  if (px >= W || py >= H) return;
-  const int64_t pix = (int64_t)py * W + px;
+  const TileLoc tl = locate(ct, tile);
+  const int px = tl.tx * kTile + (tid & 15), py = tl.ty * kTile + (tid >> 4);
+  if (px >= tl.W || py >= tl.H) return;
+  const int64_t pix = tl.pix0 + (int64_t)py * tl.W + px;
   const uint32_t start = ranges[tile].x;
   for (int q = 0; q < K; ++q) {
     const size_t o = ((size_t)tile * K + q) * kTilePix + tid;
     const int pos = selpos ? selpos[o] : -1;
-    if (o_id) o_id[pix * K + q] = pos >= 0 ? (int32_t)pid[start + pos] : -1;
+    if (o_id) o_id[pix * K + q] = pos >= 0 ? (int32_t)(pid[start + pos] - tl.v0) : -1;
     if (o_w) o_w[pix * K + q] = pos >= 0 ? selw[o] : 0.0f;
   }
   if (o_nlast) o_nlast[pix] = (int32_t)nlast[tile * kTilePix + tid];
@@ -412,64 +429,98 @@ __global__ __launch_bounds__(256) void k_export_sel(const uint32_t* __restrict__
 }
 
 // ------------------------------------------------------------- host wrappers
-template <int KMAX, bool TOPK>
-static void walk_launch(const Layout& L, const CamArgs& c, const ImageArgs& out, char* ws, hipStream_t st) {
-  hipLaunchKernelGGL((k_walk<KMAX, TOPK>), dim3(xcd_grid(L.tiles)), dim3(256), 0, st, (const WalkRec*)(ws + L.rec),
-                     (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), c.W, c.H, (int)L.ntx,
-                     (int)L.tiles, L.k, out.rgb, out.depth, out.normal, out.alpha, (uint32_t*)(ws + L.nlast),
-                     (float*)(ws + L.tfinal), (int32_t*)(ws + L.selpos), (float*)(ws + L.selw),
-                     (uint32_t*)(ws + L.status));
+template <int KMAX, bool TOPK, bool PERSIST>
+static void walk_launch_t(const Layout& L, const CamTable& ct, const Tuning& tu, const ImageArgs& out, char* ws,
+                          hipStream_t st) {
+  const void* k = reinterpret_cast<const void*>(&k_walk<KMAX, TOPK, PERSIST>);
+  hipLaunchKernelGGL((k_walk<KMAX, TOPK, PERSIST>), dim3(tile_grid(L, tu, k, 0)), dim3(256), 0, st,
+                     (const WalkRec*)(ws + L.rec), (const float4*)(ws + L.ext), (const uint32_t*)(ws + L.pid),
+                     (const uint2*)(ws + L.ranges), ct, tile_queue(L, tu, ws, kQWalk), L.k, out.rgb, out.depth, out.normal, out.alpha,
+                     (uint32_t*)(ws + L.nlast), (float*)(ws + L.tfinal), (int32_t*)(ws + L.selpos),
+                     (float*)(ws + L.selw), (uint32_t*)(ws + L.status));
 }
 
-void launch_walk(const Layout& L, const CamArgs& c, int blend, const ImageArgs& out, char* ws, hipStream_t st) {
+template <int KMAX, bool TOPK>
+static void walk_launch(const Layout& L, const CamTable& ct, const Tuning& tu, const ImageArgs& out, char* ws,
+                        hipStream_t st) {
+  if (tu.sched == kSchedPersistent) walk_launch_t<KMAX, TOPK, true>(L, ct, tu, out, ws, st);
+  else walk_launch_t<KMAX, TOPK, false>(L, ct, tu, out, ws, st);
+}
+
+void launch_walk(const Layout& L, const CamTable& ct, int blend, const Tuning& tu, const ImageArgs& out, char* ws,
+                 hipStream_t st) {
+  if (L.tiles == 0) return;
   if (blend == kFull) {
-    walk_launch<1, false>(L, c, out, ws, st);
+    walk_launch<1, false>(L, ct, tu, out, ws, st);
   } else if (L.k <= 8) {
-    walk_launch<8, true>(L, c, out, ws, st);
+    walk_launch<8, true>(L, ct, tu, out, ws, st);
   } else if (L.k <= 16) {
-    walk_launch<16, true>(L, c, out, ws, st);
+    walk_launch<16, true>(L, ct, tu, out, ws, st);
   } else {
-    walk_launch<32, true>(L, c, out, ws, st);
+    walk_launch<32, true>(L, ct, tu, out, ws, st);
   }
 }
 
-template <typename FT, int KMAX>
-static void blend_topk_launch(const SurfelArgs& s, const Layout& L, const CamArgs& c, float* out_feat, char* ws,
-                              hipStream_t st) {
-  hipLaunchKernelGGL((k_blend_topk<FT, KMAX>), dim3(xcd_grid(L.tiles)), dim3(256), 0, st,
+template <typename FT, int KMAX, int BC, bool PERSIST>
+static void blend_topk_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
+                              float* out_feat, char* ws, hipStream_t st) {
+  const void* k = reinterpret_cast<const void*>(&k_blend_topk<FT, KMAX, BC, PERSIST>);
+  hipLaunchKernelGGL((k_blend_topk<FT, KMAX, BC, PERSIST>), dim3(tile_grid(L, tu, k, 0)), dim3(256), 0, st,
                      (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos),
-                     (const float*)(ws + L.selw), (const FT*)s.feat, s.c, L.k, c.W, c.H, (int)L.ntx, (int)L.tiles,
+                     (const float*)(ws + L.selw), (const FT*)s.feat, s.c, L.k, ct, tile_queue(L, tu, ws, kQBlend),
+                     out_feat);
+}
+
+template <typename FT, int BC>
+static void blend_topk_k(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu, float* out_feat,
+                         char* ws, hipStream_t st) {
+  const bool p = tu.sched == kSchedPersistent;
+  if (L.k <= 8)
+    (p ? blend_topk_launch<FT, 8, BC, true> : blend_topk_launch<FT, 8, BC, false>)(s, L, ct, tu, out_feat, ws, st);
+  else if (L.k <= 16)
+    (p ? blend_topk_launch<FT, 16, BC, true> : blend_topk_launch<FT, 16, BC, false>)(s, L, ct, tu, out_feat, ws, st);
+  else
+    (p ? blend_topk_launch<FT, 32, BC, true> : blend_topk_launch<FT, 32, BC, false>)(s, L, ct, tu, out_feat, ws, st);
+}
+
+template <typename FT, bool PERSIST>
+static void full_feat_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
+                             float* out_feat, char* ws, hipStream_t st) {
+  const void* k = reinterpret_cast<const void*>(&k_full_feat<FT, 64, PERSIST>);
+  hipLaunchKernelGGL((k_full_feat<FT, 64, PERSIST>), dim3(tile_grid(L, tu, k, 0)), dim3(256), 0, st,
+                     (const WalkRec*)(ws + L.rec), (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges),
+                     (const FT*)s.feat, s.c, ct, tile_queue(L, tu, ws, kQBlend), (const uint32_t*)(ws + L.nlast),
                      out_feat);
 }
 
 template <typename FT>
-static void blend_launch(const SurfelArgs& s, const Layout& L, const CamArgs& c, int blend, float* out_feat,
-                         char* ws, hipStream_t st) {
+static void blend_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, int blend, const Tuning& tu,
+                         float* out_feat, char* ws, hipStream_t st) {
   if (blend == kTopK) {
-    if (L.k <= 8) blend_topk_launch<FT, 8>(s, L, c, out_feat, ws, st);
-    else if (L.k <= 16) blend_topk_launch<FT, 16>(s, L, c, out_feat, ws, st);
-    else blend_topk_launch<FT, 32>(s, L, c, out_feat, ws, st);
+    if (tu.blend_pass == 16) blend_topk_k<FT, 16>(s, L, ct, tu, out_feat, ws, st);
+    else blend_topk_k<FT, 32>(s, L, ct, tu, out_feat, ws, st);
+  } else if (tu.sched == kSchedPersistent) {
+    full_feat_launch<FT, true>(s, L, ct, tu, out_feat, ws, st);
   } else {
-    hipLaunchKernelGGL((k_full_feat<FT, 64>), dim3(xcd_grid(L.tiles)), dim3(256), 0, st, (const WalkRec*)(ws + L.rec),
-                       (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), (const FT*)s.feat, s.c, c.W,
-                       c.H, (int)L.ntx, (int)L.tiles, (const uint32_t*)(ws + L.nlast), out_feat);
+    full_feat_launch<FT, false>(s, L, ct, tu, out_feat, ws, st);
   }
 }
 
-void launch_feature_blend(const SurfelArgs& s, const Layout& L, const CamArgs& c, int blend, float* out_feat,
-                          char* ws, hipStream_t st) {
-  if (!out_feat || s.c <= 0) return;
-  if (s.dtype == kF32) blend_launch<float>(s, L, c, blend, out_feat, ws, st);
-  else if (s.dtype == kF16) blend_launch<__half>(s, L, c, blend, out_feat, ws, st);
-  else blend_launch<uint16_t>(s, L, c, blend, out_feat, ws, st);
+void launch_feature_blend(const SurfelArgs& s, const Layout& L, const CamTable& ct, int blend, const Tuning& tu,
+                          float* out_feat, char* ws, hipStream_t st) {
+  if (!out_feat || s.c <= 0 || L.tiles == 0) return;
+  if (s.dtype == kF32) blend_launch<float>(s, L, ct, blend, tu, out_feat, ws, st);
+  else if (s.dtype == kF16) blend_launch<__half>(s, L, ct, blend, tu, out_feat, ws, st);
+  else blend_launch<uint16_t>(s, L, ct, blend, tu, out_feat, ws, st);
 }
 
-void launch_export_selection(const Layout& L, const CamArgs& c, char* ws, int32_t* sel_id, float* sel_w,
+void launch_export_selection(const Layout& L, const CamTable& ct, char* ws, int32_t* sel_id, float* sel_w,
                              int32_t* n_last, float* t_final, hipStream_t st) {
+  if (L.tiles == 0) return;
   hipLaunchKernelGGL(k_export_sel, dim3((unsigned)L.tiles), dim3(256), 0, st, (const uint32_t*)(ws + L.pid),
                      (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos), (const float*)(ws + L.selw),
-                     (const uint32_t*)(ws + L.nlast), (const float*)(ws + L.tfinal), L.k, c.W, c.H, (int)L.ntx,
-                     (int)L.tiles, sel_id, sel_w, n_last, t_final);
+                     (const uint32_t*)(ws + L.nlast), (const float*)(ws + L.tfinal), L.k, ct, sel_id, sel_w, n_last,
+                     t_final);
 }
 
 }  // namespace psm

@@ -7,6 +7,7 @@ fallback: if libpsm.so is missing or the device is not usable, calls raise.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import math
 import os
 from dataclasses import dataclass
@@ -23,11 +24,14 @@ DTYPES = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2}
 FLAG_NO_SYNC = 1
 FLAG_PROFILE = 2
 NUM_STAGES = 12
+SCHED_GRID, SCHED_PERSISTENT = 0, 1
+MAX_CAMERAS = 8
 
 # Every symbol include/psm.h declares.
 EXPORTS = ("psm_create", "psm_destroy", "psm_workspace_size", "psm_forward", "psm_backward",
            "psm_read_stats", "psm_read_pairs", "psm_read_selection", "psm_profile_read", "psm_profile_reset",
-           "psm_last_error", "psm_version")
+           "psm_last_error", "psm_version", "psm_workspace_size_batch", "psm_forward_batch", "psm_backward_batch",
+           "psm_read_stats_batch", "psm_read_pairs_batch", "psm_read_selection_batch", "psm_autotune")
 
 
 class PsmError(RuntimeError):
@@ -53,7 +57,9 @@ class Camera(C.Structure):
 
 
 class Config(C.Structure):
-    _fields_ = [("k", C.c_int32), ("tile_mode", C.c_int32), ("blend", C.c_int32), ("flags", C.c_int32)]
+    _fields_ = [("k", C.c_int32), ("tile_mode", C.c_int32), ("blend", C.c_int32), ("flags", C.c_int32),
+                ("schedule", C.c_int32), ("blend_pass", C.c_int32), ("bwd_pass", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Images(C.Structure):
@@ -99,6 +105,18 @@ def lib():
                                      vp, vp, vp, C.POINTER(i64), vp]
         L.psm_read_selection.argtypes = [vp, vp, i64, C.POINTER(Camera), C.POINTER(Config), i32, i64, vp, vp,
                                          vp, vp, vp]
+        CamP, CfgP = C.POINTER(Camera), C.POINTER(Config)
+        L.psm_workspace_size_batch.argtypes = [i64, CamP, i32, CfgP, i32, i64, C.POINTER(C.c_size_t)]
+        L.psm_forward_batch.argtypes = [vp, C.POINTER(Surfels), CamP, i32, CfgP, vp, C.c_size_t, i64,
+                                        C.POINTER(Images), vp]
+        L.psm_backward_batch.argtypes = [vp, C.POINTER(Surfels), CamP, i32, CfgP, vp, C.c_size_t, i64,
+                                         C.POINTER(ImageGrads), C.POINTER(Grads), vp]
+        L.psm_read_stats_batch.argtypes = [vp, vp, i64, CamP, i32, CfgP, i32, i64, C.POINTER(Stats), vp]
+        L.psm_read_pairs_batch.argtypes = [vp, vp, i64, CamP, i32, CfgP, i32, i64, vp, vp, i64, vp, vp, vp,
+                                           C.POINTER(i64), vp]
+        L.psm_read_selection_batch.argtypes = [vp, vp, i64, CamP, i32, CfgP, i32, i64, vp, vp, vp, vp, vp]
+        L.psm_autotune.argtypes = [vp, C.POINTER(Surfels), CamP, i32, CfgP, vp, C.c_size_t, i64, C.POINTER(Images),
+                                   C.POINTER(ImageGrads), C.POINTER(Grads), i32, C.POINTER(C.c_double), vp]
         L.psm_profile_read.argtypes = [vp, i32, C.POINTER(C.c_char_p), C.POINTER(C.c_double), C.POINTER(i64)]
         L.psm_profile_reset.argtypes = [vp]
         L.psm_last_error.restype = C.c_char_p
@@ -155,10 +173,11 @@ def camera_struct(cam) -> Camera:
     return c
 
 
-def config_struct(k: int, tile_mode="ellipse", blend="topk", flags: int = 0) -> Config:
+def config_struct(k: int, tile_mode="ellipse", blend="topk", flags: int = 0, schedule: int = SCHED_GRID,
+                  blend_pass: int = 0, bwd_pass: int = 0) -> Config:
     tm = TILE_MODES[tile_mode] if isinstance(tile_mode, str) else int(tile_mode)
     bl = BLENDS[blend] if isinstance(blend, str) else int(blend)
-    return Config(int(k), tm, bl, int(flags))
+    return Config(int(k), tm, bl, int(flags), int(schedule), int(blend_pass), int(bwd_pass), 0)
 
 
 def _ptr(t):
@@ -340,3 +359,202 @@ def profile_reset(ctx: Context):
 
 def version() -> str:
     return lib().psm_version().decode()
+
+
+# ------------------------------------------------------------ camera batches
+def camera_array(cams) -> C.Array:
+    """ctypes array of Camera from scenes.Camera objects (or Camera structs)."""
+    arr = (Camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = c if isinstance(c, Camera) else camera_struct(c)
+    return arr
+
+
+def _cam_ptr(cams: C.Array):
+    return C.cast(cams, C.POINTER(Camera))
+
+
+def workspace_size_batch(n: int, cams: C.Array, cfg: Config, c: int, capacity: int) -> int:
+    out = C.c_size_t()
+    _check(lib().psm_workspace_size_batch(n, _cam_ptr(cams), len(cams), C.byref(cfg), c, capacity, C.byref(out)),
+           "psm_workspace_size_batch")
+    return int(out.value)
+
+
+def alloc_workspace_batch(n, cams: C.Array, cfg: Config, c: int, capacity: int, device) -> Workspace:
+    nbytes = workspace_size_batch(n, cams, cfg, c, capacity)
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return Workspace(buf[off:off + nbytes], capacity, n, c, cfg.k)
+
+
+def total_pixels(cams: C.Array) -> int:
+    return sum(int(c.width) * int(c.height) for c in cams)
+
+
+def alloc_images_batch(cams: C.Array, c: int, device) -> dict:
+    """Concatenated maps of all cameras: (sum W*H, channels)."""
+    P = total_pixels(cams)
+    e = lambda *s: torch.empty(*s, dtype=torch.float32, device=device)
+    return {"rgb": e(P, 3), "depth": e(P), "normal": e(P, 3), "alpha": e(P), "feat": e(P, c) if c > 0 else None}
+
+
+def split_images(maps: dict, cams: C.Array) -> list:
+    """Per-camera (H, W, ...) views of concatenated maps."""
+    out, p = [], 0
+    for cam in cams:
+        H, W = int(cam.height), int(cam.width)
+        out.append({k: None if v is None else v[p:p + H * W].reshape(H, W, *v.shape[1:]) for k, v in maps.items()})
+        p += H * W
+    return out
+
+
+def capacity_guess_batch(n: int, cams: C.Array) -> int:
+    return int(min(2**31 - 1, sum(capacity_guess(n, c) for c in cams)))
+
+
+def forward_batch_into(ctx: Context, s: Surfels, cams: C.Array, cfg: Config, ws: Workspace, out: dict,
+                       stream=None):
+    imgs = Images(*(_ptr(out.get(k)) for k in ("rgb", "depth", "normal", "alpha", "feat")))
+    st = stream if stream is not None else _stream(ctx.device)
+    _check(lib().psm_forward_batch(ctx.handle, C.byref(s), _cam_ptr(cams), len(cams), C.byref(cfg), _ptr(ws.buf),
+                                   ws.nbytes, ws.capacity, C.byref(imgs), st), "psm_forward_batch")
+
+
+def backward_batch_into(ctx: Context, s: Surfels, cams: C.Array, cfg: Config, ws: Workspace, gout: dict,
+                        grads: dict, stream=None):
+    g = ImageGrads(*(_ptr(gout.get(k)) for k in ("rgb", "depth", "normal", "alpha", "feat")))
+    gr = Grads(*(_ptr(grads.get(k)) for k in ("means", "scales", "quats", "opacity", "rgb", "feat")))
+    st = stream if stream is not None else _stream(ctx.device)
+    _check(lib().psm_backward_batch(ctx.handle, C.byref(s), _cam_ptr(cams), len(cams), C.byref(cfg),
+                                    _ptr(ws.buf), ws.nbytes, ws.capacity, C.byref(g), C.byref(gr), st),
+           "psm_backward_batch")
+
+
+def read_stats_batch(ws: Workspace, cams: C.Array, cfg: Config) -> Stats:
+    ctx = context(ws.buf.device.index or 0)
+    st = Stats()
+    _check(lib().psm_read_stats_batch(ctx.handle, _ptr(ws.buf), ws.n, _cam_ptr(cams), len(cams), C.byref(cfg),
+                                      ws.c, ws.capacity, C.byref(st), _stream(ctx.device)), "psm_read_stats_batch")
+    return st
+
+
+def forward_batch(means, scales, quats, opacity, rgb, feat, cams, k=16, tile_mode="ellipse", blend="topk",
+                  cfg: Config | None = None, capacity: int | None = None, ws: Workspace | None = None):
+    """Render several cameras in one call; returns (concatenated maps, workspace, camera array)."""
+    device = means.device
+    ctx = context(device.index or 0)
+    s = _surfels(means, scales, quats, opacity, rgb, feat)
+    cams = cams if isinstance(cams, C.Array) else camera_array(cams)
+    cfg = cfg if cfg is not None else config_struct(k, tile_mode, blend)
+    out = alloc_images_batch(cams, s.c, device)
+    cap = capacity if capacity is not None else (ws.capacity if ws is not None else capacity_guess_batch(s.n, cams))
+    for attempt in range(3):
+        if ws is None or ws.capacity < cap or ws.n != s.n or ws.c != s.c or ws.k != cfg.k:
+            ws = alloc_workspace_batch(s.n, cams, cfg, s.c, cap, device)
+        try:
+            forward_batch_into(ctx, s, cams, cfg, ws, out)
+            return out, ws, cams
+        except CapacityError:
+            st = read_stats_batch(ws, cams, cfg)
+            cap = int(min(2**31 - 1, st.pairs_required * 1.15 + 1024))
+            ws = None
+    raise RuntimeError("pair capacity could not be satisfied")
+
+
+def backward_batch(means, scales, quats, opacity, rgb, feat, cams: C.Array, ws: Workspace, gout: dict,
+                   cfg: Config) -> dict:
+    device = means.device
+    ctx = context(device.index or 0)
+    s = _surfels(means, scales, quats, opacity, rgb, feat)
+    n = s.n
+    z = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=device)
+    grads = {"means": z(n, 3), "scales": z(n, 2), "quats": z(n, 4), "opacity": z(n), "rgb": z(n, 3),
+             "feat": z(n, s.c) if s.c > 0 else None}
+    gout = {kk: (None if v is None else v.contiguous().float()) for kk, v in gout.items()}
+    backward_batch_into(ctx, s, cams, cfg, ws, gout, grads)
+    return grads
+
+
+def read_pairs_batch(ws: Workspace, cams: C.Array, cfg: Config) -> dict:
+    """Sorted pair list (global tile ids, virtual surfel ids b * n + i) and
+    per-virtual-surfel key-stage results, as CPU tensors."""
+    ctx = context(ws.buf.device.index or 0)
+    dev = ws.buf.device
+    st = read_stats_batch(ws, cams, cfg)
+    P = int(st.pairs)
+    nv = ws.n * len(cams)
+    tile = torch.empty(max(P, 1), dtype=torch.int32, device=dev)
+    ids = torch.empty(max(P, 1), dtype=torch.int32, device=dev)
+    cull = torch.empty(max(nv, 1), dtype=torch.int32, device=dev)
+    depth = torch.empty(max(nv, 1), dtype=torch.int32, device=dev)
+    count = torch.empty(max(nv, 1), dtype=torch.int32, device=dev)
+    got = C.c_int64()
+    _check(lib().psm_read_pairs_batch(ctx.handle, _ptr(ws.buf), ws.n, _cam_ptr(cams), len(cams), C.byref(cfg),
+                                      ws.c, ws.capacity, _ptr(tile), _ptr(ids), P, _ptr(cull), _ptr(depth),
+                                      _ptr(count), C.byref(got), _stream(ctx.device)), "psm_read_pairs_batch")
+    return {"P": int(got.value), "tile": tile[:P].cpu(), "id": ids[:P].cpu(), "cull": cull[:nv].cpu(),
+            "depth_bits": depth[:nv].cpu(), "count": count[:nv].cpu(), "stats": st}
+
+
+def read_selection_batch(ws: Workspace, cams: C.Array, cfg: Config) -> dict:
+    ctx = context(ws.buf.device.index or 0)
+    dev = ws.buf.device
+    P, K = total_pixels(cams), cfg.k
+    sid = torch.empty(P, K, dtype=torch.int32, device=dev)
+    sw = torch.empty(P, K, dtype=torch.float32, device=dev)
+    nl = torch.empty(P, dtype=torch.int32, device=dev)
+    tf = torch.empty(P, dtype=torch.float32, device=dev)
+    _check(lib().psm_read_selection_batch(ctx.handle, _ptr(ws.buf), ws.n, _cam_ptr(cams), len(cams),
+                                          C.byref(cfg), ws.c, ws.capacity, _ptr(sid), _ptr(sw), _ptr(nl), _ptr(tf),
+                                          _stream(ctx.device)), "psm_read_selection_batch")
+    return {"sel_id": sid, "sel_w": sw, "n_last": nl, "T_final": tf}
+
+
+# ---------------------------------------------------------------- autotuner
+def tune_cache_path() -> str:
+    return os.environ.get("PSM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "psm", "tune.json"))
+
+
+def _tune_key(s: Surfels, cams, cfg: Config, bwd: bool) -> str:
+    dims = ",".join(f"{int(c.width)}x{int(c.height)}" for c in cams)
+    return f"n={s.n};c={s.c};dt={s.feat_dtype};k={cfg.k};tm={cfg.tile_mode};bl={cfg.blend};bwd={int(bwd)};cams={dims}"
+
+
+def autotune(ctx: Context, s: Surfels, cams: C.Array, cfg: Config, ws: Workspace, out: dict,
+             gout: dict | None = None, grads: dict | None = None, reps: int = 3, cache: bool = True) -> float | None:
+    """Pick the launch choices for these shapes (the library times the
+    candidates) and write them into cfg.  Choices persist in a JSON file
+    (PSM_TUNE_CACHE); returns the best time in ms, or None on a cache hit."""
+    bwd = grads is not None
+    key = _tune_key(s, cams, cfg, bwd)
+    path = tune_cache_path()
+    table = {}
+    if cache and os.path.exists(path):
+        try:
+            with open(path) as f:
+                table = json.load(f)
+        except (OSError, ValueError):
+            table = {}
+    if cache and key in table:
+        cfg.schedule, cfg.blend_pass, cfg.bwd_pass = (int(v) for v in table[key])
+        return None
+    imgs = Images(*(_ptr(out.get(k)) for k in ("rgb", "depth", "normal", "alpha", "feat")))
+    g = ImageGrads(*(_ptr((gout or {}).get(k)) for k in ("rgb", "depth", "normal", "alpha", "feat")))
+    gr = Grads(*(_ptr((grads or {}).get(k)) for k in ("means", "scales", "quats", "opacity", "rgb", "feat")))
+    best = C.c_double()
+    _check(lib().psm_autotune(ctx.handle, C.byref(s), _cam_ptr(cams), len(cams), C.byref(cfg), _ptr(ws.buf),
+                              ws.nbytes, ws.capacity, C.byref(imgs), C.byref(g) if bwd else None,
+                              C.byref(gr) if bwd else None, int(reps), C.byref(best), _stream(ctx.device)),
+           "psm_autotune")
+    if cache:
+        table[key] = [int(cfg.schedule), int(cfg.blend_pass), int(cfg.bwd_pass)]
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            tmp = path + f".tmp{os.getpid()}"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, path)
+        except OSError:
+            pass
+    return float(best.value)

@@ -27,7 +27,7 @@ import numpy as np
 
 __all__ = [
     "Camera", "Scene", "pinhole", "uniform_box", "planes7", "street40",
-    "room6", "upstream", "config", "CONFIGS",
+    "room6", "upstream", "config", "CONFIGS", "street_cameras", "batch_config", "BATCH_RES",
 ]
 
 
@@ -305,6 +305,33 @@ CONFIGS = {
     "planes1m_1080p": ("planes7", 1_000_000, 128, 1920, 1080, None, 16, "f32"),
     "room_1296x968": ("room6", 400_000, 128, 1296, 968, None, 16, "f32"),
 }
+
+
+# Camera rig of the batched workload: 8 cameras of uneven resolution.
+BATCH_RES = ((640, 480), (800, 600), (1024, 768), (1280, 720), (1280, 960), (1600, 900),
+             (1920, 1080), (1920, 1080))
+
+
+def street_cameras(res=BATCH_RES, near: float = 0.2) -> list:
+    """Camera k at (+-2 m alternating, 0, 20 k m) looking down the street with
+    yaw +-10 deg alternating; focal length 0.75 W."""
+    cams = []
+    for k, (w, h) in enumerate(res):
+        x = 2.0 if k % 2 == 0 else -2.0
+        a = math.radians(10.0 if k % 2 == 0 else -10.0)
+        centre = np.array([x, 0.0, 20.0 * k])
+        to_world = np.array([[math.cos(a), 0.0, math.sin(a)], [0.0, 1.0, 0.0], [-math.sin(a), 0.0, math.cos(a)]])
+        R = to_world.T
+        cams.append(pinhole(w, h, None, near, R, -R @ centre))
+    return cams
+
+
+def batch_config(seed: int = 0, n: int | None = None, k: int = 16):
+    """(scene, cameras, K, feature dtype) of the batched workload: a shared
+    2M-surfel street scene, 128-d FP16 features, 8 cameras."""
+    scene = street40(2_000_000 if n is None else n, 128, seed)
+    scene.meta["config"] = "c5_street2m_8cam"
+    return scene, street_cameras(), k, "f16"
 
 
 def config(name: str, seed: int = 0, n: int | None = None):

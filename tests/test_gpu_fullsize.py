@@ -91,3 +91,51 @@ def test_fullsize_sampled_gradients(orc):
     ref = {k: v[pick] for k, v in ref.items()}
     worst = grad_errors(got, ref)
     assert max(worst.values()) <= 1e-3, worst
+
+
+@pytest.mark.parametrize("K", [8, 16, 32])
+def test_fullsize_batch_8cam(orc, K):
+    """The batched workload at full size (shared 2M-surfel street, 8 cameras
+    640x480 .. 1920x1080, 128-d FP16 features) in the launch configuration the
+    benchmark times: per-camera pair lists bit-exact, sampled pixels of every
+    camera within tolerance, the Top-K selection exact."""
+    require_gpu()
+    sc, cams, _, dtype = scenes.batch_config(k=K)
+    print(f"[fullsize] batch: n={sc.n} cams={len(cams)} C={sc.c} K={K} {dtype}", flush=True)
+    t = to_dev(sc, dtype)
+    cfg = psm.config_struct(K, "ellipse", "topk")
+    out, ws, carr = psm.forward_batch(t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"],
+                                      cams, K, cfg=cfg)
+    torch.cuda.synchronize()
+    if K == 16:
+        got = psm.read_pairs_batch(ws, carr, cfg)
+        tile = got["tile"].numpy().astype(np.int64)
+        ids = got["id"].numpy().astype(np.int64)
+        t0 = 0
+        for b, cam in enumerate(cams):
+            ntiles = ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
+            m = (tile >= t0) & (tile < t0 + ntiles)
+            ref_k = orc.keystage(sc, cam, "ellipse")
+            np.testing.assert_array_equal(tile[m] - t0, ref_k["tile"])
+            np.testing.assert_array_equal(ids[m] - b * sc.n, ref_k["id"])
+            t0 += ntiles
+        del got, tile, ids
+    per = psm.split_images(out, carr)
+    sel = psm.read_selection_batch(ws, carr, cfg)
+    feat = stored_feat(t)
+    rng = np.random.default_rng(K)
+    p0 = 0
+    for b, cam in enumerate(cams):
+        pix = _sample_pixels(cam, rng, n=400, tiles=1)
+        ref = orc.render(sc, cam, K, orc.TOPK, feat=feat, pix=pix)
+        absf = orc.render(sc, cam, K, orc.TOPK, feat=np.abs(feat), pix=pix)["feat"]
+        g = np_out(per[b])
+        flat = {k: v.reshape(cam.width * cam.height, -1)[pix] for k, v in g.items()}
+        ok = decided(ref)
+        assert (~ok).mean() < 1e-2
+        worst = image_errors(flat, ref, absf, ok, 1e-5)
+        assert max(worst.values()) <= 1.0, (b, worst)
+        hw = cam.width * cam.height
+        sid = sel["sel_id"][p0:p0 + hw].cpu().numpy()[pix]
+        np.testing.assert_array_equal(sid[ok], ref["sel_id"][ok])
+        p0 += hw

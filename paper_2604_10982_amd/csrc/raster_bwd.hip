@@ -47,6 +47,7 @@ __global__ __launch_bounds__(256) void k_feat_bwd_topk(
   __shared__ __align__(16) float s_G[kTilePix * kGRow];
   __shared__ __align__(16) float s_F[kSlotChunk * kGRow];
   __shared__ uint32_t s_mask[kSlotChunk * 8];  // pixels selecting each slot
+  __shared__ uint16_t s_mpre[kSlotChunk * 8];  // selecting pixels in the slot's earlier mask words
   __shared__ uint32_t s_off[kSlotChunk + 1];   // entry offsets per slot
   __shared__ uint32_t s_fe[kSlotChunk];        // emitted pair index per slot
   extern __shared__ __align__(16) char smem[];
@@ -95,8 +96,13 @@ __global__ __launch_bounds__(256) void k_feat_bwd_topk(
       }
       __syncthreads();
       uint32_t cnt = 0;
-      if (tid < ns)
-        for (int wd = 0; wd < 8; ++wd) cnt += (uint32_t)__popc(s_mask[tid * 8 + wd]);
+      if (tid < ns) {
+#pragma unroll
+        for (int wd = 0; wd < 8; ++wd) {
+          s_mpre[tid * 8 + wd] = (uint16_t)cnt;
+          cnt += (uint32_t)__popc(s_mask[tid * 8 + wd]);
+        }
+      }
       uint32_t tot;
       const uint32_t off = block_scan_excl(cnt, S.red, tot);
       if (tid < ns) {
@@ -109,9 +115,8 @@ __global__ __launch_bounds__(256) void k_feat_bwd_topk(
 #pragma unroll
       for (int q = 0; q < KMAX; ++q) {
         if (sl[q] >= 0) {
-          const uint32_t* m = s_mask + sl[q] * 8;
-          uint32_t rank = (uint32_t)__popc(m[tid >> 5] & ((1u << (tid & 31)) - 1u));
-          for (int wd = 0; wd < (tid >> 5); ++wd) rank += (uint32_t)__popc(m[wd]);
+          const int mw = sl[q] * 8 + (tid >> 5);
+          const uint32_t rank = (uint32_t)s_mpre[mw] + (uint32_t)__popc(s_mask[mw] & ((1u << (tid & 31)) - 1u));
           const uint32_t e = s_off[sl[q]] + rank;
           s_lw[e] = w[q];
           s_lp[e] = (uint8_t)tid;
@@ -578,13 +583,20 @@ __global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, CamTable ct, cons
     for (int j = 0; j < 16; ++j) G[j] = 0.0;
     const int64_t base = vbase[v];
     const int64_t end = min(base + (int64_t)count[v], cap);
-    for (int64_t slot = base; slot < end; ++slot) {
-      if (!gflag[slot]) continue;
-      const float4* g = reinterpret_cast<const float4*>(gpart + (size_t)slot * 16);
+    for (int64_t s0 = base; s0 < end; s0 += 8) {
+      // 8 flags in flight, then the flagged pairs' partials (emission order)
+      uint32_t f = 0;
 #pragma unroll
-      for (int qd = 0; qd < 4; ++qd) {
-        const float4 t = g[qd];
-        G[4 * qd] += t.x; G[4 * qd + 1] += t.y; G[4 * qd + 2] += t.z; G[4 * qd + 3] += t.w;
+      for (int u = 0; u < 8; ++u) f |= (s0 + u < end && gflag[s0 + u]) ? (1u << u) : 0u;
+      while (f) {
+        const int u = __ffs(f) - 1;
+        f &= f - 1u;
+        const float4* g = reinterpret_cast<const float4*>(gpart + (size_t)(s0 + u) * 16);
+#pragma unroll
+        for (int qd = 0; qd < 4; ++qd) {
+          const float4 t = g[qd];
+          G[4 * qd] += t.x; G[4 * qd + 1] += t.y; G[4 * qd + 2] += t.z; G[4 * qd + 3] += t.w;
+        }
       }
     }
     chain_rule(G, ct.cam[b], ((cv >> 8) & 1) != 0, mu, su, sv, qn, Rq, acc);
@@ -613,20 +625,37 @@ __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const 
   const int sub = lane / lpp2, cl = lane % lpp2;
   const int64_t i = ((int64_t)blockIdx.x * 4 + wave) * spw + sub;
   if (i >= n) return;
-  for (int cg = cl; cg < lpp; cg += lpp2) {
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int b = 0; b < ncam; ++b) {
-      const int64_t v = (int64_t)b * n + i;
-      const int64_t base = vbase[v];
-      const int64_t end = min(base + (int64_t)count[v], cap);
-      for (int64_t slot = base; slot < end; ++slot) {
-        if (!fflag[slot]) continue;
-        const float4 t = *reinterpret_cast<const float4*>(fpart + (size_t)slot * C + cg * 4);
-        acc.x += t.x; acc.y += t.y; acc.z += t.z; acc.w += t.w;
+  constexpr int kMaxGroups = 4;  // C <= 1024: at most 4 channel groups of 4 per lane
+  float4 acc[kMaxGroups];
+#pragma unroll
+  for (int j = 0; j < kMaxGroups; ++j) acc[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+  const int ng = (lpp + lpp2 - 1) / lpp2;  // channel groups of this lane
+  const uint64_t gmask = lpp2 == 64 ? ~0ull : ((1ull << lpp2) - 1ull);
+  for (int b = 0; b < ncam; ++b) {
+    const int64_t v = (int64_t)b * n + i;
+    const int64_t base = vbase[v];
+    const int64_t end = min(base + (int64_t)count[v], cap);
+    for (int64_t s0 = base; s0 < end; s0 += lpp2) {
+      // the group's lanes test lpp2 flags at once; flagged rows in emission order
+      const bool fl = s0 + cl < end && fflag[s0 + cl];
+      uint64_t m = (__ballot(fl) >> (sub * lpp2)) & gmask;
+      while (m) {
+        const int u = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1ull;
+        const float* row = fpart + (size_t)(s0 + u) * C;
+#pragma unroll
+        for (int j = 0; j < kMaxGroups; ++j) {
+          if (j < ng && cl + j * lpp2 < lpp) {
+            const float4 t = *reinterpret_cast<const float4*>(row + (cl + j * lpp2) * 4);
+            acc[j].x += t.x; acc[j].y += t.y; acc[j].z += t.z; acc[j].w += t.w;
+          }
+        }
       }
     }
-    *reinterpret_cast<float4*>(dfeat + (size_t)i * C + cg * 4) = acc;
   }
+#pragma unroll
+  for (int j = 0; j < kMaxGroups; ++j)
+    if (j < ng && cl + j * lpp2 < lpp) *reinterpret_cast<float4*>(dfeat + (size_t)i * C + (cl + j * lpp2) * 4) = acc[j];
 }
 
 // ------------------------------------------------------------- host wrappers

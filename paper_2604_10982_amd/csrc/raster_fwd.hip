@@ -45,24 +45,21 @@ __device__ __forceinline__ void sort_by_position(int (&p)[N], float (&w)[N]) {
   }
 }
 
-// Tile-local record from a surfel record held in scalar registers: every lane
-// of a wave evaluates the same surfel, so the record is wave-uniform.
-__device__ __forceinline__ LRec fold_uniform(const WalkRec& r, double tx0, double ty0) {
-  LRec s;
-  s.a00 = r.d0.x; s.a01 = r.d0.y; s.a10 = r.d1.x; s.a11 = r.d1.y;
-  s.e0 = r.d2.x; s.e1 = r.d2.y;
-  s.ox = tx0 - r.d3.x;
-  s.oy = ty0 - r.d3.y;
-  s.mz = r.f0.x; s.o = r.f0.y; s.r = r.f0.z; s.g = r.f0.w;
-  s.b = r.f1.x; s.n0 = r.f1.y; s.n1 = r.f1.z; s.n2 = r.f1.w;
-  return s;
+constexpr int kWalkChunk = 64;  // list entries a wave examines at once
+
+// LDS ordering between the lanes of one wave (no block barrier involved).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// Each wave walks its 64 pixels independently (no LDS, no barriers): the
-// tile's surfel ids and records are wave-uniform and come through the scalar
-// cache into SGPRs, one record ahead of the evaluation.
+// Each wave walks its 64 pixels (a 16x4 band of the tile) on its own, with no
+// block barriers: per chunk of 64 list entries every lane tests one entry's
+// footprint against the band (one vector gather of the extent records and a
+// ballot), the kept entries' records are staged, compacted, in the wave's LDS
+// slice by parallel vector loads, and the wave then evaluates them in list
+// order with broadcast reads.
 template <int KMAX, bool TOPK, bool PERSIST>
 __global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, const float4* __restrict__ ext,
                                               const uint32_t* __restrict__ pid,
@@ -72,22 +69,26 @@ __global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, c
                                               uint32_t* __restrict__ nlast, float* __restrict__ tfinal,
                                               int32_t* __restrict__ selpos, float* __restrict__ selw,
                                               uint32_t* __restrict__ status) {
+  __shared__ Staged<kWalkChunk> s_rec[4];
+  __shared__ int s_pos[4][kWalkChunk];
   __shared__ int s_item;
   for_tiles<PERSIST>(tq, &s_item, [&](const int tile) {
   const TileLoc tl = locate(ct, tile);
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tx = tl.tx, ty = tl.ty, W = tl.W, H = tl.H;
   const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
   const bool inside = px < W && py < H;
   const float lx = (float)(tid & 15) + 0.5f, ly = (float)(tid >> 4) + 0.5f;
-  const double tx0 = (double)(tx * kTile), ty0 = (double)(ty * kTile);
-  const float yb0 = (float)(ty * kTile + 4 * (tid >> 6)) + 0.5f, yb1 = yb0 + 3.0f;  // this wave's rows
+  const float tx0 = (float)(tx * kTile), ty0 = (float)(ty * kTile);
+  const float yb0 = ty0 + (float)(4 * wave) + 0.5f, yb1 = yb0 + 3.0f;  // this wave's rows
   const uint2 rg = ranges[tile];
   const int L = (int)(rg.y - rg.x);
   const uint32_t* ids = pid + rg.x;
+  Staged<kWalkChunk>& S = s_rec[wave];
+  int* spos = s_pos[wave];
 
   float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f, nx = 0.f, ny = 0.f, nz = 0.f;
-  int last = 0, walked = 0, blended = 0;
+  int last = 0, blended = 0, stop = -1;
   bool done = !inside;
   float hw[KMAX];
   int hp[KMAX];
@@ -99,67 +100,73 @@ __global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, c
   float hmin = -1.0f;
   int imin = 0, pmin = -1;
 
-  uint32_t id_next = L > 1 ? uniform_u32(ids[1]) : 0u;
-  WalkRec r_next;
-  float4 x_next;
-  if (L > 0) {
-    const uint32_t id0 = uniform_u32(ids[0]);
-    r_next = rec[id0];
-    x_next = ext[id0];
-  }
-  for (int j = 0; j < L; ++j) {
+  for (int base = 0; base < L; base += kWalkChunk) {
     if (__all(done)) break;
-    const WalkRec r = r_next;
-    const float4 x = x_next;
-    const uint32_t id_after = j + 2 < L ? uniform_u32(ids[j + 2]) : 0u;
-    if (j + 1 < L) {
-      r_next = rec[id_next];
-      x_next = ext[id_next];
+    const int j = base + lane;
+    uint32_t id = 0;
+    bool keep = false;
+    if (j < L) {
+      id = ids[j];
+      const float4 x = ext[id];
+      keep = band_meets(x.y, x.w, yb0, yb1);
     }
-    id_next = id_after;
-    if (done) continue;
-    ++walked;
-    if (!band_meets(x.y, x.w, yb0, yb1)) continue;
-    const LRec s = fold_uniform(r, tx0, ty0);
-    PixEval e;
-    if (!eval_pixel(s, lx, ly, e)) continue;
-    const float Tn = T * (1.0f - e.alpha);
-    if (Tn < kTMin) {
-      done = true;
-      continue;
+    const uint64_t mask = __ballot(keep);
+    const int nk = __popcll(mask);
+    wave_lds_sync();  // the previous chunk's reads are done
+    if (keep) {
+      const int slot = __popcll(mask & ((1ull << lane) - 1ull));
+      S.put(slot, rec[id], tx0, ty0);
+      spos[slot] = j;
     }
-    const float w = e.alpha * T;
-    cr = fmaf(w, s.r, cr);
-    cg = fmaf(w, s.g, cg);
-    cb = fmaf(w, s.b, cb);
-    dep = fmaf(w, s.mz * e.iw, dep);
-    nx = fmaf(w, s.n0, nx);
-    ny = fmaf(w, s.n1, ny);
-    nz = fmaf(w, s.n2, nz);
-    T = Tn;
-    ++blended;
-    last = j + 1;
-    if (TOPK && w > hmin) {
-      // replace the current minimum, then find the new minimum under the
-      // order (weight descending, position ascending)
-#pragma unroll
-      for (int q = 0; q < KMAX; ++q) {
-        const bool hit = q == imin;
-        hw[q] = hit ? w : hw[q];
-        hp[q] = hit ? j : hp[q];
+    wave_lds_sync();
+    for (int k = 0; k < nk; ++k) {
+      if (__all(done)) break;
+      if (done) continue;
+      const int pos = spos[k];
+      const LRec s = S.get(k);
+      PixEval e;
+      if (!eval_pixel(s, lx, ly, e)) continue;
+      const float Tn = T * (1.0f - e.alpha);
+      if (Tn < kTMin) {
+        done = true;
+        stop = pos;
+        continue;
       }
-      hmin = hw[0];
-      pmin = hp[0];
-      imin = 0;
+      const float w = e.alpha * T;
+      cr = fmaf(w, s.r, cr);
+      cg = fmaf(w, s.g, cg);
+      cb = fmaf(w, s.b, cb);
+      dep = fmaf(w, s.mz * e.iw, dep);
+      nx = fmaf(w, s.n0, nx);
+      ny = fmaf(w, s.n1, ny);
+      nz = fmaf(w, s.n2, nz);
+      T = Tn;
+      ++blended;
+      last = pos + 1;
+      if (TOPK && w > hmin) {
+        // replace the current minimum, then find the new minimum under the
+        // order (weight descending, position ascending)
 #pragma unroll
-      for (int q = 1; q < KMAX; ++q) {
-        const bool lt = hw[q] < hmin || (hw[q] == hmin && hp[q] > pmin);
-        hmin = lt ? hw[q] : hmin;
-        pmin = lt ? hp[q] : pmin;
-        imin = lt ? q : imin;
+        for (int q = 0; q < KMAX; ++q) {
+          const bool hit = q == imin;
+          hw[q] = hit ? w : hw[q];
+          hp[q] = hit ? pos : hp[q];
+        }
+        hmin = hw[0];
+        pmin = hp[0];
+        imin = 0;
+#pragma unroll
+        for (int q = 1; q < KMAX; ++q) {
+          const bool lt = hw[q] < hmin || (hw[q] == hmin && hp[q] > pmin);
+          hmin = lt ? hw[q] : hmin;
+          pmin = lt ? hp[q] : pmin;
+          imin = lt ? q : imin;
+        }
       }
     }
   }
+  // list entries this pixel walked: up to and including its stop, or all
+  const int walked = !inside ? 0 : (stop >= 0 ? stop + 1 : L);
 
   const int sp = tile * kTilePix + tid;
   nlast[sp] = (uint32_t)last;

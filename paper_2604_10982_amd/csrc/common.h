@@ -309,28 +309,56 @@ __device__ __forceinline__ void for_tiles(const TileQueue& q, int* s_item, F&& b
 }
 
 // ------------------------------------------------------------ wave helpers
+// Cross-lane exchanges without LDS: v_permlane32_swap / v_permlane16_swap
+// (gfx950) exchange halves of the wave / of 32-lane halves between two
+// registers, DPP row operations pair lanes inside a 16-lane row.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+constexpr int kDppRowRor8 = 0x128;      // lane l <- lane l ^ 8 within a row
+constexpr int kDppRowHalfMirror = 0x141;  // lane l <- lane 7 - l within 8 lanes
+constexpr int kDppXor2 = 0x4E;          // quad_perm [2,3,0,1]
+constexpr int kDppXor1 = 0xB1;          // quad_perm [1,0,3,2]
+
+// x + x(lane ^ 32) (first) and y + y(lane ^ 32) (second), for the lanes whose
+// bit 5 selects x (lanes 0-31) or y (lanes 32-63).
+__device__ __forceinline__ float swap32_add(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_add(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = swap32_add(v, v);
+  v = swap16_add(v, v);
+  v += dpp_mov<kDppRowRor8>(v);
+  v += dpp_mov<kDppRowHalfMirror>(v);
+  v += dpp_mov<kDppXor2>(v);
+  v += dpp_mov<kDppXor1>(v);
   return v;
 }
 
-// Sums 16 per-lane values over the wave with 17 exchanges instead of 96:
-// each step halves the number of values a lane carries.  Lane l returns the
-// wave total of value index (l >> 2) & 15.
+// Sums 16 per-lane values over the wave: each step halves the number of
+// values a lane carries (16 -> 8 -> 4 -> 2 -> 1), pairing lanes that differ in
+// lane bit 5, 4, 3, 2; then two in-quad steps.  Lane l returns the wave total
+// of value index (l >> 2) & 15.
 __device__ __forceinline__ float wave_reduce16(const float (&v)[16]) {
   const int lane = threadIdx.x & 63;
   float a[8], b[4], c[2];
-  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) a[i] = (b5 ? v[8 + i] : v[i]) + __shfl_xor(b5 ? v[i] : v[8 + i], 32, 64);
+  for (int i = 0; i < 8; ++i) a[i] = swap32_add(v[i], v[8 + i]);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) b[i] = (b4 ? a[4 + i] : a[i]) + __shfl_xor(b4 ? a[i] : a[4 + i], 16, 64);
+  for (int i = 0; i < 4; ++i) b[i] = swap16_add(a[i], a[4 + i]);
+  const bool b3 = lane & 8, b2 = lane & 4;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) c[i] = (b3 ? b[2 + i] : b[i]) + __shfl_xor(b3 ? b[i] : b[2 + i], 8, 64);
-  float d = (b2 ? c[1] : c[0]) + __shfl_xor(b2 ? c[0] : c[1], 4, 64);
-  d += __shfl_xor(d, 2, 64);
-  d += __shfl_xor(d, 1, 64);
+  for (int i = 0; i < 2; ++i) c[i] = (b3 ? b[2 + i] : b[i]) + dpp_mov<kDppRowRor8>(b3 ? b[i] : b[2 + i]);
+  float d = (b2 ? c[1] : c[0]) + dpp_mov<kDppRowHalfMirror>(b2 ? c[0] : c[1]);
+  d += dpp_mov<kDppXor2>(d);
+  d += dpp_mov<kDppXor1>(d);
   return d;
 }
 

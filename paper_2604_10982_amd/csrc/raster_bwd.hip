@@ -65,12 +65,11 @@ __global__ __launch_bounds__(256) void k_feat_bwd_topk(
   const float* grow = gfeat + (tl.pix0 + (int64_t)py * tl.W + px) * C;
 
   int pos[KMAX];
-  float w[KMAX], dot[KMAX];
+  float dot[KMAX];
   int mymax = -1;
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) {
     pos[q] = q < K ? selpos[tbase + (size_t)q * kTilePix + tid] : -1;
-    w[q] = q < K ? selw[tbase + (size_t)q * kTilePix + tid] : 0.0f;
     dot[q] = 0.0f;
     mymax = max(mymax, pos[q]);
   }
@@ -90,8 +89,7 @@ __global__ __launch_bounds__(256) void k_feat_bwd_topk(
         sl[q] = (s >= c0 && s < c0 + ns) ? s - c0 : -1;
         if (sl[q] >= 0) {
           atomicOr(&s_mask[sl[q] * 8 + (tid >> 5)], 1u << (tid & 31));
-          S.fid[sl[q]] = (uint32_t)(pid[start + pos[q]] - tl.v0);
-          S.lpos[sl[q]] = (uint32_t)pos[q];
+          S.lpos[sl[q]] = (uint32_t)pos[q];  // same value from every selecting pixel
         }
       }
       __syncthreads();
@@ -107,7 +105,9 @@ __global__ __launch_bounds__(256) void k_feat_bwd_topk(
       const uint32_t off = block_scan_excl(cnt, S.red, tot);
       if (tid < ns) {
         s_off[tid] = off;
-        s_fe[tid] = eid[start + S.lpos[tid]];
+        const uint32_t j = start + S.lpos[tid];
+        s_fe[tid] = eid[j];
+        S.fid[tid] = (uint32_t)(pid[j] - tl.v0);
       }
       if (tid == 0) s_off[ns] = tot;
       __syncthreads();
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_feat_bwd_topk(
           const int mw = sl[q] * 8 + (tid >> 5);
           const uint32_t rank = (uint32_t)s_mpre[mw] + (uint32_t)__popc(s_mask[mw] & ((1u << (tid & 31)) - 1u));
           const uint32_t e = s_off[sl[q]] + rank;
-          s_lw[e] = w[q];
+          s_lw[e] = selw[tbase + (size_t)q * kTilePix + tid];
           s_lp[e] = (uint8_t)tid;
         }
       }

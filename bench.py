@@ -273,6 +273,47 @@ def batch_workload(psm, scenes, steps, warmup):
             "pairs": int(st.pairs), "stages_ms": stages}
 
 
+def labels_workload(psm, means, steps, warmup, nq=64, c=32):
+    """Instance labels of the headline scene's surfels from nq localized
+    queries (c-d FP32 instance features): forward (MFMA logits + softmax) and
+    backward, timed with HIP events on the stream."""
+    import numpy as np
+    import torch
+    device = means.device
+    n = means.shape[0]
+    rng = np.random.default_rng(3)
+    f_ins = torch.tensor((rng.standard_normal((n, c)) * 3.0 / np.sqrt(c)).astype(np.float32), device=device)
+    q_feat = torch.tensor((rng.standard_normal((nq, c)) * 3.0 / np.sqrt(c)).astype(np.float32), device=device)
+    q_mean = torch.tensor(np.c_[rng.uniform(-12, 12, nq), rng.uniform(-6, 1.6, nq), rng.uniform(2, 60, nq)]
+                          .astype(np.float32), device=device)
+    prec = np.tile(np.array([0.25, 0, 0, 0.25, 0, 0.25], np.float32), (nq, 1))
+    q_prec = torch.tensor(prec, device=device)
+    ld = psm.label_width(nq)
+    out = torch.empty(n, ld, device=device)
+    dl = torch.randn(n, ld, device=device)
+    fwd = lambda: psm.instance_labels_into(means, f_ins, q_feat, q_mean, q_prec, out, ld)
+    bwd = lambda: psm.instance_labels_backward(means, f_ins, q_feat, q_mean, q_prec, dl, ld)
+    res = {}
+    for name, fn in (("fwd", fwd), ("bwd", bwd)):
+        for _ in range(warmup):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name + "_ms"] = e0.elapsed_time(e1) / steps
+    bytes_fwd = n * (12 + 4 * c + 4 * ld)
+    flops_fwd = 2.0 * n * nq * c
+    res.update({"surfels": n, "queries": nq, "feat_dim": c,
+                "fwd_hbm_gbs": bytes_fwd / (res["fwd_ms"] * 1e-3) / 1e9, "fwd_hbm_frac": bytes_fwd / (res["fwd_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "fwd_mfma_tflops": flops_fwd / (res["fwd_ms"] * 1e-3) / 1e12,
+                "note": "labels (eqs. (4)-(7)) of every surfel; bytes = means + features in + labels out"})
+    return res
+
+
 def cpu_baseline(sc, cam, K, feat64, tiles):
     """The FP64 oracle (test infrastructure) on a bounded sample of the same
     frame: forward + backward of the pixels of `tiles` random 16x16 tiles.
@@ -398,6 +439,9 @@ def main():
         feat64 = t["feat"].float().cpu().numpy().astype(np.float64)
         line["cpu_baseline"] = cpu_baseline(sc, cam, K, feat64, args.cpu_tiles)
         print(f"[bench] cpu baseline {line['cpu_baseline']['value']:.4f} it/s", file=sys.stderr, flush=True)
+    line["instance_labels"] = labels_workload(psm, t["means"], max(3, args.steps // 2), 2)
+    print(f"[bench] labels fwd {line['instance_labels']['fwd_ms']:.3f} ms, bwd {line['instance_labels']['bwd_ms']:.3f} ms",
+          file=sys.stderr, flush=True)
     if not args.no_batch:
         del t, gout
         torch.cuda.empty_cache()

@@ -251,6 +251,43 @@ psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
                         psm_images* out, const psm_image_grads* grad_out, psm_grads* grads, int32_t reps,
                         double* best_ms_out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Instance labels of surfels from localized queries (Sec. 4.1, eqs. (4)-(7)).
+ * For surfel g (centre p_g = means[g], instance feature f_g) and query q
+ * (feature f_q, Gaussian with mean mu_q and precision P_q = Sigma_q^-1):
+ *   A(q, g) = sigmoid(f_q . f_g) * exp(-(p_g - mu_q)^T P_q (p_g - mu_q) / 2)
+ *   labels(g) = softmax over the queries of A(., g).
+ * The rendered instance map, eq. (8), is the feature blend of the labels: write
+ * them into columns of the feature array passed to psm_forward (e.g. after the
+ * semantic channels) and one walk with one Top-K selection renders both.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n_q;         /* queries, 1..256 */
+  int32_t c;           /* instance feature dim, 4..512, multiple of 4 */
+  const float* feat;   /* [n_q][c] query features f_q */
+  const float* mean;   /* [n_q][3] query centres mu_q */
+  const float* prec;   /* [n_q][6] query precisions (xx, xy, xz, yy, yz, zz) */
+} psm_queries;
+
+/* labels: FP32 [n][ld] (device); columns 0 .. n_q-1 receive the labels,
+ * columns n_q .. round_up(n_q, 8)-1 zeros, other columns are untouched.
+ * ld >= round_up(n_q, 8).  f_ins: [n][c] in f_dtype (psm_dtype). */
+psm_status psm_instance_labels(psm_ctx* ctx, int64_t n, const float* means, const void* f_ins, int32_t f_dtype,
+                               const psm_queries* q, float* labels, int32_t ld, void* stream);
+
+/* Device workspace (bytes, 256-aligned) of psm_instance_labels_backward. */
+psm_status psm_instance_labels_workspace_size(int64_t n, const psm_queries* q, size_t* bytes_out);
+
+/* Gradients of L = sum(d_labels * labels) (d_labels FP32 [n][ld], columns
+ * 0 .. n_q-1 read).  Writes (overwrites) d_means [n][3], d_f_ins [n][c] (FP32
+ * for every storage dtype), d_qfeat [n_q][c], d_qmean [n_q][3], d_qprec
+ * [n_q][6] (with respect to the 6 numbers: an off-diagonal number appears twice
+ * in the matrix).  Deterministic. */
+psm_status psm_instance_labels_backward(psm_ctx* ctx, int64_t n, const float* means, const void* f_ins,
+                                        int32_t f_dtype, const psm_queries* q, const float* d_labels, int32_t ld,
+                                        void* workspace, size_t workspace_bytes, float* d_means, float* d_f_ins,
+                                        float* d_qfeat, float* d_qmean, float* d_qprec, void* stream);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* psm_last_error(void);
 

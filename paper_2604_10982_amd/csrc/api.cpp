@@ -630,6 +630,75 @@ psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
   return PSM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+psm_status validate_queries(int64_t n, const psm_queries* q, int32_t f_dtype) {
+  if (!q) return fail(PSM_ERR_INVALID_ARG, "queries are required");
+  if (n < 0 || n > 0x7FFFFFFFLL) return fail(PSM_ERR_INVALID_ARG, "n must be in [0, 2^31)");
+  if (q->n_q < 1 || q->n_q > 256) return fail(PSM_ERR_INVALID_ARG, "n_q must be in [1, 256]");
+  if (q->c < 4 || q->c > 512 || q->c % 4 != 0) return fail(PSM_ERR_INVALID_ARG, "c must be in [4, 512], c % 4 == 0");
+  if (f_dtype < 0 || f_dtype > 2) return fail(PSM_ERR_INVALID_ARG, "bad f_dtype");
+  if (!q->feat || !q->mean || !q->prec) return fail(PSM_ERR_INVALID_ARG, "null query array");
+  return PSM_OK;
+}
+
+LabelQueries label_queries(const psm_queries* q) { return LabelQueries{q->n_q, q->c, q->feat, q->mean, q->prec}; }
+
+}  // namespace
+
+extern "C" {
+
+psm_status psm_instance_labels(psm_ctx* ctx, int64_t n, const float* means, const void* f_ins, int32_t f_dtype,
+                               const psm_queries* q, float* labels, int32_t ld, void* stream) {
+  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+  psm_status r = validate_queries(n, q, f_dtype);
+  if (r != PSM_OK) return r;
+  if (ld < ((q->n_q + 7) & ~7)) return fail(PSM_ERR_INVALID_ARG, "ld must be >= round_up(n_q, 8)");
+  if (n > 0 && (!means || !f_ins || !labels)) return fail(PSM_ERR_INVALID_ARG, "null surfel or label array");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
+  launch_labels(n, means, f_ins, f_dtype, label_queries(q), labels, ld, (hipStream_t)stream);
+  r = check_hip("psm_instance_labels launch");
+  if (r != PSM_OK) return r;
+  g_err.clear();
+  return PSM_OK;
+}
+
+psm_status psm_instance_labels_workspace_size(int64_t n, const psm_queries* q, size_t* bytes_out) {
+  if (!bytes_out) return fail(PSM_ERR_INVALID_ARG, "bytes_out is null");
+  psm_status r = validate_queries(n, q, 0);
+  if (r != PSM_OK) return r;
+  *bytes_out = label_workspace_bytes(n, q->n_q, q->c);
+  return PSM_OK;
+}
+
+psm_status psm_instance_labels_backward(psm_ctx* ctx, int64_t n, const float* means, const void* f_ins,
+                                        int32_t f_dtype, const psm_queries* q, const float* d_labels, int32_t ld,
+                                        void* workspace, size_t workspace_bytes, float* d_means, float* d_f_ins,
+                                        float* d_qfeat, float* d_qmean, float* d_qprec, void* stream) {
+  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+  psm_status r = validate_queries(n, q, f_dtype);
+  if (r != PSM_OK) return r;
+  if (ld < ((q->n_q + 7) & ~7)) return fail(PSM_ERR_INVALID_ARG, "ld must be >= round_up(n_q, 8)");
+  if (n > 0 && (!means || !f_ins || !d_labels || !d_means || !d_f_ins))
+    return fail(PSM_ERR_INVALID_ARG, "null surfel-side array");
+  if (!d_qfeat || !d_qmean || !d_qprec) return fail(PSM_ERR_INVALID_ARG, "null query gradient array");
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(PSM_ERR_INVALID_ARG, "workspace must be non-null and 256-byte aligned");
+  if (workspace_bytes < label_workspace_bytes(n, q->n_q, q->c))
+    return fail(PSM_ERR_INVALID_ARG, "workspace too small");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
+  launch_labels_backward(n, means, f_ins, f_dtype, label_queries(q), d_labels, ld, (char*)workspace, d_means,
+                         d_f_ins, d_qfeat, d_qmean, d_qprec, (hipStream_t)stream);
+  r = check_hip("psm_instance_labels_backward launch");
+  if (r != PSM_OK) return r;
+  g_err.clear();
+  return PSM_OK;
+}
+
 psm_status psm_profile_read(psm_ctx* ctx, int32_t stage, const char** name_out, double* total_ms_out,
                             int64_t* calls_out) {
   if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");

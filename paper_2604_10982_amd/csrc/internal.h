@@ -89,6 +89,25 @@ void launch_feature_blend(const SurfelArgs& s, const Layout& L, const CamTable& 
 void launch_export_selection(const Layout& L, const CamTable& ct, char* ws, int32_t* sel_id, float* sel_w,
                              int32_t* n_last, float* t_final, hipStream_t st);
 
+// labels.hip: instance labels of surfels from localized queries
+struct LabelQueries {
+  int nq, c;
+  const float *feat, *mean, *prec;  // [nq][c], [nq][3], [nq][6]
+};
+inline int pow2_ge_host(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+int label_blocks16(int nq);
+int64_t label_segments(int64_t n);
+size_t label_workspace_bytes(int64_t n, int nq, int c);
+void launch_labels(int64_t n, const float* means, const void* fg, int dtype, const LabelQueries& q, float* out,
+                   int ld, hipStream_t st);
+void launch_labels_backward(int64_t n, const float* means, const void* fg, int dtype, const LabelQueries& q,
+                            const float* dl, int ld, char* ws, float* d_means, float* d_fg, float* d_qfeat,
+                            float* d_qmean, float* d_qprec, hipStream_t st);
+
 // raster_bwd.hip
 void launch_backward(const SurfelArgs& s, const CamTable& ct, int blend, const Tuning& tu, const Layout& L,
                      const ImageGradArgs& g, const GradArgs& grads, char* ws, hipStream_t st, const ProfHook& prof);

@@ -31,7 +31,8 @@ MAX_CAMERAS = 8
 EXPORTS = ("psm_create", "psm_destroy", "psm_workspace_size", "psm_forward", "psm_backward",
            "psm_read_stats", "psm_read_pairs", "psm_read_selection", "psm_profile_read", "psm_profile_reset",
            "psm_last_error", "psm_version", "psm_workspace_size_batch", "psm_forward_batch", "psm_backward_batch",
-           "psm_read_stats_batch", "psm_read_pairs_batch", "psm_read_selection_batch", "psm_autotune")
+           "psm_read_stats_batch", "psm_read_pairs_batch", "psm_read_selection_batch", "psm_autotune",
+           "psm_instance_labels", "psm_instance_labels_workspace_size", "psm_instance_labels_backward")
 
 
 class PsmError(RuntimeError):
@@ -60,6 +61,11 @@ class Config(C.Structure):
     _fields_ = [("k", C.c_int32), ("tile_mode", C.c_int32), ("blend", C.c_int32), ("flags", C.c_int32),
                 ("schedule", C.c_int32), ("blend_pass", C.c_int32), ("bwd_pass", C.c_int32),
                 ("reserved", C.c_int32)]
+
+
+class Queries(C.Structure):
+    _fields_ = [("n_q", C.c_int32), ("c", C.c_int32), ("feat", C.c_void_p), ("mean", C.c_void_p),
+                ("prec", C.c_void_p)]
 
 
 class Images(C.Structure):
@@ -117,6 +123,11 @@ def lib():
         L.psm_read_selection_batch.argtypes = [vp, vp, i64, CamP, i32, CfgP, i32, i64, vp, vp, vp, vp, vp]
         L.psm_autotune.argtypes = [vp, C.POINTER(Surfels), CamP, i32, CfgP, vp, C.c_size_t, i64, C.POINTER(Images),
                                    C.POINTER(ImageGrads), C.POINTER(Grads), i32, C.POINTER(C.c_double), vp]
+        QP = C.POINTER(Queries)
+        L.psm_instance_labels.argtypes = [vp, i64, vp, vp, i32, QP, vp, i32, vp]
+        L.psm_instance_labels_workspace_size.argtypes = [i64, QP, C.POINTER(C.c_size_t)]
+        L.psm_instance_labels_backward.argtypes = [vp, i64, vp, vp, i32, QP, vp, i32, vp, C.c_size_t, vp, vp, vp,
+                                                   vp, vp, vp]
         L.psm_profile_read.argtypes = [vp, i32, C.POINTER(C.c_char_p), C.POINTER(C.c_double), C.POINTER(i64)]
         L.psm_profile_reset.argtypes = [vp]
         L.psm_last_error.restype = C.c_char_p
@@ -558,3 +569,65 @@ def autotune(ctx: Context, s: Surfels, cams: C.Array, cfg: Config, ws: Workspace
         except OSError:
             pass
     return float(best.value)
+
+
+# ------------------------------------------------------------ instance labels
+def label_width(n_q: int) -> int:
+    """Feature columns the labels of n_q queries occupy (n_q rounded up to 8)."""
+    return (int(n_q) + 7) // 8 * 8
+
+
+def _queries(q_feat, q_mean, q_prec) -> Queries:
+    nq = q_feat.shape[0]
+    for name, t, w in (("q_feat", q_feat, q_feat.shape[1]), ("q_mean", q_mean, 3), ("q_prec", q_prec, 6)):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (nq, w):
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor of shape ({nq}, {w})")
+    return Queries(int(nq), int(q_feat.shape[1]), q_feat.data_ptr(), q_mean.data_ptr(), q_prec.data_ptr())
+
+
+def _check_surfel_side(means, f_ins):
+    n = means.shape[0]
+    if means.dtype != torch.float32 or not means.is_cuda or not means.is_contiguous() or tuple(means.shape) != (n, 3):
+        raise ValueError("means must be a contiguous float32 CUDA tensor of shape (n, 3)")
+    if f_ins.dtype not in DTYPES or not f_ins.is_cuda or not f_ins.is_contiguous() or f_ins.shape[0] != n:
+        raise ValueError("f_ins must be a contiguous (n, c) float32/float16/bfloat16 CUDA tensor")
+
+
+def instance_labels_into(means, f_ins, q_feat, q_mean, q_prec, out: torch.Tensor, ld: int, stream=None):
+    """Labels into out (FP32, row stride ld; out may be a column slice of a
+    larger feature array whose row stride is ld)."""
+    _check_surfel_side(means, f_ins)
+    q = _queries(q_feat, q_mean, q_prec)
+    ctx = context(means.device.index or 0)
+    st = stream if stream is not None else _stream(ctx.device)
+    _check(lib().psm_instance_labels(ctx.handle, means.shape[0], _ptr(means), _ptr(f_ins), DTYPES[f_ins.dtype],
+                                     C.byref(q), C.c_void_p(out.data_ptr()), int(ld), st), "psm_instance_labels")
+
+
+def instance_labels(means, f_ins, q_feat, q_mean, q_prec) -> torch.Tensor:
+    """(n, label_width(n_q)) FP32 labels; columns >= n_q are zero."""
+    out = torch.empty(means.shape[0], label_width(q_feat.shape[0]), dtype=torch.float32, device=means.device)
+    instance_labels_into(means, f_ins, q_feat, q_mean, q_prec, out, out.shape[1])
+    return out
+
+
+def instance_labels_backward(means, f_ins, q_feat, q_mean, q_prec, d_labels: torch.Tensor, ld: int) -> dict:
+    _check_surfel_side(means, f_ins)
+    q = _queries(q_feat, q_mean, q_prec)
+    ctx = context(means.device.index or 0)
+    dev = means.device
+    ws_bytes = C.c_size_t()
+    _check(lib().psm_instance_labels_workspace_size(means.shape[0], C.byref(q), C.byref(ws_bytes)),
+           "psm_instance_labels_workspace_size")
+    buf = torch.empty(int(ws_bytes.value) + 256, dtype=torch.uint8, device=dev)
+    off = (-buf.data_ptr()) % 256
+    ws = buf[off:off + int(ws_bytes.value)]
+    n, nq, c = means.shape[0], q_feat.shape[0], q_feat.shape[1]
+    z = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=dev)
+    g = {"means": z(n, 3), "f_ins": z(n, c), "q_feat": z(nq, c), "q_mean": z(nq, 3), "q_prec": z(nq, 6)}
+    _check(lib().psm_instance_labels_backward(ctx.handle, n, _ptr(means), _ptr(f_ins), DTYPES[f_ins.dtype],
+                                              C.byref(q), C.c_void_p(d_labels.data_ptr()), int(ld), _ptr(ws),
+                                              ws.numel(), _ptr(g["means"]), _ptr(g["f_ins"]), _ptr(g["q_feat"]),
+                                              _ptr(g["q_mean"]), _ptr(g["q_prec"]), _stream(ctx.device)),
+           "psm_instance_labels_backward")
+    return g

@@ -40,3 +40,46 @@ def render(means, scales, quats, opacity, rgb, feat, camera, k: int = 16, tile_m
     blended over the K largest weights per pixel (blend="topk") or over every
     contributor (blend="full")."""
     return RasterizeSurfels.apply(means, scales, quats, opacity, rgb, feat, camera, k, tile_mode, blend)
+
+
+class InstanceLabels(torch.autograd.Function):
+    """Labels of surfels from localized queries (Sec. 4.1, eqs. (4)-(7)); the
+    forward and the backward run in the library's kernels."""
+
+    @staticmethod
+    def forward(ctx, means, f_ins, q_feat, q_mean, q_prec):
+        lab = psm.instance_labels(means, f_ins, q_feat, q_mean, q_prec)
+        ctx.save_for_backward(means, f_ins, q_feat, q_mean, q_prec)
+        return lab[:, :q_feat.shape[0]]
+
+    @staticmethod
+    def backward(ctx, g):
+        means, f_ins, q_feat, q_mean, q_prec = ctx.saved_tensors
+        nq = q_feat.shape[0]
+        gl = torch.zeros(g.shape[0], psm.label_width(nq), dtype=torch.float32, device=g.device)
+        gl[:, :nq] = g
+        out = psm.instance_labels_backward(means, f_ins, q_feat, q_mean, q_prec, gl, gl.shape[1])
+        return out["means"], out["f_ins"].to(f_ins.dtype), out["q_feat"], out["q_mean"], out["q_prec"]
+
+
+def instance_labels(means, f_ins, q_feat, q_mean, q_prec):
+    """(n, n_q) labels: softmax over the queries of sigmoid(f_q . f_g) times the
+    query Gaussian's density ratio at the surfel centre."""
+    return InstanceLabels.apply(means, f_ins, q_feat, q_mean, q_prec)
+
+
+def render_panoptic(means, scales, quats, opacity, rgb, f_sem, f_ins, q_feat, q_mean, q_prec, camera, k: int = 16,
+                    tile_mode: str = "ellipse", blend: str = "topk"):
+    """One walk and one Top-K selection render the semantic features and the
+    instance labels (eq. (8)): the labels occupy the columns after the
+    semantic channels of a single FP32 feature array.  Returns (rgb, depth,
+    normal, alpha, semantic map [H,W,C_s], instance map [H,W,n_q])."""
+    labels = instance_labels(means, f_ins, q_feat, q_mean, q_prec)
+    nq, cs = q_feat.shape[0], f_sem.shape[1]
+    pad = psm.label_width(nq) - nq
+    parts = [f_sem.float(), labels]
+    if pad:
+        parts.append(torch.zeros(labels.shape[0], pad, dtype=torch.float32, device=labels.device))
+    feat = torch.cat(parts, dim=1).contiguous()
+    rgb_o, depth, normal, alpha, f = render(means, scales, quats, opacity, rgb, feat, camera, k, tile_mode, blend)
+    return rgb_o, depth, normal, alpha, f[..., :cs], f[..., cs:cs + nq]

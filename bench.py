@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--cpu-tiles", type=int, default=1200)
     ap.add_argument("--no-batch", action="store_true", help="skip the 8-camera batched workload")
+    ap.add_argument("--launch", default=None,
+                    help="schedule,blend_pass,bwd_pass for the headline form (default: the library's autotuner)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -72,7 +74,7 @@ def calibrate_copy():
 class Form:
     """One (tile mode, blend) configuration with preallocated buffers."""
 
-    def __init__(self, psm, t, cam, K, tile_mode, blend, gout, device):
+    def __init__(self, psm, t, cam, K, tile_mode, blend, gout, device, launch=None, tune=False):
         import torch
         self.psm, self.t, self.K = psm, t, K
         self.tile_mode, self.blend = tile_mode, blend
@@ -91,6 +93,19 @@ class Form:
                       "feat": z(n, c)}
         self.gout = gout
         self.ctx = psm.context(device.index or 0)
+        self.tuned_ms = None
+        if launch is not None:
+            self.cfg.schedule, self.cfg.blend_pass, self.cfg.bwd_pass = launch
+        elif tune:
+            tcfg = psm.config_struct(K, tile_mode, blend)
+            out = dict(self.out)
+            self.tuned_ms = psm.autotune(self.ctx, self.s, psm.camera_array([self.cam]), tcfg, self.ws, out,
+                                         self.gout, self.grads, reps=3, cache=False)
+            self.cfg.schedule, self.cfg.blend_pass, self.cfg.bwd_pass = tcfg.schedule, tcfg.blend_pass, tcfg.bwd_pass
+
+    def launch(self):
+        """(schedule, blend_pass, bwd_pass) in use (0 = library default)."""
+        return (int(self.cfg.schedule), int(self.cfg.blend_pass or 32), int(self.cfg.bwd_pass or 16))
 
     def step(self, bwd: bool):
         self.psm.forward_into(self.ctx, self.s, self.cam, self.cfg, self.ws, self.out)
@@ -134,10 +149,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(stage: str, workload: str):
+def measured_traffic(stage: str, workload: str, launch=None):
     """HBM bytes per launch (read + written) of a stage's kernel from the
-    committed rocprofv3 counter summary, or None when there is none or the
-    kernel sources changed since the counters were taken."""
+    committed rocprofv3 counter summary, or None when there is none, the
+    kernel sources changed since the counters were taken, or the counters
+    were taken with other launch choices."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{stage}_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -149,17 +165,19 @@ def measured_traffic(stage: str, workload: str):
                 fields[k.strip()] = v.strip().strip("`")
     if fields.get("kernel sources sha256") != kernel_source_hash():
         return None
+    if launch is not None and fields.get("launch choice") != "%d,%d,%d" % tuple(launch):
+        return None
     try:
         return float(fields["bytes per launch (read + write)"])
     except (KeyError, ValueError):
         return None
 
 
-def roofline(stages, st, K, C, S, bwd, workload=WORKLOAD):
+def roofline(stages, st, K, C, S, bwd, workload=WORKLOAD, launch=None):
     """Roofline object for the dominant stage of the step."""
     name = max(stages, key=stages.get)
     ms = stages[name]
-    traffic = measured_traffic(name, workload)
+    traffic = measured_traffic(name, workload, launch)
     if name == "walk":
         flops = FLOP_PER_EVAL * st.pairs_walked + FLOP_PER_CONTRIB * st.contributors
         a = flops / (ms * 1e-3) / 1e12
@@ -381,13 +399,17 @@ def main():
     print(f"[bench] {args.workload}: n={sc.n} {cam.width}x{cam.height} C={sc.c} K={K} {dtype}", file=sys.stderr,
           flush=True)
 
-    head = Form(psm, t, cam, K, "ellipse", "topk", gout, device)
+    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    head = Form(psm, t, cam, K, "ellipse", "topk", gout, device, launch=launch, tune=launch is None)
+    print(f"[bench] launch choice (schedule, blend_pass, bwd_pass): {head.launch()}", file=sys.stderr, flush=True)
     ms_step, stages, st = timed(head, True, args.steps, args.warmup)
     print(f"[bench] topk+ellipse fwd+bwd {ms_step:.3f} ms", file=sys.stderr, flush=True)
     ms_fwd, stages_fwd, _ = timed(head, False, args.steps, args.warmup)
     print(f"[bench] topk+ellipse fwd {ms_fwd:.3f} ms", file=sys.stderr, flush=True)
+    head_launch = head.launch()
+    head_tuned_ms = head.tuned_ms
     del head
-    base = Form(psm, t, cam, K, "aabb", "full", gout, device)
+    base = Form(psm, t, cam, K, "aabb", "full", gout, device, tune=launch is None)
     ms_base_step, stages_base, st_base = timed(base, True, max(3, args.steps // 2), 2)
     ms_base_fwd, _, _ = timed(base, False, max(3, args.steps // 2), 2)
     print(f"[bench] full+aabb fwd+bwd {ms_base_step:.3f} ms, fwd {ms_base_fwd:.3f} ms", file=sys.stderr, flush=True)
@@ -432,7 +454,10 @@ def main():
         "pairs": int(st.pairs), "pairs_walked": int(st.pairs_walked), "contributors": int(st.contributors),
         "visible": int(st.visible),
         "stages_ms": stages,
-        "roofline": roofline(stages, st, K, sc.c, S, True, args.workload),
+        "launch": {"schedule": ["grid", "persistent"][head_launch[0]], "blend_pass": head_launch[1],
+                   "bwd_pass": head_launch[2], "source": "autotuner" if launch is None else "--launch",
+                   "tuned_ms": head_tuned_ms},
+        "roofline": roofline(stages, st, K, sc.c, S, True, args.workload, head_launch),
         "ablation_fwd": ablation,
     }
     if not args.no_cpu_baseline:

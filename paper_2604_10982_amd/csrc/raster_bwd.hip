@@ -457,6 +457,7 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
 }
 
 // ------------------------------------------------------- per-surfel reduction
+
 // Chain rule of one camera's view of a surfel: from the 16 pair sums G (dL/d
 // of A^-1 (4), e (2), projected centre (2), centre depth, o, c (3), n_c (3))
 // to the surfel parameters.  The walk record was evaluated in FP64 from the
@@ -574,15 +575,24 @@ __global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, CamTable ct, cons
   const double Rq[3][3] = {{1. - 2. * (y * y + z * z), 2. * (x * y - w * z), 2. * (x * z + w * y)},
                            {2. * (x * y + w * z), 1. - 2. * (x * x + z * z), 2. * (y * z - w * x)},
                            {2. * (x * z - w * y), 2. * (y * z + w * x), 1. - 2. * (x * x + y * y)}};
+  // the next camera's pair range is loaded while this camera's is summed
+  int32_t ncv = cull[i];
+  uint32_t nvb = vbase[i], nvc = count[i];
+#pragma unroll 1
   for (int b = 0; b < ct.n; ++b) {
-    const int64_t v = (int64_t)b * n + i;
-    const int32_t cv = cull[v];
+    const int32_t cv = ncv;
+    const int64_t base = nvb;
+    const int64_t end = min(base + (int64_t)nvc, cap);
+    if (b + 1 < ct.n) {
+      const int64_t v = (int64_t)(b + 1) * n + i;
+      ncv = cull[v];
+      nvb = vbase[v];
+      nvc = count[v];
+    }
     if ((cv & 0xFF) != 0) continue;
     double G[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) G[j] = 0.0;
-    const int64_t base = vbase[v];
-    const int64_t end = min(base + (int64_t)count[v], cap);
     for (int64_t s0 = base; s0 < end; s0 += 8) {
       // 8 flags in flight, then the flagged pairs' partials (emission order)
       uint32_t f = 0;
@@ -631,10 +641,16 @@ __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const 
   for (int j = 0; j < kMaxGroups; ++j) acc[j] = make_float4(0.f, 0.f, 0.f, 0.f);
   const int ng = (lpp + lpp2 - 1) / lpp2;  // channel groups of this lane
   const uint64_t gmask = lpp2 == 64 ? ~0ull : ((1ull << lpp2) - 1ull);
+  uint32_t nvb = vbase[i], nvc = count[i];
+#pragma unroll 1
   for (int b = 0; b < ncam; ++b) {
-    const int64_t v = (int64_t)b * n + i;
-    const int64_t base = vbase[v];
-    const int64_t end = min(base + (int64_t)count[v], cap);
+    const int64_t base = nvb;
+    const int64_t end = min(base + (int64_t)nvc, cap);
+    if (b + 1 < ncam) {
+      const int64_t v = (int64_t)(b + 1) * n + i;
+      nvb = vbase[v];
+      nvc = count[v];
+    }
     for (int64_t s0 = base; s0 < end; s0 += lpp2) {
       // the group's lanes test lpp2 flags at once; flagged rows in emission order
       const bool fl = s0 + cl < end && fflag[s0 + cl];

@@ -52,7 +52,8 @@ def parse():
     ap.add_argument("--cpu-tiles", type=int, default=1200)
     ap.add_argument("--no-batch", action="store_true", help="skip the 8-camera batched workload")
     ap.add_argument("--launch", default=None,
-                    help="schedule,blend_pass,bwd_pass for the headline form (default: the library's autotuner)")
+                    help="schedule,bwd_schedule,blend_pass,bwd_pass for the headline form "
+                         "(default: the library's autotuner)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -95,17 +96,19 @@ class Form:
         self.ctx = psm.context(device.index or 0)
         self.tuned_ms = None
         if launch is not None:
-            self.cfg.schedule, self.cfg.blend_pass, self.cfg.bwd_pass = launch
+            self.cfg.schedule, self.cfg.bwd_schedule, self.cfg.blend_pass, self.cfg.bwd_pass = launch
         elif tune:
             tcfg = psm.config_struct(K, tile_mode, blend)
             out = dict(self.out)
             self.tuned_ms = psm.autotune(self.ctx, self.s, psm.camera_array([self.cam]), tcfg, self.ws, out,
                                          self.gout, self.grads, reps=3, cache=False)
-            self.cfg.schedule, self.cfg.blend_pass, self.cfg.bwd_pass = tcfg.schedule, tcfg.blend_pass, tcfg.bwd_pass
+            self.cfg.schedule, self.cfg.bwd_schedule = tcfg.schedule, tcfg.bwd_schedule
+            self.cfg.blend_pass, self.cfg.bwd_pass = tcfg.blend_pass, tcfg.bwd_pass
 
     def launch(self):
-        """(schedule, blend_pass, bwd_pass) in use (0 = library default)."""
-        return (int(self.cfg.schedule), int(self.cfg.blend_pass or 32), int(self.cfg.bwd_pass or 16))
+        """(schedule, bwd_schedule, blend_pass, bwd_pass) in use."""
+        return (int(self.cfg.schedule), int(self.cfg.bwd_schedule), int(self.cfg.blend_pass or 32),
+                int(self.cfg.bwd_pass or 16))
 
     def step(self, bwd: bool):
         self.psm.forward_into(self.ctx, self.s, self.cam, self.cfg, self.ws, self.out)
@@ -165,7 +168,7 @@ def measured_traffic(stage: str, workload: str, launch=None):
                 fields[k.strip()] = v.strip().strip("`")
     if fields.get("kernel sources sha256") != kernel_source_hash():
         return None
-    if launch is not None and fields.get("launch choice") != "%d,%d,%d" % tuple(launch):
+    if launch is not None and fields.get("launch choice") != ",".join(str(v) for v in launch):
         return None
     try:
         return float(fields["bytes per launch (read + write)"])
@@ -242,7 +245,8 @@ def batch_workload(psm, scenes, steps, warmup):
     ctx = psm.context(0)
     tune_cfg = psm.config_struct(K, "ellipse", "topk")
     tuned_ms = psm.autotune(ctx, s, carr, tune_cfg, ws, out, gout, grads, reps=3, cache=False)
-    cfg.schedule, cfg.blend_pass, cfg.bwd_pass = tune_cfg.schedule, tune_cfg.blend_pass, tune_cfg.bwd_pass
+    cfg.schedule, cfg.bwd_schedule = tune_cfg.schedule, tune_cfg.bwd_schedule
+    cfg.blend_pass, cfg.bwd_pass = tune_cfg.blend_pass, tune_cfg.bwd_pass
 
     def step(c):
         psm.forward_batch_into(ctx, s, carr, c, ws, out)
@@ -264,7 +268,7 @@ def batch_workload(psm, scenes, steps, warmup):
         raise RuntimeError("pair capacity exceeded in the batched workload")
     # the same step captured once and replayed
     gcfg = psm.config_struct(K, "ellipse", "topk", psm.FLAG_NO_SYNC, tune_cfg.schedule, tune_cfg.blend_pass,
-                             tune_cfg.bwd_pass)
+                             tune_cfg.bwd_pass, tune_cfg.bwd_schedule)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -286,6 +290,7 @@ def batch_workload(psm, scenes, steps, warmup):
                         + ", ".join(f"{c.width}x{c.height}" for c in cams),
             "pixels": P, "fwd_bwd_ms": ms, "fwd_bwd_its": 1000.0 / ms, "graph_replay_ms": gms,
             "graph_replay_its": 1000.0 / gms, "autotuned": {"schedule": ["grid", "persistent"][tune_cfg.schedule],
+                                                           "bwd_schedule": ["grid", "persistent"][tune_cfg.bwd_schedule],
                                                            "blend_pass": tune_cfg.blend_pass,
                                                            "bwd_pass": tune_cfg.bwd_pass, "tuned_ms": tuned_ms},
             "pairs": int(st.pairs), "stages_ms": stages}
@@ -401,7 +406,7 @@ def main():
 
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
     head = Form(psm, t, cam, K, "ellipse", "topk", gout, device, launch=launch, tune=launch is None)
-    print(f"[bench] launch choice (schedule, blend_pass, bwd_pass): {head.launch()}", file=sys.stderr, flush=True)
+    print(f"[bench] launch choice (schedule, bwd_schedule, blend_pass, bwd_pass): {head.launch()}", file=sys.stderr, flush=True)
     ms_step, stages, st = timed(head, True, args.steps, args.warmup)
     print(f"[bench] topk+ellipse fwd+bwd {ms_step:.3f} ms", file=sys.stderr, flush=True)
     ms_fwd, stages_fwd, _ = timed(head, False, args.steps, args.warmup)
@@ -454,8 +459,9 @@ def main():
         "pairs": int(st.pairs), "pairs_walked": int(st.pairs_walked), "contributors": int(st.contributors),
         "visible": int(st.visible),
         "stages_ms": stages,
-        "launch": {"schedule": ["grid", "persistent"][head_launch[0]], "blend_pass": head_launch[1],
-                   "bwd_pass": head_launch[2], "source": "autotuner" if launch is None else "--launch",
+        "launch": {"schedule": ["grid", "persistent"][head_launch[0]],
+                   "bwd_schedule": ["grid", "persistent"][head_launch[1]], "blend_pass": head_launch[2],
+                   "bwd_pass": head_launch[3], "source": "autotuner" if launch is None else "--launch",
                    "tuned_ms": head_tuned_ms},
         "roofline": roofline(stages, st, K, sc.c, S, True, args.workload, head_launch),
         "ablation_fwd": ablation,

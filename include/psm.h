@@ -89,13 +89,14 @@ typedef struct {
   int32_t schedule;   /* psm_schedule */
   int32_t blend_pass; /* feature channels per Top-K blend pass: 0 (= 32), 16 or 32 */
   int32_t bwd_pass;   /* feature channels per feature-backward pass: 0 (= 16), 8 or 16 */
-  int32_t reserved;   /* must be 0 */
+  int32_t bwd_schedule; /* psm_schedule of the backward's tile kernels */
 } psm_config;
 
-/* Tile scheduling of the per-tile kernels.  GRID: one workgroup per 16x16
- * tile, tiles of neighbouring ids kept on one XCD.  PERSISTENT: a grid that
- * fills the device once takes tiles from a work queue sorted longest list
- * first (the forward sorts the tiles by list length). */
+/* Tile scheduling of the per-tile kernels (forward: schedule, backward:
+ * bwd_schedule).  GRID: one workgroup per 16x16 tile, tiles of neighbouring
+ * ids kept on one XCD.  PERSISTENT: a grid that fills the device once takes
+ * tiles from a work queue ordered longest lists first (the forward orders the
+ * tiles when either schedule is persistent). */
 typedef enum { PSM_SCHED_GRID = 0, PSM_SCHED_PERSISTENT = 1 } psm_schedule;
 
 /* Skip the end-of-call status read-back (graph-safe; the caller checks
@@ -238,8 +239,8 @@ psm_status psm_read_selection_batch(psm_ctx* ctx, const void* workspace, int64_t
                                     int32_t* sel_id_out, float* sel_w_out, int32_t* n_last_out,
                                     float* t_final_out, void* stream);
 
-/* Autotuner: times every candidate launch choice (schedule, blend_pass,
- * bwd_pass) on these inputs -- forward, plus backward when grads is non-NULL
+/* Autotuner: times every candidate launch choice (schedule, bwd_schedule,
+ * blend_pass, bwd_pass) on these inputs -- forward, plus backward when grads is non-NULL
  * -- `reps` times each after one warm-up, and writes the fastest into *cfg
  * (and its median time in ms into *best_ms_out when non-NULL).  The choice is
  * cached in the context per (cameras' sizes, n, c, k, dtype, modes, backward)

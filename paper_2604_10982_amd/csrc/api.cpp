@@ -87,8 +87,8 @@ struct psm_ctx {
 namespace psm {
 
 // Persistent grids: as many blocks as fit on the device at once.
-int tile_grid(const Layout& L, const Tuning& tu, const void* kernel, size_t dyn_lds) {
-  if (tu.sched != kSchedPersistent) return xcd_grid(L.tiles);
+int tile_grid(const Layout& L, int sched, const void* kernel, size_t dyn_lds) {
+  if (sched != kSchedPersistent) return xcd_grid(L.tiles);
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
@@ -164,11 +164,11 @@ psm_status validate_common(const psm_camera* cams, int32_t n_cams, const psm_con
   if (cfg->tile_mode < 0 || cfg->tile_mode > 2) return fail(PSM_ERR_INVALID_ARG, "bad tile_mode");
   if (cfg->blend < 0 || cfg->blend > 1) return fail(PSM_ERR_INVALID_ARG, "bad blend mode");
   if (cfg->schedule < 0 || cfg->schedule > 1) return fail(PSM_ERR_INVALID_ARG, "bad schedule");
+  if (cfg->bwd_schedule < 0 || cfg->bwd_schedule > 1) return fail(PSM_ERR_INVALID_ARG, "bad bwd_schedule");
   if (cfg->blend_pass != 0 && cfg->blend_pass != 16 && cfg->blend_pass != 32)
     return fail(PSM_ERR_INVALID_ARG, "blend_pass must be 0, 16 or 32");
   if (cfg->bwd_pass != 0 && cfg->bwd_pass != 8 && cfg->bwd_pass != 16)
     return fail(PSM_ERR_INVALID_ARG, "bwd_pass must be 0, 8 or 16");
-  if (cfg->reserved != 0) return fail(PSM_ERR_INVALID_ARG, "reserved must be 0");
   if (c < 0 || c > 1024) return fail(PSM_ERR_INVALID_ARG, "c must be in [0, 1024]");
   if (c % 8 != 0) return fail(PSM_ERR_UNSUPPORTED, "c must be a multiple of 8");
   if (pair_capacity < 0 || pair_capacity > 0x7FFFFFFFLL)
@@ -221,6 +221,7 @@ CamTable cam_table(const psm_camera* cams, int32_t n_cams, int64_t n) {
 Tuning tuning_of(const psm_config* cfg) {
   Tuning t;
   t.sched = cfg->schedule;
+  t.sched_bwd = cfg->bwd_schedule;
   t.blend_pass = cfg->blend_pass == 0 ? 32 : cfg->blend_pass;
   t.bwd_pass = cfg->bwd_pass == 0 ? 16 : cfg->bwd_pass;
   return t;
@@ -287,11 +288,7 @@ void enqueue_forward(const SurfelArgs& sa, const CamTable& ct, const psm_config*
   prof.end(kStagePairSort, st);
   prof.begin(kStageRanges, st);
   launch_ranges(L, ws, st);
-  if (tu.sched == kSchedPersistent) {
-    launch_tile_keys(L, ws, st);
-    radix_sort_pairs((uint32_t*)(ws + L.tkey0), (uint32_t*)(ws + L.torder0), (uint32_t*)(ws + L.tkey1),
-                     (uint32_t*)(ws + L.torder1), status + kStTiles, L.tiles, 32, hist, nb_max, st);
-  }
+  if (tu.sched == kSchedPersistent || tu.sched_bwd == kSchedPersistent) launch_tile_order(L, ws, st);
   prof.end(kStageRanges, st);
   ImageArgs ia{out->rgb, out->depth, out->normal, out->alpha, out->feat};
   prof.begin(kStageWalk, st);
@@ -561,6 +558,7 @@ psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
   for (const TuneKey& t : ctx->tuned) {
     if (t.key == key) {
       cfg->schedule = t.tu.sched;
+      cfg->bwd_schedule = t.tu.sched_bwd;
       cfg->blend_pass = t.tu.blend_pass;
       cfg->bwd_pass = t.tu.bwd_pass;
       if (best_ms_out) *best_ms_out = t.ms;
@@ -573,12 +571,14 @@ psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
   std::vector<Tuning> cands;
   const bool feat = s->c > 0 && cfg->blend == PSM_BLEND_TOPK;
   for (int sched = 0; sched < 2; ++sched)
-    for (int bp : {16, 32})
-      for (int gp : {8, 16}) {
-        if (!feat && (bp != 32 || gp != 16)) continue;
-        if (feat && !bwd && gp != 16) continue;
-        cands.push_back(Tuning{sched, bp, gp});
-      }
+    for (int sched_bwd = 0; sched_bwd < 2; ++sched_bwd)
+      for (int bp : {16, 32})
+        for (int gp : {8, 16}) {
+          if (!bwd && sched_bwd != 0) continue;
+          if (!feat && (bp != 32 || gp != 16)) continue;
+          if (feat && !bwd && gp != 16) continue;
+          cands.push_back(Tuning{sched, sched_bwd, bp, gp});
+        }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(PSM_ERR_HIP, "hipEventCreate failed");
@@ -588,6 +588,7 @@ psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
   for (const Tuning& tu : cands) {
     psm_config c2 = *cfg;
     c2.schedule = tu.sched;
+    c2.bwd_schedule = tu.sched_bwd;
     c2.blend_pass = tu.blend_pass;
     c2.bwd_pass = tu.bwd_pass;
     c2.flags = (cfg->flags | PSM_FLAG_NO_SYNC) & ~PSM_FLAG_PROFILE;
@@ -623,6 +624,7 @@ psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
   if (h[kStOverflow]) return capacity_error(L, h);
   ctx->tuned.push_back(TuneKey{key, best, best_ms});
   cfg->schedule = best.sched;
+  cfg->bwd_schedule = best.sched_bwd;
   cfg->blend_pass = best.blend_pass;
   cfg->bwd_pass = best.bwd_pass;
   if (best_ms_out) *best_ms_out = best_ms;

@@ -114,7 +114,7 @@ struct Layout {
   int64_t n, nreal, cap, tiles, spix;  // n = virtual surfels; spix = tiles * 256 (tile-major pixels)
   int k, c, ncam;
   size_t rec, fp, ext, key0, key1, id0, id1, vbase, count, offs, cull, ptile0, ptile1, eid0, eid1, sid_emit, pid, ranges,
-      tkey0, tkey1, torder0, torder1, nlast, tfinal, selpos, selw, seldot, gflag, fflag, gpart, fpart, hist, bsum,
+      torder0, nlast, tfinal, selpos, selw, seldot, gflag, fflag, gpart, fpart, hist, bsum,
       status, total;
 };
 
@@ -149,10 +149,7 @@ inline Layout make_layout(const CamTable& ct, int k, int c, int64_t cap) {
   L.sid_emit = take(cap1 * 4);    // virtual surfel id of each emitted pair
   L.pid = take(cap1 * 4);         // virtual surfel id of each sorted pair
   L.ranges = take(t1 * 8);        // [start, end) per tile
-  L.tkey0 = take(t1 * 4);         // tile work order (longest list first), sort ping-pong
-  L.tkey1 = take(t1 * 4);
-  L.torder0 = take(t1 * 4);
-  L.torder1 = take(t1 * 4);
+  L.torder0 = take(t1 * 4);       // tile work order, longest lists first
   L.nlast = take(L.spix * 4);
   L.tfinal = take(L.spix * 4);
   L.selpos = take(L.spix * (size_t)k * 4);

@@ -44,7 +44,8 @@ struct ProfHook {
 
 // Launch choices the autotuner searches (all give identical results).
 struct Tuning {
-  int sched;       // kSchedGrid or kSchedPersistent
+  int sched;       // forward tile kernels: kSchedGrid or kSchedPersistent
+  int sched_bwd;   // backward tile kernels
   int blend_pass;  // feature channels per Top-K blend pass: 16 or 32
   int bwd_pass;    // feature channels per feature-backward pass: 8 or 16
 };
@@ -58,7 +59,7 @@ void launch_preprocess(const SurfelArgs& s, const CamTable& ct, int mode, const 
 void launch_scan_counts(const Layout& L, char* ws, hipStream_t st);
 void launch_emit(const CamTable& ct, int mode, const Layout& L, char* ws, hipStream_t st);
 void launch_ranges(const Layout& L, char* ws, hipStream_t st);
-void launch_tile_keys(const Layout& L, char* ws, hipStream_t st);
+void launch_tile_order(const Layout& L, char* ws, hipStream_t st);
 void launch_export_keys(const Layout& L, char* ws, int32_t* cull, uint32_t* depth, int32_t* count, hipStream_t st);
 
 // sort.hip: stable LSD radix sort of (key, value) pairs on bits [0, bits) of
@@ -69,14 +70,14 @@ void radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, co
 
 // Grid of a per-tile kernel: one block per tile, or (persistent) enough
 // blocks to fill the device once.
-int tile_grid(const Layout& L, const Tuning& tu, const void* kernel, size_t dyn_lds);
+int tile_grid(const Layout& L, int sched, const void* kernel, size_t dyn_lds);
 
 // Work queue of a per-tile kernel (work order sorted by the forward; queue
 // heads zeroed before each use).
-inline TileQueue tile_queue(const Layout& L, const Tuning& tu, char* ws, int q) {
+inline TileQueue tile_queue(const Layout& L, int sched, char* ws, int q) {
   TileQueue t;
   t.tiles = (int)L.tiles;
-  t.order = tu.sched == kSchedPersistent ? (const uint32_t*)(ws + L.torder0) : nullptr;
+  t.order = sched == kSchedPersistent ? (const uint32_t*)(ws + L.torder0) : nullptr;
   t.head = (uint32_t*)(ws + L.status) + kStQueue + q;
   return t;
 }

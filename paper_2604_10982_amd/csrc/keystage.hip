@@ -387,14 +387,35 @@ __global__ __launch_bounds__(256) void k_finalize_pairs(const uint32_t* __restri
   if (j == P - 1 || ptile[j + 1] != t) ranges[t].y = j + 1;
 }
 
-// Sort keys of the tile work order: longest list first (ties by tile id).
-__global__ __launch_bounds__(256) void k_tile_keys(int64_t tiles, const uint2* __restrict__ ranges,
-                                                   uint32_t* __restrict__ key, uint32_t* __restrict__ order) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= tiles) return;
-  const uint2 r = ranges[t];
-  key[t] = ~(r.y - r.x);
-  order[t] = (uint32_t)t;
+// Tile work order for the persistent scheduler, longest lists first: tiles
+// binned by the bit length of their list length (one block), the bins taken
+// in descending order.  The order within a bin does not matter: it only
+// decides which block starts a tile, never a result.
+__global__ __launch_bounds__(1024) void k_tile_order(int64_t tiles, const uint2* __restrict__ ranges,
+                                                     uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_cnt[33], s_off[33];
+  const int tid = threadIdx.x;
+  if (tid < 33) s_cnt[tid] = 0u;
+  __syncthreads();
+  for (int64_t t = tid; t < tiles; t += 1024) {
+    const uint2 r = ranges[t];
+    const uint32_t len = r.y - r.x;
+    atomicAdd(&s_cnt[len ? 32 - __clz(len) : 0], 1u);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t run = 0;
+    for (int bin = 32; bin >= 0; --bin) {
+      s_off[bin] = run;
+      run += s_cnt[bin];
+    }
+  }
+  __syncthreads();
+  for (int64_t t = tid; t < tiles; t += 1024) {
+    const uint2 r = ranges[t];
+    const uint32_t len = r.y - r.x;
+    order[atomicAdd(&s_off[len ? 32 - __clz(len) : 0], 1u)] = (uint32_t)t;
+  }
 }
 
 // ------------------------------------------------------------- host wrappers
@@ -453,10 +474,10 @@ void launch_ranges(const Layout& L, char* ws, hipStream_t st) {
                      (uint2*)(ws + L.ranges));
 }
 
-void launch_tile_keys(const Layout& L, char* ws, hipStream_t st) {
+void launch_tile_order(const Layout& L, char* ws, hipStream_t st) {
   if (L.tiles == 0) return;
-  hipLaunchKernelGGL(k_tile_keys, dim3((unsigned)cdiv(L.tiles, 256)), dim3(256), 0, st, L.tiles,
-                     (const uint2*)(ws + L.ranges), (uint32_t*)(ws + L.tkey0), (uint32_t*)(ws + L.torder0));
+  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, st, L.tiles, (const uint2*)(ws + L.ranges),
+                     (uint32_t*)(ws + L.torder0));
 }
 
 }  // namespace psm

@@ -680,17 +680,17 @@ static void feat_bwd_launch(const SurfelArgs& s, const Layout& L, const CamTable
                             const ImageGradArgs& g, char* ws, hipStream_t st) {
   const size_t shm = (size_t)kTilePix * L.k * 5;  // entry weights + entry pixels
   const void* k = reinterpret_cast<const void*>(&k_feat_bwd_topk<FT, KMAX, GC, PERSIST>);
-  hipLaunchKernelGGL((k_feat_bwd_topk<FT, KMAX, GC, PERSIST>), dim3(tile_grid(L, tu, k, shm)), dim3(256), shm, st,
+  hipLaunchKernelGGL((k_feat_bwd_topk<FT, KMAX, GC, PERSIST>), dim3(tile_grid(L, tu.sched_bwd, k, shm)), dim3(256), shm, st,
                      (const uint32_t*)(ws + L.pid), (const uint32_t*)(ws + L.eid0), (const uint2*)(ws + L.ranges),
                      (const int32_t*)(ws + L.selpos), (const float*)(ws + L.selw), (const FT*)s.feat, g.feat, s.c, L.k,
-                     ct, tile_queue(L, tu, ws, kQFeatBwd), (float*)(ws + L.seldot), (float*)(ws + L.fpart),
+                     ct, tile_queue(L, tu.sched_bwd, ws, kQFeatBwd), (float*)(ws + L.seldot), (float*)(ws + L.fpart),
                      (uint8_t*)(ws + L.fflag));
 }
 
 template <typename FT, int GC>
 static void feat_bwd_k(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
                        const ImageGradArgs& g, char* ws, hipStream_t st) {
-  const bool p = tu.sched == kSchedPersistent;
+  const bool p = tu.sched_bwd == kSchedPersistent;
   if (L.k <= 8) (p ? feat_bwd_launch<FT, 8, GC, true> : feat_bwd_launch<FT, 8, GC, false>)(s, L, ct, tu, g, ws, st);
   else if (L.k <= 16)
     (p ? feat_bwd_launch<FT, 16, GC, true> : feat_bwd_launch<FT, 16, GC, false>)(s, L, ct, tu, g, ws, st);
@@ -701,10 +701,10 @@ template <int MODE, typename FT, bool PERSIST>
 static void walk_bwd_launch_t(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
                               const ImageGradArgs& g, bool want_f, char* ws, hipStream_t st) {
   const void* k = reinterpret_cast<const void*>(&k_walk_bwd<MODE, FT, PERSIST>);
-  hipLaunchKernelGGL((k_walk_bwd<MODE, FT, PERSIST>), dim3(tile_grid(L, tu, k, 0)), dim3(256), 0, st,
+  hipLaunchKernelGGL((k_walk_bwd<MODE, FT, PERSIST>), dim3(tile_grid(L, tu.sched_bwd, k, 0)), dim3(256), 0, st,
                      (const WalkRec*)(ws + L.rec), (const float4*)(ws + L.ext), (const uint32_t*)(ws + L.pid),
                      (const uint32_t*)(ws + L.eid0), (const uint2*)(ws + L.ranges), ct,
-                     tile_queue(L, tu, ws, kQWalkBwd), L.k,
+                     tile_queue(L, tu.sched_bwd, ws, kQWalkBwd), L.k,
                      (const uint32_t*)(ws + L.nlast), (const float*)(ws + L.tfinal), (const int32_t*)(ws + L.selpos),
                      (const float*)(ws + L.seldot), g.rgb, g.depth, g.normal, g.alpha, want_f ? g.feat : nullptr,
                      (const FT*)s.feat, s.c, (float*)(ws + L.gpart), (uint8_t*)(ws + L.gflag), (float*)(ws + L.fpart),
@@ -714,7 +714,7 @@ static void walk_bwd_launch_t(const SurfelArgs& s, const Layout& L, const CamTab
 template <int MODE, typename FT>
 static void walk_bwd_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
                             const ImageGradArgs& g, bool want_f, char* ws, hipStream_t st) {
-  if (tu.sched == kSchedPersistent) walk_bwd_launch_t<MODE, FT, true>(s, L, ct, tu, g, want_f, ws, st);
+  if (tu.sched_bwd == kSchedPersistent) walk_bwd_launch_t<MODE, FT, true>(s, L, ct, tu, g, want_f, ws, st);
   else walk_bwd_launch_t<MODE, FT, false>(s, L, ct, tu, g, want_f, ws, st);
 }
 

@@ -440,9 +440,10 @@ template <int KMAX, bool TOPK, bool PERSIST>
 static void walk_launch_t(const Layout& L, const CamTable& ct, const Tuning& tu, const ImageArgs& out, char* ws,
                           hipStream_t st) {
   const void* k = reinterpret_cast<const void*>(&k_walk<KMAX, TOPK, PERSIST>);
-  hipLaunchKernelGGL((k_walk<KMAX, TOPK, PERSIST>), dim3(tile_grid(L, tu, k, 0)), dim3(256), 0, st,
+  hipLaunchKernelGGL((k_walk<KMAX, TOPK, PERSIST>), dim3(tile_grid(L, tu.sched, k, 0)), dim3(256), 0, st,
                      (const WalkRec*)(ws + L.rec), (const float4*)(ws + L.ext), (const uint32_t*)(ws + L.pid),
-                     (const uint2*)(ws + L.ranges), ct, tile_queue(L, tu, ws, kQWalk), L.k, out.rgb, out.depth, out.normal, out.alpha,
+                     (const uint2*)(ws + L.ranges), ct, tile_queue(L, tu.sched, ws, kQWalk), L.k, out.rgb, out.depth,
+                     out.normal, out.alpha,
                      (uint32_t*)(ws + L.nlast), (float*)(ws + L.tfinal), (int32_t*)(ws + L.selpos),
                      (float*)(ws + L.selw), (uint32_t*)(ws + L.status));
 }
@@ -472,9 +473,9 @@ template <typename FT, int KMAX, int BC, bool PERSIST>
 static void blend_topk_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
                               float* out_feat, char* ws, hipStream_t st) {
   const void* k = reinterpret_cast<const void*>(&k_blend_topk<FT, KMAX, BC, PERSIST>);
-  hipLaunchKernelGGL((k_blend_topk<FT, KMAX, BC, PERSIST>), dim3(tile_grid(L, tu, k, 0)), dim3(256), 0, st,
+  hipLaunchKernelGGL((k_blend_topk<FT, KMAX, BC, PERSIST>), dim3(tile_grid(L, tu.sched, k, 0)), dim3(256), 0, st,
                      (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos),
-                     (const float*)(ws + L.selw), (const FT*)s.feat, s.c, L.k, ct, tile_queue(L, tu, ws, kQBlend),
+                     (const float*)(ws + L.selw), (const FT*)s.feat, s.c, L.k, ct, tile_queue(L, tu.sched, ws, kQBlend),
                      out_feat);
 }
 
@@ -494,9 +495,9 @@ template <typename FT, bool PERSIST>
 static void full_feat_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
                              float* out_feat, char* ws, hipStream_t st) {
   const void* k = reinterpret_cast<const void*>(&k_full_feat<FT, 64, PERSIST>);
-  hipLaunchKernelGGL((k_full_feat<FT, 64, PERSIST>), dim3(tile_grid(L, tu, k, 0)), dim3(256), 0, st,
+  hipLaunchKernelGGL((k_full_feat<FT, 64, PERSIST>), dim3(tile_grid(L, tu.sched, k, 0)), dim3(256), 0, st,
                      (const WalkRec*)(ws + L.rec), (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges),
-                     (const FT*)s.feat, s.c, ct, tile_queue(L, tu, ws, kQBlend), (const uint32_t*)(ws + L.nlast),
+                     (const FT*)s.feat, s.c, ct, tile_queue(L, tu.sched, ws, kQBlend), (const uint32_t*)(ws + L.nlast),
                      out_feat);
 }
 

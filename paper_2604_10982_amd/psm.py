@@ -60,7 +60,7 @@ class Camera(C.Structure):
 class Config(C.Structure):
     _fields_ = [("k", C.c_int32), ("tile_mode", C.c_int32), ("blend", C.c_int32), ("flags", C.c_int32),
                 ("schedule", C.c_int32), ("blend_pass", C.c_int32), ("bwd_pass", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("bwd_schedule", C.c_int32)]
 
 
 class Queries(C.Structure):
@@ -185,10 +185,12 @@ def camera_struct(cam) -> Camera:
 
 
 def config_struct(k: int, tile_mode="ellipse", blend="topk", flags: int = 0, schedule: int = SCHED_GRID,
-                  blend_pass: int = 0, bwd_pass: int = 0) -> Config:
+                  blend_pass: int = 0, bwd_pass: int = 0, bwd_schedule: int | None = None) -> Config:
+    """bwd_schedule defaults to the forward's schedule."""
     tm = TILE_MODES[tile_mode] if isinstance(tile_mode, str) else int(tile_mode)
     bl = BLENDS[blend] if isinstance(blend, str) else int(blend)
-    return Config(int(k), tm, bl, int(flags), int(schedule), int(blend_pass), int(bwd_pass), 0)
+    bs = int(schedule) if bwd_schedule is None else int(bwd_schedule)
+    return Config(int(k), tm, bl, int(flags), int(schedule), int(blend_pass), int(bwd_pass), bs)
 
 
 def _ptr(t):
@@ -547,8 +549,8 @@ def autotune(ctx: Context, s: Surfels, cams: C.Array, cfg: Config, ws: Workspace
                 table = json.load(f)
         except (OSError, ValueError):
             table = {}
-    if cache and key in table:
-        cfg.schedule, cfg.blend_pass, cfg.bwd_pass = (int(v) for v in table[key])
+    if cache and key in table and len(table[key]) == 4:
+        cfg.schedule, cfg.bwd_schedule, cfg.blend_pass, cfg.bwd_pass = (int(v) for v in table[key])
         return None
     imgs = Images(*(_ptr(out.get(k)) for k in ("rgb", "depth", "normal", "alpha", "feat")))
     g = ImageGrads(*(_ptr((gout or {}).get(k)) for k in ("rgb", "depth", "normal", "alpha", "feat")))
@@ -559,7 +561,7 @@ def autotune(ctx: Context, s: Surfels, cams: C.Array, cfg: Config, ws: Workspace
                               C.byref(gr) if bwd else None, int(reps), C.byref(best), _stream(ctx.device)),
            "psm_autotune")
     if cache:
-        table[key] = [int(cfg.schedule), int(cfg.blend_pass), int(cfg.bwd_pass)]
+        table[key] = [int(cfg.schedule), int(cfg.bwd_schedule), int(cfg.blend_pass), int(cfg.bwd_pass)]
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
             tmp = path + f".tmp{os.getpid()}"

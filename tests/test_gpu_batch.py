@@ -133,8 +133,8 @@ def test_batch_gradients(orc, blend):
     assert max(worst.values()) <= 1e-3, worst
 
 
-CHOICES = [(psm.SCHED_GRID, 32, 16), (psm.SCHED_PERSISTENT, 32, 16), (psm.SCHED_GRID, 16, 8),
-           (psm.SCHED_PERSISTENT, 16, 8)]
+CHOICES = [(psm.SCHED_GRID, psm.SCHED_GRID, 32, 16), (psm.SCHED_PERSISTENT, psm.SCHED_PERSISTENT, 32, 16),
+           (psm.SCHED_GRID, psm.SCHED_PERSISTENT, 16, 8), (psm.SCHED_PERSISTENT, psm.SCHED_GRID, 16, 8)]
 
 
 @pytest.mark.parametrize("blend", ["topk", "full"])
@@ -147,8 +147,8 @@ def test_launch_choices_are_bit_identical(blend):
     K = 16
     _, flat = _upstream(cams, sc.c)
     res = []
-    for sched, bp, gp in CHOICES:
-        cfg = psm.config_struct(K, "ellipse", blend, schedule=sched, blend_pass=bp, bwd_pass=gp)
+    for sched, sched_b, bp, gp in CHOICES:
+        cfg = psm.config_struct(K, "ellipse", blend, schedule=sched, blend_pass=bp, bwd_pass=gp, bwd_schedule=sched_b)
         out, ws, carr = psm.forward_batch(*_args(t), cams, K, cfg=cfg)
         gr = psm.backward_batch(*_args(t), carr, ws, flat, cfg)
         torch.cuda.synchronize()
@@ -177,10 +177,12 @@ def test_autotune(tmp_path, monkeypatch):
     ctx = psm.context(0)
     ms = psm.autotune(ctx, s, cams, cfg, ws, out, flat, grads, reps=2)
     assert ms is not None and ms > 0
-    assert cfg.schedule in (0, 1) and cfg.blend_pass in (16, 32) and cfg.bwd_pass in (8, 16)
+    assert cfg.schedule in (0, 1) and cfg.bwd_schedule in (0, 1) and cfg.blend_pass in (16, 32)
+    assert cfg.bwd_pass in (8, 16)
     cfg2 = psm.config_struct(K)
     assert psm.autotune(ctx, s, cams, cfg2, ws, out, flat, grads) is None  # cached
-    assert (cfg2.schedule, cfg2.blend_pass, cfg2.bwd_pass) == (cfg.schedule, cfg.blend_pass, cfg.bwd_pass)
+    assert (cfg2.schedule, cfg2.bwd_schedule, cfg2.blend_pass, cfg2.bwd_pass) == \
+        (cfg.schedule, cfg.bwd_schedule, cfg.blend_pass, cfg.bwd_pass)
     psm.forward_batch_into(ctx, s, cams, cfg, ws, out)
     torch.cuda.synchronize()
     for k in MAPS:

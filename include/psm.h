@@ -88,7 +88,7 @@ typedef struct {
    * A backward must use the values of its forward. */
   int32_t schedule;   /* psm_schedule */
   int32_t blend_pass; /* feature channels per Top-K blend pass: 0 (= 32), 16 or 32 */
-  int32_t bwd_pass;   /* feature channels per feature-backward pass: 0 (= 16), 8 or 16 */
+  int32_t bwd_pass;   /* feature channels per feature-backward pass: 0 (= 16), 16 or 32 */
   int32_t bwd_schedule; /* psm_schedule of the backward's tile kernels */
 } psm_config;
 

@@ -167,8 +167,8 @@ psm_status validate_common(const psm_camera* cams, int32_t n_cams, const psm_con
   if (cfg->bwd_schedule < 0 || cfg->bwd_schedule > 1) return fail(PSM_ERR_INVALID_ARG, "bad bwd_schedule");
   if (cfg->blend_pass != 0 && cfg->blend_pass != 16 && cfg->blend_pass != 32)
     return fail(PSM_ERR_INVALID_ARG, "blend_pass must be 0, 16 or 32");
-  if (cfg->bwd_pass != 0 && cfg->bwd_pass != 8 && cfg->bwd_pass != 16)
-    return fail(PSM_ERR_INVALID_ARG, "bwd_pass must be 0, 8 or 16");
+  if (cfg->bwd_pass != 0 && cfg->bwd_pass != 16 && cfg->bwd_pass != 32)
+    return fail(PSM_ERR_INVALID_ARG, "bwd_pass must be 0, 16 or 32");
   if (c < 0 || c > 1024) return fail(PSM_ERR_INVALID_ARG, "c must be in [0, 1024]");
   if (c % 8 != 0) return fail(PSM_ERR_UNSUPPORTED, "c must be a multiple of 8");
   if (pair_capacity < 0 || pair_capacity > 0x7FFFFFFFLL)
@@ -573,7 +573,7 @@ psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
   for (int sched = 0; sched < 2; ++sched)
     for (int sched_bwd = 0; sched_bwd < 2; ++sched_bwd)
       for (int bp : {16, 32})
-        for (int gp : {8, 16}) {
+        for (int gp : {16, 32}) {
           if (!bwd && sched_bwd != 0) continue;
           if (!feat && (bp != 32 || gp != 16)) continue;
           if (feat && !bwd && gp != 16) continue;

@@ -393,6 +393,16 @@ __device__ __forceinline__ void load_vec<uint16_t>(const uint16_t* p, float* v) 
     v[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);
   }
 }
+// FP32 matrix-core product on a 16 x 16 tile, k = 4 (v_mfma_f32_16x16x4f32):
+// lane l supplies A[l & 15][l >> 4] and B[l >> 4][l & 15] and holds
+// D[4 (l >> 4) + r][l & 15] in component r.  Products are exact and summed in
+// FP32 in a fixed order, so a sequence of these is deterministic.
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4v mfma_16x16x4(float a, float b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 template <typename FT>
 __device__ __forceinline__ float load_one(const FT* p);
 template <>

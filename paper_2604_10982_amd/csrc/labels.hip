@@ -21,12 +21,6 @@
 
 namespace psm {
 
-typedef float f4v __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ f4v mfma_16x16x4(float a, float b, f4v c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
 // Reductions over the 16 lanes of a DPP row (rotations inside the row).
 __device__ __forceinline__ float row_sum16(float v) {
   v += dpp_mov<0x128>(v);  // row_ror:8

@@ -29,174 +29,218 @@ constexpr int kBB = 32;          // surfels per backward batch
 constexpr int kNV = 17;          // per-pixel values reduced per surfel
 
 // ------------------------------------------------------------ Top-K feature
-// Per tile: the tile's distinct selected surfels get slots (list order); each
-// slot gets the list of (pixel, weight) entries that selected it, in pixel
-// order.  Per pass of GC channels the pixels' feature gradients and the
-// slots' feature rows are staged in LDS, then
-//   thread = pixel:             dot[q] += g_F(p) . f_slot(q)    (registers)
-//   thread = (slot, 4 channels): row = sum over the slot's entries of w g_F(p)
-// and each row is written at the emitted index of its (tile, surfel) pair.
+// Per tile, the distinct selected surfels of the tile (a few dozen: each is
+// chosen by about a hundred of the 256 pixels for K = 16) get slots in list
+// order, 64 per chunk.  With G = the pixels' feature gradients (256 x C),
+// F = the slots' feature rows and W = the selection weights (pixel x slot,
+// zero where the pixel did not select the slot), the adjoint needs
+//   dots = G F^T  at the selected (pixel, slot) entries   (alpha adjoint)
+//   rows = W^T G                                           (feature gradient)
+// and the weight matrix of a tile is dense enough (about half its entries)
+// that both run as dense FP32 matrix-core products.  Wave w owns pixels
+// [64 w, 64 w + 64): its dots tiles, and its share of the rows (a sum over
+// its pixels), added across the 4 waves in wave order.  Per pass of GC
+// channels G and F are staged in LDS with odd row strides, so the operand
+// reads (16 rows x 4 columns and 4 rows x 16 columns) meet almost no bank
+// conflicts; the next pass's loads are in flight during the products.
+// Every sum has a fixed order: results do not depend on the pass width or
+// the tile schedule.
+constexpr int kFbSlots = 64;             // slots per chunk: 4 blocks of 16
+constexpr int kWStride = kTilePix + 1;   // LDS row stride of the per-selection arrays
+
 template <typename FT, int KMAX, int GC, bool PERSIST>
-__global__ __launch_bounds__(256) void k_feat_bwd_topk(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 ? 2 : 1))) void k_feat_bwd_topk(
     const uint32_t* __restrict__ pid, const uint32_t* __restrict__ eid, const uint2* __restrict__ ranges,
     const int32_t* __restrict__ selpos, const float* __restrict__ selw, const FT* __restrict__ feat,
     const float* __restrict__ gfeat, int C, int K, CamTable ct, TileQueue tq, float* __restrict__ seldot,
     float* __restrict__ fpart, uint8_t* __restrict__ fflag) {
-  constexpr int kGC = GC, kGRow = GC + 4;  // channels per pass, LDS row stride
+  static_assert(GC % 16 == 0, "pass width is a multiple of the MFMA tile");
+  constexpr int GS = GC + 1;               // row stride of the staged G, F (floats)
+  constexpr int NCB = GC / 16;             // channel blocks per pass
+  constexpr int FPT = kFbSlots * GC / 256; // staged F values per thread
   __shared__ SelShared S;
-  __shared__ __align__(16) float s_G[kTilePix * kGRow];
-  __shared__ __align__(16) float s_F[kSlotChunk * kGRow];
-  __shared__ uint32_t s_mask[kSlotChunk * 8];  // pixels selecting each slot
-  __shared__ uint16_t s_mpre[kSlotChunk * 8];  // selecting pixels in the slot's earlier mask words
-  __shared__ uint32_t s_off[kSlotChunk + 1];   // entry offsets per slot
-  __shared__ uint32_t s_fe[kSlotChunk];        // emitted pair index per slot
-  extern __shared__ __align__(16) char smem[];
-  float* s_lw = reinterpret_cast<float*>(smem);                    // [256 K] entry weights
-  uint8_t* s_lp = reinterpret_cast<uint8_t*>(s_lw + kTilePix * K);  // [256 K] entry pixels
+  __shared__ float s_G[kTilePix * GS];     // G rows of the pass; then the waves' partial rows
+  __shared__ float s_F[kFbSlots * GS];
+  __shared__ uint8_t s_q[kTilePix * kFbSlots];  // selection index of (pixel, slot), 0xFF = none
+  __shared__ uint32_t s_fe[kFbSlots];           // emitted pair index per slot
+  extern __shared__ float s_w[];                // [K][kWStride]: weights, replaced by dots
   __shared__ int s_item;
 
   for_tiles<PERSIST>(tq, &s_item, [&](const int tile) {
   const TileLoc tl = locate(ct, tile);
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   const int px = tl.tx * kTile + (tid & 15), py = tl.ty * kTile + (tid >> 4);
   const bool inside = px < tl.W && py < tl.H;
   const uint32_t start = ranges[tile].x;
   const size_t tbase = (size_t)tile * K * kTilePix;
   const float* grow = gfeat + (tl.pix0 + (int64_t)py * tl.W + px) * C;
+  const int p0 = wave * 64;  // first pixel of this wave
 
-  int pos[KMAX];
-  float dot[KMAX];
-  int mymax = -1;
+  // the selection positions are re-read where needed (an L2 hit) rather
+  // than held in registers through the products
+  auto load_pos = [&](int (&pos)[KMAX]) {
 #pragma unroll
-  for (int q = 0; q < KMAX; ++q) {
-    pos[q] = q < K ? selpos[tbase + (size_t)q * kTilePix + tid] : -1;
-    dot[q] = 0.0f;
-    mymax = max(mymax, pos[q]);
+    for (int q = 0; q < KMAX; ++q) pos[q] = q < K ? selpos[tbase + (size_t)q * kTilePix + tid] : -1;
+  };
+  int maxpos;
+  {
+    int pos[KMAX];
+    load_pos(pos);
+    int mymax = -1;
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+      // unselected entries keep weight 0 and report dot 0
+      if (q < K) s_w[q * kWStride + tid] = pos[q] >= 0 ? selw[tbase + (size_t)q * kTilePix + tid] : 0.0f;
+      mymax = max(mymax, pos[q]);
+    }
+    maxpos = block_max(mymax, S.red);
   }
-  const int maxpos = block_max(mymax, S.red);
 
   for (int w0 = 0; w0 <= maxpos; w0 += kWinPos) {
     const int nw = window_words(maxpos, w0);
-    const int Uw = build_window(S, pos, K, w0, nw);
-    for (int c0 = 0; c0 < Uw; c0 += kSlotChunk) {
-      const int ns = min(kSlotChunk, Uw - c0);
-      for (int i = tid; i < ns * 8; i += 256) s_mask[i] = 0u;
+    int Uw;
+    {
+      int pos[KMAX];
+      load_pos(pos);
+      Uw = build_window(S, pos, K, w0, nw);
+    }
+    for (int c0 = 0; c0 < Uw; c0 += kFbSlots) {
+      const int ns = min(kFbSlots, Uw - c0), nb = (ns + 15) >> 4;
+      for (int i = tid; i < kTilePix * kFbSlots / 16; i += 256)
+        reinterpret_cast<uint4*>(s_q)[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
       __syncthreads();
-      int sl[KMAX];
+      int pos[KMAX];
+      load_pos(pos);
 #pragma unroll
       for (int q = 0; q < KMAX; ++q) {
-        const int s = q < K ? slot_of(S, pos[q], w0, nw) : -1;
-        sl[q] = (s >= c0 && s < c0 + ns) ? s - c0 : -1;
-        if (sl[q] >= 0) {
-          atomicOr(&s_mask[sl[q] * 8 + (tid >> 5)], 1u << (tid & 31));
-          S.lpos[sl[q]] = (uint32_t)pos[q];  // same value from every selecting pixel
+        const int sl = q < K ? slot_of(S, pos[q], w0, nw) - c0 : -1;
+        if (sl >= 0 && sl < ns) {
+          s_q[tid * kFbSlots + sl] = (uint8_t)q;
+          S.lpos[sl] = (uint32_t)pos[q];  // same value from every selecting pixel
         }
       }
       __syncthreads();
-      uint32_t cnt = 0;
       if (tid < ns) {
-#pragma unroll
-        for (int wd = 0; wd < 8; ++wd) {
-          s_mpre[tid * 8 + wd] = (uint16_t)cnt;
-          cnt += (uint32_t)__popc(s_mask[tid * 8 + wd]);
-        }
-      }
-      uint32_t tot;
-      const uint32_t off = block_scan_excl(cnt, S.red, tot);
-      if (tid < ns) {
-        s_off[tid] = off;
         const uint32_t j = start + S.lpos[tid];
         s_fe[tid] = eid[j];
         S.fid[tid] = (uint32_t)(pid[j] - tl.v0);
       }
-      if (tid == 0) s_off[ns] = tot;
       __syncthreads();
-      // entries of each slot in pixel order: rank = selecting pixels before this one
+      f4v dacc[4][4];
 #pragma unroll
-      for (int q = 0; q < KMAX; ++q) {
-        if (sl[q] >= 0) {
-          const int mw = sl[q] * 8 + (tid >> 5);
-          const uint32_t rank = (uint32_t)s_mpre[mw] + (uint32_t)__popc(s_mask[mw] & ((1u << (tid & 31)) - 1u));
-          const uint32_t e = s_off[sl[q]] + rank;
-          s_lw[e] = selw[tbase + (size_t)q * kTilePix + tid];
-          s_lp[e] = (uint8_t)tid;
-        }
-      }
-      __syncthreads();
+      for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb) dacc[pb][sb] = f4v{0.f, 0.f, 0.f, 0.f};
 
-      for (int cc = 0; cc < C; cc += kGC) {
-        float4 g[kGC / 4];
+      float gv[GC], fv[FPT];
+      auto load_pass = [&](int cc) {
 #pragma unroll
-        for (int j = 0; j < kGC / 4; ++j) {
+        for (int j = 0; j < GC / 4; ++j) {
           const int c = cc + 4 * j;
-          g[j] = inside && c < C ? *reinterpret_cast<const float4*>(grow + c) : make_float4(0.f, 0.f, 0.f, 0.f);
-          *reinterpret_cast<float4*>(s_G + tid * kGRow + 4 * j) = g[j];
+          const float4 g = inside && c < C ? *reinterpret_cast<const float4*>(grow + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+          gv[4 * j] = g.x;
+          gv[4 * j + 1] = g.y;
+          gv[4 * j + 2] = g.z;
+          gv[4 * j + 3] = g.w;
         }
-        for (int item = tid; item < ns * (kGC / 4); item += 256) {
-          const int s = item / (kGC / 4), j = item % (kGC / 4), c = cc + 4 * j;
-          const float4 f = c < C ? load4<FT>(feat + (size_t)S.fid[s] * C + c) : make_float4(0.f, 0.f, 0.f, 0.f);
-          *reinterpret_cast<float4*>(s_F + s * kGRow + 4 * j) = f;
+#pragma unroll
+        for (int u = 0; u < FPT; ++u) {
+          const int item = tid + 256 * u, sidx = item / GC, c = cc + item % GC;
+          fv[u] = sidx < ns && c < C ? load_one<FT>(feat + (size_t)S.fid[sidx] * C + c) : 0.0f;
+        }
+      };
+      load_pass(0);
+      for (int cc = 0; cc < C; cc += GC) {
+#pragma unroll
+        for (int c = 0; c < GC; ++c) s_G[tid * GS + c] = gv[c];
+#pragma unroll
+        for (int u = 0; u < FPT; ++u) {
+          const int item = tid + 256 * u;
+          s_F[(item / GC) * GS + item % GC] = fv[u];
         }
         __syncthreads();
+        if (cc + GC < C) load_pass(cc + GC);
+        // dots: D[p][s] += G[p][c] F[s][c], 4 channels per step
+#pragma unroll 2
+        for (int ks = 0; ks < GC / 4; ++ks) {
+          float fb[4];
 #pragma unroll
-        for (int q = 0; q < KMAX; ++q) {
-          if (sl[q] >= 0) {
-            const float* fr = s_F + sl[q] * kGRow;
-            float d = dot[q];
+          for (int sb = 0; sb < 4; ++sb) fb[sb] = sb < nb ? s_F[(16 * sb + li) * GS + 4 * ks + lk] : 0.0f;
 #pragma unroll
-            for (int j = 0; j < kGC / 4; ++j) {
-              const float4 f = *reinterpret_cast<const float4*>(fr + 4 * j);
-              d = fmaf(g[j].x, f.x, d);
-              d = fmaf(g[j].y, f.y, d);
-              d = fmaf(g[j].z, f.z, d);
-              d = fmaf(g[j].w, f.w, d);
-            }
-            dot[q] = d;
+          for (int pb = 0; pb < 4; ++pb) {
+            const float ga = s_G[(p0 + 16 * pb + li) * GS + 4 * ks + lk];
+#pragma unroll
+            for (int sb = 0; sb < 4; ++sb)
+              if (sb < nb) dacc[pb][sb] = mfma_16x16x4(ga, fb[sb], dacc[pb][sb]);
           }
         }
-        for (int item = tid; item < ns * (kGC / 4); item += 256) {
-          const int s = item / (kGC / 4), j = item % (kGC / 4), c = cc + 4 * j;
-          const int e1 = (int)s_off[s + 1];
-          int e = (int)s_off[s];
-          float4 a[4];
+        // rows: R[s][c] += W[p][s] G[p][c] over this wave's pixels, 4 per step
+        f4v racc[4][NCB];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) a[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-          for (; e + 4 <= e1; e += 4) {
+        for (int sb = 0; sb < 4; ++sb)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const float wt = s_lw[e + u];
-              const float4 x = *reinterpret_cast<const float4*>(s_G + (int)s_lp[e + u] * kGRow + 4 * j);
-              a[u].x = fmaf(wt, x.x, a[u].x);
-              a[u].y = fmaf(wt, x.y, a[u].y);
-              a[u].z = fmaf(wt, x.z, a[u].z);
-              a[u].w = fmaf(wt, x.w, a[u].w);
+          for (int cb = 0; cb < NCB; ++cb) racc[sb][cb] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+        for (int ks = 0; ks < 16; ++ks) {
+          // A operand W[p][s] at lane (s, p): the pixel's selection index of
+          // the slot, then its weight
+          const int p = p0 + 4 * ks + lk;
+          float wa[4];
+#pragma unroll
+          for (int sb = 0; sb < 4; ++sb) {
+            const int q = sb < nb ? (int)s_q[p * kFbSlots + 16 * sb + li] : 0xFF;
+            wa[sb] = q != 0xFF ? s_w[q * kWStride + p] : 0.0f;
+          }
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) {
+            const float gb = s_G[p * GS + 16 * cb + li];
+#pragma unroll
+            for (int sb = 0; sb < 4; ++sb)
+              if (sb < nb) racc[sb][cb] = mfma_16x16x4(wa[sb], gb, racc[sb][cb]);
+          }
+        }
+        __syncthreads();  // every wave is done with the staged G
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+            if (sb < nb) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                s_G[(p0 + 16 * sb + 4 * lk + r) * GS + 16 * cb + li] = racc[sb][cb][r];
             }
-          }
-#pragma unroll
-          for (int u = 0; u < 3; ++u) {
-            if (e + u < e1) {
-              const float wt = s_lw[e + u];
-              const float4 x = *reinterpret_cast<const float4*>(s_G + (int)s_lp[e + u] * kGRow + 4 * j);
-              a[u].x = fmaf(wt, x.x, a[u].x);
-              a[u].y = fmaf(wt, x.y, a[u].y);
-              a[u].z = fmaf(wt, x.z, a[u].z);
-              a[u].w = fmaf(wt, x.w, a[u].w);
-            }
-          }
-          if (c < C) {
-            const float4 r = make_float4((a[0].x + a[1].x) + (a[2].x + a[3].x), (a[0].y + a[1].y) + (a[2].y + a[3].y),
-                                         (a[0].z + a[1].z) + (a[2].z + a[3].z), (a[0].w + a[1].w) + (a[2].w + a[3].w));
-            *reinterpret_cast<float4*>(fpart + (size_t)s_fe[s] * C + c) = r;
-          }
+        __syncthreads();
+        for (int item = tid; item < ns * GC; item += 256) {
+          const int sidx = item / GC, c = item % GC;
+          const float* r = s_G + sidx * GS + c;
+          const float v = ((r[0] + r[64 * GS]) + r[128 * GS]) + r[192 * GS];
+          if (cc + c < C) fpart[(size_t)s_fe[sidx] * C + cc + c] = v;
         }
         __syncthreads();
       }
+      // dots of the selected entries replace their (already consumed) weights
+#pragma unroll
+      for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb)
+          if (sb < nb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int p = p0 + 16 * pb + 4 * lk + r;
+              const int q = s_q[p * kFbSlots + 16 * sb + li];
+              if (q != 0xFF) s_w[q * kWStride + p] = dacc[pb][sb][r];
+            }
+          }
       if (tid < ns) fflag[s_fe[tid]] = 1;
+      __syncthreads();
     }
   }
+  __syncthreads();
 #pragma unroll
   for (int q = 0; q < KMAX; ++q)
-    if (q < K) seldot[tbase + (size_t)q * kTilePix + tid] = pos[q] >= 0 ? dot[q] : 0.0f;
+    if (q < K) seldot[tbase + (size_t)q * kTilePix + tid] = s_w[q * kWStride + tid];
+  __syncthreads();
   });
 }
 
@@ -678,7 +722,7 @@ __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const 
 template <typename FT, int KMAX, int GC, bool PERSIST>
 static void feat_bwd_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
                             const ImageGradArgs& g, char* ws, hipStream_t st) {
-  const size_t shm = (size_t)kTilePix * L.k * 5;  // entry weights + entry pixels
+  const size_t shm = (size_t)kWStride * L.k * sizeof(float);  // weights, then dots
   const void* k = reinterpret_cast<const void*>(&k_feat_bwd_topk<FT, KMAX, GC, PERSIST>);
   hipLaunchKernelGGL((k_feat_bwd_topk<FT, KMAX, GC, PERSIST>), dim3(tile_grid(L, tu.sched_bwd, k, shm)), dim3(256), shm, st,
                      (const uint32_t*)(ws + L.pid), (const uint32_t*)(ws + L.eid0), (const uint2*)(ws + L.ranges),
@@ -727,7 +771,7 @@ static void backward_typed(const SurfelArgs& s, const CamTable& ct, int blend, c
     if (blend == kTopK) {
       prof.begin(kStageBwdFeature, st);
       if (want_f) {
-        if (tu.bwd_pass == 8) feat_bwd_k<FT, 8>(s, L, ct, tu, g, ws, st);
+        if (tu.bwd_pass == 32) feat_bwd_k<FT, 32>(s, L, ct, tu, g, ws, st);
         else feat_bwd_k<FT, 16>(s, L, ct, tu, g, ws, st);
       } else {
         launch_fill_u32(ws + L.seldot, 0u, L.spix * (int64_t)L.k, st);

@@ -393,6 +393,13 @@ __device__ __forceinline__ void load_vec<uint16_t>(const uint16_t* p, float* v) 
     v[2 * i + 1] = __uint_as_float(w[i] & 0xFFFF0000u);
   }
 }
+// LDS ordering between the lanes of one wave (no block barrier involved).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // FP32 matrix-core product on a 16 x 16 tile, k = 4 (v_mfma_f32_16x16x4f32):
 // lane l supplies A[l & 15][l >> 4] and B[l >> 4][l & 15] and holds
 // D[4 (l >> 4) + r][l & 15] in component r.  Products are exact and summed in

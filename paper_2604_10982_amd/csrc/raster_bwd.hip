@@ -594,6 +594,11 @@ __device__ __forceinline__ void chain_rule(const double (&G)[16], const CamArgs&
 // Thread per surfel: for each camera in order, the sum of its pairs' partials
 // (its emitted range [vbase, vbase + count), in emission order), then that
 // camera's chain rule; the cameras' contributions are added in camera order.
+// A surfel's pair count ranges from 0 to several hundred (a heavy tail), so
+// the wave's 64 ranges are read as one flat sequence: lane l loads pair
+// t0 + l of it (coalesced), the batch is staged in LDS, and each surfel's
+// lane adds its own pairs of the batch.  The sums are the same, term by
+// term, as a per-surfel loop over its range.
 __global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, CamTable ct, const uint32_t* __restrict__ vbase,
                                                     const uint32_t* __restrict__ count, int64_t cap,
                                                     const float* __restrict__ gpart,
@@ -603,15 +608,21 @@ __global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, CamTable ct, cons
                                                     float* __restrict__ d_means, float* __restrict__ d_scales,
                                                     float* __restrict__ d_quats, float* __restrict__ d_opacity,
                                                     float* __restrict__ d_rgb) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  constexpr int kPS = 17;  // LDS row stride of a staged pair (16 partials)
+  __shared__ float s_part[4][64 * kPS];
+  __shared__ uint32_t s_pre[4][64];
+  __shared__ uint32_t s_vb[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = ((int64_t)blockIdx.x * 4 + wave) * 64 + lane;
+  const bool valid = i < n;  // every lane stays: the wave shares the pair loads
+  const int64_t ii = valid ? i : 0;
   SurfelGrad acc;
   for (int j = 0; j < 3; ++j) acc.mu[j] = acc.rgb[j] = 0.0;
   for (int j = 0; j < 4; ++j) acc.q[j] = 0.0;
   acc.su = acc.sv = acc.o = 0.0;
-  const double mu[3] = {means[3 * i], means[3 * i + 1], means[3 * i + 2]};
-  const double su = scales[2 * i], sv = scales[2 * i + 1];
-  const double q0 = quats[4 * i], q1 = quats[4 * i + 1], q2 = quats[4 * i + 2], q3 = quats[4 * i + 3];
+  const double mu[3] = {means[3 * ii], means[3 * ii + 1], means[3 * ii + 2]};
+  const double su = scales[2 * ii], sv = scales[2 * ii + 1];
+  const double q0 = quats[4 * ii], q1 = quats[4 * ii + 1], q2 = quats[4 * ii + 2], q3 = quats[4 * ii + 3];
   const double qq = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
   const double rn = qq > 0.0 ? 1.0 / sqrt(qq) : 0.0;
   const double qn[4] = {q0 * rn, q1 * rn, q2 * rn, q3 * rn};
@@ -619,42 +630,76 @@ __global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, CamTable ct, cons
   const double Rq[3][3] = {{1. - 2. * (y * y + z * z), 2. * (x * y - w * z), 2. * (x * z + w * y)},
                            {2. * (x * y + w * z), 1. - 2. * (x * x + z * z), 2. * (y * z - w * x)},
                            {2. * (x * z - w * y), 2. * (y * z + w * x), 1. - 2. * (x * x + y * y)}};
+  float* part = s_part[wave];
   // the next camera's pair range is loaded while this camera's is summed
-  int32_t ncv = cull[i];
-  uint32_t nvb = vbase[i], nvc = count[i];
+  int32_t ncv = valid ? cull[i] : 1;
+  uint32_t nvb = valid ? vbase[i] : 0u, nvc = valid ? count[i] : 0u;
 #pragma unroll 1
   for (int b = 0; b < ct.n; ++b) {
     const int32_t cv = ncv;
-    const int64_t base = nvb;
-    const int64_t end = min(base + (int64_t)nvc, cap);
-    if (b + 1 < ct.n) {
+    const uint32_t vb = nvb;
+    const int64_t end = min((int64_t)vb + (int64_t)nvc, cap);
+    if (b + 1 < ct.n && valid) {
       const int64_t v = (int64_t)(b + 1) * n + i;
       ncv = cull[v];
       nvb = vbase[v];
       nvc = count[v];
     }
-    if ((cv & 0xFF) != 0) continue;
+    const bool live = valid && (cv & 0xFF) == 0;
+    const uint32_t cnt = live && end > (int64_t)vb ? (uint32_t)(end - (int64_t)vb) : 0u;
+    // the wave's pairs as one flat sequence: surfel l owns [pre_l, pre_l + cnt_l)
+    uint32_t xs = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(xs, o, 64);
+      if (lane >= o) xs += t;
+    }
+    const uint32_t pre = xs - cnt, total = __shfl(xs, 63, 64);
+    s_pre[wave][lane] = pre;
+    s_vb[wave][lane] = vb;
+    wave_lds_sync();
     double G[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) G[j] = 0.0;
-    for (int64_t s0 = base; s0 < end; s0 += 8) {
-      // 8 flags in flight, then the flagged pairs' partials (emission order)
-      uint32_t f = 0;
+    for (uint32_t t0 = 0; t0 < total; t0 += 64) {
+      // 64 consecutive pairs of the sequence, one per lane; unflagged pairs
+      // stage zeros (adding +0 leaves a sum unchanged)
+      const uint32_t t = t0 + (uint32_t)lane;
+      float4 r[4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) f |= (s0 + u < end && gflag[s0 + u]) ? (1u << u) : 0u;
-      while (f) {
-        const int u = __ffs(f) - 1;
-        f &= f - 1u;
-        const float4* g = reinterpret_cast<const float4*>(gpart + (size_t)(s0 + u) * 16);
+      for (int qd = 0; qd < 4; ++qd) r[qd] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (t < total) {
+        int o = 0;  // owner: the last surfel whose range starts at or before t
 #pragma unroll
-        for (int qd = 0; qd < 4; ++qd) {
-          const float4 t = g[qd];
-          G[4 * qd] += t.x; G[4 * qd + 1] += t.y; G[4 * qd + 2] += t.z; G[4 * qd + 3] += t.w;
+        for (int step = 32; step > 0; step >>= 1)
+          if (s_pre[wave][o + step] <= t) o += step;
+        const uint32_t pr = s_vb[wave][o] + (t - s_pre[wave][o]);
+        if (gflag[pr]) {
+          const float4* g = reinterpret_cast<const float4*>(gpart + (size_t)pr * 16);
+#pragma unroll
+          for (int qd = 0; qd < 4; ++qd) r[qd] = g[qd];
         }
       }
+#pragma unroll
+      for (int qd = 0; qd < 4; ++qd) {
+        part[lane * kPS + 4 * qd] = r[qd].x;
+        part[lane * kPS + 4 * qd + 1] = r[qd].y;
+        part[lane * kPS + 4 * qd + 2] = r[qd].z;
+        part[lane * kPS + 4 * qd + 3] = r[qd].w;
+      }
+      wave_lds_sync();
+      // each surfel adds its pairs of this batch in emission order
+      const uint32_t lo = max(pre, t0), hi = min(pre + cnt, t0 + 64u);
+      for (uint32_t u = lo; u < hi; ++u) {
+        const float* pp = part + (u - t0) * kPS;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) G[j] += pp[j];
+      }
+      wave_lds_sync();
     }
-    chain_rule(G, ct.cam[b], ((cv >> 8) & 1) != 0, mu, su, sv, qn, Rq, acc);
+    if (live) chain_rule(G, ct.cam[b], ((cv >> 8) & 1) != 0, mu, su, sv, qn, Rq, acc);
   }
+  if (!valid) return;
   // unit quaternion: project out the radial component
   const double dot = w * acc.q[0] + x * acc.q[1] + y * acc.q[2] + z * acc.q[3];
   for (int j = 0; j < 4; ++j) d_quats[4 * i + j] = (float)((acc.q[j] - qn[j] * dot) * rn);
@@ -680,6 +725,7 @@ __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const 
   const int64_t i = ((int64_t)blockIdx.x * 4 + wave) * spw + sub;
   if (i >= n) return;
   constexpr int kMaxGroups = 4;  // C <= 1024: at most 4 channel groups of 4 per lane
+  constexpr int kRowsInFlight = 4;
   float4 acc[kMaxGroups];
 #pragma unroll
   for (int j = 0; j < kMaxGroups; ++j) acc[j] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -696,20 +742,34 @@ __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const 
       nvc = count[v];
     }
     for (int64_t s0 = base; s0 < end; s0 += lpp2) {
-      // the group's lanes test lpp2 flags at once; flagged rows in emission order
+      // the group's lanes test lpp2 flags at once; flagged rows in emission
+      // order, up to kRowsInFlight rows loaded before they are added
       const bool fl = s0 + cl < end && fflag[s0 + cl];
       uint64_t m = (__ballot(fl) >> (sub * lpp2)) & gmask;
       while (m) {
-        const int u = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1ull;
-        const float* row = fpart + (size_t)(s0 + u) * C;
+        int us[kRowsInFlight];
 #pragma unroll
-        for (int j = 0; j < kMaxGroups; ++j) {
-          if (j < ng && cl + j * lpp2 < lpp) {
-            const float4 t = *reinterpret_cast<const float4*>(row + (cl + j * lpp2) * 4);
-            acc[j].x += t.x; acc[j].y += t.y; acc[j].z += t.z; acc[j].w += t.w;
-          }
+        for (int r = 0; r < kRowsInFlight; ++r) {
+          us[r] = m ? __ffsll((unsigned long long)m) - 1 : -1;
+          m &= m - 1ull;
         }
+        float4 t[kRowsInFlight][kMaxGroups];
+#pragma unroll
+        for (int r = 0; r < kRowsInFlight; ++r) {
+          const float* row = fpart + (size_t)(s0 + max(us[r], 0)) * C;
+#pragma unroll
+          for (int j = 0; j < kMaxGroups; ++j)
+            t[r][j] = us[r] >= 0 && j < ng && cl + j * lpp2 < lpp
+                          ? *reinterpret_cast<const float4*>(row + (cl + j * lpp2) * 4)
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int r = 0; r < kRowsInFlight; ++r)
+#pragma unroll
+          for (int j = 0; j < kMaxGroups; ++j)
+            if (us[r] >= 0) {
+              acc[j].x += t[r][j].x; acc[j].y += t[r][j].y; acc[j].z += t[r][j].z; acc[j].w += t[r][j].w;
+            }
       }
     }
   }

@@ -47,13 +47,6 @@ __device__ __forceinline__ void sort_by_position(int (&p)[N], float (&w)[N]) {
 
 constexpr int kWalkChunk = 64;  // list entries a wave examines at once
 
-// LDS ordering between the lanes of one wave (no block barrier involved).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Each wave walks its 64 pixels (a 16x4 band of the tile) on its own, with no
 // block barriers: per chunk of 64 list entries every lane tests one entry's
 // footprint against the band (one vector gather of the extent records and a

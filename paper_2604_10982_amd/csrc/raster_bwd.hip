@@ -263,6 +263,9 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
   // dense-blend mode only: feature chunk of the batch and the batch weights
   __shared__ float s_fc[MODE == kFull ? kBB : 1][64];
   __shared__ __align__(16) float s_om[MODE == kFull ? kBB : 1][kTilePix];
+  // Top-K mode: every pixel's selected list positions and feature dots
+  // ([K][256] each), read back to front by the pixel's own lane
+  extern __shared__ int s_sel[];
   __shared__ int s_item;
 
   for_tiles<PERSIST>(tq, &s_item, [&](const int tile) {
@@ -291,12 +294,18 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
   int kp = -1, nextsel = -1;
   float nextdot = 0.0f;
   const size_t tbase = (size_t)tile * K * kTilePix;
+  int* s_sp = s_sel;
+  float* s_sd = reinterpret_cast<float*>(s_sel + K * kTilePix);
   if (MODE == kTopK) {
-    for (int q = 0; q < K; ++q)
-      if (selpos[tbase + (size_t)q * kTilePix + tid] >= 0) kp = q;
+    for (int q = 0; q < K; ++q) {
+      const int sq = selpos[tbase + (size_t)q * kTilePix + tid];
+      s_sp[q * kTilePix + tid] = sq;
+      s_sd[q * kTilePix + tid] = seldot[tbase + (size_t)q * kTilePix + tid];
+      if (sq >= 0) kp = q;
+    }
     if (kp >= 0) {
-      nextsel = selpos[tbase + (size_t)kp * kTilePix + tid];
-      nextdot = seldot[tbase + (size_t)kp * kTilePix + tid];
+      nextsel = s_sp[kp * kTilePix + tid];
+      nextdot = s_sd[kp * kTilePix + tid];
     }
   }
   const bool has_gf = MODE == kFull && g_feat != nullptr && inside;
@@ -354,28 +363,28 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
 #pragma unroll 1
     for (int k = nb - 1; k >= 0; --k) {
       const int pos = lo + k;
-      float v[kNV];
-#pragma unroll
-      for (int i = 0; i < kNV; ++i) v[i] = 0.0f;
+      // the pixel's terms are products of these scalars, all zero where the
+      // pixel does not take part
+      float w = 0.0f, du1 = 0.0f, dv1 = 0.0f, dw1 = 0.0f, dzi = 0.0f, dop = 0.0f, ex = 0.0f, ey = 0.0f;
       bool contrib = false;
-      float wgt = 0.0f;
       if (pos < my_last && ((band >> k) & 1u)) {
         const LRec s = s_r.get(k);
         PixEval e;
         if (eval_pixel(s, lx, ly, e)) {
           contrib = true;
-          const float one_m = 1.0f - e.alpha;
-          const float Tb = T / one_m;
-          const float w = e.alpha * Tb;
-          wgt = w;
+          // 1 / (1 - alpha) once for both quotients: alpha <= 0.99, so the
+          // reciprocal's relative error (about 1 ulp) stays that small
+          const float r1m = __builtin_amdgcn_rcpf(1.0f - e.alpha);
+          const float Tb = T * r1m;
+          w = e.alpha * Tb;
           const float u = e.u, vv = e.v, z = s.mz * e.iw;
           float eF = 0.0f;
           if (MODE == kTopK) {
             if (pos == nextsel) {
               eF = nextdot;
               --kp;
-              nextsel = kp >= 0 ? selpos[tbase + (size_t)kp * kTilePix + tid] : -1;
-              nextdot = kp >= 0 ? seldot[tbase + (size_t)kp * kTilePix + tid] : 0.0f;
+              nextsel = kp >= 0 ? s_sp[kp * kTilePix + tid] : -1;
+              nextdot = kp >= 0 ? s_sd[kp * kTilePix + tid] : 0.0f;
             }
           } else {
 #pragma unroll
@@ -383,32 +392,28 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
               if (q == k) eF = phi[q];
           }
           const float ei = gC0 * s.r + gC1 * s.g + gC2 * s.b + gD * z + gN0 * s.n0 + gN1 * s.n1 + gN2 * s.n2 + eF;
-          const float da = Tb * ei - (suffix - gA * Tfin) / one_m;
+          const float da = Tb * ei - (suffix - gA * Tfin) * r1m;
           suffix = fmaf(w, ei, suffix);
           T = Tb;
-          const float dop = e.clamped ? 0.0f : da * e.G;
+          dop = e.clamped ? 0.0f : da * e.G;
           const float drho = e.clamped ? 0.0f : -0.5f * da * e.alpha;
           const float du = 2.0f * u * drho, dv = 2.0f * vv * drho;
           const float dz = w * gD;
-          const float du1 = du * e.iw, dv1 = dv * e.iw;
-          const float dw1 = -(du * u + dv * vv + dz * z) * e.iw;
-          v[0] = du1 * e.dx; v[1] = du1 * e.dy; v[2] = du1;
-          v[3] = dv1 * e.dx; v[4] = dv1 * e.dy; v[5] = dv1;
-          v[6] = dw1 * e.dx; v[7] = dw1 * e.dy; v[8] = dw1;
-          v[9] = dz * e.iw;
-          v[10] = dop;
-          v[11] = w * gC0; v[12] = w * gC1; v[13] = w * gC2;
-          v[14] = w * gN0; v[15] = w * gN1; v[16] = w * gN2;
+          du1 = du * e.iw;
+          dv1 = dv * e.iw;
+          dw1 = -(du * u + dv * vv + dz * z) * e.iw;
+          dzi = dz * e.iw;
+          ex = e.dx;
+          ey = e.dy;
         }
       }
-      if constexpr (MODE == kFull) s_om[k][tid] = wgt;
+      if constexpr (MODE == kFull) s_om[k][tid] = w;
       const bool any = __any(contrib);
       if (any) {
-        float v16[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) v16[i] = v[i];
+        float v16[16] = {du1 * ex, du1 * ey, du1, dv1 * ex, dv1 * ey, dv1, dw1 * ex, dw1 * ey,
+                         dw1,      dzi,      dop, w * gC0,  w * gC1,  w * gC2, w * gN0,  w * gN1};
         const float tot = wave_reduce16(v16);
-        const float last = wave_sum(v[16]);
+        const float last = wave_sum(w * gN2);
         if ((lane & 3) == 0) s_part[wave][k][(lane >> 2) & 15] = tot;
         if (lane == 0) s_part[wave][k][16] = last;
       }
@@ -805,7 +810,8 @@ template <int MODE, typename FT, bool PERSIST>
 static void walk_bwd_launch_t(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
                               const ImageGradArgs& g, bool want_f, char* ws, hipStream_t st) {
   const void* k = reinterpret_cast<const void*>(&k_walk_bwd<MODE, FT, PERSIST>);
-  hipLaunchKernelGGL((k_walk_bwd<MODE, FT, PERSIST>), dim3(tile_grid(L, tu.sched_bwd, k, 0)), dim3(256), 0, st,
+  const size_t shm = MODE == kTopK ? (size_t)L.k * kTilePix * 8 : 0;  // selection positions + dots
+  hipLaunchKernelGGL((k_walk_bwd<MODE, FT, PERSIST>), dim3(tile_grid(L, tu.sched_bwd, k, shm)), dim3(256), shm, st,
                      (const WalkRec*)(ws + L.rec), (const float4*)(ws + L.ext), (const uint32_t*)(ws + L.pid),
                      (const uint32_t*)(ws + L.eid0), (const uint2*)(ws + L.ranges), ct,
                      tile_queue(L, tu.sched_bwd, ws, kQWalkBwd), L.k,

@@ -54,7 +54,7 @@ constexpr int kWalkChunk = 64;  // list entries a wave examines at once
 // slice by parallel vector loads, and the wave then evaluates them in list
 // order with broadcast reads.
 template <int KMAX, bool TOPK, bool PERSIST>
-__global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, const float4* __restrict__ ext,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_walk(const WalkRec* __restrict__ rec, const float4* __restrict__ ext,
                                               const uint32_t* __restrict__ pid,
                                               const uint2* __restrict__ ranges, CamTable ct, TileQueue tq,
                                               int K, float* __restrict__ o_rgb, float* __restrict__ o_depth,
@@ -83,15 +83,15 @@ __global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, c
   float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f, nx = 0.f, ny = 0.f, nz = 0.f;
   int last = 0, blended = 0, stop = -1;
   bool done = !inside;
-  float hw[KMAX];
-  int hp[KMAX];
+  // Top-K heap: one 64-bit key per entry, weight bits above the complemented
+  // list position.  Weights are positive, so unsigned key order is the order
+  // (weight, then earlier position) of eq. (18); an empty entry is key 0 and
+  // entries beyond K can never be the minimum.
+  uint64_t hk[KMAX];
 #pragma unroll
-  for (int q = 0; q < KMAX; ++q) {
-    hw[q] = q < K ? -1.0f : INFINITY;
-    hp[q] = -1;
-  }
-  float hmin = -1.0f;
-  int imin = 0, pmin = -1;
+  for (int q = 0; q < KMAX; ++q) hk[q] = q < K ? 0ull : ~0ull;
+  uint64_t kmin = 0ull;
+  int imin = 0;
 
   for (int base = 0; base < L; base += kWalkChunk) {
     if (__all(done)) break;
@@ -136,24 +136,22 @@ __global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, c
       T = Tn;
       ++blended;
       last = pos + 1;
-      if (TOPK && w > hmin) {
-        // replace the current minimum, then find the new minimum under the
-        // order (weight descending, position ascending)
+      if (TOPK) {
+        // a later position loses ties, so the new entry enters iff its key
+        // exceeds the minimum key; it replaces the minimum, then the new
+        // minimum is found (branch-free selects)
+        const uint64_t key = ((uint64_t)__float_as_uint(w) << 32) | (uint32_t)~(uint32_t)pos;
+        if (key > kmin) {
 #pragma unroll
-        for (int q = 0; q < KMAX; ++q) {
-          const bool hit = q == imin;
-          hw[q] = hit ? w : hw[q];
-          hp[q] = hit ? pos : hp[q];
-        }
-        hmin = hw[0];
-        pmin = hp[0];
-        imin = 0;
+          for (int q = 0; q < KMAX; ++q) hk[q] = q == imin ? key : hk[q];
+          kmin = hk[0];
+          imin = 0;
 #pragma unroll
-        for (int q = 1; q < KMAX; ++q) {
-          const bool lt = hw[q] < hmin || (hw[q] == hmin && hp[q] > pmin);
-          hmin = lt ? hw[q] : hmin;
-          pmin = lt ? hp[q] : pmin;
-          imin = lt ? q : imin;
+          for (int q = 1; q < KMAX; ++q) {
+            const bool lt = hk[q] < kmin;
+            kmin = lt ? hk[q] : kmin;
+            imin = lt ? q : imin;
+          }
         }
       }
     }
@@ -192,9 +190,14 @@ __global__ __launch_bounds__(256) void k_walk(const WalkRec* __restrict__ rec, c
     if (o_alpha) o_alpha[pix] = 1.0f - T;
   }
   if (TOPK) {
+    float hw[KMAX];
+    int hp[KMAX];
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q)
-      if (!(hw[q] >= 0.0f) || q >= K) hp[q] = 0x7FFFFFFF;
+    for (int q = 0; q < KMAX; ++q) {
+      const bool used = q < K && hk[q] != 0ull;
+      hw[q] = __uint_as_float((uint32_t)(hk[q] >> 32));
+      hp[q] = used ? (int)~(uint32_t)hk[q] : 0x7FFFFFFF;
+    }
     sort_by_position<KMAX>(hp, hw);
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) {

@@ -19,6 +19,8 @@
 //   the feature dot products and feature-gradient rows tile-wide.
 // k_reduce_geo / k_reduce_feat: per surfel, sum of its pairs' partials, then
 //   the chain rule to mu, s, q (FP64, as the forward's walk record).
+#include <type_traits>
+
 #include "common.h"
 #include "internal.h"
 #include "select.h"
@@ -39,14 +41,25 @@ constexpr int kNV = 17;          // per-pixel values reduced per surfel
 // and the weight matrix of a tile is dense enough (about half its entries)
 // that both run as dense FP32 matrix-core products.  Wave w owns pixels
 // [64 w, 64 w + 64): its dots tiles, and its share of the rows (a sum over
-// its pixels), added across the 4 waves in wave order.  Per pass of GC
-// channels G and F are staged in LDS with odd row strides, so the operand
-// reads (16 rows x 4 columns and 4 rows x 16 columns) meet almost no bank
-// conflicts; the next pass's loads are in flight during the products.
-// Every sum has a fixed order: results do not depend on the pass width or
-// the tile schedule.
-constexpr int kFbSlots = 64;             // slots per chunk: 4 blocks of 16
-constexpr int kWStride = kTilePix + 1;   // LDS row stride of the per-selection arrays
+// its pixels), added across the 4 waves in wave order.  The number of
+// 16-slot blocks of a chunk is a compile-time parameter of the product
+// loops (one instantiation per count), so they carry no branches.  Per pass
+// of GC channels G and F are staged in LDS; every layout below keeps the
+// operand reads free of bank conflicts (see the strides).  Every sum has a
+// fixed order: results do not depend on the pass width or the tile
+// schedule.
+constexpr int kFbSlots = 64;   // slots per chunk: 4 blocks of 16
+constexpr int kQStride = 72;   // bytes per pixel row of the selection map
+constexpr int kWRow = 288;     // floats per selection row of the weight array
+
+// Selection map: the byte of (pixel p, slot s) holds the index q of the
+// pixel's selection of s (0xFF = none); the 4 slots s = li + 16 sb share one
+// dword, so a lane reads its 4 slot blocks at once.
+__device__ __forceinline__ int qmap_off(int p, int s) { return p * kQStride + (s & 15) * 4 + (s >> 4); }
+// Weight (later dot) of selection q of pixel p.  Row offsets are 288 q plus
+// (q & 7) + 16 ((q >> 3) & 1), so the rows of the up to 16 selections of two
+// pixels 8 apart fall in disjoint bank sets.
+__device__ __forceinline__ int wsel_off(int q, int p) { return q * kWRow + (q & 7) + ((q & 8) << 1) + p; }
 
 template <typename FT, int KMAX, int GC, bool PERSIST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 ? 2 : 1))) void k_feat_bwd_topk(
@@ -55,15 +68,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
     const float* __restrict__ gfeat, int C, int K, CamTable ct, TileQueue tq, float* __restrict__ seldot,
     float* __restrict__ fpart, uint8_t* __restrict__ fflag) {
   static_assert(GC % 16 == 0, "pass width is a multiple of the MFMA tile");
-  constexpr int GS = GC + 1;               // row stride of the staged G, F (floats)
-  constexpr int NCB = GC / 16;             // channel blocks per pass
-  constexpr int FPT = kFbSlots * GC / 256; // staged F values per thread
+  // Row stride of the staged G and F: = 2 mod 4, so a 16-row x 2-column read
+  // (lanes 0-31 of an operand fetch) touches 32 distinct banks, and 8 rows
+  // apart is 16 banks apart.
+  constexpr int GS = GC + 2;
+  constexpr int NCB = GC / 16;              // channel blocks per pass
+  constexpr int FPT = kFbSlots * GC / 256;  // staged F values per thread
   __shared__ SelShared S;
-  __shared__ float s_G[kTilePix * GS];     // G rows of the pass; then the waves' partial rows
+  __shared__ __align__(16) float s_G[kTilePix * GS];  // G rows of the pass; then the waves' partial rows
   __shared__ float s_F[kFbSlots * GS];
-  __shared__ uint8_t s_q[kTilePix * kFbSlots];  // selection index of (pixel, slot), 0xFF = none
-  __shared__ uint32_t s_fe[kFbSlots];           // emitted pair index per slot
-  extern __shared__ float s_w[];                // [K][kWStride]: weights, replaced by dots
+  __shared__ __align__(16) uint8_t s_q[kTilePix * kQStride];
+  __shared__ uint32_t s_fe[kFbSlots];  // emitted pair index per slot
+  extern __shared__ float s_w[];       // selection weights, replaced by dots
   __shared__ int s_item;
 
   for_tiles<PERSIST>(tq, &s_item, [&](const int tile) {
@@ -91,7 +107,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) {
       // unselected entries keep weight 0 and report dot 0
-      if (q < K) s_w[q * kWStride + tid] = pos[q] >= 0 ? selw[tbase + (size_t)q * kTilePix + tid] : 0.0f;
+      if (q < K) s_w[wsel_off(q, tid)] = pos[q] >= 0 ? selw[tbase + (size_t)q * kTilePix + tid] : 0.0f;
       mymax = max(mymax, pos[q]);
     }
     maxpos = block_max(mymax, S.red);
@@ -107,17 +123,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
     }
     for (int c0 = 0; c0 < Uw; c0 += kFbSlots) {
       const int ns = min(kFbSlots, Uw - c0), nb = (ns + 15) >> 4;
-      for (int i = tid; i < kTilePix * kFbSlots / 16; i += 256)
+      for (int i = tid; i < kTilePix * kQStride / 16; i += 256)
         reinterpret_cast<uint4*>(s_q)[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
       __syncthreads();
-      int pos[KMAX];
-      load_pos(pos);
+      {
+        int pos[KMAX];
+        load_pos(pos);
 #pragma unroll
-      for (int q = 0; q < KMAX; ++q) {
-        const int sl = q < K ? slot_of(S, pos[q], w0, nw) - c0 : -1;
-        if (sl >= 0 && sl < ns) {
-          s_q[tid * kFbSlots + sl] = (uint8_t)q;
-          S.lpos[sl] = (uint32_t)pos[q];  // same value from every selecting pixel
+        for (int q = 0; q < KMAX; ++q) {
+          const int sl = q < K ? slot_of(S, pos[q], w0, nw) - c0 : -1;
+          if (sl >= 0 && sl < ns) {
+            s_q[qmap_off(tid, sl)] = (uint8_t)q;
+            S.lpos[sl] = (uint32_t)pos[q];  // same value from every selecting pixel
+          }
         }
       }
       __syncthreads();
@@ -127,111 +145,124 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
         S.fid[tid] = (uint32_t)(pid[j] - tl.v0);
       }
       __syncthreads();
-      f4v dacc[4][4];
-#pragma unroll
-      for (int pb = 0; pb < 4; ++pb)
-#pragma unroll
-        for (int sb = 0; sb < 4; ++sb) dacc[pb][sb] = f4v{0.f, 0.f, 0.f, 0.f};
 
-      float gv[GC], fv[FPT];
-      auto load_pass = [&](int cc) {
+      auto chunk = [&](auto nb_c) {
+        constexpr int NB = decltype(nb_c)::value;
+        f4v dacc[4][NB];
 #pragma unroll
-        for (int j = 0; j < GC / 4; ++j) {
-          const int c = cc + 4 * j;
-          const float4 g = inside && c < C ? *reinterpret_cast<const float4*>(grow + c) : make_float4(0.f, 0.f, 0.f, 0.f);
-          gv[4 * j] = g.x;
-          gv[4 * j + 1] = g.y;
-          gv[4 * j + 2] = g.z;
-          gv[4 * j + 3] = g.w;
-        }
+        for (int pb = 0; pb < 4; ++pb)
 #pragma unroll
-        for (int u = 0; u < FPT; ++u) {
-          const int item = tid + 256 * u, sidx = item / GC, c = cc + item % GC;
-          fv[u] = sidx < ns && c < C ? load_one<FT>(feat + (size_t)S.fid[sidx] * C + c) : 0.0f;
-        }
-      };
-      load_pass(0);
-      for (int cc = 0; cc < C; cc += GC) {
+          for (int sb = 0; sb < NB; ++sb) dacc[pb][sb] = f4v{0.f, 0.f, 0.f, 0.f};
+        float gv[GC], fv[FPT];
+        auto load_pass = [&](int cc) {
 #pragma unroll
-        for (int c = 0; c < GC; ++c) s_G[tid * GS + c] = gv[c];
+          for (int j = 0; j < GC / 4; ++j) {
+            const int c = cc + 4 * j;
+            const float4 g =
+                inside && c < C ? *reinterpret_cast<const float4*>(grow + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+            gv[4 * j] = g.x;
+            gv[4 * j + 1] = g.y;
+            gv[4 * j + 2] = g.z;
+            gv[4 * j + 3] = g.w;
+          }
 #pragma unroll
-        for (int u = 0; u < FPT; ++u) {
-          const int item = tid + 256 * u;
-          s_F[(item / GC) * GS + item % GC] = fv[u];
-        }
-        __syncthreads();
-        if (cc + GC < C) load_pass(cc + GC);
-        // dots: D[p][s] += G[p][c] F[s][c], 4 channels per step
+          for (int u = 0; u < FPT; ++u) {
+            const int item = tid + 256 * u, sidx = item / GC, c = cc + item % GC;
+            fv[u] = sidx < ns && c < C ? load_one<FT>(feat + (size_t)S.fid[sidx] * C + c) : 0.0f;
+          }
+        };
+        load_pass(0);
+        for (int cc = 0; cc < C; cc += GC) {
+#pragma unroll
+          for (int c = 0; c < GC; c += 2)
+            *reinterpret_cast<float2*>(s_G + tid * GS + c) = make_float2(gv[c], gv[c + 1]);
+#pragma unroll
+          for (int u = 0; u < FPT; ++u) {
+            const int item = tid + 256 * u;
+            s_F[(item / GC) * GS + item % GC] = fv[u];
+          }
+          __syncthreads();
+          if (cc + GC < C) load_pass(cc + GC);
+          // dots: D[p][s] += G[p][c] F[s][c], 4 channels per step
 #pragma unroll 2
-        for (int ks = 0; ks < GC / 4; ++ks) {
-          float fb[4];
+          for (int ks = 0; ks < GC / 4; ++ks) {
+            float fb[NB], ga[4];
 #pragma unroll
-          for (int sb = 0; sb < 4; ++sb) fb[sb] = sb < nb ? s_F[(16 * sb + li) * GS + 4 * ks + lk] : 0.0f;
+            for (int sb = 0; sb < NB; ++sb) fb[sb] = s_F[(16 * sb + li) * GS + 4 * ks + lk];
 #pragma unroll
-          for (int pb = 0; pb < 4; ++pb) {
-            const float ga = s_G[(p0 + 16 * pb + li) * GS + 4 * ks + lk];
+            for (int pb = 0; pb < 4; ++pb) ga[pb] = s_G[(p0 + 16 * pb + li) * GS + 4 * ks + lk];
 #pragma unroll
-            for (int sb = 0; sb < 4; ++sb)
-              if (sb < nb) dacc[pb][sb] = mfma_16x16x4(ga, fb[sb], dacc[pb][sb]);
+            for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+              for (int sb = 0; sb < NB; ++sb) dacc[pb][sb] = mfma_16x16x4(ga[pb], fb[sb], dacc[pb][sb]);
           }
-        }
-        // rows: R[s][c] += W[p][s] G[p][c] over this wave's pixels, 4 per step
-        f4v racc[4][NCB];
+          // rows: R[s][c] += W[p][s] G[p][c] over this wave's pixels; step ks
+          // takes the 4 pixels base + 8 k (k = lane group)
+          f4v racc[NB][NCB];
 #pragma unroll
-        for (int sb = 0; sb < 4; ++sb)
+          for (int sb = 0; sb < NB; ++sb)
 #pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) racc[sb][cb] = f4v{0.f, 0.f, 0.f, 0.f};
+            for (int cb = 0; cb < NCB; ++cb) racc[sb][cb] = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
-        for (int ks = 0; ks < 16; ++ks) {
-          // A operand W[p][s] at lane (s, p): the pixel's selection index of
-          // the slot, then its weight
-          const int p = p0 + 4 * ks + lk;
-          float wa[4];
+          for (int ks = 0; ks < 16; ++ks) {
+            const int p = p0 + (ks & 7) + 32 * (ks >> 3) + 8 * lk;
+            // A operand W[p][s] at lane (s, p): selection index, then weight
+            const uint32_t qd = *reinterpret_cast<const uint32_t*>(s_q + p * kQStride + 4 * li);
+            float wa[NB];
 #pragma unroll
-          for (int sb = 0; sb < 4; ++sb) {
-            const int q = sb < nb ? (int)s_q[p * kFbSlots + 16 * sb + li] : 0xFF;
-            wa[sb] = q != 0xFF ? s_w[q * kWStride + p] : 0.0f;
+            for (int sb = 0; sb < NB; ++sb) {
+              const int q = (int)((qd >> (8 * sb)) & 0xFFu);
+              const float x = s_w[wsel_off(min(q, K - 1), p)];  // always in range
+              wa[sb] = q != 0xFF ? x : 0.0f;
+            }
+            float gb[NCB];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) gb[cb] = s_G[p * GS + 16 * cb + li];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+              for (int sb = 0; sb < NB; ++sb) racc[sb][cb] = mfma_16x16x4(wa[sb], gb[cb], racc[sb][cb]);
           }
+          __syncthreads();  // every wave is done with the staged G
+          // partial row of slot s of wave w at row 64 w + perm(s), perm
+          // swapping bits 2 and 3 of s (lanes 0-31 then write 16 banks apart)
 #pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) {
-            const float gb = s_G[p * GS + 16 * cb + li];
+          for (int sb = 0; sb < NB; ++sb)
 #pragma unroll
-            for (int sb = 0; sb < 4; ++sb)
-              if (sb < nb) racc[sb][cb] = mfma_16x16x4(wa[sb], gb, racc[sb][cb]);
-          }
-        }
-        __syncthreads();  // every wave is done with the staged G
-#pragma unroll
-        for (int sb = 0; sb < 4; ++sb)
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb)
-            if (sb < nb) {
+            for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
               for (int r = 0; r < 4; ++r)
-                s_G[(p0 + 16 * sb + 4 * lk + r) * GS + 16 * cb + li] = racc[sb][cb][r];
-            }
-        __syncthreads();
-        for (int item = tid; item < ns * GC; item += 256) {
-          const int sidx = item / GC, c = item % GC;
-          const float* r = s_G + sidx * GS + c;
-          const float v = ((r[0] + r[64 * GS]) + r[128 * GS]) + r[192 * GS];
-          if (cc + c < C) fpart[(size_t)s_fe[sidx] * C + cc + c] = v;
+                s_G[(p0 + 16 * sb + 8 * (lk & 1) + 4 * (lk >> 1) + r) * GS + 16 * cb + li] = racc[sb][cb][r];
+          __syncthreads();
+          for (int item = tid; item < ns * GC; item += 256) {
+            const int sidx = item / GC, c = item % GC;
+            const int row = (sidx & ~12) | ((sidx & 4) << 1) | ((sidx & 8) >> 1);
+            const float* r = s_G + row * GS + c;
+            const float v = ((r[0] + r[64 * GS]) + r[128 * GS]) + r[192 * GS];
+            if (cc + c < C) fpart[(size_t)s_fe[sidx] * C + cc + c] = v;
+          }
+          __syncthreads();
         }
-        __syncthreads();
-      }
-      // dots of the selected entries replace their (already consumed) weights
+        // dots of the selected entries replace their (already consumed) weights
 #pragma unroll
-      for (int pb = 0; pb < 4; ++pb)
+        for (int pb = 0; pb < 4; ++pb)
 #pragma unroll
-        for (int sb = 0; sb < 4; ++sb)
-          if (sb < nb) {
+          for (int r = 0; r < 4; ++r) {
+            const int p = p0 + 16 * pb + 4 * lk + r;
+            const uint32_t qd = *reinterpret_cast<const uint32_t*>(s_q + p * kQStride + 4 * li);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int p = p0 + 16 * pb + 4 * lk + r;
-              const int q = s_q[p * kFbSlots + 16 * sb + li];
-              if (q != 0xFF) s_w[q * kWStride + p] = dacc[pb][sb][r];
+            for (int sb = 0; sb < NB; ++sb) {
+              const int q = (int)((qd >> (8 * sb)) & 0xFFu);
+              if (q != 0xFF) s_w[wsel_off(q, p)] = dacc[pb][sb][r];
             }
           }
+      };
+      switch (nb) {
+        case 1: chunk(std::integral_constant<int, 1>{}); break;
+        case 2: chunk(std::integral_constant<int, 2>{}); break;
+        case 3: chunk(std::integral_constant<int, 3>{}); break;
+        default: chunk(std::integral_constant<int, 4>{}); break;
+      }
       if (tid < ns) fflag[s_fe[tid]] = 1;
       __syncthreads();
     }
@@ -239,7 +270,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < KMAX; ++q)
-    if (q < K) seldot[tbase + (size_t)q * kTilePix + tid] = s_w[q * kWStride + tid];
+    if (q < K) seldot[tbase + (size_t)q * kTilePix + tid] = s_w[wsel_off(q, tid)];
   __syncthreads();
   });
 }
@@ -787,7 +818,7 @@ __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const 
 template <typename FT, int KMAX, int GC, bool PERSIST>
 static void feat_bwd_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
                             const ImageGradArgs& g, char* ws, hipStream_t st) {
-  const size_t shm = (size_t)kWStride * L.k * sizeof(float);  // weights, then dots
+  const size_t shm = (size_t)kWRow * L.k * sizeof(float);  // weights, then dots
   const void* k = reinterpret_cast<const void*>(&k_feat_bwd_topk<FT, KMAX, GC, PERSIST>);
   hipLaunchKernelGGL((k_feat_bwd_topk<FT, KMAX, GC, PERSIST>), dim3(tile_grid(L, tu.sched_bwd, k, shm)), dim3(256), shm, st,
                      (const uint32_t*)(ws + L.pid), (const uint32_t*)(ws + L.eid0), (const uint2*)(ws + L.ranges),

@@ -99,24 +99,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) pos[q] = q < K ? selpos[tbase + (size_t)q * kTilePix + tid] : -1;
   };
-  int maxpos;
+  // list positions are below the tile's list length, which bounds the
+  // windows (no block-wide maximum of the selections needed)
+  const int lastpos = (int)(ranges[tile].y - start) - 1;
+  int Uw0 = 0;
   {
     int pos[KMAX];
     load_pos(pos);
-    int mymax = -1;
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q) {
-      // unselected entries keep weight 0 and report dot 0
+    for (int q = 0; q < KMAX; ++q)  // unselected entries keep weight 0 and report dot 0
       if (q < K) s_w[wsel_off(q, tid)] = pos[q] >= 0 ? selw[tbase + (size_t)q * kTilePix + tid] : 0.0f;
-      mymax = max(mymax, pos[q]);
-    }
-    maxpos = block_max(mymax, S.red);
+    if (lastpos >= 0) Uw0 = build_window(S, pos, K, 0, window_words(lastpos, 0));
   }
 
-  for (int w0 = 0; w0 <= maxpos; w0 += kWinPos) {
-    const int nw = window_words(maxpos, w0);
-    int Uw;
-    {
+  for (int w0 = 0; w0 <= lastpos; w0 += kWinPos) {
+    const int nw = window_words(lastpos, w0);
+    int Uw = Uw0;
+    if (w0 > 0) {
       int pos[KMAX];
       load_pos(pos);
       Uw = build_window(S, pos, K, w0, nw);
@@ -153,6 +152,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
         for (int pb = 0; pb < 4; ++pb)
 #pragma unroll
           for (int sb = 0; sb < NB; ++sb) dacc[pb][sb] = f4v{0.f, 0.f, 0.f, 0.f};
+        // rows A operand for the whole chunk: W[p][s] at lane (s, p) of step
+        // ks, whose 4 pixels are base + 8 k (k = lane group)
+        float wa[NB][16];
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+          const int p = p0 + (ks & 7) + 32 * (ks >> 3) + 8 * lk;
+          const uint32_t qd = *reinterpret_cast<const uint32_t*>(s_q + p * kQStride + 4 * li);
+#pragma unroll
+          for (int sb = 0; sb < NB; ++sb) {
+            const int q = (int)((qd >> (8 * sb)) & 0xFFu);
+            const float x = s_w[wsel_off(min(q, K - 1), p)];  // always in range
+            wa[sb][ks] = q != 0xFF ? x : 0.0f;
+          }
+        }
         float gv[GC], fv[FPT];
         auto load_pass = [&](int cc) {
 #pragma unroll
@@ -203,25 +216,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
           for (int sb = 0; sb < NB; ++sb)
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) racc[sb][cb] = f4v{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+#pragma unroll
           for (int ks = 0; ks < 16; ++ks) {
             const int p = p0 + (ks & 7) + 32 * (ks >> 3) + 8 * lk;
-            // A operand W[p][s] at lane (s, p): selection index, then weight
-            const uint32_t qd = *reinterpret_cast<const uint32_t*>(s_q + p * kQStride + 4 * li);
-            float wa[NB];
-#pragma unroll
-            for (int sb = 0; sb < NB; ++sb) {
-              const int q = (int)((qd >> (8 * sb)) & 0xFFu);
-              const float x = s_w[wsel_off(min(q, K - 1), p)];  // always in range
-              wa[sb] = q != 0xFF ? x : 0.0f;
-            }
             float gb[NCB];
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) gb[cb] = s_G[p * GS + 16 * cb + li];
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-              for (int sb = 0; sb < NB; ++sb) racc[sb][cb] = mfma_16x16x4(wa[sb], gb[cb], racc[sb][cb]);
+              for (int sb = 0; sb < NB; ++sb) racc[sb][cb] = mfma_16x16x4(wa[sb][ks], gb[cb], racc[sb][cb]);
           }
           __syncthreads();  // every wave is done with the staged G
           // partial row of slot s of wave w at row 64 w + perm(s), perm

@@ -50,16 +50,11 @@ constexpr int kNV = 17;          // per-pixel values reduced per surfel
 // schedule.
 constexpr int kFbSlots = 64;   // slots per chunk: 4 blocks of 16
 constexpr int kQStride = 72;   // bytes per pixel row of the selection map
-constexpr int kWRow = 288;     // floats per selection row of the weight array
 
 // Selection map: the byte of (pixel p, slot s) holds the index q of the
 // pixel's selection of s (0xFF = none); the 4 slots s = li + 16 sb share one
 // dword, so a lane reads its 4 slot blocks at once.
 __device__ __forceinline__ int qmap_off(int p, int s) { return p * kQStride + (s & 15) * 4 + (s >> 4); }
-// Weight (later dot) of selection q of pixel p.  Row offsets are 288 q plus
-// (q & 7) + 16 ((q >> 3) & 1), so the rows of the up to 16 selections of two
-// pixels 8 apart fall in disjoint bank sets.
-__device__ __forceinline__ int wsel_off(int q, int p) { return q * kWRow + (q & 7) + ((q & 8) << 1) + p; }
 
 template <typename FT, int KMAX, int GC, bool PERSIST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 ? 2 : 1))) void k_feat_bwd_topk(

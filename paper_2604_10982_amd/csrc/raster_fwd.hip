@@ -269,14 +269,14 @@ __global__ __launch_bounds__(256) void k_blend_topk(const uint32_t* __restrict__
 
   int pos[KMAX];
   float w[KMAX];
-  int mymax = -1;
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) {
     pos[q] = q < K ? selpos[tbase + (size_t)q * kTilePix + tid] : -1;
     w[q] = q < K ? selw[tbase + (size_t)q * kTilePix + tid] : 0.0f;
-    mymax = max(mymax, pos[q]);
   }
-  const int maxpos = block_max(mymax, S.red);
+  // list positions are below the tile's list length, which bounds the
+  // windows (no block-wide maximum of the selections needed)
+  const int maxpos = (int)(ranges[tile].y - start) - 1;
 
   // One window whose slots fit one chunk: rank once, stage per channel pass.
   int sl[KMAX];

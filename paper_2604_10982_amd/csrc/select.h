@@ -103,6 +103,14 @@ __device__ __forceinline__ int slot_of(const SelShared& S, int pos, int w0, int 
   return (int)(S.pref[r >> 5] + (uint32_t)__popc(m & ((1u << (r & 31)) - 1u)));
 }
 
+// LDS array of the tile's selection weights, one row of 256 pixels per
+// selection index q (the feature kernels' matrix operand W[p][slot] is looked
+// up here).  Row offsets are 288 q plus (q & 7) + 16 ((q >> 3) & 1), so the
+// rows of the up to 16 selections of two pixels 8 apart fall in disjoint bank
+// sets.
+constexpr int kWRow = 288;  // floats per selection row
+__device__ __forceinline__ int wsel_off(int q, int p) { return q * kWRow + (q & 7) + ((q & 8) << 1) + p; }
+
 // Four consecutive feature channels as float.
 template <typename FT>
 __device__ __forceinline__ float4 load4(const FT* p);

@@ -75,16 +75,17 @@ def calibrate_copy():
 class Form:
     """One (tile mode, blend) configuration with preallocated buffers."""
 
-    def __init__(self, psm, t, cam, K, tile_mode, blend, gout, device, launch=None, tune=False):
+    def __init__(self, psm, t, cam, K, tile_mode, blend, gout, device, launch=None, tune=False, flags=0):
         import torch
         self.psm, self.t, self.K = psm, t, K
         self.tile_mode, self.blend = tile_mode, blend
         self.cam = psm.camera_struct(cam)
-        self.cfg = psm.config_struct(K, tile_mode, blend, psm.FLAG_NO_SYNC | psm.FLAG_PROFILE)
+        self.cfg = psm.config_struct(K, tile_mode, blend, psm.FLAG_NO_SYNC | psm.FLAG_PROFILE | flags)
         self.s = psm._surfels(t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"])
         _, ws = psm.forward(t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"], self.cam, K,
-                            tile_mode, blend)
-        st = psm.read_stats(ws, self.s.n, self.cam, psm.config_struct(K, tile_mode, blend), self.s.c, ws.capacity)
+                            tile_mode, blend, flags=flags)
+        st = psm.read_stats(ws, self.s.n, self.cam, psm.config_struct(K, tile_mode, blend, flags), self.s.c,
+                            ws.capacity)
         cap = int(st.pairs_required * 1.05 + 4096)
         self.ws = psm.alloc_workspace(self.s.n, self.cam, self.cfg, self.s.c, cap, device)
         self.out = psm.alloc_images(self.cam, self.s.c, device)
@@ -414,6 +415,16 @@ def main():
     head_launch = head.launch()
     head_tuned_ms = head.tuned_ms
     del head
+    # exact work reduction: the opacity-aware footprint (same outputs, fewer pairs)
+    opa = Form(psm, t, cam, K, "ellipse", "topk", gout, device, launch=head_launch, flags=psm.FLAG_OPACITY_FOOTPRINT)
+    ms_opa, _, st_opa = timed(opa, True, args.steps, args.warmup)
+    print(f"[bench] opacity-aware footprint fwd+bwd {ms_opa:.3f} ms, pairs {st_opa.pairs} (standard {st.pairs})",
+          file=sys.stderr, flush=True)
+    opacity_footprint = {"fwd_bwd_ms": ms_opa, "fwd_bwd_its": 1000.0 / ms_opa, "pairs": int(st_opa.pairs),
+                         "pairs_standard": int(st.pairs),
+                         "note": "PSM_FLAG_OPACITY_FOOTPRINT: tile footprint of rho <= min(9, 2 ln(255 o)); "
+                                 "outputs and gradients bit-identical to the standard footprint"}
+    del opa
     base = Form(psm, t, cam, K, "aabb", "full", gout, device, tune=launch is None)
     ms_base_step, stages_base, st_base = timed(base, True, max(3, args.steps // 2), 2)
     ms_base_fwd, _, _ = timed(base, False, max(3, args.steps // 2), 2)
@@ -456,6 +467,7 @@ def main():
                             "fwd_ms": ms_base_fwd, "fwd_bwd_ms": ms_base_step, "pairs": int(st_base.pairs),
                             "stages_ms": stages_base},
         "speedup_vs_dense_aabb": {"fwd": ms_base_fwd / ms_fwd, "fwd_bwd": ms_base_step / ms_step},
+        "opacity_footprint": opacity_footprint,
         "pairs": int(st.pairs), "pairs_walked": int(st.pairs_walked), "contributors": int(st.contributors),
         "visible": int(st.visible),
         "stages_ms": stages,

@@ -105,6 +105,13 @@ typedef enum { PSM_SCHED_GRID = 0, PSM_SCHED_PERSISTENT = 1 } psm_schedule;
 /* Record a HIP event pair around every stage on the call's stream; read the
  * accumulated stage times with psm_profile_read. */
 #define PSM_FLAG_PROFILE 2
+/* Opacity-aware footprint (an exact work reduction of the key stage): a pixel
+ * is skipped when alpha = o exp(-rho/2) < 1/255 (Sec. 3.1), so a surfel's tile
+ * footprint is the ellipse of rho <= min(9, 2 ln(255 o)) (plus a 2^-10 margin,
+ * rounded up to a multiple of 2^-12) instead of rho <= 9.  Cull decisions,
+ * images, selections and gradients are unchanged bit for bit; faint surfels
+ * emit fewer (tile, surfel) pairs. */
+#define PSM_FLAG_OPACITY_FOOTPRINT 4
 
 typedef struct { float *rgb, *depth, *normal, *alpha, *feat; } psm_images;
 typedef struct { const float *rgb, *depth, *normal, *alpha, *feat; } psm_image_grads;

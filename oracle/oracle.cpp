@@ -77,7 +77,22 @@ struct KeyF {
   float ecx, ecy, S00, S01, S11, ex, ey, gam, kk;  // ellipse centre, shape; kk = |c * det A|
 };
 
-KeyF key_f32(const float* mu, const float* sc, const float* q, const Cam& k) {
+// Opacity-aware footprint bound (exact work reduction, reading of Sec. 3.1):
+// alpha = o G < 1/255 skips a pixel, G = exp(-rho/2), so only rho <=
+// 2 ln(255 o) can contribute.  The bound is widened by 2^-10 (absolute, then
+// relative), rounded up to the 2^-12 grid in double precision, kept at least
+// 2^-12 and at most the standard footprint radius^2.
+float opacity_foot2_f32(float o) {
+  double bound = 2.0 * std::log(255.0 * (double)o);
+  double widened = (bound + 1.0 / 1024.0) * (1.0 + 1.0 / 1024.0);
+  double grid = std::ceil(widened * 4096.0) / 4096.0;
+  if (!(grid >= 1.0 / 4096.0)) grid = 1.0 / 4096.0;
+  if (grid > (double)kFoot2F) grid = (double)kFoot2F;
+  return (float)grid;
+}
+
+// foot2: radius^2 of the listed footprint; culling always uses kFoot2F.
+KeyF key_f32(const float* mu, const float* sc, const float* q, const Cam& k, float foot2 = kFoot2F) {
   KeyF r;
   std::memset(&r, 0, sizeof(r));
   // quaternion (w,x,y,z) -> unit
@@ -131,6 +146,14 @@ KeyF key_f32(const float* mu, const float* sc, const float* q, const Cam& k) {
   float S11 = cc * ((A10 * A10 + A11 * A11) + cc * (w1 * w1));
   if (!(S00 > 0.0f && S11 > 0.0f && S00 < 1e24f && S11 < 1e24f)) {
     r.cull = kCullDegenerate; return r;
+  }
+  if (foot2 != kFoot2F) {
+    // smaller listed footprint: the same shape formulas at radius^2 foot2
+    gam = 1.0f - foot2 * g2;
+    cc = foot2 / gam;
+    S00 = cc * ((A00 * A00 + A01 * A01) + cc * (w0 * w0));
+    S01 = cc * ((A00 * A10 + A01 * A11) + cc * (w0 * w1));
+    S11 = cc * ((A10 * A10 + A11 * A11) + cc * (w1 * w1));
   }
   r.cull = kVisible;
   r.depth_bits = fbits(mc[2]);
@@ -452,8 +475,9 @@ extern "C" {
 // `mode`, and 8 footprint floats (ellipse centre x y, S00 S01 S11, ex ey, gamma) when fp_out
 // is non-null.  If cap >= P, also writes the P pairs sorted by
 // (tile, depth bits, surfel id).  Returns P.
+// opacity: non-null selects the opacity-aware footprint (per-surfel opacities).
 int64_t orc_keystage(int64_t n, const float* means, const float* scales, const float* quats,
-                     const float* cam, int tw, int th, int mode,
+                     const float* opacity, const float* cam, int tw, int th, int mode,
                      int32_t* cull_out, uint32_t* depth_out, int32_t* flip_out, int32_t* count_out,
                      float* fp_out, int64_t cap, int32_t* tile_out, int32_t* id_out) {
   Cam k = load_cam(cam);
@@ -465,7 +489,8 @@ int64_t orc_keystage(int64_t n, const float* means, const float* scales, const f
     std::vector<Row> rows;
 #pragma omp for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
-      key[i] = key_f32(means + 3 * i, scales + 2 * i, quats + 4 * i, k);
+      const float foot2 = opacity ? opacity_foot2_f32(opacity[i]) : kFoot2F;
+      key[i] = key_f32(means + 3 * i, scales + 2 * i, quats + 4 * i, k, foot2);
       if (key[i].cull == kVisible) {
         footprint(key[i], k, tw, th, mode, rows);
         int64_t c = 0;

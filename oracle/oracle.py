@@ -48,7 +48,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int
         L.orc_keystage.restype = i64
-        L.orc_keystage.argtypes = [i64, vp, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, i64, vp, vp]
+        L.orc_keystage.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, i64, vp, vp]
         L.orc_eval_points.restype = None
         L.orc_eval_points.argtypes = [i64, vp, vp, vp, vp, i64, vp, vp, vp, vp]
         L.orc_render.restype = None
@@ -76,12 +76,15 @@ def _scene_args(scene):
     return (_c32(scene.means), _c32(scene.scales), _c32(scene.quats))
 
 
-def keystage(scene, cam, mode="ellipse", tile=16, pairs=True) -> dict:
+def keystage(scene, cam, mode="ellipse", tile=16, pairs=True, opacity_footprint=False) -> dict:
     """FP32 key stage: cull codes, depth bits, flips, counts, footprint floats
-    and (optionally) the sorted pair list (tile ids, surfel ids)."""
+    and (optionally) the sorted pair list (tile ids, surfel ids).
+    ``opacity_footprint``: list the footprint of rho <= min(9, 2 ln(255 o))
+    (widened and rounded up, see oracle.cpp) instead of rho <= 9."""
     m = MODES[mode] if isinstance(mode, str) else int(mode)
     n = scene.n
     mu, sc, q = _scene_args(scene)
+    op = _c32(scene.opacity) if opacity_footprint else None
     camv = cam.as_array()
     cull = np.zeros(n, np.int32)
     depth = np.zeros(n, np.uint32)
@@ -89,13 +92,13 @@ def keystage(scene, cam, mode="ellipse", tile=16, pairs=True) -> dict:
     count = np.zeros(n, np.int32)
     fp = np.zeros((n, 8), np.float32)
     L = lib()
-    P = L.orc_keystage(n, _vp(mu), _vp(sc), _vp(q), _vp(camv), tile, tile, m,
+    P = L.orc_keystage(n, _vp(mu), _vp(sc), _vp(q), _vp(op), _vp(camv), tile, tile, m,
                        _vp(cull), _vp(depth), _vp(flip), _vp(count), _vp(fp), 0, None, None)
     out = {"cull": cull, "depth_bits": depth, "flip": flip, "count": count, "fp": fp, "P": int(P)}
     if pairs:
         tiles = np.zeros(max(P, 1), np.int32)
         ids = np.zeros(max(P, 1), np.int32)
-        L.orc_keystage(n, _vp(mu), _vp(sc), _vp(q), _vp(camv), tile, tile, m,
+        L.orc_keystage(n, _vp(mu), _vp(sc), _vp(q), _vp(op), _vp(camv), tile, tile, m,
                        None, None, None, None, None, P, _vp(tiles), _vp(ids))
         out["tile"] = tiles[:P]
         out["id"] = ids[:P]

@@ -270,7 +270,7 @@ void enqueue_forward(const SurfelArgs& sa, const CamTable& ct, const psm_config*
   launch_fill_u32(ws + L.ranges, 0u, L.tiles * 2, st);
   prof.end(kStageFill, st);
   prof.begin(kStagePreprocess, st);
-  launch_preprocess(sa, ct, cfg->tile_mode, L, ws, st);
+  launch_preprocess(sa, ct, cfg->tile_mode, (cfg->flags & PSM_FLAG_OPACITY_FOOTPRINT) != 0, L, ws, st);
   prof.end(kStagePreprocess, st);
   prof.begin(kStageDepthSort, st);
   radix_sort_pairs((uint32_t*)(ws + L.key0), (uint32_t*)(ws + L.id0), (uint32_t*)(ws + L.key1),

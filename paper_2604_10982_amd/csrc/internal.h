@@ -54,8 +54,8 @@ enum : int { kSchedGrid = 0, kSchedPersistent = 1 };
 // keystage.hip
 void launch_fill_u32(void* p, uint32_t v, int64_t count, hipStream_t st);
 void launch_init_status(uint32_t* status, int64_t n, int64_t tiles, hipStream_t st);
-void launch_preprocess(const SurfelArgs& s, const CamTable& ct, int mode, const Layout& L, char* ws,
-                       hipStream_t st);
+void launch_preprocess(const SurfelArgs& s, const CamTable& ct, int mode, bool opacity_foot, const Layout& L,
+                       char* ws, hipStream_t st);
 void launch_scan_counts(const Layout& L, char* ws, hipStream_t st);
 void launch_emit(const CamTable& ct, int mode, const Layout& L, char* ws, hipStream_t st);
 void launch_ranges(const Layout& L, char* ws, hipStream_t st);

@@ -31,7 +31,22 @@ struct Key {
   Foot f;
 };
 
-__device__ __noinline__ Key key_stage(const float* mu, const float* sc, const float* qq, const Cam& k) {
+// Opacity-aware footprint radius^2 (an exact work reduction): a pixel is
+// skipped when alpha = o exp(-rho/2) < 1/255 (Sec. 3.1), i.e. when
+// rho > 2 ln(255 o), so a surfel's footprint only needs rho <= min(9,
+// 2 ln(255 o)).  The bound gets a 2^-10 absolute and relative margin (the
+// per-pixel FP32 alpha is within a few ulp of exact) and is rounded up to a
+// multiple of 2^-12 in FP64, which is exact in FP32, so correctly rounded
+// and faithful FP64 logarithms give the same value.
+__device__ __forceinline__ float opacity_foot2(float o) {
+  const double L = 2.0 * log(255.0 * (double)o);
+  const double r = ceil((L + 0x1p-10) * (1.0 + 0x1p-10) * 4096.0) * (1.0 / 4096.0);
+  return (float)fmin((double)kFoot2, fmax(r, 1.0 / 4096.0));
+}
+
+// foot2: footprint radius^2 (kFoot2, or the opacity-aware bound).  The cull
+// decisions always use kFoot2, so both footprints keep the same visible set.
+__device__ __noinline__ Key key_stage(const float* mu, const float* sc, const float* qq, const Cam& k, float foot2) {
   Key r;
   r.cull = 0;
   r.flip = 0;
@@ -76,12 +91,20 @@ __device__ __noinline__ Key key_stage(const float* mu, const float* sc, const fl
   const float A11 = k.fy * ((b[1] - my * b[2]) * iz);
   const float dA = A00 * A11 - A01 * A10;
   if (!(fabsf(dA) > 0.0f)) { r.cull = 4; return r; }
-  const float cc = kFoot2 / gam;
+  float cc = kFoot2 / gam;
   const float w0 = A00 * p + A01 * q, w1 = A10 * p + A11 * q;
-  const float S00 = cc * ((A00 * A00 + A01 * A01) + cc * (w0 * w0));
-  const float S01 = cc * ((A00 * A10 + A01 * A11) + cc * (w0 * w1));
-  const float S11 = cc * ((A10 * A10 + A11 * A11) + cc * (w1 * w1));
+  float S00 = cc * ((A00 * A00 + A01 * A01) + cc * (w0 * w0));
+  float S01 = cc * ((A00 * A10 + A01 * A11) + cc * (w0 * w1));
+  float S11 = cc * ((A10 * A10 + A11 * A11) + cc * (w1 * w1));
   if (!(S00 > 0.0f && S11 > 0.0f && S00 < 1e24f && S11 < 1e24f)) { r.cull = 4; return r; }
+  float gf = gam;
+  if (foot2 != kFoot2) {  // the same ellipse formulas at the smaller radius
+    gf = 1.0f - foot2 * g2;
+    cc = foot2 / gf;
+    S00 = cc * ((A00 * A00 + A01 * A01) + cc * (w0 * w0));
+    S01 = cc * ((A00 * A10 + A01 * A11) + cc * (w0 * w1));
+    S11 = cc * ((A10 * A10 + A11 * A11) + cc * (w1 * w1));
+  }
   r.mc2 = mc[2]; r.p = p; r.q = q; r.xc = xc; r.yc = yc;
   r.A00 = A00; r.A01 = A01; r.A10 = A10; r.A11 = A11; r.dA = dA;
   r.f.ecx = xc - cc * w0;
@@ -89,7 +112,7 @@ __device__ __noinline__ Key key_stage(const float* mu, const float* sc, const fl
   r.f.S00 = S00; r.f.S01 = S01; r.f.S11 = S11;
   r.f.ex = sqrtf(S00);
   r.f.ey = sqrtf(S11);
-  r.f.gam = gam;
+  r.f.gam = gf;
   r.f.kk = fabsf(cc * dA);
   return r;
 }
@@ -199,7 +222,8 @@ __global__ void k_init_status(uint32_t* __restrict__ st, uint32_t n, uint32_t ti
 __global__ __launch_bounds__(256) void k_preprocess(
     int64_t nv, const float* __restrict__ means, const float* __restrict__ scales,
     const float* __restrict__ quats, const float* __restrict__ opacity, const float* __restrict__ rgb,
-    CamTable ct, int mode, WalkRec* __restrict__ rec, float4* __restrict__ fp, float4* __restrict__ ext,
+    CamTable ct, int mode, int opacity_foot, WalkRec* __restrict__ rec, float4* __restrict__ fp,
+    float4* __restrict__ ext,
     uint32_t* __restrict__ key, uint32_t* __restrict__ ids, uint32_t* __restrict__ count,
     int32_t* __restrict__ cull, uint32_t* __restrict__ status) {
   __shared__ uint32_t s_cnt[5];
@@ -214,7 +238,8 @@ __global__ __launch_bounds__(256) void k_preprocess(
     const int b = camera_of(ct, v);
     const int64_t i = v - (int64_t)b * ct.nsurf;
     const Cam& cam = s_cam[b];
-    const Key kk = key_stage(means + 3 * i, scales + 2 * i, quats + 4 * i, cam);
+    const float foot2 = opacity_foot ? opacity_foot2(opacity[i]) : kFoot2;
+    const Key kk = key_stage(means + 3 * i, scales + 2 * i, quats + 4 * i, cam, foot2);
     ids[v] = (uint32_t)v;
     cull[v] = kk.cull | (kk.flip << 8);  // bit 8: normal flipped toward the camera
     atomicAdd(&s_cnt[kk.cull], 1u);
@@ -429,11 +454,12 @@ void launch_init_status(uint32_t* status, int64_t n, int64_t tiles, hipStream_t 
   hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, st, status, (uint32_t)n, (uint32_t)tiles);
 }
 
-void launch_preprocess(const SurfelArgs& s, const CamTable& ct, int mode, const Layout& L, char* ws,
-                       hipStream_t st) {
+void launch_preprocess(const SurfelArgs& s, const CamTable& ct, int mode, bool opacity_foot, const Layout& L,
+                       char* ws, hipStream_t st) {
   if (L.n == 0) return;
   hipLaunchKernelGGL(k_preprocess, dim3((unsigned)cdiv(L.n, 256)), dim3(256), 0, st, L.n, s.means, s.scales,
-                     s.quats, s.opacity, s.rgb, ct, mode, (WalkRec*)(ws + L.rec), (float4*)(ws + L.fp),
+                     s.quats, s.opacity, s.rgb, ct, mode, opacity_foot ? 1 : 0, (WalkRec*)(ws + L.rec),
+                     (float4*)(ws + L.fp),
                      (float4*)(ws + L.ext),
                      (uint32_t*)(ws + L.key0), (uint32_t*)(ws + L.id0), (uint32_t*)(ws + L.count),
                      (int32_t*)(ws + L.cull), (uint32_t*)(ws + L.status));

@@ -23,6 +23,7 @@ BLENDS = {"full": 0, "topk": 1}
 DTYPES = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2}
 FLAG_NO_SYNC = 1
 FLAG_PROFILE = 2
+FLAG_OPACITY_FOOTPRINT = 4
 NUM_STAGES = 12
 SCHED_GRID, SCHED_PERSISTENT = 0, 1
 MAX_CAMERAS = 8
@@ -275,14 +276,16 @@ def backward_into(ctx: Context, s: Surfels, cam: Camera, cfg: Config, ws: Worksp
 
 
 def forward(means, scales, quats, opacity, rgb, feat, camera, k=16, tile_mode="ellipse", blend="topk",
-            capacity: int | None = None, ws: Workspace | None = None):
+            capacity: int | None = None, ws: Workspace | None = None, flags: int = 0):
     """Render; returns (images dict, workspace).  The workspace holds the
-    state the backward needs.  Re-allocates once if the pairs do not fit."""
+    state the backward needs.  Re-allocates once if the pairs do not fit.
+    ``flags``: FLAG_* options of the key stage and the walks (e.g.
+    FLAG_OPACITY_FOOTPRINT); the backward takes the same flags."""
     device = means.device
     ctx = context(device.index or 0)
     s = _surfels(means, scales, quats, opacity, rgb, feat)
     cam = camera if isinstance(camera, Camera) else camera_struct(camera)
-    cfg = config_struct(k, tile_mode, blend)
+    cfg = config_struct(k, tile_mode, blend, flags)
     out = alloc_images(cam, s.c, device)
     cap = capacity if capacity is not None else (ws.capacity if ws is not None else capacity_guess(s.n, cam))
     for attempt in range(3):
@@ -299,12 +302,12 @@ def forward(means, scales, quats, opacity, rgb, feat, camera, k=16, tile_mode="e
 
 
 def backward(means, scales, quats, opacity, rgb, feat, camera, ws: Workspace, gout: dict, k=16,
-             tile_mode="ellipse", blend="topk") -> dict:
+             tile_mode="ellipse", blend="topk", flags: int = 0) -> dict:
     device = means.device
     ctx = context(device.index or 0)
     s = _surfels(means, scales, quats, opacity, rgb, feat)
     cam = camera if isinstance(camera, Camera) else camera_struct(camera)
-    cfg = config_struct(k, tile_mode, blend)
+    cfg = config_struct(k, tile_mode, blend, flags)
     n = s.n
     z = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=device)
     grads = {"means": z(n, 3), "scales": z(n, 2), "quats": z(n, 4), "opacity": z(n), "rgb": z(n, 3),

@@ -194,3 +194,95 @@ def test_precise_tile_reduces_pairs_on_plane_scenes(orc):
     p = {m: orc.keystage(sc, cam, m, pairs=False)["P"] for m in ("sphere", "aabb", "ellipse")}
     assert p["ellipse"] < p["aabb"] < p["sphere"]
     assert p["ellipse"] < 0.8 * p["sphere"]
+
+
+# ---------------------------------------------------------------- opacity-aware footprint
+def _opacity_r2(o):
+    """Listed radius^2 of the opacity-aware footprint, restated from its
+    definition: alpha = o exp(-rho/2) >= 1/255 needs rho <= 2 ln(255 o); the
+    bound is widened by 2^-10 (absolute, then relative), rounded up to a
+    multiple of 2^-12, and clamped to [2^-12, R_FOOT2]."""
+    b = 2.0 * math.log(255.0 * float(o)) if o > 0 else -math.inf
+    r = math.ceil((b + 2.0 ** -10) * (1.0 + 2.0 ** -10) * 4096.0) / 4096.0 if b > -math.inf else 0.0
+    return min(R_FOOT2, max(r, 2.0 ** -12))
+
+
+def faint_scene(n=300, seed=9, c=8):
+    """varied_scene with mostly faint surfels (opacities down to below 1/255)."""
+    sc = varied_scene(n, seed, c)
+    rng = np.random.default_rng(seed + 1)
+    op = np.clip(rng.beta(0.6, 3.0, n), 0.002, 0.99).astype(np.float32)
+    return Scene(sc.means, sc.scales, sc.quats, op, sc.rgb, sc.feat)
+
+
+def test_opacity_footprint_no_false_negatives_and_subset(orc):
+    sc, cam = faint_scene(), pinhole(96, 80, f=80.0)
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    rho, _ = orc.eval_points(sc, cam, xs.ravel() + 0.5, ys.ravel() + 0.5)
+    alpha = sc.opacity.astype(np.float64)[:, None] * np.exp(-0.5 * rho)
+    tile_of_pix = (ys.ravel() // 16) * ((cam.width + 15) // 16) + xs.ravel() // 16
+    si, pi = np.nonzero((rho <= 9.0) & (alpha >= 1.0 / 255.0))
+    required = set(zip(tile_of_pix[pi].tolist(), si.tolist()))
+    assert len(required) > 200
+    for mode in ("sphere", "aabb", "ellipse"):
+        std = orc.keystage(sc, cam, mode)
+        opa = orc.keystage(sc, cam, mode, opacity_footprint=True)
+        got = pair_set(opa)
+        assert not (required - got), mode
+        assert got <= pair_set(std), mode
+        assert opa["P"] < 0.9 * std["P"], mode
+        # culling and depth keys do not change
+        np.testing.assert_array_equal(opa["cull"], std["cull"])
+        np.testing.assert_array_equal(opa["depth_bits"], std["depth_bits"])
+
+
+def test_opacity_footprint_is_the_exact_ellipse_of_its_radius(orc):
+    sc, cam = faint_scene(), pinhole(96, 80, f=80.0)
+    ks = orc.keystage(sc, cam, "ellipse", opacity_footprint=True)
+    got = pair_set(ks)
+    ntx, nty = (cam.width + 15) // 16, (cam.height + 15) // 16
+    checked = mism = 0
+    for i in np.nonzero(ks["cull"] == 0)[0]:
+        M = _camera_matrix(sc, cam, i)
+        r2 = _opacity_r2(sc.opacity[i])
+        for ty in range(nty):
+            for tx in range(ntx):
+                hull = (16 * tx + 0.5, min(16 * tx + 15.5, cam.width - 0.5),
+                        16 * ty + 0.5, min(16 * ty + 15.5, cam.height - 0.5))
+                lo = _ellipse_meets(M, r2 * (1 - 1e-4), hull)
+                hi = _ellipse_meets(M, r2 * (1 + 1e-4), hull)
+                listed = (ty * ntx + tx, int(i)) in got
+                checked += 1
+                if lo == hi:
+                    assert listed == lo, (i, tx, ty)
+                else:
+                    mism += 1
+    assert checked > 5000
+    assert mism < 0.01 * checked
+
+
+@pytest.mark.parametrize("o", [0.05, 0.2, 1.0 / 255.0, 0.9])
+def test_opacity_circle_footprint_by_hand(orc, o):
+    cam = pinhole(160, 128, f=100.0)
+    X0, Y0, z0, s = 0.13, -0.07, 2.5, 0.21
+    sc = Scene(np.array([[X0, Y0, z0]], np.float32), np.array([[s, s]], np.float32),
+               np.array([[1, 0, 0, 0]], np.float32), np.array([o], np.float32),
+               np.ones((1, 3), np.float32), np.zeros((1, 4), np.float32))
+    f32 = lambda v: float(np.float32(v))
+    X0, Y0, z0, s = map(f32, (X0, Y0, z0, s))
+    xc, yc = cam.fx * X0 / z0 + cam.cx, cam.fy * Y0 / z0 + cam.cy
+    R = math.sqrt(_opacity_r2(np.float32(o))) * cam.fx * s / z0
+    ntx, nty = 10, 8
+    exp = set()
+    for ty in range(nty):
+        for tx in range(ntx):
+            dx = max(16 * tx + 0.5 - xc, 0, xc - (16 * tx + 15.5))
+            dy = max(16 * ty + 0.5 - yc, 0, yc - (16 * ty + 15.5))
+            d = math.hypot(dx, dy)
+            assert abs(d - R) > 1e-3 * R
+            if d <= R:
+                exp.add(ty * ntx + tx)
+    ks = orc.keystage(sc, cam, "ellipse", opacity_footprint=True)
+    assert set(ks["tile"].tolist()) == exp
+    if o >= 0.5:   # 2 ln(255 o) > 9: the standard footprint
+        assert set(orc.keystage(sc, cam, "ellipse")["tile"].tolist()) == exp

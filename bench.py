@@ -88,7 +88,10 @@ class Form:
                             ws.capacity)
         cap = int(st.pairs_required * 1.05 + 4096)
         self.ws = psm.alloc_workspace(self.s.n, self.cam, self.cfg, self.s.c, cap, device)
-        self.out = psm.alloc_images(self.cam, self.s.c, device)
+        feature_only = bool(flags & psm.FLAG_FEATURE_ONLY)
+        self.out = psm.alloc_images(self.cam, self.s.c, device, feature_only=feature_only)
+        if feature_only:  # only the feature map is rendered, so only its upstream gradient
+            gout = {k: (v if k == "feat" else None) for k, v in gout.items()}
         n, c = self.s.n, self.s.c
         z = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=device)
         self.grads = {"means": z(n, 3), "scales": z(n, 2), "quats": z(n, 4), "opacity": z(n), "rgb": z(n, 3),
@@ -425,6 +428,18 @@ def main():
                          "note": "PSM_FLAG_OPACITY_FOOTPRINT: tile footprint of rho <= min(9, 2 ln(255 o)); "
                                  "outputs and gradients bit-identical to the standard footprint"}
     del opa
+    # exact work reduction: feature-only rendering stops a pixel once its Top-K set is final
+    fo = Form(psm, t, cam, K, "ellipse", "topk", gout, device, launch=head_launch, flags=psm.FLAG_FEATURE_ONLY)
+    ms_fo_step, stages_fo, st_fo = timed(fo, True, args.steps, args.warmup)
+    ms_fo_fwd, _, _ = timed(fo, False, args.steps, args.warmup)
+    print(f"[bench] feature-only fwd {ms_fo_fwd:.3f} ms, fwd+bwd {ms_fo_step:.3f} ms, contributors "
+          f"{st_fo.contributors} (full walk {st.contributors})", file=sys.stderr, flush=True)
+    feature_only = {"fwd_ms": ms_fo_fwd, "fwd_fps": 1000.0 / ms_fo_fwd, "fwd_bwd_ms": ms_fo_step,
+                    "fwd_bwd_its": 1000.0 / ms_fo_step, "contributors": int(st_fo.contributors),
+                    "contributors_full_walk": int(st.contributors), "walk_ms": stages_fo.get("walk"),
+                    "note": "PSM_FLAG_FEATURE_ONLY: feature map and Top-K selection bit-identical to the full walk; "
+                            "no RGB/depth/normal/alpha maps; backward of the feature loss"}
+    del fo
     base = Form(psm, t, cam, K, "aabb", "full", gout, device, tune=launch is None)
     ms_base_step, stages_base, st_base = timed(base, True, max(3, args.steps // 2), 2)
     ms_base_fwd, _, _ = timed(base, False, max(3, args.steps // 2), 2)
@@ -468,6 +483,7 @@ def main():
                             "stages_ms": stages_base},
         "speedup_vs_dense_aabb": {"fwd": ms_base_fwd / ms_fwd, "fwd_bwd": ms_base_step / ms_step},
         "opacity_footprint": opacity_footprint,
+        "feature_only": feature_only,
         "pairs": int(st.pairs), "pairs_walked": int(st.pairs_walked), "contributors": int(st.contributors),
         "visible": int(st.visible),
         "stages_ms": stages,

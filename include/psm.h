@@ -112,6 +112,15 @@ typedef enum { PSM_SCHED_GRID = 0, PSM_SCHED_PERSISTENT = 1 } psm_schedule;
  * images, selections and gradients are unchanged bit for bit; faint surfels
  * emit fewer (tile, surfel) pairs. */
 #define PSM_FLAG_OPACITY_FOOTPRINT 4
+/* Feature-only rendering (an exact work reduction of the forward walk): with
+ * the Top-K blend and c > 0, a pixel stops walking once it holds K weights
+ * and fl(0.99 T) is at most the smallest of them, since no later weight
+ * alpha T' (alpha <= 0.99, T' <= T) can enter the K largest (a tie goes to
+ * the earlier surfel).  The selection and the feature map equal those of the
+ * full walk bit for bit; only the feature map is rendered (rgb, depth, normal
+ * and alpha outputs, and their upstream gradients, must be null), and the
+ * backward gives the gradients of the feature loss. */
+#define PSM_FLAG_FEATURE_ONLY 8
 
 typedef struct { float *rgb, *depth, *normal, *alpha, *feat; } psm_images;
 typedef struct { const float *rgb, *depth, *normal, *alpha, *feat; } psm_image_grads;

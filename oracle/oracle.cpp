@@ -24,6 +24,7 @@
 //
 // Parity pins for each function live in tests/test_oracle_*.py.
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -427,14 +428,19 @@ struct Margins {
 };
 
 // Front-to-back walk of one pixel (eq. (1)): skip non-hits and alpha < 1/255,
-// stop before a surfel that would take T below 1e-4.
+// stop before a surfel that would take T below 1e-4.  With topk_stop = K > 0
+// (feature-only rendering) the walk also ends once K weights are held and
+// 0.99 T is at most the smallest of them: every later weight is alpha T' with
+// alpha <= 0.99 and T' <= T, so none can enter the K largest (a tie goes to
+// the earlier surfel), and the Top-K selection is that of the full walk.
 void walk_pixel(const Scene& sc, const Prepared& P, const Cam& k, int px, int py,
-                std::vector<Contrib>& out, double& T_final, Margins& margin) {
+                std::vector<Contrib>& out, double& T_final, Margins& margin, int topk_stop = 0) {
   out.clear();
   margin = Margins();
   const double x = px + 0.5, y = py + 0.5;
   const auto& bin = P.bins[(size_t)(py / P.th) * P.ntx + (px / P.tw)];
   double T = 1.0;
+  std::vector<double> held;  // the K largest weights so far, a min-heap
   for (int64_t id : bin) {
     Eval e = eval_pixel(P.geo[id], sc.opacity[id], x, y);
     if (std::isfinite(e.rho)) margin.m[0] = std::min(margin.m[0], std::fabs(e.rho - kCut2) / kCut2);
@@ -448,6 +454,19 @@ void walk_pixel(const Scene& sc, const Prepared& P, const Cam& k, int px, int py
     if (Tn < kTMin) break;
     out.push_back({id, e.alpha, T, e.alpha * T, e.z, e.clamped});
     T = Tn;
+    if (topk_stop > 0) {
+      const double w = out.back().w;
+      const auto gt = std::greater<double>();
+      if ((int)held.size() < topk_stop) {
+        held.push_back(w);
+        std::push_heap(held.begin(), held.end(), gt);
+      } else if (w > held.front()) {
+        std::pop_heap(held.begin(), held.end(), gt);
+        held.back() = w;
+        std::push_heap(held.begin(), held.end(), gt);
+      }
+      if ((int)held.size() == topk_stop && kAlphaMax * T <= held.front()) break;
+    }
   }
   T_final = T;
 }
@@ -587,7 +606,7 @@ void orc_render(int64_t n, const float* means, const float* scales, const float*
       const int px = (int)(p % k.W), py = (int)(p / k.W);
       double T_final, gap;
       Margins margin;
-      walk_pixel(sc, P, k, px, py, cs, T_final, margin);
+      walk_pixel(sc, P, k, px, py, cs, T_final, margin, blend == 2 ? K : 0);
       double col[3] = {0, 0, 0}, nor[3] = {0, 0, 0}, dep = 0;
       for (const Contrib& c : cs) {
         const Geo<double>& g = P.geo[c.id];
@@ -597,9 +616,9 @@ void orc_render(int64_t n, const float* means, const float* scales, const float*
         }
         dep += c.w * c.z;
       }
-      if (blend == 1) select_topk(cs, K, sel, gap);
+      if (blend >= 1) select_topk(cs, K, sel, gap);
       else { sel.assign(cs.size(), 1); gap = INFINITY; }
-      if (blend == 1) margin.m[3] = gap;
+      if (blend >= 1) margin.m[3] = gap;
       if (feat_out) {
         double* F = feat_out + e * C;
         for (int j = 0; j < C; ++j) F[j] = 0;
@@ -665,10 +684,10 @@ void orc_backward(int64_t n, const float* means, const float* scales, const floa
       const int px = (int)(p % k.W), py = (int)(p / k.W);
       double T_final, gap;
       Margins margin;
-      walk_pixel(sc, P, k, px, py, cs, T_final, margin);
+      walk_pixel(sc, P, k, px, py, cs, T_final, margin, blend == 2 ? K : 0);
       const int m = (int)cs.size();
       if (m == 0) continue;
-      if (blend == 1) select_topk(cs, K, sel, gap);
+      if (blend >= 1) select_topk(cs, K, sel, gap);
       else sel.assign(m, 1);
       const double* gC = g_rgb + 3 * e;
       const double* gN = g_normal + 3 * e;
@@ -754,8 +773,8 @@ void orc_decisions(int64_t n, const float* means, const float* scales, const flo
       const int64_t p = pix[e];
       double T_final, gap;
       Margins margin;
-      walk_pixel(sc, P, k, (int)(p % k.W), (int)(p / k.W), cs, T_final, margin);
-      if (blend == 1) select_topk(cs, K, sel, gap);
+      walk_pixel(sc, P, k, (int)(p % k.W), (int)(p / k.W), cs, T_final, margin, blend == 2 ? K : 0);
+      if (blend >= 1) select_topk(cs, K, sel, gap);
       else sel.assign(cs.size(), 1);
       uint64_t h = 1469598103934665603ull;
       for (size_t i = 0; i < cs.size(); ++i) {

@@ -18,6 +18,9 @@ SRC = os.path.join(HERE, "oracle.cpp")
 
 SPHERE, AABB, ELLIPSE = 0, 1, 2
 FULL, TOPK = 0, 1
+# Top-K with the feature-only stop: a pixel's walk ends once no later surfel can
+# enter its K largest weights (selection and feature map unchanged).
+TOPK_FEATURE_ONLY = 2
 MODES = {"sphere": SPHERE, "aabb": AABB, "ellipse": ELLIPSE}
 
 _lib = None

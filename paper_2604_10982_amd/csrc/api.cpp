@@ -169,6 +169,8 @@ psm_status validate_common(const psm_camera* cams, int32_t n_cams, const psm_con
     return fail(PSM_ERR_INVALID_ARG, "blend_pass must be 0, 16 or 32");
   if (cfg->bwd_pass != 0 && cfg->bwd_pass != 16 && cfg->bwd_pass != 32)
     return fail(PSM_ERR_INVALID_ARG, "bwd_pass must be 0, 16 or 32");
+  if ((cfg->flags & PSM_FLAG_FEATURE_ONLY) && (cfg->blend != PSM_BLEND_TOPK || c == 0))
+    return fail(PSM_ERR_INVALID_ARG, "PSM_FLAG_FEATURE_ONLY needs the Top-K blend and c > 0");
   if (c < 0 || c > 1024) return fail(PSM_ERR_INVALID_ARG, "c must be in [0, 1024]");
   if (c % 8 != 0) return fail(PSM_ERR_UNSUPPORTED, "c must be a multiple of 8");
   if (pair_capacity < 0 || pair_capacity > 0x7FFFFFFFLL)
@@ -292,7 +294,7 @@ void enqueue_forward(const SurfelArgs& sa, const CamTable& ct, const psm_config*
   prof.end(kStageRanges, st);
   ImageArgs ia{out->rgb, out->depth, out->normal, out->alpha, out->feat};
   prof.begin(kStageWalk, st);
-  launch_walk(L, ct, cfg->blend, tu, ia, ws, st);
+  launch_walk(L, ct, cfg->blend, tu, ia, (cfg->flags & PSM_FLAG_FEATURE_ONLY) != 0, ws, st);
   prof.end(kStageWalk, st);
   prof.begin(kStageBlend, st);
   launch_feature_blend(sa, L, ct, cfg->blend, tu, out->feat, ws, st);
@@ -313,6 +315,9 @@ psm_status forward_impl(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
   r = check_workspace(L, workspace, workspace_bytes);
   if (r != PSM_OK) return r;
   if (s->c > 0 && !out->feat) return fail(PSM_ERR_INVALID_ARG, "out->feat is required when c > 0");
+  if ((cfg->flags & PSM_FLAG_FEATURE_ONLY) && (out->rgb || out->depth || out->normal || out->alpha))
+    return fail(PSM_ERR_INVALID_ARG, "PSM_FLAG_FEATURE_ONLY renders only the feature map: pass null rgb, depth, "
+                                     "normal and alpha");
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)stream;
@@ -341,6 +346,8 @@ psm_status backward_impl(psm_ctx* ctx, const psm_surfels* s, const psm_camera* c
   if (s->n > 0 && (!grads->means || !grads->scales || !grads->quats || !grads->opacity || !grads->rgb ||
                    (s->c > 0 && !grads->feat)))
     return fail(PSM_ERR_INVALID_ARG, "every gradient array is required");
+  if ((cfg->flags & PSM_FLAG_FEATURE_ONLY) && (grad_out->rgb || grad_out->depth || grad_out->normal || grad_out->alpha))
+    return fail(PSM_ERR_INVALID_ARG, "PSM_FLAG_FEATURE_ONLY takes only the feature map's upstream gradient");
   const CamTable ct = cam_table(cams, n_cams, s->n);
   const Layout L = make_layout(ct, cfg->k, s->c, pair_capacity);
   r = check_workspace(L, workspace, workspace_bytes);

@@ -83,8 +83,8 @@ inline TileQueue tile_queue(const Layout& L, int sched, char* ws, int q) {
 }
 
 // raster_fwd.hip
-void launch_walk(const Layout& L, const CamTable& ct, int blend, const Tuning& tu, const ImageArgs& out, char* ws,
-                 hipStream_t st);
+void launch_walk(const Layout& L, const CamTable& ct, int blend, const Tuning& tu, const ImageArgs& out,
+                 bool feat_only, char* ws, hipStream_t st);
 void launch_feature_blend(const SurfelArgs& s, const Layout& L, const CamTable& ct, int blend, const Tuning& tu,
                           float* out_feat, char* ws, hipStream_t st);
 void launch_export_selection(const Layout& L, const CamTable& ct, char* ws, int32_t* sel_id, float* sel_w,

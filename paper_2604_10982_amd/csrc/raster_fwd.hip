@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                               float* __restrict__ o_normal, float* __restrict__ o_alpha,
                                               uint32_t* __restrict__ nlast, float* __restrict__ tfinal,
                                               int32_t* __restrict__ selpos, float* __restrict__ selw,
-                                              uint32_t* __restrict__ status) {
+                                              uint32_t* __restrict__ status, int feat_only) {
   __shared__ Staged<kWalkChunk> s_rec[4];
   __shared__ int s_pos[4][kWalkChunk];
   __shared__ int s_item;
@@ -152,6 +152,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             kmin = lt ? hk[q] : kmin;
             imin = lt ? q : imin;
           }
+        }
+        // feature-only rendering: with K weights held, a later weight is
+        // alpha T' <= fl(0.99 T) (alpha <= 0.99, T' <= T, rounding is
+        // monotone) and loses a tie, so once fl(0.99 T) <= the smallest held
+        // weight the selection is final and the pixel stops
+        if (feat_only && kmin != 0ull && kAlphaMax * T <= __uint_as_float((uint32_t)(kmin >> 32))) {
+          done = true;
+          stop = pos;
         }
       }
     }
@@ -433,35 +441,35 @@ __global__ __launch_bounds__(256) void k_export_sel(const uint32_t* __restrict__
 
 // ------------------------------------------------------------- host wrappers
 template <int KMAX, bool TOPK, bool PERSIST>
-static void walk_launch_t(const Layout& L, const CamTable& ct, const Tuning& tu, const ImageArgs& out, char* ws,
-                          hipStream_t st) {
+static void walk_launch_t(const Layout& L, const CamTable& ct, const Tuning& tu, const ImageArgs& out,
+                          bool feat_only, char* ws, hipStream_t st) {
   const void* k = reinterpret_cast<const void*>(&k_walk<KMAX, TOPK, PERSIST>);
   hipLaunchKernelGGL((k_walk<KMAX, TOPK, PERSIST>), dim3(tile_grid(L, tu.sched, k, 0)), dim3(256), 0, st,
                      (const WalkRec*)(ws + L.rec), (const float4*)(ws + L.ext), (const uint32_t*)(ws + L.pid),
                      (const uint2*)(ws + L.ranges), ct, tile_queue(L, tu.sched, ws, kQWalk), L.k, out.rgb, out.depth,
                      out.normal, out.alpha,
                      (uint32_t*)(ws + L.nlast), (float*)(ws + L.tfinal), (int32_t*)(ws + L.selpos),
-                     (float*)(ws + L.selw), (uint32_t*)(ws + L.status));
+                     (float*)(ws + L.selw), (uint32_t*)(ws + L.status), feat_only ? 1 : 0);
 }
 
 template <int KMAX, bool TOPK>
-static void walk_launch(const Layout& L, const CamTable& ct, const Tuning& tu, const ImageArgs& out, char* ws,
-                        hipStream_t st) {
-  if (tu.sched == kSchedPersistent) walk_launch_t<KMAX, TOPK, true>(L, ct, tu, out, ws, st);
-  else walk_launch_t<KMAX, TOPK, false>(L, ct, tu, out, ws, st);
+static void walk_launch(const Layout& L, const CamTable& ct, const Tuning& tu, const ImageArgs& out, bool feat_only,
+                        char* ws, hipStream_t st) {
+  if (tu.sched == kSchedPersistent) walk_launch_t<KMAX, TOPK, true>(L, ct, tu, out, feat_only, ws, st);
+  else walk_launch_t<KMAX, TOPK, false>(L, ct, tu, out, feat_only, ws, st);
 }
 
-void launch_walk(const Layout& L, const CamTable& ct, int blend, const Tuning& tu, const ImageArgs& out, char* ws,
-                 hipStream_t st) {
+void launch_walk(const Layout& L, const CamTable& ct, int blend, const Tuning& tu, const ImageArgs& out,
+                 bool feat_only, char* ws, hipStream_t st) {
   if (L.tiles == 0) return;
   if (blend == kFull) {
-    walk_launch<1, false>(L, ct, tu, out, ws, st);
+    walk_launch<1, false>(L, ct, tu, out, false, ws, st);
   } else if (L.k <= 8) {
-    walk_launch<8, true>(L, ct, tu, out, ws, st);
+    walk_launch<8, true>(L, ct, tu, out, feat_only, ws, st);
   } else if (L.k <= 16) {
-    walk_launch<16, true>(L, ct, tu, out, ws, st);
+    walk_launch<16, true>(L, ct, tu, out, feat_only, ws, st);
   } else {
-    walk_launch<32, true>(L, ct, tu, out, ws, st);
+    walk_launch<32, true>(L, ct, tu, out, feat_only, ws, st);
   }
 }
 

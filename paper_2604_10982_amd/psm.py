@@ -24,6 +24,7 @@ DTYPES = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2}
 FLAG_NO_SYNC = 1
 FLAG_PROFILE = 2
 FLAG_OPACITY_FOOTPRINT = 4
+FLAG_FEATURE_ONLY = 8
 NUM_STAGES = 12
 SCHED_GRID, SCHED_PERSISTENT = 0, 1
 MAX_CAMERAS = 8
@@ -246,9 +247,12 @@ def _surfels(means, scales, quats, opacity, rgb, feat) -> Surfels:
                    fp, c, dt)
 
 
-def alloc_images(cam: Camera, c: int, device) -> dict:
+def alloc_images(cam: Camera, c: int, device, feature_only: bool = False) -> dict:
+    """Output maps; with ``feature_only`` (FLAG_FEATURE_ONLY) only the feature map."""
     H, W = cam.height, cam.width
     e = lambda *s: torch.empty(*s, dtype=torch.float32, device=device)
+    if feature_only:
+        return {"rgb": None, "depth": None, "normal": None, "alpha": None, "feat": e(H, W, c)}
     return {"rgb": e(H, W, 3), "depth": e(H, W), "normal": e(H, W, 3), "alpha": e(H, W),
             "feat": e(H, W, c) if c > 0 else None}
 
@@ -286,7 +290,7 @@ def forward(means, scales, quats, opacity, rgb, feat, camera, k=16, tile_mode="e
     s = _surfels(means, scales, quats, opacity, rgb, feat)
     cam = camera if isinstance(camera, Camera) else camera_struct(camera)
     cfg = config_struct(k, tile_mode, blend, flags)
-    out = alloc_images(cam, s.c, device)
+    out = alloc_images(cam, s.c, device, feature_only=bool(flags & FLAG_FEATURE_ONLY))
     cap = capacity if capacity is not None else (ws.capacity if ws is not None else capacity_guess(s.n, cam))
     for attempt in range(3):
         if ws is None or ws.capacity < cap or ws.n != s.n or ws.c != s.c or ws.k != cfg.k:
@@ -313,6 +317,8 @@ def backward(means, scales, quats, opacity, rgb, feat, camera, ws: Workspace, go
     grads = {"means": z(n, 3), "scales": z(n, 2), "quats": z(n, 4), "opacity": z(n), "rgb": z(n, 3),
              "feat": z(n, s.c) if s.c > 0 else None}
     gout = {kk: (None if v is None else v.contiguous().float()) for kk, v in gout.items()}
+    if flags & FLAG_FEATURE_ONLY:  # only the feature map was rendered
+        gout = {kk: (v if kk == "feat" else None) for kk, v in gout.items()}
     backward_into(ctx, s, cam, cfg, ws, gout, grads)
     return grads
 

@@ -341,6 +341,47 @@ def labels_workload(psm, means, steps, warmup, nq=64, c=32):
     return res
 
 
+FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
+
+
+def attention_workload(psm, steps, warmup, nq=64, c=32, d=32):
+    """Frustum-local cross-attention (eqs. (9)-(11)) of nq queries over the
+    surfels of a 2M-surfel street scene that meet a 1920x1080 camera's
+    frustum; c-d FP32 instance features, d-d projections.  Timed with HIP
+    events on the stream (cull + compaction + projections + attention)."""
+    import numpy as np
+    import torch
+    from paper_2604_10982_amd import scenes
+    device = torch.device("cuda:0")
+    sc = scenes.street40(2_000_000, 8, seed=1)
+    cam = scenes.street_cameras()[-1]
+    rng = np.random.default_rng(4)
+    T = lambda a: torch.tensor(np.ascontiguousarray(a, np.float32), device=device)
+    means, scales = T(sc.means), T(sc.scales)
+    feat = T(rng.standard_normal((sc.n, c)) * 0.8)
+    q = T(rng.standard_normal((nq, c)))
+    wq, wk, wv = (T(rng.standard_normal((c, d)) / np.sqrt(c)) for _ in range(3))
+    run = lambda: psm.frustum_attention(means, scales, feat, q, wq, wk, wv, cam, 16.0)
+    _, act = psm.frustum_attention(means, scales, feat, q, wq, wk, wv, cam, 16.0, return_active=True)
+    m = int(act.sum().item())
+    for _ in range(warmup):
+        run()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # per active key: K and V projections (2 c d MACs), scores and P V (2 nq d MACs)
+    flops = 2.0 * m * (2 * c * d + 2 * nq * d)
+    return {"ms": ms, "surfels": sc.n, "active": m, "queries": nq, "feat_dim": c, "proj_dim": d,
+            "mfma_tflops": flops / (ms * 1e-3) / 1e12, "mfma_frac": flops / (ms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS,
+            "note": "psm_frustum_attention: 99% frustum cull, compaction, FP32 MFMA projections, scores, online "
+                    "softmax and P V; flops = 2 M (2 c d + 2 n_q d) over the M active surfels"}
+
+
 def cpu_baseline(sc, cam, K, feat64, tiles):
     """The FP64 oracle (test infrastructure) on a bounded sample of the same
     frame: forward + backward of the pixels of `tiles` random 16x16 tiles.
@@ -499,6 +540,10 @@ def main():
         line["cpu_baseline"] = cpu_baseline(sc, cam, K, feat64, args.cpu_tiles)
         print(f"[bench] cpu baseline {line['cpu_baseline']['value']:.4f} it/s", file=sys.stderr, flush=True)
     line["instance_labels"] = labels_workload(psm, t["means"], max(3, args.steps // 2), 2)
+    line["frustum_attention"] = attention_workload(psm, max(3, args.steps // 2), 2)
+    fa = line["frustum_attention"]
+    print(f"[bench] frustum attention {fa['ms']:.3f} ms, {fa['active']} active of {fa['surfels']}, "
+          f"{fa['mfma_tflops']:.1f} TFLOP/s", file=sys.stderr, flush=True)
     print(f"[bench] labels fwd {line['instance_labels']['fwd_ms']:.3f} ms, bwd {line['instance_labels']['bwd_ms']:.3f} ms",
           file=sys.stderr, flush=True)
     if not args.no_batch:

@@ -305,6 +305,42 @@ psm_status psm_instance_labels_backward(psm_ctx* ctx, int64_t n, const float* me
                                         void* workspace, size_t workspace_bytes, float* d_means, float* d_f_ins,
                                         float* d_qfeat, float* d_qmean, float* d_qprec, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Frustum-local cross-attention of instance queries over surfels (Sec. 4.1,
+ * eqs. (9)-(11)):
+ *   active set V: surfels whose 99% confidence disk (rho <= -2 ln 0.01 in its
+ *     plane) has a bounding sphere (radius 3.0349 max(s_u, s_v)) meeting the
+ *     view frustum: not wholly behind the near plane or outside one of the
+ *     planes through the camera centre and the image borders (FP32);
+ *   K_j = f_j + psi(mu_j), V_j = f_j,  psi_c(mu) = sin or cos (for c / 3 even
+ *     or odd) of 2^(c / 6) pi mu_(c mod 3) / pos_length;
+ *   e_ij = (Q_i W_Q) . (K_j W_K) / sqrt(d),
+ *   out_i = sum over j in V of softmax_j(e_ij) (V_j W_V)   (zero if V is empty).
+ * FP32 matrix-core products; deterministic (fixed split of the active list,
+ * merged in order).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n_q;          /* queries, 1..256 */
+  int32_t c;            /* feature width C; (c, d) in (16,16) (32,32) (64,32) (64,64) */
+  int32_t d;            /* projection width d */
+  int32_t feat_dtype;   /* psm_dtype of feat */
+  const void* feat;     /* [n][c] instance features f_j (device, 16-byte aligned) */
+  const float* q;       /* [n_q][c] query tokens Q_i (device) */
+  const float* wq;      /* [c][d] W_Q (device) */
+  const float* wk;      /* [c][d] W_K (device) */
+  const float* wv;      /* [c][d] W_V (device) */
+  float pos_length;     /* length scale L of psi, > 0 */
+} psm_attention;
+
+/* Device workspace (bytes, 256-aligned) of psm_frustum_attention. */
+psm_status psm_frustum_attention_workspace_size(psm_ctx* ctx, int64_t n, const psm_attention* a, size_t* bytes_out);
+
+/* out: FP32 [n_q][d] (device).  active: optional uint8 [n] (device), 1 for the
+ * surfels of V.  means [n][3], scales [n][2] (device).  Enqueued on stream. */
+psm_status psm_frustum_attention(psm_ctx* ctx, int64_t n, const float* means, const float* scales,
+                                 const psm_camera* cam, const psm_attention* a, void* workspace,
+                                 size_t workspace_bytes, float* out, uint8_t* active, void* stream);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* psm_last_error(void);
 

@@ -708,6 +708,74 @@ psm_status psm_instance_labels_backward(psm_ctx* ctx, int64_t n, const float* me
   return PSM_OK;
 }
 
+// ------------------------------------------------------ frustum attention
+static psm_status validate_attention(int64_t n, const psm_attention* a) {
+  if (!a) return fail(PSM_ERR_INVALID_ARG, "attention description is null");
+  if (n < 0 || n > 0x7FFFFFFFLL) return fail(PSM_ERR_INVALID_ARG, "n must be in [0, 2^31)");
+  if (a->n_q < 1 || a->n_q > 256) return fail(PSM_ERR_INVALID_ARG, "n_q must be in [1, 256]");
+  if (!attention_supported(a->c, a->d))
+    return fail(PSM_ERR_UNSUPPORTED, "(c, d) must be (16,16), (32,32), (64,32) or (64,64)");
+  if (a->feat_dtype < 0 || a->feat_dtype > 2) return fail(PSM_ERR_INVALID_ARG, "bad feat_dtype");
+  if (!a->q || !a->wq || !a->wk || !a->wv) return fail(PSM_ERR_INVALID_ARG, "null query or projection array");
+  if (n > 0 && !a->feat) return fail(PSM_ERR_INVALID_ARG, "null feature array");
+  if (!(a->pos_length > 0.0f)) return fail(PSM_ERR_INVALID_ARG, "pos_length must be > 0");
+  return PSM_OK;
+}
+
+static int attention_blocks(const psm_ctx* ctx) { return std::max(64, 4 * ctx->cu_count); }
+
+psm_status psm_frustum_attention_workspace_size(psm_ctx* ctx, int64_t n, const psm_attention* a, size_t* bytes_out) {
+  if (!ctx || !bytes_out) return fail(PSM_ERR_INVALID_ARG, "ctx and bytes_out are required");
+  psm_status r = validate_attention(n, a);
+  if (r != PSM_OK) return r;
+  *bytes_out = attention_workspace_bytes(n, a->n_q, a->d, attention_blocks(ctx));
+  return PSM_OK;
+}
+
+psm_status psm_frustum_attention(psm_ctx* ctx, int64_t n, const float* means, const float* scales,
+                                 const psm_camera* cam, const psm_attention* a, void* workspace,
+                                 size_t workspace_bytes, float* out, uint8_t* active, void* stream) {
+  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+  psm_status r = validate_attention(n, a);
+  if (r != PSM_OK) return r;
+  if (!cam) return fail(PSM_ERR_INVALID_ARG, "camera is null");
+  r = validate_camera(cam);
+  if (r != PSM_OK) return r;
+  if (n > 0 && (!means || !scales)) return fail(PSM_ERR_INVALID_ARG, "null surfel array");
+  if (!out) return fail(PSM_ERR_INVALID_ARG, "out is null");
+  const int nblk = attention_blocks(ctx);
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(PSM_ERR_INVALID_ARG, "workspace must be non-null and 256-byte aligned");
+  if (workspace_bytes < attention_workspace_bytes(n, a->n_q, a->d, nblk))
+    return fail(PSM_ERR_INVALID_ARG, "workspace too small");
+  if (n > 0 && reinterpret_cast<uintptr_t>(a->feat) % 16 != 0)
+    return fail(PSM_ERR_INVALID_ARG, "feature array must be 16-byte aligned");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
+  AttentionArgs aa{};
+  aa.n = n;
+  aa.means = means;
+  aa.scales = scales;
+  const CamTable ct = cam_table(cam, 1, n);
+  aa.cam = ct.cam[0];
+  aa.nq = a->n_q;
+  aa.c = a->c;
+  aa.d = a->d;
+  aa.feat = a->feat;
+  aa.feat_dtype = a->feat_dtype;
+  aa.q = a->q;
+  aa.wq = a->wq;
+  aa.wk = a->wk;
+  aa.wv = a->wv;
+  aa.pos_length = a->pos_length;
+  aa.nblk = nblk;
+  launch_attention(aa, (char*)workspace, out, active, (hipStream_t)stream);
+  r = check_hip("psm_frustum_attention launch");
+  if (r != PSM_OK) return r;
+  g_err.clear();
+  return PSM_OK;
+}
+
 psm_status psm_profile_read(psm_ctx* ctx, int32_t stage, const char** name_out, double* total_ms_out,
                             int64_t* calls_out) {
   if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");

@@ -113,4 +113,22 @@ void launch_labels_backward(int64_t n, const float* means, const void* fg, int d
 void launch_backward(const SurfelArgs& s, const CamTable& ct, int blend, const Tuning& tu, const Layout& L,
                      const ImageGradArgs& g, const GradArgs& grads, char* ws, hipStream_t st, const ProfHook& prof);
 
+// Frustum-local cross-attention (attention.hip).
+struct AttentionArgs {
+  int64_t n;
+  const float* means;
+  const float* scales;
+  CamArgs cam;
+  int nq, c, d;
+  const void* feat;
+  int feat_dtype;
+  const float *q, *wq, *wk, *wv;
+  float pos_length;
+  int nblk;    // attention blocks (key ranges)
+  int64_t nb;  // cull blocks (set by the launcher)
+};
+bool attention_supported(int c, int d);
+size_t attention_workspace_bytes(int64_t n, int nq, int d, int nblk);
+void launch_attention(const AttentionArgs& a, char* ws, float* out, uint8_t* active_out, hipStream_t st);
+
 }  // namespace psm

@@ -34,7 +34,8 @@ EXPORTS = ("psm_create", "psm_destroy", "psm_workspace_size", "psm_forward", "ps
            "psm_read_stats", "psm_read_pairs", "psm_read_selection", "psm_profile_read", "psm_profile_reset",
            "psm_last_error", "psm_version", "psm_workspace_size_batch", "psm_forward_batch", "psm_backward_batch",
            "psm_read_stats_batch", "psm_read_pairs_batch", "psm_read_selection_batch", "psm_autotune",
-           "psm_instance_labels", "psm_instance_labels_workspace_size", "psm_instance_labels_backward")
+           "psm_instance_labels", "psm_instance_labels_workspace_size", "psm_instance_labels_backward",
+           "psm_frustum_attention_workspace_size", "psm_frustum_attention")
 
 
 class PsmError(RuntimeError):
@@ -68,6 +69,12 @@ class Config(C.Structure):
 class Queries(C.Structure):
     _fields_ = [("n_q", C.c_int32), ("c", C.c_int32), ("feat", C.c_void_p), ("mean", C.c_void_p),
                 ("prec", C.c_void_p)]
+
+
+class Attention(C.Structure):
+    _fields_ = [("n_q", C.c_int32), ("c", C.c_int32), ("d", C.c_int32), ("feat_dtype", C.c_int32),
+                ("feat", C.c_void_p), ("q", C.c_void_p), ("wq", C.c_void_p), ("wk", C.c_void_p), ("wv", C.c_void_p),
+                ("pos_length", C.c_float)]
 
 
 class Images(C.Structure):
@@ -130,6 +137,9 @@ def lib():
         L.psm_instance_labels_workspace_size.argtypes = [i64, QP, C.POINTER(C.c_size_t)]
         L.psm_instance_labels_backward.argtypes = [vp, i64, vp, vp, i32, QP, vp, i32, vp, C.c_size_t, vp, vp, vp,
                                                    vp, vp, vp]
+        AP = C.POINTER(Attention)
+        L.psm_frustum_attention_workspace_size.argtypes = [vp, i64, AP, C.POINTER(C.c_size_t)]
+        L.psm_frustum_attention.argtypes = [vp, i64, vp, vp, C.POINTER(Camera), AP, vp, C.c_size_t, vp, vp, vp]
         L.psm_profile_read.argtypes = [vp, i32, C.POINTER(C.c_char_p), C.POINTER(C.c_double), C.POINTER(i64)]
         L.psm_profile_reset.argtypes = [vp]
         L.psm_last_error.restype = C.c_char_p
@@ -642,3 +652,38 @@ def instance_labels_backward(means, f_ins, q_feat, q_mean, q_prec, d_labels: tor
                                               _ptr(g["q_mean"]), _ptr(g["q_prec"]), _stream(ctx.device)),
            "psm_instance_labels_backward")
     return g
+
+
+# ------------------------------------------------------------ frustum attention
+def _attention(feat, q, wq, wk, wv, pos_length) -> Attention:
+    for name, t in (("feat", feat), ("q", q), ("wq", wq), ("wk", wk), ("wv", wv)):
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    for name, t in (("q", q), ("wq", wq), ("wk", wk), ("wv", wv)):
+        if t.dtype != torch.float32:
+            raise ValueError(f"{name} must be float32")
+    return Attention(int(q.shape[0]), int(q.shape[1]), int(wq.shape[1]), DTYPES[feat.dtype], _ptr(feat), _ptr(q),
+                     _ptr(wq), _ptr(wk), _ptr(wv), float(pos_length))
+
+
+def frustum_attention(means, scales, feat, q, wq, wk, wv, camera, pos_length: float, return_active: bool = False):
+    """Cross-attention of the queries q [n_q, C] over the surfels whose 99%
+    disk meets the camera's frustum (Sec. 4.1, eqs. (9)-(11)): [n_q, d] FP32,
+    and with ``return_active`` the uint8 active mask [n]."""
+    dev = means.device
+    ctx = context(dev.index or 0)
+    cam = camera if isinstance(camera, Camera) else camera_struct(camera)
+    a = _attention(feat, q, wq, wk, wv, pos_length)
+    n = int(means.shape[0])
+    ws_bytes = C.c_size_t()
+    _check(lib().psm_frustum_attention_workspace_size(ctx.handle, n, C.byref(a), C.byref(ws_bytes)),
+           "psm_frustum_attention_workspace_size")
+    buf = torch.empty(int(ws_bytes.value) + 256, dtype=torch.uint8, device=dev)
+    off = (-buf.data_ptr()) % 256
+    ws = buf[off:off + int(ws_bytes.value)]
+    out = torch.empty(a.n_q, a.d, dtype=torch.float32, device=dev)
+    act = torch.empty(max(n, 1), dtype=torch.uint8, device=dev) if return_active else None
+    _check(lib().psm_frustum_attention(ctx.handle, n, _ptr(means), _ptr(scales), C.byref(cam), C.byref(a), _ptr(ws),
+                                       ws.numel(), _ptr(out), _ptr(act), _stream(ctx.device)),
+           "psm_frustum_attention")
+    return (out, act[:n]) if return_active else out

@@ -382,6 +382,33 @@ def attention_workload(psm, steps, warmup, nq=64, c=32, d=32):
                     "softmax and P V; flops = 2 M (2 c d + 2 n_q d) over the M active surfels"}
 
 
+def geometry_workload(psm, means, scales, quats, sc, steps, warmup, k=512):
+    """SOGMM geometric loss (eq. (3), eq. (13), L_iso) of the headline scene's
+    surfels against a k-component synthetic plane prior: MAP assignment, both
+    losses and their gradients, timed with HIP events on the stream."""
+    import numpy as np
+    import torch
+    from paper_2604_10982_amd import scenes
+    gm = [torch.tensor(a, device=means.device) for a in scenes.plane_gmm(sc, k, seed=3)]
+    run = lambda: psm.geometry_loss(means, scales, quats, gm[0], gm[1], gm[2], 0.4)
+    for _ in range(warmup):
+        run()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    n = int(means.shape[0])
+    flops = 23.0 * n * k   # per (surfel, component) score: 3 sub, 9 mul, 8 add (FP32), 3 for the minimum
+    return {"ms": ms, "surfels": n, "components": k, "surfels_per_s": n / (ms * 1e-3),
+            "alu_tflops": flops / (ms * 1e-3) / 1e12, "alu_frac": flops / (ms * 1e-3) / 1e12 / FP32_VALU_PEAK_TFLOPS,
+            "note": "psm_geometry_loss: FP32 MAP scan over the components staged in LDS, FP64 loss terms and "
+                    "gradients, ordered FP64 sums"}
+
+
 def cpu_baseline(sc, cam, K, feat64, tiles):
     """The FP64 oracle (test infrastructure) on a bounded sample of the same
     frame: forward + backward of the pixels of `tiles` random 16x16 tiles.
@@ -540,6 +567,9 @@ def main():
         line["cpu_baseline"] = cpu_baseline(sc, cam, K, feat64, args.cpu_tiles)
         print(f"[bench] cpu baseline {line['cpu_baseline']['value']:.4f} it/s", file=sys.stderr, flush=True)
     line["instance_labels"] = labels_workload(psm, t["means"], max(3, args.steps // 2), 2)
+    line["geometry_loss"] = geometry_workload(psm, t["means"], t["scales"], t["quats"], sc, max(3, args.steps // 2), 2)
+    print(f"[bench] geometry loss {line['geometry_loss']['ms']:.3f} ms "
+          f"({line['geometry_loss']['alu_tflops']:.1f} TFLOP/s)", file=sys.stderr, flush=True)
     line["frustum_attention"] = attention_workload(psm, max(3, args.steps // 2), 2)
     fa = line["frustum_attention"]
     print(f"[bench] frustum attention {fa['ms']:.3f} ms, {fa['active']} active of {fa['surfels']}, "

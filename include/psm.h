@@ -341,6 +341,37 @@ psm_status psm_frustum_attention(psm_ctx* ctx, int64_t n, const float* means, co
                                  const psm_camera* cam, const psm_attention* a, void* workspace,
                                  size_t workspace_bytes, float* out, uint8_t* active, void* stream);
 
+/* ------------------------------------------------------------------------
+ * SOGMM geometric loss of surfels (Sec. 3.2 eq. (3), Sec. 4.2 eq. (13) and the
+ * anisotropy term).  Plane prior component k: weight pi_k, mean mu_k,
+ * covariance Sigma_k; reference normal n_k = eigenvector of Sigma_k's smallest
+ * eigenvalue.  Surfel i takes the component of largest posterior
+ * pi_k N(mu_i; mu_k, Sigma_k) (smallest FP32 score
+ * (x - mu_k)^T Sigma_k^-1 (x - mu_k) + ln det Sigma_k - 2 ln pi_k, ties to the
+ * lower index), and
+ *   L_geo = sum_i |(mu_i - mu_k) . n_k| + lambda_n (1 - |n_i . n_k|),
+ *   L_iso = sum_i (s_i1 - s_i2)^2
+ * with n_i the third column of the rotation of the normalised quaternion.
+ * Gradients hold the assignment fixed (sign subgradient 0 at zero).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t k;            /* components, 1..2^20 */
+  const float* mean;    /* [k][3] (device) */
+  const float* cov;     /* [k][6] (xx, xy, xz, yy, yz, zz), positive definite (device) */
+  const float* weight;  /* [k] mixing weights > 0 (device) */
+} psm_gmm;
+
+/* Device workspace (bytes, 256-aligned) of psm_geometry_loss. */
+psm_status psm_geometry_loss_workspace_size(int64_t n, const psm_gmm* g, size_t* bytes_out);
+
+/* losses: FP64 [2] (device) = (L_geo, L_iso); assign: optional int32 [n]
+ * (device); d_means [n][3], d_scales [n][2], d_quats [n][4] (device) are
+ * overwritten with dL_geo/dmu, dL_iso/ds and dL_geo/dq.  Deterministic. */
+psm_status psm_geometry_loss(psm_ctx* ctx, int64_t n, const float* means, const float* scales, const float* quats,
+                             const psm_gmm* g, float lambda_n, void* workspace, size_t workspace_bytes,
+                             double* losses, int32_t* assign, float* d_means, float* d_scales, float* d_quats,
+                             void* stream);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* psm_last_error(void);
 

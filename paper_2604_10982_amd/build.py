@@ -28,7 +28,7 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(HERE, "..", "include"),
 ]
-SOURCES = ["keystage.hip", "sort.hip", "raster_fwd.hip", "raster_bwd.hip", "labels.hip", "attention.hip", "api.cpp"]
+SOURCES = ["keystage.hip", "sort.hip", "raster_fwd.hip", "raster_bwd.hip", "labels.hip", "attention.hip", "geometry.hip", "api.cpp"]
 
 
 def _compile(src: str) -> str:

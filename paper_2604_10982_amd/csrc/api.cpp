@@ -776,6 +776,47 @@ psm_status psm_frustum_attention(psm_ctx* ctx, int64_t n, const float* means, co
   return PSM_OK;
 }
 
+// ------------------------------------------------------- geometric loss
+static psm_status validate_gmm(int64_t n, const psm_gmm* g) {
+  if (!g) return fail(PSM_ERR_INVALID_ARG, "gmm is null");
+  if (n < 0 || n > 0x7FFFFFFFLL) return fail(PSM_ERR_INVALID_ARG, "n must be in [0, 2^31)");
+  if (g->k < 1 || g->k > (1 << 20)) return fail(PSM_ERR_INVALID_ARG, "k must be in [1, 2^20]");
+  if (!g->mean || !g->cov || !g->weight) return fail(PSM_ERR_INVALID_ARG, "null gmm array");
+  return PSM_OK;
+}
+
+psm_status psm_geometry_loss_workspace_size(int64_t n, const psm_gmm* g, size_t* bytes_out) {
+  if (!bytes_out) return fail(PSM_ERR_INVALID_ARG, "bytes_out is null");
+  psm_status r = validate_gmm(n, g);
+  if (r != PSM_OK) return r;
+  *bytes_out = geometry_workspace_bytes(n, g->k);
+  return PSM_OK;
+}
+
+psm_status psm_geometry_loss(psm_ctx* ctx, int64_t n, const float* means, const float* scales, const float* quats,
+                             const psm_gmm* g, float lambda_n, void* workspace, size_t workspace_bytes,
+                             double* losses, int32_t* assign, float* d_means, float* d_scales, float* d_quats,
+                             void* stream) {
+  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+  psm_status r = validate_gmm(n, g);
+  if (r != PSM_OK) return r;
+  if (!losses) return fail(PSM_ERR_INVALID_ARG, "losses is null");
+  if (n > 0 && (!means || !scales || !quats || !d_means || !d_scales || !d_quats))
+    return fail(PSM_ERR_INVALID_ARG, "null surfel or gradient array");
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(PSM_ERR_INVALID_ARG, "workspace must be non-null and 256-byte aligned");
+  if (workspace_bytes < geometry_workspace_bytes(n, g->k)) return fail(PSM_ERR_INVALID_ARG, "workspace too small");
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
+  GeometryArgs a{n, means, scales, quats, g->k, g->mean, g->cov, g->weight, lambda_n, losses, assign,
+                 d_means, d_scales, d_quats};
+  launch_geometry_loss(a, (char*)workspace, (hipStream_t)stream);
+  r = check_hip("psm_geometry_loss launch");
+  if (r != PSM_OK) return r;
+  g_err.clear();
+  return PSM_OK;
+}
+
 psm_status psm_profile_read(psm_ctx* ctx, int32_t stage, const char** name_out, double* total_ms_out,
                             int64_t* calls_out) {
   if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");

@@ -131,4 +131,18 @@ bool attention_supported(int c, int d);
 size_t attention_workspace_bytes(int64_t n, int nq, int d, int nblk);
 void launch_attention(const AttentionArgs& a, char* ws, float* out, uint8_t* active_out, hipStream_t st);
 
+// SOGMM geometric loss (geometry.hip).
+struct GeometryArgs {
+  int64_t n;
+  const float *means, *scales, *quats;
+  int k;
+  const float *gmean, *gcov, *gweight;
+  float lambda_n;
+  double* losses;   // [2] device
+  int32_t* assign;  // optional [n]
+  float *d_means, *d_scales, *d_quats;
+};
+size_t geometry_workspace_bytes(int64_t n, int k);
+void launch_geometry_loss(const GeometryArgs& a, char* ws, hipStream_t st);
+
 }  // namespace psm

@@ -35,7 +35,8 @@ EXPORTS = ("psm_create", "psm_destroy", "psm_workspace_size", "psm_forward", "ps
            "psm_last_error", "psm_version", "psm_workspace_size_batch", "psm_forward_batch", "psm_backward_batch",
            "psm_read_stats_batch", "psm_read_pairs_batch", "psm_read_selection_batch", "psm_autotune",
            "psm_instance_labels", "psm_instance_labels_workspace_size", "psm_instance_labels_backward",
-           "psm_frustum_attention_workspace_size", "psm_frustum_attention")
+           "psm_frustum_attention_workspace_size", "psm_frustum_attention",
+           "psm_geometry_loss_workspace_size", "psm_geometry_loss")
 
 
 class PsmError(RuntimeError):
@@ -75,6 +76,10 @@ class Attention(C.Structure):
     _fields_ = [("n_q", C.c_int32), ("c", C.c_int32), ("d", C.c_int32), ("feat_dtype", C.c_int32),
                 ("feat", C.c_void_p), ("q", C.c_void_p), ("wq", C.c_void_p), ("wk", C.c_void_p), ("wv", C.c_void_p),
                 ("pos_length", C.c_float)]
+
+
+class Gmm(C.Structure):
+    _fields_ = [("k", C.c_int32), ("mean", C.c_void_p), ("cov", C.c_void_p), ("weight", C.c_void_p)]
 
 
 class Images(C.Structure):
@@ -137,6 +142,9 @@ def lib():
         L.psm_instance_labels_workspace_size.argtypes = [i64, QP, C.POINTER(C.c_size_t)]
         L.psm_instance_labels_backward.argtypes = [vp, i64, vp, vp, i32, QP, vp, i32, vp, C.c_size_t, vp, vp, vp,
                                                    vp, vp, vp]
+        GP = C.POINTER(Gmm)
+        L.psm_geometry_loss_workspace_size.argtypes = [i64, GP, C.POINTER(C.c_size_t)]
+        L.psm_geometry_loss.argtypes = [vp, i64, vp, vp, vp, GP, C.c_float, vp, C.c_size_t, vp, vp, vp, vp, vp, vp]
         AP = C.POINTER(Attention)
         L.psm_frustum_attention_workspace_size.argtypes = [vp, i64, AP, C.POINTER(C.c_size_t)]
         L.psm_frustum_attention.argtypes = [vp, i64, vp, vp, C.POINTER(Camera), AP, vp, C.c_size_t, vp, vp, vp]
@@ -687,3 +695,35 @@ def frustum_attention(means, scales, feat, q, wq, wk, wv, camera, pos_length: fl
                                        ws.numel(), _ptr(out), _ptr(act), _stream(ctx.device)),
            "psm_frustum_attention")
     return (out, act[:n]) if return_active else out
+
+
+# ------------------------------------------------------------ geometric loss
+def geometry_loss(means, scales, quats, g_mean, g_cov, g_weight, lambda_n: float, return_assign: bool = False):
+    """SOGMM geometric loss (eq. (3), eq. (13)) and anisotropy term: returns
+    {"geo", "iso" (FP64 device scalars), "d_means", "d_scales", "d_quats"} and
+    with ``return_assign`` the int32 component of every surfel."""
+    for name, t in (("means", means), ("scales", scales), ("quats", quats), ("g_mean", g_mean), ("g_cov", g_cov),
+                    ("g_weight", g_weight)):
+        if not t.is_contiguous() or t.dtype != torch.float32:
+            raise ValueError(f"{name} must be contiguous float32")
+    dev = means.device
+    ctx = context(dev.index or 0)
+    n = int(means.shape[0])
+    g = Gmm(int(g_mean.shape[0]), _ptr(g_mean), _ptr(g_cov), _ptr(g_weight))
+    ws_bytes = C.c_size_t()
+    _check(lib().psm_geometry_loss_workspace_size(n, C.byref(g), C.byref(ws_bytes)), "psm_geometry_loss_workspace_size")
+    buf = torch.empty(int(ws_bytes.value) + 256, dtype=torch.uint8, device=dev)
+    off = (-buf.data_ptr()) % 256
+    ws = buf[off:off + int(ws_bytes.value)]
+    losses = torch.empty(2, dtype=torch.float64, device=dev)
+    z = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=dev)
+    out = {"d_means": z(n, 3), "d_scales": z(n, 2), "d_quats": z(n, 4)}
+    asg = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if return_assign else None
+    _check(lib().psm_geometry_loss(ctx.handle, n, _ptr(means), _ptr(scales), _ptr(quats), C.byref(g),
+                                   float(lambda_n), _ptr(ws), ws.numel(), _ptr(losses), _ptr(asg),
+                                   _ptr(out["d_means"]), _ptr(out["d_scales"]), _ptr(out["d_quats"]),
+                                   _stream(ctx.device)), "psm_geometry_loss")
+    out["geo"], out["iso"] = losses[0], losses[1]
+    if return_assign:
+        out["assign"] = asg[:n]
+    return out

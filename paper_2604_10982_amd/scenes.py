@@ -342,3 +342,24 @@ def config(name: str, seed: int = 0, n: int | None = None):
     scene = fn(n0 if n is None else n, c, seed)
     scene.meta["config"] = name
     return scene, pinhole(w, h, f), k, dtype
+
+
+def plane_gmm(scene, k: int, seed: int = 0, extent=(1.5, 1.5, 0.03)):
+    """Synthetic plane prior standing in for a LiDAR SOGMM: k components
+    centred on random surfels of the scene, each flat along that surfel's own
+    plane (standard deviations `extent` times U(0.7, 1.3) along the surfel's
+    tangent axes and its normal), Dirichlet(1) mixing weights.
+    Returns FP32 (mean [k,3], cov [k,6] as xx xy xz yy yz zz, weight [k])."""
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(scene.n, k, replace=False)
+    q = scene.quats[pick].astype(np.float64)
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    R = np.stack([np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], 1),
+                  np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], 1),
+                  np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], 1)], 1)
+    sd = np.asarray(extent) * rng.uniform(0.7, 1.3, (k, 3))
+    S = np.einsum("kij,kj,klj->kil", R, sd ** 2, R)
+    cov6 = np.stack([S[:, i, j] for i, j in ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))], 1)
+    return (scene.means[pick].astype(np.float32), cov6.astype(np.float32),
+            rng.dirichlet(np.ones(k)).astype(np.float32))

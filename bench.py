@@ -508,6 +508,16 @@ def main():
                     "note": "PSM_FLAG_FEATURE_ONLY: feature map and Top-K selection bit-identical to the full walk; "
                             "no RGB/depth/normal/alpha maps; backward of the feature loss"}
     del fo
+    # renormalised Top-K (the selected weights rescaled to sum 1)
+    rn = Form(psm, t, cam, K, "ellipse", "topk", gout, device, launch=head_launch, flags=psm.FLAG_TOPK_RENORM)
+    ms_rn_step, _, _ = timed(rn, True, args.steps, args.warmup)
+    ms_rn_fwd, _, _ = timed(rn, False, args.steps, args.warmup)
+    print(f"[bench] renormalised Top-K fwd {ms_rn_fwd:.3f} ms, fwd+bwd {ms_rn_step:.3f} ms", file=sys.stderr,
+          flush=True)
+    topk_renorm = {"fwd_ms": ms_rn_fwd, "fwd_fps": 1000.0 / ms_rn_fwd, "fwd_bwd_ms": ms_rn_step,
+                   "fwd_bwd_its": 1000.0 / ms_rn_step,
+                   "note": "PSM_FLAG_TOPK_RENORM: feature map sum_sel w f / sum_sel w and its backward"}
+    del rn
     base = Form(psm, t, cam, K, "aabb", "full", gout, device, tune=launch is None)
     ms_base_step, stages_base, st_base = timed(base, True, max(3, args.steps // 2), 2)
     ms_base_fwd, _, _ = timed(base, False, max(3, args.steps // 2), 2)
@@ -552,6 +562,7 @@ def main():
         "speedup_vs_dense_aabb": {"fwd": ms_base_fwd / ms_fwd, "fwd_bwd": ms_base_step / ms_step},
         "opacity_footprint": opacity_footprint,
         "feature_only": feature_only,
+        "topk_renorm": topk_renorm,
         "pairs": int(st.pairs), "pairs_walked": int(st.pairs_walked), "contributors": int(st.contributors),
         "visible": int(st.visible),
         "stages_ms": stages,

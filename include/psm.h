@@ -121,6 +121,11 @@ typedef enum { PSM_SCHED_GRID = 0, PSM_SCHED_PERSISTENT = 1 } psm_schedule;
  * and alpha outputs, and their upstream gradients, must be null), and the
  * backward gives the gradients of the feature loss. */
 #define PSM_FLAG_FEATURE_ONLY 8
+/* Renormalised Top-K (a variant of eq. (18)): the feature map is
+ * sum_sel w_k f_k / sum_sel w_k, the selected weights rescaled to sum 1 (zero
+ * where nothing is selected); the backward differentiates the quotient.
+ * Needs the Top-K blend and c > 0. */
+#define PSM_FLAG_TOPK_RENORM 16
 
 typedef struct { float *rgb, *depth, *normal, *alpha, *feat; } psm_images;
 typedef struct { const float *rgb, *depth, *normal, *alpha, *feat; } psm_image_grads;

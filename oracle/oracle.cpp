@@ -622,9 +622,15 @@ void orc_render(int64_t n, const float* means, const float* scales, const float*
       if (feat_out) {
         double* F = feat_out + e * C;
         for (int j = 0; j < C; ++j) F[j] = 0;
+        double Wsel = 0;
         for (size_t i = 0; i < cs.size(); ++i)
-          if (sel[i])
+          if (sel[i]) {
+            Wsel += cs[i].w;
             for (int j = 0; j < C; ++j) F[j] += cs[i].w * feat[cs[i].id * (int64_t)C + j];
+          }
+        // blend mode 3: Top-K with the selected weights renormalised to sum 1
+        if (blend == 3 && Wsel > 0)
+          for (int j = 0; j < C; ++j) F[j] /= Wsel;
       }
       for (int j = 0; j < 3; ++j) {
         if (rgb_out) rgb_out[3 * e + j] = col[j];
@@ -693,13 +699,31 @@ void orc_backward(int64_t n, const float* means, const float* scales, const floa
       const double* gN = g_normal + 3 * e;
       const double gD = g_depth[e], gA = g_alpha[e];
       const double* gF = g_feat + e * C;
+      // renormalised Top-K (blend mode 3): F = sum_sel w_i f_i / W, so the
+      // feature part of d/dw_i is gF . (f_i - F) / W and d/df_i = w_i gF / W
+      double Wsel = 0.0, gFF = 0.0;
+      if (blend == 3) {
+        for (int i = 0; i < m; ++i)
+          if (sel[i]) Wsel += cs[i].w;
+        if (Wsel > 0)
+          for (int i = 0; i < m; ++i)
+            if (sel[i]) {
+              double d = 0;
+              for (int j = 0; j < C; ++j) d += gF[j] * feat[cs[i].id * (int64_t)C + j];
+              gFF += cs[i].w * d / Wsel;
+            }
+      }
       // e_i = d<upstream, outputs>/d(weight of contributor i)
       e_i.assign(m, 0.0);
       for (int i = 0; i < m; ++i) {
         const int64_t id = cs[i].id;
         double v = gD * cs[i].z;
         for (int j = 0; j < 3; ++j) v += gC[j] * rgb[3 * id + j] + gN[j] * P.geo[id].nc[j];
-        if (sel[i]) for (int j = 0; j < C; ++j) v += gF[j] * feat[id * (int64_t)C + j];
+        if (sel[i]) {
+          double d = 0;
+          for (int j = 0; j < C; ++j) d += gF[j] * feat[id * (int64_t)C + j];
+          v += blend == 3 ? (Wsel > 0 ? (d - gFF) / Wsel : 0.0) : d;
+        }
         e_i[i] = v;
       }
       // out = sum_i w_i x_i with w_i = alpha_i prod_{j<i}(1 - alpha_j), and
@@ -717,11 +741,13 @@ void orc_backward(int64_t n, const float* means, const float* scales, const floa
 #pragma omp atomic
           d_rgb[3 * id + j] += c.w * gC[j];
         }
-        if (sel[i])
+        if (sel[i]) {
+          const double wf = blend == 3 ? (Wsel > 0 ? c.w / Wsel : 0.0) : c.w;
           for (int j = 0; j < C; ++j) {
 #pragma omp atomic
-            d_feat[id * (int64_t)C + j] += c.w * gF[j];
+            d_feat[id * (int64_t)C + j] += wf * gF[j];
           }
+        }
         // chain through alpha, depth and normal with dual numbers
         D10 o;
         Geo<D10> g = geo_dual(sc.in(id), k, P.key[id].flip, o);

@@ -21,6 +21,8 @@ FULL, TOPK = 0, 1
 # Top-K with the feature-only stop: a pixel's walk ends once no later surfel can
 # enter its K largest weights (selection and feature map unchanged).
 TOPK_FEATURE_ONLY = 2
+# Top-K with the selected weights renormalised to sum 1 (F = sum w f / sum w).
+TOPK_RENORM = 3
 MODES = {"sphere": SPHERE, "aabb": AABB, "ellipse": ELLIPSE}
 
 _lib = None

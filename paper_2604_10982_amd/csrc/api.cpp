@@ -169,6 +169,8 @@ psm_status validate_common(const psm_camera* cams, int32_t n_cams, const psm_con
     return fail(PSM_ERR_INVALID_ARG, "blend_pass must be 0, 16 or 32");
   if (cfg->bwd_pass != 0 && cfg->bwd_pass != 16 && cfg->bwd_pass != 32)
     return fail(PSM_ERR_INVALID_ARG, "bwd_pass must be 0, 16 or 32");
+  if ((cfg->flags & PSM_FLAG_TOPK_RENORM) && (cfg->blend != PSM_BLEND_TOPK || c == 0))
+    return fail(PSM_ERR_INVALID_ARG, "PSM_FLAG_TOPK_RENORM needs the Top-K blend and c > 0");
   if ((cfg->flags & PSM_FLAG_FEATURE_ONLY) && (cfg->blend != PSM_BLEND_TOPK || c == 0))
     return fail(PSM_ERR_INVALID_ARG, "PSM_FLAG_FEATURE_ONLY needs the Top-K blend and c > 0");
   if (c < 0 || c > 1024) return fail(PSM_ERR_INVALID_ARG, "c must be in [0, 1024]");
@@ -297,7 +299,7 @@ void enqueue_forward(const SurfelArgs& sa, const CamTable& ct, const psm_config*
   launch_walk(L, ct, cfg->blend, tu, ia, (cfg->flags & PSM_FLAG_FEATURE_ONLY) != 0, ws, st);
   prof.end(kStageWalk, st);
   prof.begin(kStageBlend, st);
-  launch_feature_blend(sa, L, ct, cfg->blend, tu, out->feat, ws, st);
+  launch_feature_blend(sa, L, ct, cfg->blend, tu, out->feat, (cfg->flags & PSM_FLAG_TOPK_RENORM) != 0, ws, st);
   prof.end(kStageBlend, st);
 }
 
@@ -357,7 +359,8 @@ psm_status backward_impl(psm_ctx* ctx, const psm_surfels* s, const psm_camera* c
   hipStream_t st = (hipStream_t)stream;
   ImageGradArgs g{grad_out->rgb, grad_out->depth, grad_out->normal, grad_out->alpha, grad_out->feat};
   GradArgs ga{grads->means, grads->scales, grads->quats, grads->opacity, grads->rgb, grads->feat};
-  launch_backward(surfel_args(s), ct, cfg->blend, tuning_of(cfg), L, g, ga, (char*)workspace, st,
+  launch_backward(surfel_args(s), ct, cfg->blend, tuning_of(cfg), L, g, ga, (cfg->flags & PSM_FLAG_TOPK_RENORM) != 0,
+                  (char*)workspace, st,
                   hook_for(ctx, cfg));
   r = check_hip("psm_backward launch");
   if (r != PSM_OK) return r;

@@ -86,7 +86,7 @@ inline TileQueue tile_queue(const Layout& L, int sched, char* ws, int q) {
 void launch_walk(const Layout& L, const CamTable& ct, int blend, const Tuning& tu, const ImageArgs& out,
                  bool feat_only, char* ws, hipStream_t st);
 void launch_feature_blend(const SurfelArgs& s, const Layout& L, const CamTable& ct, int blend, const Tuning& tu,
-                          float* out_feat, char* ws, hipStream_t st);
+                          float* out_feat, bool renorm, char* ws, hipStream_t st);
 void launch_export_selection(const Layout& L, const CamTable& ct, char* ws, int32_t* sel_id, float* sel_w,
                              int32_t* n_last, float* t_final, hipStream_t st);
 
@@ -111,7 +111,8 @@ void launch_labels_backward(int64_t n, const float* means, const void* fg, int d
 
 // raster_bwd.hip
 void launch_backward(const SurfelArgs& s, const CamTable& ct, int blend, const Tuning& tu, const Layout& L,
-                     const ImageGradArgs& g, const GradArgs& grads, char* ws, hipStream_t st, const ProfHook& prof);
+                     const ImageGradArgs& g, const GradArgs& grads, bool renorm, char* ws, hipStream_t st,
+                     const ProfHook& prof);
 
 // Frustum-local cross-attention (attention.hip).
 struct AttentionArgs {

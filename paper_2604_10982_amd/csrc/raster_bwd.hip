@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
     const uint32_t* __restrict__ pid, const uint32_t* __restrict__ eid, const uint2* __restrict__ ranges,
     const int32_t* __restrict__ selpos, const float* __restrict__ selw, const FT* __restrict__ feat,
     const float* __restrict__ gfeat, int C, int K, CamTable ct, TileQueue tq, float* __restrict__ seldot,
-    float* __restrict__ fpart, uint8_t* __restrict__ fflag) {
+    float* __restrict__ fpart, uint8_t* __restrict__ fflag, int renorm) {
   static_assert(GC % 16 == 0, "pass width is a multiple of the MFMA tile");
   // Row stride of the staged G and F: = 2 mod 4, so a 16-row x 2-column read
   // (lanes 0-31 of an operand fetch) touches 32 distinct banks, and 8 rows
@@ -98,12 +98,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
   // windows (no block-wide maximum of the selections needed)
   const int lastpos = (int)(ranges[tile].y - start) - 1;
   int Uw0 = 0;
+  float rw = 1.0f;  // renormalised Top-K: 1 / (sum of the pixel's selected weights)
   {
     int pos[KMAX];
     load_pos(pos);
+    float wsum = 0.0f;
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q)  // unselected entries keep weight 0 and report dot 0
-      if (q < K) s_w[wsel_off(q, tid)] = pos[q] >= 0 ? selw[tbase + (size_t)q * kTilePix + tid] : 0.0f;
+    for (int q = 0; q < KMAX; ++q) {  // unselected entries keep weight 0 and report dot 0
+      const float wq = q < K && pos[q] >= 0 ? selw[tbase + (size_t)q * kTilePix + tid] : 0.0f;
+      if (q < K) s_w[wsel_off(q, tid)] = wq;
+      wsum += wq;
+    }
+    if (renorm) rw = wsum > 0.0f ? 1.0f / wsum : 0.0f;
     if (lastpos >= 0) Uw0 = build_window(S, pos, K, 0, window_words(lastpos, 0));
   }
 
@@ -168,10 +174,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
             const int c = cc + 4 * j;
             const float4 g =
                 inside && c < C ? *reinterpret_cast<const float4*>(grow + c) : make_float4(0.f, 0.f, 0.f, 0.f);
-            gv[4 * j] = g.x;
-            gv[4 * j + 1] = g.y;
-            gv[4 * j + 2] = g.z;
-            gv[4 * j + 3] = g.w;
+            // renormalised Top-K: the rows and dots see g / W (rw = 1 otherwise)
+            gv[4 * j] = g.x * rw;
+            gv[4 * j + 1] = g.y * rw;
+            gv[4 * j + 2] = g.z * rw;
+            gv[4 * j + 3] = g.w * rw;
           }
 #pragma unroll
           for (int u = 0; u < FPT; ++u) {
@@ -267,9 +274,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
     }
   }
   __syncthreads();
+  // renormalised Top-K: d/dw_q of F = sum w f / W is g.(f_q - F) / W, i.e.
+  // dot'_q - sum_j (w_j / W) dot'_j with dot' = (g / W) . f
+  float cshift = 0.0f;
+  if (renorm) {
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q)
+      if (q < K) {
+        const float wq = selpos[tbase + (size_t)q * kTilePix + tid] >= 0 ? selw[tbase + (size_t)q * kTilePix + tid] : 0.0f;
+        cshift = fmaf(wq, s_w[wsel_off(q, tid)], cshift);
+      }
+    cshift *= rw;
+  }
 #pragma unroll
   for (int q = 0; q < KMAX; ++q)
-    if (q < K) seldot[tbase + (size_t)q * kTilePix + tid] = s_w[wsel_off(q, tid)];
+    if (q < K) seldot[tbase + (size_t)q * kTilePix + tid] = s_w[wsel_off(q, tid)] - cshift;
   __syncthreads();
   });
 }
@@ -816,24 +835,24 @@ __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const 
 // ------------------------------------------------------------- host wrappers
 template <typename FT, int KMAX, int GC, bool PERSIST>
 static void feat_bwd_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
-                            const ImageGradArgs& g, char* ws, hipStream_t st) {
+                            const ImageGradArgs& g, bool renorm, char* ws, hipStream_t st) {
   const size_t shm = (size_t)kWRow * L.k * sizeof(float);  // weights, then dots
   const void* k = reinterpret_cast<const void*>(&k_feat_bwd_topk<FT, KMAX, GC, PERSIST>);
   hipLaunchKernelGGL((k_feat_bwd_topk<FT, KMAX, GC, PERSIST>), dim3(tile_grid(L, tu.sched_bwd, k, shm)), dim3(256), shm, st,
                      (const uint32_t*)(ws + L.pid), (const uint32_t*)(ws + L.eid0), (const uint2*)(ws + L.ranges),
                      (const int32_t*)(ws + L.selpos), (const float*)(ws + L.selw), (const FT*)s.feat, g.feat, s.c, L.k,
                      ct, tile_queue(L, tu.sched_bwd, ws, kQFeatBwd), (float*)(ws + L.seldot), (float*)(ws + L.fpart),
-                     (uint8_t*)(ws + L.fflag));
+                     (uint8_t*)(ws + L.fflag), renorm ? 1 : 0);
 }
 
 template <typename FT, int GC>
 static void feat_bwd_k(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
-                       const ImageGradArgs& g, char* ws, hipStream_t st) {
+                       const ImageGradArgs& g, bool rn, char* ws, hipStream_t st) {
   const bool p = tu.sched_bwd == kSchedPersistent;
-  if (L.k <= 8) (p ? feat_bwd_launch<FT, 8, GC, true> : feat_bwd_launch<FT, 8, GC, false>)(s, L, ct, tu, g, ws, st);
+  if (L.k <= 8) (p ? feat_bwd_launch<FT, 8, GC, true> : feat_bwd_launch<FT, 8, GC, false>)(s, L, ct, tu, g, rn, ws, st);
   else if (L.k <= 16)
-    (p ? feat_bwd_launch<FT, 16, GC, true> : feat_bwd_launch<FT, 16, GC, false>)(s, L, ct, tu, g, ws, st);
-  else (p ? feat_bwd_launch<FT, 32, GC, true> : feat_bwd_launch<FT, 32, GC, false>)(s, L, ct, tu, g, ws, st);
+    (p ? feat_bwd_launch<FT, 16, GC, true> : feat_bwd_launch<FT, 16, GC, false>)(s, L, ct, tu, g, rn, ws, st);
+  else (p ? feat_bwd_launch<FT, 32, GC, true> : feat_bwd_launch<FT, 32, GC, false>)(s, L, ct, tu, g, rn, ws, st);
 }
 
 template <int MODE, typename FT, bool PERSIST>
@@ -860,15 +879,15 @@ static void walk_bwd_launch(const SurfelArgs& s, const Layout& L, const CamTable
 
 template <typename FT>
 static void backward_typed(const SurfelArgs& s, const CamTable& ct, int blend, const Tuning& tu, const Layout& L,
-                           const ImageGradArgs& g, const GradArgs& gr, char* ws, hipStream_t st,
+                           const ImageGradArgs& g, const GradArgs& gr, bool renorm, char* ws, hipStream_t st,
                            const ProfHook& prof) {
   const bool want_f = g.feat != nullptr && s.c > 0;
   if (L.tiles > 0) {
     if (blend == kTopK) {
       prof.begin(kStageBwdFeature, st);
       if (want_f) {
-        if (tu.bwd_pass == 32) feat_bwd_k<FT, 32>(s, L, ct, tu, g, ws, st);
-        else feat_bwd_k<FT, 16>(s, L, ct, tu, g, ws, st);
+        if (tu.bwd_pass == 32) feat_bwd_k<FT, 32>(s, L, ct, tu, g, renorm, ws, st);
+        else feat_bwd_k<FT, 16>(s, L, ct, tu, g, renorm, ws, st);
       } else {
         launch_fill_u32(ws + L.seldot, 0u, L.spix * (int64_t)L.k, st);
       }
@@ -903,15 +922,16 @@ static void backward_typed(const SurfelArgs& s, const CamTable& ct, int blend, c
 }
 
 void launch_backward(const SurfelArgs& s, const CamTable& ct, int blend, const Tuning& tu, const Layout& L,
-                     const ImageGradArgs& g, const GradArgs& grads, char* ws, hipStream_t st, const ProfHook& prof) {
+                     const ImageGradArgs& g, const GradArgs& grads, bool renorm, char* ws, hipStream_t st,
+                     const ProfHook& prof) {
   prof.begin(kStageFill, st);
   launch_fill_u32(ws + L.gflag, 0u, cdiv(std::max<int64_t>(L.cap, 1), 4), st);
   launch_fill_u32(ws + L.fflag, 0u, cdiv(std::max<int64_t>(L.cap, 1), 4), st);
   launch_fill_u32((uint32_t*)(ws + L.status) + kStQueue + kQFeatBwd, 0u, 2, st);
   prof.end(kStageFill, st);
-  if (s.dtype == kF32) backward_typed<float>(s, ct, blend, tu, L, g, grads, ws, st, prof);
-  else if (s.dtype == kF16) backward_typed<__half>(s, ct, blend, tu, L, g, grads, ws, st, prof);
-  else backward_typed<uint16_t>(s, ct, blend, tu, L, g, grads, ws, st, prof);
+  if (s.dtype == kF32) backward_typed<float>(s, ct, blend, tu, L, g, grads, renorm, ws, st, prof);
+  else if (s.dtype == kF16) backward_typed<__half>(s, ct, blend, tu, L, g, grads, renorm, ws, st, prof);
+  else backward_typed<uint16_t>(s, ct, blend, tu, L, g, grads, renorm, ws, st, prof);
 }
 
 }  // namespace psm

@@ -261,7 +261,7 @@ __global__ __launch_bounds__(256) void k_blend_topk(const uint32_t* __restrict__
                                                     const int32_t* __restrict__ selpos,
                                                     const float* __restrict__ selw, const FT* __restrict__ feat,
                                                     int C, int K, CamTable ct, TileQueue tq,
-                                                    float* __restrict__ o_feat) {
+                                                    float* __restrict__ o_feat, int renorm) {
   __shared__ SelShared S;
   constexpr int kBRow = BC + 4;
   __shared__ __align__(16) float s_F[kSlotChunk * kBRow];
@@ -285,6 +285,10 @@ __global__ __launch_bounds__(256) void k_blend_topk(const uint32_t* __restrict__
   // list positions are below the tile's list length, which bounds the
   // windows (no block-wide maximum of the selections needed)
   const int maxpos = (int)(ranges[tile].y - start) - 1;
+  float wsum = 0.0f;
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) wsum += pos[q] >= 0 ? w[q] : 0.0f;
+  const float rw = wsum > 0.0f ? 1.0f / wsum : 0.0f;
 
   // One window whose slots fit one chunk: rank once, stage per channel pass.
   int sl[KMAX];
@@ -334,6 +338,10 @@ __global__ __launch_bounds__(256) void k_blend_topk(const uint32_t* __restrict__
       }
     }
     if (inside) {
+      if (renorm) {  // renormalised Top-K: the selected weights scaled to sum 1
+#pragma unroll
+        for (int c = 0; c < BC; ++c) acc[c] *= rw;
+      }
 #pragma unroll
       for (int c = 0; c < BC; c += 4)
         if (cc + c < C)
@@ -475,24 +483,26 @@ void launch_walk(const Layout& L, const CamTable& ct, int blend, const Tuning& t
 
 template <typename FT, int KMAX, int BC, bool PERSIST>
 static void blend_topk_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
-                              float* out_feat, char* ws, hipStream_t st) {
+                              float* out_feat, bool renorm, char* ws, hipStream_t st) {
   const void* k = reinterpret_cast<const void*>(&k_blend_topk<FT, KMAX, BC, PERSIST>);
   hipLaunchKernelGGL((k_blend_topk<FT, KMAX, BC, PERSIST>), dim3(tile_grid(L, tu.sched, k, 0)), dim3(256), 0, st,
                      (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos),
                      (const float*)(ws + L.selw), (const FT*)s.feat, s.c, L.k, ct, tile_queue(L, tu.sched, ws, kQBlend),
-                     out_feat);
+                     out_feat, renorm ? 1 : 0);
 }
 
 template <typename FT, int BC>
 static void blend_topk_k(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu, float* out_feat,
-                         char* ws, hipStream_t st) {
+                         bool rn, char* ws, hipStream_t st) {
   const bool p = tu.sched == kSchedPersistent;
   if (L.k <= 8)
-    (p ? blend_topk_launch<FT, 8, BC, true> : blend_topk_launch<FT, 8, BC, false>)(s, L, ct, tu, out_feat, ws, st);
+    (p ? blend_topk_launch<FT, 8, BC, true> : blend_topk_launch<FT, 8, BC, false>)(s, L, ct, tu, out_feat, rn, ws, st);
   else if (L.k <= 16)
-    (p ? blend_topk_launch<FT, 16, BC, true> : blend_topk_launch<FT, 16, BC, false>)(s, L, ct, tu, out_feat, ws, st);
+    (p ? blend_topk_launch<FT, 16, BC, true> : blend_topk_launch<FT, 16, BC, false>)(s, L, ct, tu, out_feat, rn, ws,
+                                                                                      st);
   else
-    (p ? blend_topk_launch<FT, 32, BC, true> : blend_topk_launch<FT, 32, BC, false>)(s, L, ct, tu, out_feat, ws, st);
+    (p ? blend_topk_launch<FT, 32, BC, true> : blend_topk_launch<FT, 32, BC, false>)(s, L, ct, tu, out_feat, rn, ws,
+                                                                                      st);
 }
 
 template <typename FT, bool PERSIST>
@@ -507,10 +517,10 @@ static void full_feat_launch(const SurfelArgs& s, const Layout& L, const CamTabl
 
 template <typename FT>
 static void blend_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, int blend, const Tuning& tu,
-                         float* out_feat, char* ws, hipStream_t st) {
+                         float* out_feat, bool renorm, char* ws, hipStream_t st) {
   if (blend == kTopK) {
-    if (tu.blend_pass == 16) blend_topk_k<FT, 16>(s, L, ct, tu, out_feat, ws, st);
-    else blend_topk_k<FT, 32>(s, L, ct, tu, out_feat, ws, st);
+    if (tu.blend_pass == 16) blend_topk_k<FT, 16>(s, L, ct, tu, out_feat, renorm, ws, st);
+    else blend_topk_k<FT, 32>(s, L, ct, tu, out_feat, renorm, ws, st);
   } else if (tu.sched == kSchedPersistent) {
     full_feat_launch<FT, true>(s, L, ct, tu, out_feat, ws, st);
   } else {
@@ -519,11 +529,11 @@ static void blend_launch(const SurfelArgs& s, const Layout& L, const CamTable& c
 }
 
 void launch_feature_blend(const SurfelArgs& s, const Layout& L, const CamTable& ct, int blend, const Tuning& tu,
-                          float* out_feat, char* ws, hipStream_t st) {
+                          float* out_feat, bool renorm, char* ws, hipStream_t st) {
   if (!out_feat || s.c <= 0 || L.tiles == 0) return;
-  if (s.dtype == kF32) blend_launch<float>(s, L, ct, blend, tu, out_feat, ws, st);
-  else if (s.dtype == kF16) blend_launch<__half>(s, L, ct, blend, tu, out_feat, ws, st);
-  else blend_launch<uint16_t>(s, L, ct, blend, tu, out_feat, ws, st);
+  if (s.dtype == kF32) blend_launch<float>(s, L, ct, blend, tu, out_feat, renorm, ws, st);
+  else if (s.dtype == kF16) blend_launch<__half>(s, L, ct, blend, tu, out_feat, renorm, ws, st);
+  else blend_launch<uint16_t>(s, L, ct, blend, tu, out_feat, renorm, ws, st);
 }
 
 void launch_export_selection(const Layout& L, const CamTable& ct, char* ws, int32_t* sel_id, float* sel_w,

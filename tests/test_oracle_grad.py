@@ -28,7 +28,7 @@ def _loss(orc, sc, cam, g, K, blend, pix):
     return sum(float((r[k].reshape(len(pix), -1) * gi[k]).sum()) for k in gi)
 
 
-@pytest.mark.parametrize("blend", [0, 1])
+@pytest.mark.parametrize("blend", [0, 1, 3])
 def test_finite_differences(orc, blend):
     sc, cam = small_scene()
     K = 3

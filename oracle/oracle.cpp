@@ -48,6 +48,13 @@ constexpr float kFoot2F = 9.0087890625f;  // 9 * (1 + 2^-10), exact in FP32
 constexpr double kAlphaMin = 1.0 / 255.0;
 constexpr double kAlphaMax = 0.99;
 constexpr double kTMin = 1e-4;
+// Optional screen-space low-pass filter (the 2DGS variant): the kernel value
+// is the larger of the ray-splat Gaussian and an isotropic screen-space
+// Gaussian of variance 1/2 px^2 about the projected centre c, i.e.
+// rho = min(u^2 + v^2, 2 |x - c|^2).  Its listed disk has radius^2
+// foot2 / 2 + 1/16 about the FP32 centre (1/16 px^2 covers the FP32 centre's
+// rounding at any image size).
+constexpr float kLpPadF = 0.0625f;
 
 enum Cull { kVisible = 0, kCullQuat = 1, kCullNear = 2, kCullDisk = 3, kCullDegenerate = 4 };
 enum Mode { kSphere = 0, kAabb = 1, kEllipse = 2 };
@@ -76,6 +83,7 @@ struct KeyF {
   uint32_t depth_bits;
   int flip;
   float ecx, ecy, S00, S01, S11, ex, ey, gam, kk;  // ellipse centre, shape; kk = |c * det A|
+  float xc, yc, rf2;  // projected centre; low-pass disk radius^2 (0: no filter)
 };
 
 // Opacity-aware footprint bound (exact work reduction, reading of Sec. 3.1):
@@ -93,7 +101,9 @@ float opacity_foot2_f32(float o) {
 }
 
 // foot2: radius^2 of the listed footprint; culling always uses kFoot2F.
-KeyF key_f32(const float* mu, const float* sc, const float* q, const Cam& k, float foot2 = kFoot2F) {
+// lowpass: also list the low-pass filter's disk.
+KeyF key_f32(const float* mu, const float* sc, const float* q, const Cam& k, float foot2 = kFoot2F,
+             int lowpass = 0) {
   KeyF r;
   std::memset(&r, 0, sizeof(r));
   // quaternion (w,x,y,z) -> unit
@@ -164,6 +174,8 @@ KeyF key_f32(const float* mu, const float* sc, const float* q, const Cam& k, flo
   r.S00 = S00; r.S01 = S01; r.S11 = S11;
   r.ex = std::sqrt(S00); r.ey = std::sqrt(S11);
   r.gam = gam; r.kk = std::fabs(cc * dA);
+  r.xc = xc; r.yc = yc;
+  r.rf2 = lowpass ? 0.5f * foot2 + kLpPadF : 0.0f;
   return r;
 }
 
@@ -181,42 +193,72 @@ bool span_f32(float lo, float hi, int npix, int tsz, int nt, int& t0, int& t1) {
 
 struct Row { int ty, tx0, tx1; };
 
-// Footprint rows of a visible surfel for one mode.
+// Footprint rows of a visible surfel for one mode.  With the low-pass filter
+// the footprint is the union with the filter's disk: its bounding box joins
+// the box of every mode, and in the exact mode each row takes the hull of the
+// ellipse's and the disk's x-extents within the row's band.
 void footprint(const KeyF& f, const Cam& k, int tw, int th, int mode, std::vector<Row>& rows) {
   rows.clear();
   const int ntx = (k.W + tw - 1) / tw, nty = (k.H + th - 1) / th;
+  const bool lp = f.rf2 > 0.0f;
+  const float rf = lp ? std::sqrt(f.rf2) : 0.0f;
   int ax0, ax1, ay0, ay1;
+  float bx0, bx1, by0, by1;
   if (mode == kSphere) {
     float hs = 0.5f * (f.S00 + f.S11);
     float hd = 0.5f * (f.S00 - f.S11);
     float lmax = hs + std::sqrt(hd * hd + f.S01 * f.S01);
     float rr = std::fmax(std::sqrt(lmax), std::fmax(f.ex, f.ey));
-    if (!span_f32(f.ecx - rr, f.ecx + rr, k.W, tw, ntx, ax0, ax1)) return;
-    if (!span_f32(f.ecy - rr, f.ecy + rr, k.H, th, nty, ay0, ay1)) return;
-    for (int ty = ay0; ty <= ay1; ++ty) rows.push_back({ty, ax0, ax1});
-    return;
+    bx0 = f.ecx - rr; bx1 = f.ecx + rr; by0 = f.ecy - rr; by1 = f.ecy + rr;
+  } else {
+    bx0 = f.ecx - f.ex; bx1 = f.ecx + f.ex; by0 = f.ecy - f.ey; by1 = f.ecy + f.ey;
   }
-  if (!span_f32(f.ecx - f.ex, f.ecx + f.ex, k.W, tw, ntx, ax0, ax1)) return;
-  if (!span_f32(f.ecy - f.ey, f.ecy + f.ey, k.H, th, nty, ay0, ay1)) return;
-  if (mode == kAabb) {
+  if (lp) {
+    bx0 = std::fmin(bx0, f.xc - rf); bx1 = std::fmax(bx1, f.xc + rf);
+    by0 = std::fmin(by0, f.yc - rf); by1 = std::fmax(by1, f.yc + rf);
+  }
+  if (!span_f32(bx0, bx1, k.W, tw, ntx, ax0, ax1)) return;
+  if (!span_f32(by0, by1, k.H, th, nty, ay0, ay1)) return;
+  if (mode != kEllipse) {
     for (int ty = ay0; ty <= ay1; ++ty) rows.push_back({ty, ax0, ax1});
     return;
   }
   // exact ellipse: per tile row, the x-extent of E within the row's band
   const float yr = f.S01 / f.ex;  // dy of the rightmost point of E
   for (int ty = ay0; ty <= ay1; ++ty) {
-    float ylo = ((float)(ty * th) + 0.5f) - f.ecy;
-    float yhi = std::fmin((float)(ty * th) + ((float)th - 0.5f), (float)k.H - 0.5f) - f.ecy;
+    float rlo = (float)(ty * th) + 0.5f;
+    float rhi = std::fmin((float)(ty * th) + ((float)th - 0.5f), (float)k.H - 0.5f);
+    float ylo = rlo - f.ecy;
+    float yhi = rhi - f.ecy;
     float lo = std::fmax(ylo, -f.ey), hi = std::fmin(yhi, f.ey);
-    if (!(lo <= hi)) continue;
-    float dR = std::fmin(std::fmax(yr, lo), hi);
-    float dL = std::fmin(std::fmax(-yr, lo), hi);
-    float hR = std::sqrt(std::fmax(0.0f, (f.S11 - dR * dR) / f.gam)) * f.kk;
-    float hL = std::sqrt(std::fmax(0.0f, (f.S11 - dL * dL) / f.gam)) * f.kk;
-    float xR = (f.S01 * dR + hR) / f.S11;
-    float xL = (f.S01 * dL - hL) / f.S11;
+    bool have = false;
+    float xl = 0.0f, xr = 0.0f;
+    if (lo <= hi) {
+      float dR = std::fmin(std::fmax(yr, lo), hi);
+      float dL = std::fmin(std::fmax(-yr, lo), hi);
+      float hR = std::sqrt(std::fmax(0.0f, (f.S11 - dR * dR) / f.gam)) * f.kk;
+      float hL = std::sqrt(std::fmax(0.0f, (f.S11 - dL * dL) / f.gam)) * f.kk;
+      float xR = (f.S01 * dR + hR) / f.S11;
+      float xL = (f.S01 * dL - hL) / f.S11;
+      xl = f.ecx + xL;
+      xr = f.ecx + xR;
+      have = true;
+    }
+    if (lp) {  // the disk's chord nearest its centre within the band
+      float dlo = rlo - f.yc, dhi = rhi - f.yc;
+      float dy = std::fmin(std::fmax(0.0f, dlo), dhi);
+      float h2 = f.rf2 - dy * dy;
+      if (h2 >= 0.0f) {
+        float h = std::sqrt(h2);
+        float dl = f.xc - h, dr = f.xc + h;
+        xl = have ? std::fmin(xl, dl) : dl;
+        xr = have ? std::fmax(xr, dr) : dr;
+        have = true;
+      }
+    }
+    if (!have) continue;
     int x0, x1;
-    if (!span_f32(f.ecx + xL, f.ecx + xR, k.W, tw, ntx, x0, x1)) continue;
+    if (!span_f32(xl, xr, k.W, tw, ntx, x0, x1)) continue;
     x0 = std::max(x0, ax0); x1 = std::min(x1, ax1);
     if (x0 <= x1) rows.push_back({ty, x0, x1});
   }
@@ -328,19 +370,35 @@ Geo<D10> geo_dual(const SurfIn& in, const Cam& k, int flip, D10& o) {
 }
 
 // Per-(pixel, surfel) evaluation (Sec. 3.1): rho = u^2 + v^2, hit iff
-// rho <= r^2, alpha = min(0.99, o exp(-rho/2)).
+// rho <= r^2, alpha = min(0.99, o exp(-rho/2)).  With the low-pass filter
+// rho = min(u^2 + v^2, 2 |x - c|^2); where the filter term is the smaller
+// (ties go to the ray-splat term) the depth is the centre's camera depth.
 struct Eval {
   bool hit;
   double rho, G, alpha, z;
   bool clamped;
+  bool filt;        // the filter term was taken
+  double bmargin;   // relative gap between the two terms (INFINITY: no filter)
 };
 
-Eval eval_pixel(const Geo<double>& g, double o, double x, double y) {
+Eval eval_pixel(const Geo<double>& g, double o, double x, double y, bool lowpass = false) {
   Eval e{};
+  e.bmargin = INFINITY;
   double u, v, z;
-  if (!solve_uv(g, x, y, u, v, z)) { e.hit = false; e.rho = INFINITY; return e; }
-  e.rho = u * u + v * v;
-  e.z = z;
+  const bool ok = solve_uv(g, x, y, u, v, z);
+  e.rho = ok ? u * u + v * v : INFINITY;
+  e.z = ok ? z : 0.0;
+  if (lowpass) {
+    const double cx = g.M[2] / g.M[8], cy = g.M[5] / g.M[8];  // projected centre
+    const double rf = 2.0 * ((x - cx) * (x - cx) + (y - cy) * (y - cy));
+    e.bmargin = std::fabs(e.rho - rf) / std::max(e.rho, rf);
+    if (!(e.rho <= rf)) {
+      e.filt = true;
+      e.rho = rf;
+      e.z = g.M[8];
+    }
+  }
+  if (!std::isfinite(e.rho)) { e.hit = false; e.rho = INFINITY; return e; }
   e.hit = e.rho <= kCut2;
   e.G = std::exp(-0.5 * e.rho);
   double a = o * e.G;
@@ -355,6 +413,7 @@ struct Scene {
   const float *means, *scales, *quats, *opacity, *rgb;
   const double* feat;  // N x C, already rounded to the storage dtype
   int C;
+  int lowpass;  // screen-space low-pass filter on
   SurfIn in(int64_t i) const { return {means + 3 * i, scales + 2 * i, quats + 4 * i, opacity[i]}; }
 };
 
@@ -404,6 +463,11 @@ void prepare(const Scene& sc, const Cam& k, int tw, int th, Prepared& P) {
       double dy = std::sqrt(std::max(0.0, Cs[1][2] * Cs[1][2] - Cs[1][1] * Cs[2][2])) / std::fabs(Cs[2][2]);
       x0 = xc - dx; x1 = xc + dx; y0 = yc - dy; y1 = yc + dy;
     }
+    if (sc.lowpass) {  // the filter's disk 2 |x - c|^2 <= r^2, inflated by 1%
+      const double cx = M[2] / M[8], cy = M[5] / M[8], rl = std::sqrt(0.5 * kCut2) * 1.01;
+      x0 = std::min(x0, cx - rl); x1 = std::max(x1, cx + rl);
+      y0 = std::min(y0, cy - rl); y1 = std::max(y1, cy + rl);
+    }
     int tx0 = (int)std::max(0.0, std::floor((x0 - 0.5) / tw));
     int tx1 = (int)std::min((double)P.ntx - 1, std::floor((x1 - 0.5) / tw));
     int ty0 = (int)std::max(0.0, std::floor((y0 - 0.5) / th));
@@ -418,6 +482,7 @@ struct Contrib {
   int64_t id;
   double alpha, T, w, z;
   bool clamped;
+  bool filt;  // low-pass filter term taken
 };
 
 // Relative distance of the pixel's decisions from their thresholds, by kind:
@@ -442,9 +507,10 @@ void walk_pixel(const Scene& sc, const Prepared& P, const Cam& k, int px, int py
   double T = 1.0;
   std::vector<double> held;  // the K largest weights so far, a min-heap
   for (int64_t id : bin) {
-    Eval e = eval_pixel(P.geo[id], sc.opacity[id], x, y);
+    Eval e = eval_pixel(P.geo[id], sc.opacity[id], x, y, sc.lowpass != 0);
     if (std::isfinite(e.rho)) margin.m[0] = std::min(margin.m[0], std::fabs(e.rho - kCut2) / kCut2);
     if (!e.hit) continue;
+    margin.m[0] = std::min(margin.m[0], e.bmargin);  // which term a hit takes
     double a_raw = sc.opacity[id] * e.G;
     margin.m[1] = std::min(margin.m[1], std::fabs(a_raw / kAlphaMax - 1.0));
     margin.m[1] = std::min(margin.m[1], std::fabs(e.alpha / kAlphaMin - 1.0));
@@ -452,7 +518,7 @@ void walk_pixel(const Scene& sc, const Prepared& P, const Cam& k, int px, int py
     double Tn = T * (1.0 - e.alpha);
     margin.m[2] = std::min(margin.m[2], std::fabs(Tn / kTMin - 1.0));
     if (Tn < kTMin) break;
-    out.push_back({id, e.alpha, T, e.alpha * T, e.z, e.clamped});
+    out.push_back({id, e.alpha, T, e.alpha * T, e.z, e.clamped, e.filt});
     T = Tn;
     if (topk_stop > 0) {
       const double w = out.back().w;
@@ -495,8 +561,9 @@ extern "C" {
 // is non-null.  If cap >= P, also writes the P pairs sorted by
 // (tile, depth bits, surfel id).  Returns P.
 // opacity: non-null selects the opacity-aware footprint (per-surfel opacities).
+// lowpass: list the union with the low-pass filter's disk.
 int64_t orc_keystage(int64_t n, const float* means, const float* scales, const float* quats,
-                     const float* opacity, const float* cam, int tw, int th, int mode,
+                     const float* opacity, const float* cam, int tw, int th, int mode, int lowpass,
                      int32_t* cull_out, uint32_t* depth_out, int32_t* flip_out, int32_t* count_out,
                      float* fp_out, int64_t cap, int32_t* tile_out, int32_t* id_out) {
   Cam k = load_cam(cam);
@@ -509,7 +576,7 @@ int64_t orc_keystage(int64_t n, const float* means, const float* scales, const f
 #pragma omp for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
       const float foot2 = opacity ? opacity_foot2_f32(opacity[i]) : kFoot2F;
-      key[i] = key_f32(means + 3 * i, scales + 2 * i, quats + 4 * i, k, foot2);
+      key[i] = key_f32(means + 3 * i, scales + 2 * i, quats + 4 * i, k, foot2, lowpass);
       if (key[i].cull == kVisible) {
         footprint(key[i], k, tw, th, mode, rows);
         int64_t c = 0;
@@ -585,13 +652,13 @@ void orc_eval_points(int64_t n, const float* means, const float* scales, const f
 // and the four decision margins (see Margins).
 void orc_render(int64_t n, const float* means, const float* scales, const float* quats,
                 const float* opacity, const float* rgb, const double* feat, int C,
-                const float* cam, int tw, int th, int K, int blend,
+                const float* cam, int tw, int th, int K, int blend, int lowpass,
                 int64_t npix, const int64_t* pix,
                 double* rgb_out, double* depth_out, double* normal_out, double* alpha_out,
                 double* feat_out, int32_t* ncontrib_out, double* tfinal_out, int64_t* last_out,
                 int64_t* sel_id_out, double* sel_w_out, double* margin_out) {
   Cam k = load_cam(cam);
-  Scene sc{n, means, scales, quats, opacity, rgb, feat, C};
+  Scene sc{n, means, scales, quats, opacity, rgb, feat, C, lowpass};
   Prepared P;
   prepare(sc, k, tw, th, P);
   const int64_t S = (int64_t)k.W * k.H;
@@ -667,14 +734,14 @@ void orc_render(int64_t n, const float* means, const float* scales, const float*
 // still take part in every pixel's walk).
 void orc_backward(int64_t n, const float* means, const float* scales, const float* quats,
                   const float* opacity, const float* rgb, const double* feat, int C,
-                  const float* cam, int tw, int th, int K, int blend,
+                  const float* cam, int tw, int th, int K, int blend, int lowpass,
                   int64_t npix, const int64_t* pix,
                   const double* g_rgb, const double* g_depth, const double* g_normal,
                   const double* g_alpha, const double* g_feat, const uint8_t* mask,
                   double* d_means, double* d_scales, double* d_quats, double* d_opacity,
                   double* d_rgb, double* d_feat) {
   Cam k = load_cam(cam);
-  Scene sc{n, means, scales, quats, opacity, rgb, feat, C};
+  Scene sc{n, means, scales, quats, opacity, rgb, feat, C, lowpass};
   Prepared P;
   prepare(sc, k, tw, th, P);
   const int64_t S = (int64_t)k.W * k.H;
@@ -751,9 +818,15 @@ void orc_backward(int64_t n, const float* means, const float* scales, const floa
         // chain through alpha, depth and normal with dual numbers
         D10 o;
         Geo<D10> g = geo_dual(sc.in(id), k, P.key[id].flip, o);
-        D10 u, v, z;
-        solve_uv(g, px + 0.5, py + 0.5, u, v, z);
-        D10 rho = u * u + v * v;
+        D10 u, v, z, rho;
+        if (c.filt) {  // low-pass term: 2 |x - c|^2 about the projected centre, centre depth
+          const D10 dx = D10(px + 0.5) - g.M[2] / g.M[8], dy = D10(py + 0.5) - g.M[5] / g.M[8];
+          rho = 2.0 * (dx * dx + dy * dy);
+          z = g.M[8];
+        } else {
+          solve_uv(g, px + 0.5, py + 0.5, u, v, z);
+          rho = u * u + v * v;
+        }
         D10 alpha = o * dexp(-0.5 * rho);
         double grad[kNP];
         for (int t = 0; t < kNP; ++t) {
@@ -784,10 +857,10 @@ void orc_backward(int64_t n, const float* means, const float* scales, const floa
 // the ordered contributor ids, the clamp flags and the Top-K set, hashed.
 void orc_decisions(int64_t n, const float* means, const float* scales, const float* quats,
                    const float* opacity, const float* rgb, const double* feat, int C,
-                   const float* cam, int tw, int th, int K, int blend,
+                   const float* cam, int tw, int th, int K, int blend, int lowpass,
                    int64_t npix, const int64_t* pix, uint64_t* sig_out) {
   Cam k = load_cam(cam);
-  Scene sc{n, means, scales, quats, opacity, rgb, feat, C};
+  Scene sc{n, means, scales, quats, opacity, rgb, feat, C, lowpass};
   Prepared P;
   prepare(sc, k, tw, th, P);
 #pragma omp parallel
@@ -804,7 +877,7 @@ void orc_decisions(int64_t n, const float* means, const float* scales, const flo
       else sel.assign(cs.size(), 1);
       uint64_t h = 1469598103934665603ull;
       for (size_t i = 0; i < cs.size(); ++i) {
-        uint64_t v = (uint64_t)cs[i].id * 4 + (cs[i].clamped ? 2 : 0) + (sel[i] ? 1 : 0);
+        uint64_t v = (uint64_t)cs[i].id * 8 + (cs[i].filt ? 4 : 0) + (cs[i].clamped ? 2 : 0) + (sel[i] ? 1 : 0);
         h = (h ^ v) * 1099511628211ull;
       }
       sig_out[e] = h;

@@ -53,17 +53,17 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int
         L.orc_keystage.restype = i64
-        L.orc_keystage.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, i64, vp, vp]
+        L.orc_keystage.argtypes = [i64, vp, vp, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp, i64, vp, vp]
         L.orc_eval_points.restype = None
         L.orc_eval_points.argtypes = [i64, vp, vp, vp, vp, i64, vp, vp, vp, vp]
         L.orc_render.restype = None
-        L.orc_render.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, vp, i32, i32, i32, i32, i64, vp,
+        L.orc_render.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, vp, i32, i32, i32, i32, i32, i64, vp,
                                  vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_backward.restype = None
-        L.orc_backward.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, vp, i32, i32, i32, i32, i64, vp,
+        L.orc_backward.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, vp, i32, i32, i32, i32, i32, i64, vp,
                                    vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_decisions.restype = None
-        L.orc_decisions.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, vp, i32, i32, i32, i32, i64, vp, vp]
+        L.orc_decisions.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, vp, i32, i32, i32, i32, i32, i64, vp, vp]
         L.orc_num_threads.restype = i32
         _lib = L
     return _lib
@@ -81,11 +81,13 @@ def _scene_args(scene):
     return (_c32(scene.means), _c32(scene.scales), _c32(scene.quats))
 
 
-def keystage(scene, cam, mode="ellipse", tile=16, pairs=True, opacity_footprint=False) -> dict:
+def keystage(scene, cam, mode="ellipse", tile=16, pairs=True, opacity_footprint=False, lowpass=False) -> dict:
     """FP32 key stage: cull codes, depth bits, flips, counts, footprint floats
     and (optionally) the sorted pair list (tile ids, surfel ids).
     ``opacity_footprint``: list the footprint of rho <= min(9, 2 ln(255 o))
-    (widened and rounded up, see oracle.cpp) instead of rho <= 9."""
+    (widened and rounded up, see oracle.cpp) instead of rho <= 9.
+    ``lowpass``: the footprint also covers the screen-space low-pass filter's
+    disk 2 |x - c|^2 <= 9 (widened, see oracle.cpp)."""
     m = MODES[mode] if isinstance(mode, str) else int(mode)
     n = scene.n
     mu, sc, q = _scene_args(scene)
@@ -97,13 +99,13 @@ def keystage(scene, cam, mode="ellipse", tile=16, pairs=True, opacity_footprint=
     count = np.zeros(n, np.int32)
     fp = np.zeros((n, 8), np.float32)
     L = lib()
-    P = L.orc_keystage(n, _vp(mu), _vp(sc), _vp(q), _vp(op), _vp(camv), tile, tile, m,
+    P = L.orc_keystage(n, _vp(mu), _vp(sc), _vp(q), _vp(op), _vp(camv), tile, tile, m, int(lowpass),
                        _vp(cull), _vp(depth), _vp(flip), _vp(count), _vp(fp), 0, None, None)
     out = {"cull": cull, "depth_bits": depth, "flip": flip, "count": count, "fp": fp, "P": int(P)}
     if pairs:
         tiles = np.zeros(max(P, 1), np.int32)
         ids = np.zeros(max(P, 1), np.int32)
-        L.orc_keystage(n, _vp(mu), _vp(sc), _vp(q), _vp(op), _vp(camv), tile, tile, m,
+        L.orc_keystage(n, _vp(mu), _vp(sc), _vp(q), _vp(op), _vp(camv), tile, tile, m, int(lowpass),
                        None, None, None, None, None, P, _vp(tiles), _vp(ids))
         out["tile"] = tiles[:P]
         out["id"] = ids[:P]
@@ -126,9 +128,11 @@ def _pix(pix):
     return None if pix is None else np.ascontiguousarray(pix, np.int64)
 
 
-def render(scene, cam, K=16, blend=TOPK, feat=None, pix=None, tile=16) -> dict:
+def render(scene, cam, K=16, blend=TOPK, feat=None, pix=None, tile=16, lowpass=False) -> dict:
     """FP64 forward render.  ``feat`` overrides scene.feat (e.g. the values of
-    a bf16-rounded copy); ``pix`` restricts the render to listed pixels."""
+    a bf16-rounded copy); ``pix`` restricts the render to listed pixels;
+    ``lowpass`` applies the screen-space low-pass filter,
+    rho = min(u^2 + v^2, 2 |x - c|^2)."""
     n, Cn = scene.n, scene.c
     mu, sc, q = _scene_args(scene)
     f64 = np.ascontiguousarray(scene.feat if feat is None else feat, np.float64)
@@ -141,7 +145,7 @@ def render(scene, cam, K=16, blend=TOPK, feat=None, pix=None, tile=16) -> dict:
         "sel_id": np.zeros((cnt, K), np.int64), "sel_w": np.zeros((cnt, K)), "margins": np.zeros((cnt, 4)),
     }
     lib().orc_render(n, _vp(mu), _vp(sc), _vp(q), _vp(_c32(scene.opacity)), _vp(_c32(scene.rgb)),
-                     _vp(f64), Cn, _vp(cam.as_array()), tile, tile, K, int(blend),
+                     _vp(f64), Cn, _vp(cam.as_array()), tile, tile, K, int(blend), int(lowpass),
                      0 if pix is None else pix.size, _vp(pix),
                      _vp(o["rgb"]), _vp(o["depth"]), _vp(o["normal"]), _vp(o["alpha"]), _vp(o["feat"]),
                      _vp(o["ncontrib"]), _vp(o["T_final"]), _vp(o["last"]), _vp(o["sel_id"]),
@@ -156,7 +160,8 @@ def render(scene, cam, K=16, blend=TOPK, feat=None, pix=None, tile=16) -> dict:
     return o
 
 
-def backward(scene, cam, grads: dict, K=16, blend=TOPK, feat=None, pix=None, mask=None, tile=16) -> dict:
+def backward(scene, cam, grads: dict, K=16, blend=TOPK, feat=None, pix=None, mask=None, tile=16,
+             lowpass=False) -> dict:
     """FP64 gradients of L = sum(upstream * outputs).  ``grads`` holds the
     upstream maps (full images, or per listed pixel when ``pix`` is given)."""
     n, Cn = scene.n, scene.c
@@ -170,7 +175,7 @@ def backward(scene, cam, grads: dict, K=16, blend=TOPK, feat=None, pix=None, mas
     d = {"means": np.zeros((n, 3)), "scales": np.zeros((n, 2)), "quats": np.zeros((n, 4)),
          "opacity": np.zeros(n), "rgb": np.zeros((n, 3)), "feat": np.zeros((n, Cn))}
     lib().orc_backward(n, _vp(mu), _vp(sc), _vp(q), _vp(_c32(scene.opacity)), _vp(_c32(scene.rgb)),
-                       _vp(f64), Cn, _vp(cam.as_array()), tile, tile, K, int(blend),
+                       _vp(f64), Cn, _vp(cam.as_array()), tile, tile, K, int(blend), int(lowpass),
                        0 if pix is None else pix.size, _vp(pix),
                        _vp(g["rgb"]), _vp(g["depth"]), _vp(g["normal"]), _vp(g["alpha"]), _vp(g["feat"]),
                        _vp(mask_a), _vp(d["means"]), _vp(d["scales"]), _vp(d["quats"]),
@@ -178,13 +183,14 @@ def backward(scene, cam, grads: dict, K=16, blend=TOPK, feat=None, pix=None, mas
     return d
 
 
-def decisions(scene, cam, pix, K=16, blend=TOPK, feat=None, tile=16) -> np.ndarray:
-    """Per-pixel hash of the ordered contributor set, clamp flags and Top-K set."""
+def decisions(scene, cam, pix, K=16, blend=TOPK, feat=None, tile=16, lowpass=False) -> np.ndarray:
+    """Per-pixel hash of the ordered contributor set, clamp flags, low-pass
+    branches and Top-K set."""
     mu, sc, q = _scene_args(scene)
     f64 = np.ascontiguousarray(scene.feat if feat is None else feat, np.float64)
     pix = _pix(pix)
     sig = np.zeros(pix.size, np.uint64)
     lib().orc_decisions(scene.n, _vp(mu), _vp(sc), _vp(q), _vp(_c32(scene.opacity)),
                         _vp(_c32(scene.rgb)), _vp(f64), scene.c, _vp(cam.as_array()), tile, tile,
-                        K, int(blend), pix.size, _vp(pix), _vp(sig))
+                        K, int(blend), int(lowpass), pix.size, _vp(pix), _vp(sig))
     return sig

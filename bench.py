@@ -518,6 +518,16 @@ def main():
                    "fwd_bwd_its": 1000.0 / ms_rn_step,
                    "note": "PSM_FLAG_TOPK_RENORM: feature map sum_sel w f / sum_sel w and its backward"}
     del rn
+    # screen-space low-pass filter (the 2DGS variant of the surfel kernel)
+    lpf = Form(psm, t, cam, K, "ellipse", "topk", gout, device, launch=head_launch, flags=psm.FLAG_LOWPASS)
+    ms_lp_step, _, st_lp = timed(lpf, True, args.steps, args.warmup)
+    ms_lp_fwd, _, _ = timed(lpf, False, args.steps, args.warmup)
+    print(f"[bench] low-pass filter fwd {ms_lp_fwd:.3f} ms, fwd+bwd {ms_lp_step:.3f} ms, pairs {st_lp.pairs}",
+          file=sys.stderr, flush=True)
+    lowpass = {"fwd_ms": ms_lp_fwd, "fwd_fps": 1000.0 / ms_lp_fwd, "fwd_bwd_ms": ms_lp_step,
+               "fwd_bwd_its": 1000.0 / ms_lp_step, "pairs": int(st_lp.pairs),
+               "note": "PSM_FLAG_LOWPASS: rho = min(u^2 + v^2, 2 |x - c|^2); footprint = union with the filter disk"}
+    del lpf
     base = Form(psm, t, cam, K, "aabb", "full", gout, device, tune=launch is None)
     ms_base_step, stages_base, st_base = timed(base, True, max(3, args.steps // 2), 2)
     ms_base_fwd, _, _ = timed(base, False, max(3, args.steps // 2), 2)
@@ -563,6 +573,7 @@ def main():
         "opacity_footprint": opacity_footprint,
         "feature_only": feature_only,
         "topk_renorm": topk_renorm,
+        "lowpass": lowpass,
         "pairs": int(st.pairs), "pairs_walked": int(st.pairs_walked), "contributors": int(st.contributors),
         "visible": int(st.visible),
         "stages_ms": stages,

@@ -126,6 +126,13 @@ typedef enum { PSM_SCHED_GRID = 0, PSM_SCHED_PERSISTENT = 1 } psm_schedule;
  * where nothing is selected); the backward differentiates the quotient.
  * Needs the Top-K blend and c > 0. */
 #define PSM_FLAG_TOPK_RENORM 16
+/* Screen-space low-pass filter (the 2D surfel splatting variant of the
+ * surfel kernel, Sec. 3.1): rho = min(u^2 + v^2, 2 |x - c|^2) with c the
+ * projected surfel centre in pixels; where the filter term is the smaller the
+ * depth is the centre's camera depth.  The listed footprint is the union with
+ * the filter's disk (radius^2 = footprint radius^2 / 2 + 1/16 px^2 about the
+ * FP32 centre).  Any blend and tile mode. */
+#define PSM_FLAG_LOWPASS 32
 
 typedef struct { float *rgb, *depth, *normal, *alpha, *feat; } psm_images;
 typedef struct { const float *rgb, *depth, *normal, *alpha, *feat; } psm_image_grads;

@@ -169,6 +169,9 @@ psm_status validate_common(const psm_camera* cams, int32_t n_cams, const psm_con
     return fail(PSM_ERR_INVALID_ARG, "blend_pass must be 0, 16 or 32");
   if (cfg->bwd_pass != 0 && cfg->bwd_pass != 16 && cfg->bwd_pass != 32)
     return fail(PSM_ERR_INVALID_ARG, "bwd_pass must be 0, 16 or 32");
+  if (cfg->flags & ~(PSM_FLAG_NO_SYNC | PSM_FLAG_PROFILE | PSM_FLAG_OPACITY_FOOTPRINT | PSM_FLAG_FEATURE_ONLY |
+                     PSM_FLAG_TOPK_RENORM | PSM_FLAG_LOWPASS))
+    return fail(PSM_ERR_INVALID_ARG, "unknown flag bits");
   if ((cfg->flags & PSM_FLAG_TOPK_RENORM) && (cfg->blend != PSM_BLEND_TOPK || c == 0))
     return fail(PSM_ERR_INVALID_ARG, "PSM_FLAG_TOPK_RENORM needs the Top-K blend and c > 0");
   if ((cfg->flags & PSM_FLAG_FEATURE_ONLY) && (cfg->blend != PSM_BLEND_TOPK || c == 0))
@@ -274,7 +277,8 @@ void enqueue_forward(const SurfelArgs& sa, const CamTable& ct, const psm_config*
   launch_fill_u32(ws + L.ranges, 0u, L.tiles * 2, st);
   prof.end(kStageFill, st);
   prof.begin(kStagePreprocess, st);
-  launch_preprocess(sa, ct, cfg->tile_mode, (cfg->flags & PSM_FLAG_OPACITY_FOOTPRINT) != 0, L, ws, st);
+  const bool lp = (cfg->flags & PSM_FLAG_LOWPASS) != 0;
+  launch_preprocess(sa, ct, cfg->tile_mode, (cfg->flags & PSM_FLAG_OPACITY_FOOTPRINT) != 0, lp, L, ws, st);
   prof.end(kStagePreprocess, st);
   prof.begin(kStageDepthSort, st);
   radix_sort_pairs((uint32_t*)(ws + L.key0), (uint32_t*)(ws + L.id0), (uint32_t*)(ws + L.key1),
@@ -296,10 +300,10 @@ void enqueue_forward(const SurfelArgs& sa, const CamTable& ct, const psm_config*
   prof.end(kStageRanges, st);
   ImageArgs ia{out->rgb, out->depth, out->normal, out->alpha, out->feat};
   prof.begin(kStageWalk, st);
-  launch_walk(L, ct, cfg->blend, tu, ia, (cfg->flags & PSM_FLAG_FEATURE_ONLY) != 0, ws, st);
+  launch_walk(L, ct, cfg->blend, tu, ia, (cfg->flags & PSM_FLAG_FEATURE_ONLY) != 0, lp, ws, st);
   prof.end(kStageWalk, st);
   prof.begin(kStageBlend, st);
-  launch_feature_blend(sa, L, ct, cfg->blend, tu, out->feat, (cfg->flags & PSM_FLAG_TOPK_RENORM) != 0, ws, st);
+  launch_feature_blend(sa, L, ct, cfg->blend, tu, out->feat, (cfg->flags & PSM_FLAG_TOPK_RENORM) != 0, lp, ws, st);
   prof.end(kStageBlend, st);
 }
 
@@ -360,7 +364,7 @@ psm_status backward_impl(psm_ctx* ctx, const psm_surfels* s, const psm_camera* c
   ImageGradArgs g{grad_out->rgb, grad_out->depth, grad_out->normal, grad_out->alpha, grad_out->feat};
   GradArgs ga{grads->means, grads->scales, grads->quats, grads->opacity, grads->rgb, grads->feat};
   launch_backward(surfel_args(s), ct, cfg->blend, tuning_of(cfg), L, g, ga, (cfg->flags & PSM_FLAG_TOPK_RENORM) != 0,
-                  (char*)workspace, st,
+                  (cfg->flags & PSM_FLAG_LOWPASS) != 0, (char*)workspace, st,
                   hook_for(ctx, cfg));
   r = check_hip("psm_backward launch");
   if (r != PSM_OK) return r;

@@ -15,6 +15,9 @@ constexpr float kCut2 = 9.0f;
 constexpr float kCut = 3.0f;
 // Footprint radius^2 = 9 (1 + 2^-10): a superset of the FP32 per-pixel test.
 constexpr float kFoot2 = 9.0087890625f;
+// Low-pass filter disk in the footprint: radius^2 = foot2 / 2 + 1/16 about the
+// FP32 projected centre (the pad covers that centre's rounding).
+constexpr float kLpPad = 0.0625f;
 // Thresholds the paper leaves to the 3DGS conventions.
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
@@ -231,25 +234,55 @@ struct Staged {
 // alpha = min(0.99, o exp(-rho/2)).  Returns true for a contributor
 // (hit and alpha >= 1/255).  The hit decision is taken in FP64; rho, alpha
 // and the values handed on are FP32.
+//
+// LP: the optional screen-space low-pass filter (the 2DGS variant),
+// rho = min(u^2 + v^2, 2 |d|^2) with d the pixel's offset from the projected
+// centre; the term is chosen in FP64, ties to the ray-splat term.  Where the
+// filter term is taken (filt), u = v = 0 and iw = 1, so the depth mz * iw is
+// the centre's depth.
 struct PixEval {
   float dx, dy, u, v, iw, G, alpha;
-  bool clamped;
+  bool clamped, filt;
 };
 
+template <bool LP = false>
 __device__ __forceinline__ bool eval_pixel(const LRec& s, float lx, float ly, PixEval& e) {
   const double dx = (double)lx + s.ox, dy = (double)ly + s.oy;
   const double u1 = fma(s.a00, dx, s.a01 * dy);
   const double v1 = fma(s.a10, dx, s.a11 * dy);
   const double w1 = 1.0 - fma(s.e0, dx, s.e1 * dy);
   const double num = fma(u1, u1, v1 * v1);
-  if (!(w1 > 0.0) || !(num <= 9.0 * (w1 * w1))) return false;
-  e.dx = (float)dx;
-  e.dy = (float)dy;
-  const float wf = (float)w1;
-  e.iw = __builtin_amdgcn_rcpf(wf);
-  e.u = (float)u1 * e.iw;
-  e.v = (float)v1 * e.iw;
-  const float rho = fmaf(e.u, e.u, e.v * e.v);
+  float rho;
+  if constexpr (LP) {
+    const double rf = 2.0 * fma(dx, dx, dy * dy);
+    const bool splat = w1 > 0.0 && num <= rf * (w1 * w1);
+    if (splat ? !(num <= 9.0 * (w1 * w1)) : !(rf <= 9.0)) return false;
+    e.filt = !splat;
+    e.dx = (float)dx;
+    e.dy = (float)dy;
+    if (splat) {
+      const float wf = (float)w1;
+      e.iw = __builtin_amdgcn_rcpf(wf);
+      e.u = (float)u1 * e.iw;
+      e.v = (float)v1 * e.iw;
+      rho = fmaf(e.u, e.u, e.v * e.v);
+    } else {
+      e.iw = 1.0f;
+      e.u = 0.0f;
+      e.v = 0.0f;
+      rho = 2.0f * fmaf(e.dx, e.dx, e.dy * e.dy);
+    }
+  } else {
+    if (!(w1 > 0.0) || !(num <= 9.0 * (w1 * w1))) return false;
+    e.filt = false;
+    e.dx = (float)dx;
+    e.dy = (float)dy;
+    const float wf = (float)w1;
+    e.iw = __builtin_amdgcn_rcpf(wf);
+    e.u = (float)u1 * e.iw;
+    e.v = (float)v1 * e.iw;
+    rho = fmaf(e.u, e.u, e.v * e.v);
+  }
   e.G = __builtin_amdgcn_exp2f(rho * -0.72134752044448170f);  // exp(-rho/2)
   const float oG = s.o * e.G;
   e.clamped = oG > kAlphaMax;

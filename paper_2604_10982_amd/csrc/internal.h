@@ -54,7 +54,8 @@ enum : int { kSchedGrid = 0, kSchedPersistent = 1 };
 // keystage.hip
 void launch_fill_u32(void* p, uint32_t v, int64_t count, hipStream_t st);
 void launch_init_status(uint32_t* status, int64_t n, int64_t tiles, hipStream_t st);
-void launch_preprocess(const SurfelArgs& s, const CamTable& ct, int mode, bool opacity_foot, const Layout& L,
+void launch_preprocess(const SurfelArgs& s, const CamTable& ct, int mode, bool opacity_foot, bool lowpass,
+                       const Layout& L,
                        char* ws, hipStream_t st);
 void launch_scan_counts(const Layout& L, char* ws, hipStream_t st);
 void launch_emit(const CamTable& ct, int mode, const Layout& L, char* ws, hipStream_t st);
@@ -84,9 +85,9 @@ inline TileQueue tile_queue(const Layout& L, int sched, char* ws, int q) {
 
 // raster_fwd.hip
 void launch_walk(const Layout& L, const CamTable& ct, int blend, const Tuning& tu, const ImageArgs& out,
-                 bool feat_only, char* ws, hipStream_t st);
+                 bool feat_only, bool lowpass, char* ws, hipStream_t st);
 void launch_feature_blend(const SurfelArgs& s, const Layout& L, const CamTable& ct, int blend, const Tuning& tu,
-                          float* out_feat, bool renorm, char* ws, hipStream_t st);
+                          float* out_feat, bool renorm, bool lowpass, char* ws, hipStream_t st);
 void launch_export_selection(const Layout& L, const CamTable& ct, char* ws, int32_t* sel_id, float* sel_w,
                              int32_t* n_last, float* t_final, hipStream_t st);
 
@@ -111,7 +112,7 @@ void launch_labels_backward(int64_t n, const float* means, const void* fg, int d
 
 // raster_bwd.hip
 void launch_backward(const SurfelArgs& s, const CamTable& ct, int blend, const Tuning& tu, const Layout& L,
-                     const ImageGradArgs& g, const GradArgs& grads, bool renorm, char* ws, hipStream_t st,
+                     const ImageGradArgs& g, const GradArgs& grads, bool renorm, bool lowpass, char* ws, hipStream_t st,
                      const ProfHook& prof);
 
 // Frustum-local cross-attention (attention.hip).

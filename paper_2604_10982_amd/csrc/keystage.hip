@@ -17,9 +17,11 @@ namespace psm {
 
 using Cam = CamArgs;
 
-// Projected cutoff ellipse of a visible surfel.
+// Projected cutoff ellipse of a visible surfel; with the low-pass filter also
+// the projected centre and the filter disk's radius^2 (rf2 = 0: no filter).
 struct Foot {
   float ecx, ecy, S00, S01, S11, ex, ey, gam, kk;
+  float xc, yc, rf2;
 };
 
 // Quantities of the prescribed FP32 key stage for one surfel.
@@ -46,7 +48,9 @@ __device__ __forceinline__ float opacity_foot2(float o) {
 
 // foot2: footprint radius^2 (kFoot2, or the opacity-aware bound).  The cull
 // decisions always use kFoot2, so both footprints keep the same visible set.
-__device__ __noinline__ Key key_stage(const float* mu, const float* sc, const float* qq, const Cam& k, float foot2) {
+// lowpass: the footprint also takes the low-pass filter's disk.
+__device__ __noinline__ Key key_stage(const float* mu, const float* sc, const float* qq, const Cam& k, float foot2,
+                                      int lowpass) {
   Key r;
   r.cull = 0;
   r.flip = 0;
@@ -114,6 +118,9 @@ __device__ __noinline__ Key key_stage(const float* mu, const float* sc, const fl
   r.f.ey = sqrtf(S11);
   r.f.gam = gf;
   r.f.kk = fabsf(cc * dA);
+  r.f.xc = xc;
+  r.f.yc = yc;
+  r.f.rf2 = lowpass ? 0.5f * foot2 + kLpPad : 0.0f;
   return r;
 }
 
@@ -167,40 +174,78 @@ __device__ __forceinline__ bool tile_span(float lo, float hi, int npix, int nt, 
 }
 
 // Calls fn(ty, tx0, tx1) for each tile row of the footprint of mode `mode`.
+// With the low-pass filter the footprint is the union with the filter's disk:
+// the disk's box joins every mode's box, and the exact mode takes, per row,
+// the hull of the ellipse's and the disk's x-extents within the row's band.
 template <class F>
 __device__ __forceinline__ void for_each_row(const Foot& f, int mode, int W, int H, int ntx, int nty, F&& fn) {
+  const bool lp = f.rf2 > 0.0f;
+  const float rf = lp ? sqrtf(f.rf2) : 0.0f;
   int ax0, ax1, ay0, ay1;
+  float bx0, bx1, by0, by1;
   if (mode == kSphere) {
     const float hs = 0.5f * (f.S00 + f.S11);
     const float hd = 0.5f * (f.S00 - f.S11);
     const float lmax = hs + sqrtf(hd * hd + f.S01 * f.S01);
     const float rr = fmaxf(sqrtf(lmax), fmaxf(f.ex, f.ey));
-    if (!tile_span(f.ecx - rr, f.ecx + rr, W, ntx, ax0, ax1)) return;
-    if (!tile_span(f.ecy - rr, f.ecy + rr, H, nty, ay0, ay1)) return;
-    for (int ty = ay0; ty <= ay1; ++ty) fn(ty, ax0, ax1);
-    return;
+    bx0 = f.ecx - rr;
+    bx1 = f.ecx + rr;
+    by0 = f.ecy - rr;
+    by1 = f.ecy + rr;
+  } else {
+    bx0 = f.ecx - f.ex;
+    bx1 = f.ecx + f.ex;
+    by0 = f.ecy - f.ey;
+    by1 = f.ecy + f.ey;
   }
-  if (!tile_span(f.ecx - f.ex, f.ecx + f.ex, W, ntx, ax0, ax1)) return;
-  if (!tile_span(f.ecy - f.ey, f.ecy + f.ey, H, nty, ay0, ay1)) return;
-  if (mode == kAabb) {
+  if (lp) {
+    bx0 = fminf(bx0, f.xc - rf);
+    bx1 = fmaxf(bx1, f.xc + rf);
+    by0 = fminf(by0, f.yc - rf);
+    by1 = fmaxf(by1, f.yc + rf);
+  }
+  if (!tile_span(bx0, bx1, W, ntx, ax0, ax1)) return;
+  if (!tile_span(by0, by1, H, nty, ay0, ay1)) return;
+  if (mode != kEllipse) {
     for (int ty = ay0; ty <= ay1; ++ty) fn(ty, ax0, ax1);
     return;
   }
   // exact ellipse: x-extent of the ellipse inside each tile row's band
   const float yr = f.S01 / f.ex;
   for (int ty = ay0; ty <= ay1; ++ty) {
-    const float ylo = ((float)(ty * kTile) + 0.5f) - f.ecy;
-    const float yhi = fminf((float)(ty * kTile) + ((float)kTile - 0.5f), (float)H - 0.5f) - f.ecy;
+    const float rlo = (float)(ty * kTile) + 0.5f;
+    const float rhi = fminf((float)(ty * kTile) + ((float)kTile - 0.5f), (float)H - 0.5f);
+    const float ylo = rlo - f.ecy;
+    const float yhi = rhi - f.ecy;
     const float lo = fmaxf(ylo, -f.ey), hi = fminf(yhi, f.ey);
-    if (!(lo <= hi)) continue;
-    const float dR = fminf(fmaxf(yr, lo), hi);
-    const float dL = fminf(fmaxf(-yr, lo), hi);
-    const float hR = sqrtf(fmaxf(0.0f, (f.S11 - dR * dR) / f.gam)) * f.kk;
-    const float hL = sqrtf(fmaxf(0.0f, (f.S11 - dL * dL) / f.gam)) * f.kk;
-    const float xR = (f.S01 * dR + hR) / f.S11;
-    const float xL = (f.S01 * dL - hL) / f.S11;
+    bool have = false;
+    float xl = 0.0f, xr = 0.0f;
+    if (lo <= hi) {
+      const float dR = fminf(fmaxf(yr, lo), hi);
+      const float dL = fminf(fmaxf(-yr, lo), hi);
+      const float hR = sqrtf(fmaxf(0.0f, (f.S11 - dR * dR) / f.gam)) * f.kk;
+      const float hL = sqrtf(fmaxf(0.0f, (f.S11 - dL * dL) / f.gam)) * f.kk;
+      const float xR = (f.S01 * dR + hR) / f.S11;
+      const float xL = (f.S01 * dL - hL) / f.S11;
+      xl = f.ecx + xL;
+      xr = f.ecx + xR;
+      have = true;
+    }
+    if (lp) {  // the disk's widest chord within the band
+      const float dlo = rlo - f.yc, dhi = rhi - f.yc;
+      const float dy = fminf(fmaxf(0.0f, dlo), dhi);
+      const float h2 = f.rf2 - dy * dy;
+      if (h2 >= 0.0f) {
+        const float h = sqrtf(h2);
+        const float dl = f.xc - h, dr = f.xc + h;
+        xl = have ? fminf(xl, dl) : dl;
+        xr = have ? fmaxf(xr, dr) : dr;
+        have = true;
+      }
+    }
+    if (!have) continue;
     int x0, x1;
-    if (!tile_span(f.ecx + xL, f.ecx + xR, W, ntx, x0, x1)) continue;
+    if (!tile_span(xl, xr, W, ntx, x0, x1)) continue;
     x0 = max(x0, ax0);
     x1 = min(x1, ax1);
     if (x0 <= x1) fn(ty, x0, x1);
@@ -222,7 +267,7 @@ __global__ void k_init_status(uint32_t* __restrict__ st, uint32_t n, uint32_t ti
 __global__ __launch_bounds__(256) void k_preprocess(
     int64_t nv, const float* __restrict__ means, const float* __restrict__ scales,
     const float* __restrict__ quats, const float* __restrict__ opacity, const float* __restrict__ rgb,
-    CamTable ct, int mode, int opacity_foot, WalkRec* __restrict__ rec, float4* __restrict__ fp,
+    CamTable ct, int mode, int opacity_foot, int lowpass, WalkRec* __restrict__ rec, float4* __restrict__ fp,
     float4* __restrict__ ext,
     uint32_t* __restrict__ key, uint32_t* __restrict__ ids, uint32_t* __restrict__ count,
     int32_t* __restrict__ cull, uint32_t* __restrict__ status) {
@@ -239,7 +284,7 @@ __global__ __launch_bounds__(256) void k_preprocess(
     const int64_t i = v - (int64_t)b * ct.nsurf;
     const Cam& cam = s_cam[b];
     const float foot2 = opacity_foot ? opacity_foot2(opacity[i]) : kFoot2;
-    const Key kk = key_stage(means + 3 * i, scales + 2 * i, quats + 4 * i, cam, foot2);
+    const Key kk = key_stage(means + 3 * i, scales + 2 * i, quats + 4 * i, cam, foot2, lowpass);
     ids[v] = (uint32_t)v;
     cull[v] = kk.cull | (kk.flip << 8);  // bit 8: normal flipped toward the camera
     atomicAdd(&s_cnt[kk.cull], 1u);
@@ -254,8 +299,15 @@ __global__ __launch_bounds__(256) void k_preprocess(
       count[v] = c;
       fp[3 * v + 0] = make_float4(kk.f.ecx, kk.f.ecy, kk.f.S00, kk.f.S01);
       fp[3 * v + 1] = make_float4(kk.f.S11, kk.f.ex, kk.f.ey, kk.f.gam);
-      fp[3 * v + 2] = make_float4(kk.f.kk, 0.0f, 0.0f, 0.0f);
-      ext[v] = make_float4(kk.f.ecx, kk.f.ecy, kk.f.ex, kk.f.ey);
+      fp[3 * v + 2] = make_float4(kk.f.kk, kk.f.xc, kk.f.yc, kk.f.rf2);
+      if (lowpass) {  // the walks' band culling sees the union's extent
+        const float rf = sqrtf(kk.f.rf2);
+        const float x0 = fminf(kk.f.ecx - kk.f.ex, kk.f.xc - rf), x1 = fmaxf(kk.f.ecx + kk.f.ex, kk.f.xc + rf);
+        const float y0 = fminf(kk.f.ecy - kk.f.ey, kk.f.yc - rf), y1 = fmaxf(kk.f.ecy + kk.f.ey, kk.f.yc + rf);
+        ext[v] = make_float4(0.5f * (x0 + x1), 0.5f * (y0 + y1), 0.5f * (x1 - x0), 0.5f * (y1 - y0));
+      } else {
+        ext[v] = make_float4(kk.f.ecx, kk.f.ecy, kk.f.ex, kk.f.ey);
+      }
       walk_record(means + 3 * i, scales + 2 * i, quats + 4 * i, opacity[i], rgb + 3 * i, kk.nc, cam,
                   rec + v);
     }
@@ -366,7 +418,7 @@ __global__ __launch_bounds__(256) void k_emit(int64_t nv, const uint32_t* __rest
   const int b = camera_of(ct, v);
   const int ntx = ct.ntx[b], t0 = ct.tile0[b];
   const float4 f0 = fp[3 * (size_t)v], f1 = fp[3 * (size_t)v + 1], f2 = fp[3 * (size_t)v + 2];
-  const Foot f{f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w, f2.x};
+  const Foot f{f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w, f2.x, f2.y, f2.z, f2.w};
   int64_t o = offs[r];
   for_each_row(f, mode, ct.cam[b].W, ct.cam[b].H, ntx, ct.nty[b], [&](int ty, int x0, int x1) {
     for (int tx = x0; tx <= x1; ++tx, ++o) {
@@ -454,11 +506,11 @@ void launch_init_status(uint32_t* status, int64_t n, int64_t tiles, hipStream_t 
   hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, st, status, (uint32_t)n, (uint32_t)tiles);
 }
 
-void launch_preprocess(const SurfelArgs& s, const CamTable& ct, int mode, bool opacity_foot, const Layout& L,
-                       char* ws, hipStream_t st) {
+void launch_preprocess(const SurfelArgs& s, const CamTable& ct, int mode, bool opacity_foot, bool lowpass,
+                       const Layout& L, char* ws, hipStream_t st) {
   if (L.n == 0) return;
   hipLaunchKernelGGL(k_preprocess, dim3((unsigned)cdiv(L.n, 256)), dim3(256), 0, st, L.n, s.means, s.scales,
-                     s.quats, s.opacity, s.rgb, ct, mode, opacity_foot ? 1 : 0, (WalkRec*)(ws + L.rec),
+                     s.quats, s.opacity, s.rgb, ct, mode, opacity_foot ? 1 : 0, lowpass ? 1 : 0, (WalkRec*)(ws + L.rec),
                      (float4*)(ws + L.fp),
                      (float4*)(ws + L.ext),
                      (uint32_t*)(ws + L.key0), (uint32_t*)(ws + L.id0), (uint32_t*)(ws + L.count),

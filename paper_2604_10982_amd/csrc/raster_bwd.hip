@@ -28,7 +28,9 @@
 namespace psm {
 
 constexpr int kBB = 32;          // surfels per backward batch
-constexpr int kNV = 17;          // per-pixel values reduced per surfel
+// per-pixel values reduced per surfel: 17, and 2 more (the low-pass filter
+// term's centre gradient) with the filter
+constexpr int nv_of(bool lp) { return lp ? 19 : 17; }
 
 // ------------------------------------------------------------ Top-K feature
 // Per tile, the distinct selected surfels of the tile (a few dozen: each is
@@ -294,7 +296,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
 }
 
 // ------------------------------------------------------------- walk backward
-template <int MODE, typename FT, bool PERSIST>
+template <int MODE, typename FT, bool PERSIST, bool LP>
 __global__ __launch_bounds__(256) void k_walk_bwd(
     const WalkRec* __restrict__ rec, const float4* __restrict__ ext, const uint32_t* __restrict__ pid, const uint32_t* __restrict__ eid,
     const uint2* __restrict__ ranges, CamTable ct, TileQueue tq, int K, const uint32_t* __restrict__ nlast,
@@ -306,6 +308,7 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
   __shared__ Staged<kBB> s_r;
   __shared__ float2 s_band[kBB];  // (ecy, ey) of the batch, for band culling
   __shared__ uint32_t s_id[kBB];
+  constexpr int kNV = nv_of(LP);
   __shared__ float s_part[4][kBB][kNV];
   __shared__ uint32_t s_has[4][kBB];
   __shared__ int s_lmax;
@@ -415,11 +418,12 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
       // the pixel's terms are products of these scalars, all zero where the
       // pixel does not take part
       float w = 0.0f, du1 = 0.0f, dv1 = 0.0f, dw1 = 0.0f, dzi = 0.0f, dop = 0.0f, ex = 0.0f, ey = 0.0f;
+      float gcx = 0.0f, gcy = 0.0f;  // low-pass term: direct gradient of the projected centre
       bool contrib = false;
       if (pos < my_last && ((band >> k) & 1u)) {
         const LRec s = s_r.get(k);
         PixEval e;
-        if (eval_pixel(s, lx, ly, e)) {
+        if (eval_pixel<LP>(s, lx, ly, e)) {
           contrib = true;
           // 1 / (1 - alpha) once for both quotients: alpha <= 0.99, so the
           // reciprocal's relative error (about 1 ulp) stays that small
@@ -446,14 +450,21 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
           T = Tb;
           dop = e.clamped ? 0.0f : da * e.G;
           const float drho = e.clamped ? 0.0f : -0.5f * da * e.alpha;
-          const float du = 2.0f * u * drho, dv = 2.0f * vv * drho;
           const float dz = w * gD;
-          du1 = du * e.iw;
-          dv1 = dv * e.iw;
-          dw1 = -(du * u + dv * vv + dz * z) * e.iw;
-          dzi = dz * e.iw;
-          ex = e.dx;
-          ey = e.dy;
+          if (LP && e.filt) {
+            // rho = 2 |d|^2 with d = pixel - centre, depth = centre depth
+            gcx = -4.0f * drho * e.dx;
+            gcy = -4.0f * drho * e.dy;
+            dzi = dz;
+          } else {
+            const float du = 2.0f * u * drho, dv = 2.0f * vv * drho;
+            du1 = du * e.iw;
+            dv1 = dv * e.iw;
+            dw1 = -(du * u + dv * vv + dz * z) * e.iw;
+            dzi = dz * e.iw;
+            ex = e.dx;
+            ey = e.dy;
+          }
         }
       }
       if constexpr (MODE == kFull) s_om[k][tid] = w;
@@ -465,6 +476,13 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
         const float last = wave_sum(w * gN2);
         if ((lane & 3) == 0) s_part[wave][k][(lane >> 2) & 15] = tot;
         if (lane == 0) s_part[wave][k][16] = last;
+        if constexpr (LP) {
+          const float c0 = wave_sum(gcx), c1 = wave_sum(gcy);
+          if (lane == 0) {
+            s_part[wave][k][17] = c0;
+            s_part[wave][k][18] = c1;
+          }
+        }
       }
       if (lane == 0) s_has[wave][k] = any ? 1u : 0u;
     }
@@ -491,8 +509,12 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
         // u' = A^-1 d, w' = 1 - e.d with d = pixel - centre; d depends on the
         // centre with slope -1
         g[0] = make_float4(t[0], t[1], t[3], t[4]);
-        g[1] = make_float4(-t[6], -t[7], -(a00 * t[2] + a10 * t[5] - e0 * t[8]),
-                           -(a01 * t[2] + a11 * t[5] - e1 * t[8]));
+        float gxc = -(a00 * t[2] + a10 * t[5] - e0 * t[8]), gyc = -(a01 * t[2] + a11 * t[5] - e1 * t[8]);
+        if constexpr (LP) {
+          gxc += t[17];
+          gyc += t[18];
+        }
+        g[1] = make_float4(-t[6], -t[7], gxc, gyc);
         g[2] = make_float4(t[9], t[10], t[11], t[12]);
         g[3] = make_float4(t[13], t[14], t[15], t[16]);
         gflag[slot] = 1;
@@ -855,13 +877,13 @@ static void feat_bwd_k(const SurfelArgs& s, const Layout& L, const CamTable& ct,
   else (p ? feat_bwd_launch<FT, 32, GC, true> : feat_bwd_launch<FT, 32, GC, false>)(s, L, ct, tu, g, rn, ws, st);
 }
 
-template <int MODE, typename FT, bool PERSIST>
+template <int MODE, typename FT, bool PERSIST, bool LP>
 static void walk_bwd_launch_t(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
                               const ImageGradArgs& g, bool want_f, char* ws, hipStream_t st) {
-  const void* k = reinterpret_cast<const void*>(&k_walk_bwd<MODE, FT, PERSIST>);
+  const void* k = reinterpret_cast<const void*>(&k_walk_bwd<MODE, FT, PERSIST, LP>);
   const size_t shm = MODE == kTopK ? (size_t)L.k * kTilePix * 8 : 0;  // selection positions + dots
-  hipLaunchKernelGGL((k_walk_bwd<MODE, FT, PERSIST>), dim3(tile_grid(L, tu.sched_bwd, k, shm)), dim3(256), shm, st,
-                     (const WalkRec*)(ws + L.rec), (const float4*)(ws + L.ext), (const uint32_t*)(ws + L.pid),
+  hipLaunchKernelGGL((k_walk_bwd<MODE, FT, PERSIST, LP>), dim3(tile_grid(L, tu.sched_bwd, k, shm)), dim3(256), shm,
+                     st, (const WalkRec*)(ws + L.rec), (const float4*)(ws + L.ext), (const uint32_t*)(ws + L.pid),
                      (const uint32_t*)(ws + L.eid0), (const uint2*)(ws + L.ranges), ct,
                      tile_queue(L, tu.sched_bwd, ws, kQWalkBwd), L.k,
                      (const uint32_t*)(ws + L.nlast), (const float*)(ws + L.tfinal), (const int32_t*)(ws + L.selpos),
@@ -872,15 +894,20 @@ static void walk_bwd_launch_t(const SurfelArgs& s, const Layout& L, const CamTab
 
 template <int MODE, typename FT>
 static void walk_bwd_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
-                            const ImageGradArgs& g, bool want_f, char* ws, hipStream_t st) {
-  if (tu.sched_bwd == kSchedPersistent) walk_bwd_launch_t<MODE, FT, true>(s, L, ct, tu, g, want_f, ws, st);
-  else walk_bwd_launch_t<MODE, FT, false>(s, L, ct, tu, g, want_f, ws, st);
+                            const ImageGradArgs& g, bool want_f, bool lp, char* ws, hipStream_t st) {
+  const bool p = tu.sched_bwd == kSchedPersistent;
+  if (lp)
+    (p ? walk_bwd_launch_t<MODE, FT, true, true> : walk_bwd_launch_t<MODE, FT, false, true>)(s, L, ct, tu, g, want_f,
+                                                                                           ws, st);
+  else
+    (p ? walk_bwd_launch_t<MODE, FT, true, false> : walk_bwd_launch_t<MODE, FT, false, false>)(s, L, ct, tu, g,
+                                                                                             want_f, ws, st);
 }
 
 template <typename FT>
 static void backward_typed(const SurfelArgs& s, const CamTable& ct, int blend, const Tuning& tu, const Layout& L,
-                           const ImageGradArgs& g, const GradArgs& gr, bool renorm, char* ws, hipStream_t st,
-                           const ProfHook& prof) {
+                           const ImageGradArgs& g, const GradArgs& gr, bool renorm, bool lp, char* ws,
+                           hipStream_t st, const ProfHook& prof) {
   const bool want_f = g.feat != nullptr && s.c > 0;
   if (L.tiles > 0) {
     if (blend == kTopK) {
@@ -893,11 +920,11 @@ static void backward_typed(const SurfelArgs& s, const CamTable& ct, int blend, c
       }
       prof.end(kStageBwdFeature, st);
       prof.begin(kStageBwdWalk, st);
-      walk_bwd_launch<kTopK, FT>(s, L, ct, tu, g, want_f, ws, st);
+      walk_bwd_launch<kTopK, FT>(s, L, ct, tu, g, want_f, lp, ws, st);
       prof.end(kStageBwdWalk, st);
     } else {
       prof.begin(kStageBwdWalk, st);
-      walk_bwd_launch<kFull, FT>(s, L, ct, tu, g, want_f, ws, st);
+      walk_bwd_launch<kFull, FT>(s, L, ct, tu, g, want_f, lp, ws, st);
       prof.end(kStageBwdWalk, st);
     }
   }
@@ -922,16 +949,16 @@ static void backward_typed(const SurfelArgs& s, const CamTable& ct, int blend, c
 }
 
 void launch_backward(const SurfelArgs& s, const CamTable& ct, int blend, const Tuning& tu, const Layout& L,
-                     const ImageGradArgs& g, const GradArgs& grads, bool renorm, char* ws, hipStream_t st,
-                     const ProfHook& prof) {
+                     const ImageGradArgs& g, const GradArgs& grads, bool renorm, bool lowpass, char* ws,
+                     hipStream_t st, const ProfHook& prof) {
   prof.begin(kStageFill, st);
   launch_fill_u32(ws + L.gflag, 0u, cdiv(std::max<int64_t>(L.cap, 1), 4), st);
   launch_fill_u32(ws + L.fflag, 0u, cdiv(std::max<int64_t>(L.cap, 1), 4), st);
   launch_fill_u32((uint32_t*)(ws + L.status) + kStQueue + kQFeatBwd, 0u, 2, st);
   prof.end(kStageFill, st);
-  if (s.dtype == kF32) backward_typed<float>(s, ct, blend, tu, L, g, grads, renorm, ws, st, prof);
-  else if (s.dtype == kF16) backward_typed<__half>(s, ct, blend, tu, L, g, grads, renorm, ws, st, prof);
-  else backward_typed<uint16_t>(s, ct, blend, tu, L, g, grads, renorm, ws, st, prof);
+  if (s.dtype == kF32) backward_typed<float>(s, ct, blend, tu, L, g, grads, renorm, lowpass, ws, st, prof);
+  else if (s.dtype == kF16) backward_typed<__half>(s, ct, blend, tu, L, g, grads, renorm, lowpass, ws, st, prof);
+  else backward_typed<uint16_t>(s, ct, blend, tu, L, g, grads, renorm, lowpass, ws, st, prof);
 }
 
 }  // namespace psm

@@ -53,7 +53,7 @@ constexpr int kWalkChunk = 64;  // list entries a wave examines at once
 // ballot), the kept entries' records are staged, compacted, in the wave's LDS
 // slice by parallel vector loads, and the wave then evaluates them in list
 // order with broadcast reads.
-template <int KMAX, bool TOPK, bool PERSIST>
+template <int KMAX, bool TOPK, bool PERSIST, bool LP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_walk(const WalkRec* __restrict__ rec, const float4* __restrict__ ext,
                                               const uint32_t* __restrict__ pid,
                                               const uint2* __restrict__ ranges, CamTable ct, TileQueue tq,
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       const int pos = spos[k];
       const LRec s = S.get(k);
       PixEval e;
-      if (!eval_pixel(s, lx, ly, e)) continue;
+      if (!eval_pixel<LP>(s, lx, ly, e)) continue;
       const float Tn = T * (1.0f - e.alpha);
       if (Tn < kTMin) {
         done = true;
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(256) void k_blend_topk(const uint32_t* __restrict__
 
 constexpr int kFullBatch = 64;
 
-template <typename FT, int CH, bool PERSIST>
+template <typename FT, int CH, bool PERSIST, bool LP>
 __global__ __launch_bounds__(256) void k_full_feat(const WalkRec* __restrict__ rec, const uint32_t* __restrict__ pid,
                                                    const uint2* __restrict__ ranges, const FT* __restrict__ feat,
                                                    int C, CamTable ct, TileQueue tq,
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(256) void k_full_feat(const WalkRec* __restrict__ r
         if (base + k >= my_last) break;
         const LRec s = s_r.get(k);
         PixEval ev;
-        if (!eval_pixel(s, lx, ly, ev)) continue;
+        if (!eval_pixel<LP>(s, lx, ly, ev)) continue;
         const float w = ev.alpha * T;
 #pragma unroll
         for (int c = 0; c < CH; ++c) acc[c] = fmaf(w, s_f[k][c], acc[c]);
@@ -448,11 +448,11 @@ __global__ __launch_bounds__(256) void k_export_sel(const uint32_t* __restrict__
 }
 
 // ------------------------------------------------------------- host wrappers
-template <int KMAX, bool TOPK, bool PERSIST>
+template <int KMAX, bool TOPK, bool PERSIST, bool LP>
 static void walk_launch_t(const Layout& L, const CamTable& ct, const Tuning& tu, const ImageArgs& out,
                           bool feat_only, char* ws, hipStream_t st) {
-  const void* k = reinterpret_cast<const void*>(&k_walk<KMAX, TOPK, PERSIST>);
-  hipLaunchKernelGGL((k_walk<KMAX, TOPK, PERSIST>), dim3(tile_grid(L, tu.sched, k, 0)), dim3(256), 0, st,
+  const void* k = reinterpret_cast<const void*>(&k_walk<KMAX, TOPK, PERSIST, LP>);
+  hipLaunchKernelGGL((k_walk<KMAX, TOPK, PERSIST, LP>), dim3(tile_grid(L, tu.sched, k, 0)), dim3(256), 0, st,
                      (const WalkRec*)(ws + L.rec), (const float4*)(ws + L.ext), (const uint32_t*)(ws + L.pid),
                      (const uint2*)(ws + L.ranges), ct, tile_queue(L, tu.sched, ws, kQWalk), L.k, out.rgb, out.depth,
                      out.normal, out.alpha,
@@ -462,22 +462,27 @@ static void walk_launch_t(const Layout& L, const CamTable& ct, const Tuning& tu,
 
 template <int KMAX, bool TOPK>
 static void walk_launch(const Layout& L, const CamTable& ct, const Tuning& tu, const ImageArgs& out, bool feat_only,
-                        char* ws, hipStream_t st) {
-  if (tu.sched == kSchedPersistent) walk_launch_t<KMAX, TOPK, true>(L, ct, tu, out, feat_only, ws, st);
-  else walk_launch_t<KMAX, TOPK, false>(L, ct, tu, out, feat_only, ws, st);
+                        bool lp, char* ws, hipStream_t st) {
+  const bool p = tu.sched == kSchedPersistent;
+  if (lp)
+    (p ? walk_launch_t<KMAX, TOPK, true, true> : walk_launch_t<KMAX, TOPK, false, true>)(L, ct, tu, out, feat_only, ws,
+                                                                                       st);
+  else
+    (p ? walk_launch_t<KMAX, TOPK, true, false> : walk_launch_t<KMAX, TOPK, false, false>)(L, ct, tu, out, feat_only,
+                                                                                         ws, st);
 }
 
 void launch_walk(const Layout& L, const CamTable& ct, int blend, const Tuning& tu, const ImageArgs& out,
-                 bool feat_only, char* ws, hipStream_t st) {
+                 bool feat_only, bool lowpass, char* ws, hipStream_t st) {
   if (L.tiles == 0) return;
   if (blend == kFull) {
-    walk_launch<1, false>(L, ct, tu, out, false, ws, st);
+    walk_launch<1, false>(L, ct, tu, out, false, lowpass, ws, st);
   } else if (L.k <= 8) {
-    walk_launch<8, true>(L, ct, tu, out, feat_only, ws, st);
+    walk_launch<8, true>(L, ct, tu, out, feat_only, lowpass, ws, st);
   } else if (L.k <= 16) {
-    walk_launch<16, true>(L, ct, tu, out, feat_only, ws, st);
+    walk_launch<16, true>(L, ct, tu, out, feat_only, lowpass, ws, st);
   } else {
-    walk_launch<32, true>(L, ct, tu, out, feat_only, ws, st);
+    walk_launch<32, true>(L, ct, tu, out, feat_only, lowpass, ws, st);
   }
 }
 
@@ -505,11 +510,11 @@ static void blend_topk_k(const SurfelArgs& s, const Layout& L, const CamTable& c
                                                                                       st);
 }
 
-template <typename FT, bool PERSIST>
+template <typename FT, bool PERSIST, bool LP>
 static void full_feat_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
                              float* out_feat, char* ws, hipStream_t st) {
-  const void* k = reinterpret_cast<const void*>(&k_full_feat<FT, 64, PERSIST>);
-  hipLaunchKernelGGL((k_full_feat<FT, 64, PERSIST>), dim3(tile_grid(L, tu.sched, k, 0)), dim3(256), 0, st,
+  const void* k = reinterpret_cast<const void*>(&k_full_feat<FT, 64, PERSIST, LP>);
+  hipLaunchKernelGGL((k_full_feat<FT, 64, PERSIST, LP>), dim3(tile_grid(L, tu.sched, k, 0)), dim3(256), 0, st,
                      (const WalkRec*)(ws + L.rec), (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges),
                      (const FT*)s.feat, s.c, ct, tile_queue(L, tu.sched, ws, kQBlend), (const uint32_t*)(ws + L.nlast),
                      out_feat);
@@ -517,23 +522,24 @@ static void full_feat_launch(const SurfelArgs& s, const Layout& L, const CamTabl
 
 template <typename FT>
 static void blend_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, int blend, const Tuning& tu,
-                         float* out_feat, bool renorm, char* ws, hipStream_t st) {
+                         float* out_feat, bool renorm, bool lp, char* ws, hipStream_t st) {
+  const bool p = tu.sched == kSchedPersistent;
   if (blend == kTopK) {
     if (tu.blend_pass == 16) blend_topk_k<FT, 16>(s, L, ct, tu, out_feat, renorm, ws, st);
     else blend_topk_k<FT, 32>(s, L, ct, tu, out_feat, renorm, ws, st);
-  } else if (tu.sched == kSchedPersistent) {
-    full_feat_launch<FT, true>(s, L, ct, tu, out_feat, ws, st);
+  } else if (lp) {
+    (p ? full_feat_launch<FT, true, true> : full_feat_launch<FT, false, true>)(s, L, ct, tu, out_feat, ws, st);
   } else {
-    full_feat_launch<FT, false>(s, L, ct, tu, out_feat, ws, st);
+    (p ? full_feat_launch<FT, true, false> : full_feat_launch<FT, false, false>)(s, L, ct, tu, out_feat, ws, st);
   }
 }
 
 void launch_feature_blend(const SurfelArgs& s, const Layout& L, const CamTable& ct, int blend, const Tuning& tu,
-                          float* out_feat, bool renorm, char* ws, hipStream_t st) {
+                          float* out_feat, bool renorm, bool lowpass, char* ws, hipStream_t st) {
   if (!out_feat || s.c <= 0 || L.tiles == 0) return;
-  if (s.dtype == kF32) blend_launch<float>(s, L, ct, blend, tu, out_feat, renorm, ws, st);
-  else if (s.dtype == kF16) blend_launch<__half>(s, L, ct, blend, tu, out_feat, renorm, ws, st);
-  else blend_launch<uint16_t>(s, L, ct, blend, tu, out_feat, renorm, ws, st);
+  if (s.dtype == kF32) blend_launch<float>(s, L, ct, blend, tu, out_feat, renorm, lowpass, ws, st);
+  else if (s.dtype == kF16) blend_launch<__half>(s, L, ct, blend, tu, out_feat, renorm, lowpass, ws, st);
+  else blend_launch<uint16_t>(s, L, ct, blend, tu, out_feat, renorm, lowpass, ws, st);
 }
 
 void launch_export_selection(const Layout& L, const CamTable& ct, char* ws, int32_t* sel_id, float* sel_w,

@@ -26,6 +26,7 @@ FLAG_PROFILE = 2
 FLAG_OPACITY_FOOTPRINT = 4
 FLAG_FEATURE_ONLY = 8
 FLAG_TOPK_RENORM = 16
+FLAG_LOWPASS = 32
 NUM_STAGES = 12
 SCHED_GRID, SCHED_PERSISTENT = 0, 1
 MAX_CAMERAS = 8

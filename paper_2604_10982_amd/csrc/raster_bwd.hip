@@ -791,11 +791,12 @@ __global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, CamTable ct, cons
 __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const uint32_t* __restrict__ vbase,
                                                      const uint32_t* __restrict__ count, int64_t cap,
                                                      const float* __restrict__ fpart,
-                                                     const uint8_t* __restrict__ fflag, int C,
+                                                     const uint8_t* __restrict__ fflag, int C, int lpp2,
                                                      float* __restrict__ dfeat) {
+  // lpp2 lanes (a power of two) per surfel, each lane up to 4 float4 channel
+  // groups: a wave reduces 64 / lpp2 surfels at once
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lpp = C / 4;
-  const int lpp2 = lpp >= 64 ? 64 : pow2_ge(lpp);
   const int spw = 64 / lpp2;
   const int sub = lane / lpp2, cl = lane % lpp2;
   const int64_t i = ((int64_t)blockIdx.x * 4 + wave) * spw + sub;
@@ -936,12 +937,13 @@ static void backward_typed(const SurfelArgs& s, const CamTable& ct, int blend, c
                        (const float*)(ws + L.gpart), (const uint8_t*)(ws + L.gflag), s.means, s.scales, s.quats,
                        (const int32_t*)(ws + L.cull), gr.means, gr.scales, gr.quats, gr.opacity, gr.rgb);
     if (s.c > 0 && gr.feat) {
+      // two channel groups per lane (at most 4 for C = 1024): more surfels,
+      // and so more independent row loads, in flight per wave
       const int lpp = s.c / 4;
-      int lpp2 = 1;
-      while (lpp2 < lpp && lpp2 < 64) lpp2 <<= 1;
+      const int lpp2 = std::min(64, pow2_ge_host((lpp + 1) / 2));
       const int per_block = 4 * (64 / lpp2);
       hipLaunchKernelGGL(k_reduce_feat, dim3((unsigned)cdiv(s.n, per_block)), dim3(256), 0, st, s.n, ct.n, vbase,
-                         count, L.cap, (const float*)(ws + L.fpart), (const uint8_t*)(ws + L.fflag), s.c,
+                         count, L.cap, (const float*)(ws + L.fpart), (const uint8_t*)(ws + L.fflag), s.c, lpp2,
                          gr.feat);
     }
   }

@@ -99,3 +99,50 @@ def test_lowpass_gradients_match_oracle(orc, case, blend):
     got = {k: v.cpu().numpy().astype(np.float64) for k, v in got.items()}
     worst = grad_errors(got, ref)
     assert max(worst.values()) <= 1e-3, worst
+
+
+def test_lowpass_batch_equals_single_renders():
+    require_gpu()
+    sc = scenes.street40(40_000, 16, seed=3, scale_mu=np.log(0.01))
+    cams = scenes.street_cameras(((200, 150), (96, 64), (333, 211)))
+    t = to_dev(sc, "f16")
+    K = 8
+    cfg = psm.config_struct(K, "ellipse", "topk", LP)
+    out, ws, carr = psm.forward_batch(t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"], cams,
+                                      K, cfg=cfg)
+    torch.cuda.synchronize()
+    per = psm.split_images(out, carr)
+    sel = psm.read_selection_batch(ws, carr, cfg)
+    p0 = 0
+    for b, cam in enumerate(cams):
+        single, ws1 = _fwd(t, cam, K, "ellipse", "topk", LP)
+        for k in ("rgb", "depth", "normal", "alpha", "feat"):
+            assert torch.equal(per[b][k], single[k]), (b, k)
+        s1 = psm.read_selection(ws1, psm.camera_struct(cam), cfg)
+        hw = cam.height * cam.width
+        assert torch.equal(sel["sel_id"][p0:p0 + hw].reshape(cam.height, cam.width, K), s1["sel_id"])
+        p0 += hw
+
+
+def test_lowpass_with_feature_variants(orc):
+    """The filter composes with the feature-only stop (selection and features
+    bit-identical to the filtered full walk) and with the renormalised Top-K
+    (features vs the oracle)."""
+    require_gpu()
+    sc, cam, K = _cases()["mixed3k_ragged"]()
+    t = to_dev(sc)
+    out0, ws0 = _fwd(t, cam, K, "ellipse", "topk", LP)
+    out1, ws1 = _fwd(t, cam, K, "ellipse", "topk", LP | psm.FLAG_FEATURE_ONLY)
+    assert torch.equal(out0["feat"], out1["feat"])
+    c0 = psm.config_struct(K, "ellipse", "topk", LP)
+    s0 = psm.read_selection(ws0, psm.camera_struct(cam), c0)
+    s1 = psm.read_selection(ws1, psm.camera_struct(cam), psm.config_struct(K, "ellipse", "topk",
+                                                                          LP | psm.FLAG_FEATURE_ONLY))
+    assert torch.equal(s0["sel_id"], s1["sel_id"]) and torch.equal(s0["sel_w"], s1["sel_w"])
+    out2, _ = _fwd(t, cam, K, "ellipse", "topk", LP | psm.FLAG_TOPK_RENORM)
+    feat = stored_feat(t)
+    ref = orc.render(sc, cam, K, orc.TOPK_RENORM, feat=feat, lowpass=True)
+    absf = orc.render(sc, cam, K, orc.TOPK_RENORM, feat=np.abs(feat), lowpass=True)["feat"]
+    ok = decided(ref)
+    worst = image_errors(np_out(out2), ref, absf, ok, 1e-5)
+    assert max(worst.values()) <= 1.0, worst

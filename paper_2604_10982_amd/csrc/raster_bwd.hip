@@ -788,12 +788,13 @@ __global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, CamTable ct, cons
 
 // Lane group per surfel: dL/df = sum over cameras (in order) of the sum of its
 // pairs' rows (emission order).
+template <int NG>
 __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const uint32_t* __restrict__ vbase,
                                                      const uint32_t* __restrict__ count, int64_t cap,
                                                      const float* __restrict__ fpart,
                                                      const uint8_t* __restrict__ fflag, int C, int lpp2,
                                                      float* __restrict__ dfeat) {
-  // lpp2 lanes (a power of two) per surfel, each lane up to 4 float4 channel
+  // lpp2 lanes (a power of two) per surfel, each lane up to NG float4 channel
   // groups: a wave reduces 64 / lpp2 surfels at once
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lpp = C / 4;
@@ -801,7 +802,7 @@ __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const 
   const int sub = lane / lpp2, cl = lane % lpp2;
   const int64_t i = ((int64_t)blockIdx.x * 4 + wave) * spw + sub;
   if (i >= n) return;
-  constexpr int kMaxGroups = 4;  // C <= 1024: at most 4 channel groups of 4 per lane
+  constexpr int kMaxGroups = NG;  // channel groups of 4 per lane (the registers it needs)
   constexpr int kRowsInFlight = 4;
   float4 acc[kMaxGroups];
 #pragma unroll
@@ -942,7 +943,9 @@ static void backward_typed(const SurfelArgs& s, const CamTable& ct, int blend, c
       const int lpp = s.c / 4;
       const int lpp2 = std::min(64, pow2_ge_host((lpp + 1) / 2));
       const int per_block = 4 * (64 / lpp2);
-      hipLaunchKernelGGL(k_reduce_feat, dim3((unsigned)cdiv(s.n, per_block)), dim3(256), 0, st, s.n, ct.n, vbase,
+      const int ng = (lpp + lpp2 - 1) / lpp2;  // 1 or 2 up to C = 512, else at most 4
+      auto k = ng <= 2 ? k_reduce_feat<2> : k_reduce_feat<4>;
+      hipLaunchKernelGGL(k, dim3((unsigned)cdiv(s.n, per_block)), dim3(256), 0, st, s.n, ct.n, vbase,
                          count, L.cap, (const float*)(ws + L.fpart), (const uint8_t*)(ws + L.fflag), s.c, lpp2,
                          gr.feat);
     }

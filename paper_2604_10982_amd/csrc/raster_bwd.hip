@@ -297,7 +297,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
 
 // ------------------------------------------------------------- walk backward
 template <int MODE, typename FT, bool PERSIST, bool LP>
-__global__ __launch_bounds__(256) void k_walk_bwd(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTopK ? 4 : 1))) void k_walk_bwd(
     const WalkRec* __restrict__ rec, const float4* __restrict__ ext, const uint32_t* __restrict__ pid, const uint32_t* __restrict__ eid,
     const uint2* __restrict__ ranges, CamTable ct, TileQueue tq, int K, const uint32_t* __restrict__ nlast,
     const float* __restrict__ tfinal,
@@ -315,8 +315,11 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
   // dense-blend mode only: feature chunk of the batch and the batch weights
   __shared__ float s_fc[MODE == kFull ? kBB : 1][64];
   __shared__ __align__(16) float s_om[MODE == kFull ? kBB : 1][kTilePix];
-  // Top-K mode: every pixel's selected list positions and feature dots
-  // ([K][256] each), read back to front by the pixel's own lane
+  // Top-K mode: every pixel's selected list positions ([K][256]), read back
+  // to front by the pixel's own lane; the feature dots stay in global memory,
+  // each loaded when the previous one is used (16 KB of LDS instead of 32 KB
+  // for K = 16 lets four blocks share a CU, with the kernel's registers held
+  // to 128 for four waves per SIMD)
   extern __shared__ int s_sel[];
   __shared__ int s_item;
 
@@ -347,17 +350,16 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
   float nextdot = 0.0f;
   const size_t tbase = (size_t)tile * K * kTilePix;
   int* s_sp = s_sel;
-  float* s_sd = reinterpret_cast<float*>(s_sel + K * kTilePix);
+  const float* g_sd = seldot + tbase + tid;  // this pixel's dots, read one ahead of their use
   if (MODE == kTopK) {
     for (int q = 0; q < K; ++q) {
       const int sq = selpos[tbase + (size_t)q * kTilePix + tid];
       s_sp[q * kTilePix + tid] = sq;
-      s_sd[q * kTilePix + tid] = seldot[tbase + (size_t)q * kTilePix + tid];
       if (sq >= 0) kp = q;
     }
     if (kp >= 0) {
       nextsel = s_sp[kp * kTilePix + tid];
-      nextdot = s_sd[kp * kTilePix + tid];
+      nextdot = g_sd[(size_t)kp * kTilePix];
     }
   }
   const bool has_gf = MODE == kFull && g_feat != nullptr && inside;
@@ -437,7 +439,7 @@ __global__ __launch_bounds__(256) void k_walk_bwd(
               eF = nextdot;
               --kp;
               nextsel = kp >= 0 ? s_sp[kp * kTilePix + tid] : -1;
-              nextdot = kp >= 0 ? s_sd[kp * kTilePix + tid] : 0.0f;
+              nextdot = kp >= 0 ? g_sd[(size_t)kp * kTilePix] : 0.0f;
             }
           } else {
 #pragma unroll
@@ -883,7 +885,7 @@ template <int MODE, typename FT, bool PERSIST, bool LP>
 static void walk_bwd_launch_t(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
                               const ImageGradArgs& g, bool want_f, char* ws, hipStream_t st) {
   const void* k = reinterpret_cast<const void*>(&k_walk_bwd<MODE, FT, PERSIST, LP>);
-  const size_t shm = MODE == kTopK ? (size_t)L.k * kTilePix * 8 : 0;  // selection positions + dots
+  const size_t shm = MODE == kTopK ? (size_t)L.k * kTilePix * 4 : 0;  // selection positions
   hipLaunchKernelGGL((k_walk_bwd<MODE, FT, PERSIST, LP>), dim3(tile_grid(L, tu.sched_bwd, k, shm)), dim3(256), shm,
                      st, (const WalkRec*)(ws + L.rec), (const float4*)(ws + L.ext), (const uint32_t*)(ws + L.pid),
                      (const uint32_t*)(ws + L.eid0), (const uint2*)(ws + L.ranges), ct,

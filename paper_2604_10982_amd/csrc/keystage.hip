@@ -49,7 +49,7 @@ __device__ __forceinline__ float opacity_foot2(float o) {
 // foot2: footprint radius^2 (kFoot2, or the opacity-aware bound).  The cull
 // decisions always use kFoot2, so both footprints keep the same visible set.
 // lowpass: the footprint also takes the low-pass filter's disk.
-__device__ __noinline__ Key key_stage(const float* mu, const float* sc, const float* qq, const Cam& k, float foot2,
+__device__ __forceinline__ Key key_stage(const float* mu, const float* sc, const float* qq, const Cam& k, float foot2,
                                       int lowpass) {
   Key r;
   r.cull = 0;
@@ -127,7 +127,7 @@ __device__ __noinline__ Key key_stage(const float* mu, const float* sc, const fl
 // Walk record of a visible surfel (not part of any decision): the centred,
 // depth-normalised homography's A^-1, e = (p, q) A^-1 and the projected centre,
 // evaluated and kept in FP64 (the per-pixel solve is FP64 as well).
-__device__ __noinline__ void walk_record(const float* mu_f, const float* sc, const float* qf, float o,
+__device__ __forceinline__ void walk_record(const float* mu_f, const float* sc, const float* qf, float o,
                                          const float* rgb, const float* nc, const Cam& k, WalkRec* out) {
   const double q0 = qf[0], q1 = qf[1], q2 = qf[2], q3 = qf[3];
   const double rn = 1.0 / sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);

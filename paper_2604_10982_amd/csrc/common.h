@@ -45,7 +45,8 @@ enum : int {
   kStWalked = 12,  // 64-bit: pixel x list-entry evaluations of the forward walk
   kStBlended = 14, // 64-bit: blended (pixel, surfel) pairs
   kStQueue = 16,   // 16 .. 19: work-queue heads of the persistent tile kernels
-  kStWords = 20
+  kStWide = 20,    // tiles the Top-K blend left to its windowed pass
+  kStWords = 21
 };
 enum : int { kQWalk = 0, kQBlend = 1, kQFeatBwd = 2, kQWalkBwd = 3 };
 // Radix sort tiling.
@@ -117,7 +118,7 @@ struct Layout {
   int64_t n, nreal, cap, tiles, spix;  // n = virtual surfels; spix = tiles * 256 (tile-major pixels)
   int k, c, ncam;
   size_t rec, fp, ext, key0, key1, id0, id1, vbase, count, offs, cull, ptile0, ptile1, eid0, eid1, sid_emit, pid, ranges,
-      torder0, nlast, tfinal, selpos, selw, seldot, gflag, fflag, gpart, fpart, hist, bsum,
+      torder0, wide, nlast, tfinal, selpos, selw, seldot, gflag, fflag, gpart, fpart, hist, bsum,
       status, total;
 };
 
@@ -153,6 +154,7 @@ inline Layout make_layout(const CamTable& ct, int k, int c, int64_t cap) {
   L.pid = take(cap1 * 4);         // virtual surfel id of each sorted pair
   L.ranges = take(t1 * 8);        // [start, end) per tile
   L.torder0 = take(t1 * 4);       // tile work order, longest lists first
+  L.wide = take(t1 * 4);          // tiles of the Top-K blend's windowed pass
   L.nlast = take(L.spix * 4);
   L.tfinal = take(L.spix * 4);
   L.selpos = take(L.spix * (size_t)k * 4);

@@ -255,18 +255,27 @@ __device__ __forceinline__ void blend_chunk(const float* s_F, const int (&sl)[KM
 }
 
 // Thread per pixel; the tile's distinct selected rows are staged in LDS once
-// per pass of BC channels and read by slot.
-template <typename FT, int KMAX, int BC, bool PERSIST>
-__global__ __launch_bounds__(256) void k_blend_topk(const uint32_t* __restrict__ pid, const uint2* __restrict__ ranges,
+// per pass of BC channels and read by slot.  Two passes over the tiles:
+//   WIDE = false: tiles whose selected positions fit one ranking window and
+//     whose distinct rows fit one staged chunk (the common case): rank once,
+//     stage and blend per channel pass.  Other tiles are appended to a list.
+//   WIDE = false leaves out the windowed code, which keeps its registers (and
+//     so its occupancy) to what the common case needs.
+//   WIDE = true: the listed tiles, window by window and chunk by chunk.
+// Both take a pixel's selections in ascending list position, so a tile's
+// result does not depend on the pass that blends it.
+template <typename FT, int KMAX, int BC, bool PERSIST, bool WIDE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE || KMAX > 16 ? 1 : 4))) void k_blend_topk(const uint32_t* __restrict__ pid, const uint2* __restrict__ ranges,
                                                     const int32_t* __restrict__ selpos,
                                                     const float* __restrict__ selw, const FT* __restrict__ feat,
                                                     int C, int K, CamTable ct, TileQueue tq,
-                                                    float* __restrict__ o_feat, int renorm) {
+                                                    float* __restrict__ o_feat, int renorm,
+                                                    uint32_t* __restrict__ wide, uint32_t* __restrict__ status) {
   __shared__ SelShared S;
   constexpr int kBRow = BC + 4;
   __shared__ __align__(16) float s_F[kSlotChunk * kBRow];
   __shared__ int s_item;
-  for_tiles<PERSIST>(tq, &s_item, [&](const int tile) {
+  auto body = [&](const int tile) {
   const TileLoc tl = locate(ct, tile);
   const int tid = threadIdx.x;
   const int px = tl.tx * kTile + (tid & 15), py = tl.ty * kTile + (tid >> 4);
@@ -289,34 +298,58 @@ __global__ __launch_bounds__(256) void k_blend_topk(const uint32_t* __restrict__
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) wsum += pos[q] >= 0 ? w[q] : 0.0f;
   const float rw = wsum > 0.0f ? 1.0f / wsum : 0.0f;
+  // writes channels [cc, cc + BC) of this pixel's feature row
+  auto put = [&](int cc, float (&acc)[BC]) {
+    if (inside) {
+      if (renorm) {  // renormalised Top-K: the selected weights scaled to sum 1
+#pragma unroll
+        for (int c = 0; c < BC; ++c) acc[c] *= rw;
+      }
+#pragma unroll
+      for (int c = 0; c < BC; c += 4)
+        if (cc + c < C)
+          *reinterpret_cast<float4*>(out + cc + c) = make_float4(acc[c], acc[c + 1], acc[c + 2], acc[c + 3]);
+    }
+  };
 
-  // One window whose slots fit one chunk: rank once, stage per channel pass.
-  int sl[KMAX];
-  int U = 0;
-  const bool one_window = maxpos < kWinPos;
-  if (maxpos >= 0 && one_window) {
-    U = build_window(S, pos, K, 0, window_words(maxpos, 0));
+  if constexpr (!WIDE) {
+    // one window whose slots fit one chunk: rank once, stage per channel pass
+    int sl[KMAX];
+    int U = 0;
+    const bool one_window = maxpos < kWinPos;
+    if (maxpos >= 0 && one_window) {
+      U = build_window(S, pos, K, 0, window_words(maxpos, 0));
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q) sl[q] = q < K ? slot_of(S, pos[q], 0, window_words(maxpos, 0)) : -1;
-  }
-  const bool cached = maxpos >= 0 && one_window && U <= kSlotChunk;
-  if (cached) {
+      for (int q = 0; q < KMAX; ++q) sl[q] = q < K ? slot_of(S, pos[q], 0, window_words(maxpos, 0)) : -1;
+    }
+    const bool cached = maxpos < 0 || (one_window && U <= kSlotChunk);  // block-uniform
+    if (!cached) {
+      if (tid == 0) wide[atomicAdd(&status[kStWide], 1u)] = (uint32_t)tile;
+      return;
+    }
+    if (maxpos >= 0) {
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q)
-      if (sl[q] >= 0) S.fid[sl[q]] = (uint32_t)(pid[start + pos[q]] - tl.v0);
-  }
-  __syncthreads();
-
-  for (int cc = 0; cc < C; cc += BC) {
-    float acc[BC];
+      for (int q = 0; q < KMAX; ++q)
+        if (sl[q] >= 0) S.fid[sl[q]] = (uint32_t)(pid[start + pos[q]] - tl.v0);
+    }
+    __syncthreads();
+    for (int cc = 0; cc < C; cc += BC) {
+      float acc[BC];
 #pragma unroll
-    for (int c = 0; c < BC; ++c) acc[c] = 0.0f;
-    if (cached) {
-      stage_rows<FT, BC>(s_F, S.fid, U, feat, C, cc);
-      __syncthreads();
-      blend_chunk<KMAX, BC>(s_F, sl, w, K, acc);
-      __syncthreads();
-    } else {
+      for (int c = 0; c < BC; ++c) acc[c] = 0.0f;
+      if (maxpos >= 0) {
+        stage_rows<FT, BC>(s_F, S.fid, U, feat, C, cc);
+        __syncthreads();
+        blend_chunk<KMAX, BC>(s_F, sl, w, K, acc);
+        __syncthreads();
+      }
+      put(cc, acc);
+    }
+  } else {
+    for (int cc = 0; cc < C; cc += BC) {
+      float acc[BC];
+#pragma unroll
+      for (int c = 0; c < BC; ++c) acc[c] = 0.0f;
       for (int w0 = 0; w0 <= maxpos; w0 += kWinPos) {
         const int nw = window_words(maxpos, w0);
         const int Uw = build_window(S, pos, K, w0, nw);
@@ -336,19 +369,19 @@ __global__ __launch_bounds__(256) void k_blend_topk(const uint32_t* __restrict__
           __syncthreads();
         }
       }
-    }
-    if (inside) {
-      if (renorm) {  // renormalised Top-K: the selected weights scaled to sum 1
-#pragma unroll
-        for (int c = 0; c < BC; ++c) acc[c] *= rw;
-      }
-#pragma unroll
-      for (int c = 0; c < BC; c += 4)
-        if (cc + c < C)
-          *reinterpret_cast<float4*>(out + cc + c) = make_float4(acc[c], acc[c + 1], acc[c + 2], acc[c + 3]);
+      put(cc, acc);
     }
   }
-  });
+  };
+  if constexpr (WIDE) {
+    const uint32_t nwide = status[kStWide];
+    for (uint32_t i = blockIdx.x; i < nwide; i += gridDim.x) {
+      __syncthreads();  // the previous tile's LDS reads are done
+      body((int)wide[i]);
+    }
+  } else {
+    for_tiles<PERSIST>(tq, &s_item, body);
+  }
 }
 
 constexpr int kFullBatch = 64;
@@ -489,11 +522,21 @@ void launch_walk(const Layout& L, const CamTable& ct, int blend, const Tuning& t
 template <typename FT, int KMAX, int BC, bool PERSIST>
 static void blend_topk_launch(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
                               float* out_feat, bool renorm, char* ws, hipStream_t st) {
-  const void* k = reinterpret_cast<const void*>(&k_blend_topk<FT, KMAX, BC, PERSIST>);
-  hipLaunchKernelGGL((k_blend_topk<FT, KMAX, BC, PERSIST>), dim3(tile_grid(L, tu.sched, k, 0)), dim3(256), 0, st,
-                     (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos),
+  uint32_t* status = (uint32_t*)(ws + L.status);
+  uint32_t* wide = (uint32_t*)(ws + L.wide);
+  launch_fill_u32(status + kStWide, 0u, 1, st);
+  const void* k = reinterpret_cast<const void*>(&k_blend_topk<FT, KMAX, BC, PERSIST, false>);
+  hipLaunchKernelGGL((k_blend_topk<FT, KMAX, BC, PERSIST, false>), dim3(tile_grid(L, tu.sched, k, 0)), dim3(256), 0,
+                     st, (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos),
                      (const float*)(ws + L.selw), (const FT*)s.feat, s.c, L.k, ct, tile_queue(L, tu.sched, ws, kQBlend),
-                     out_feat, renorm ? 1 : 0);
+                     out_feat, renorm ? 1 : 0, wide, status);
+  // the listed tiles (usually none): a fixed grid strides over the list,
+  // whose length it reads on the device
+  const unsigned gw = (unsigned)std::min<int64_t>(L.tiles, 1024);
+  hipLaunchKernelGGL((k_blend_topk<FT, KMAX, BC, false, true>), dim3(gw), dim3(256), 0, st,
+                     (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos),
+                     (const float*)(ws + L.selw), (const FT*)s.feat, s.c, L.k, ct, TileQueue{nullptr, nullptr, 0},
+                     out_feat, renorm ? 1 : 0, wide, status);
 }
 
 template <typename FT, int BC>

@@ -526,9 +526,10 @@ static void blend_topk_launch(const SurfelArgs& s, const Layout& L, const CamTab
   uint32_t* wide = (uint32_t*)(ws + L.wide);
   launch_fill_u32(status + kStWide, 0u, 1, st);
   const void* k = reinterpret_cast<const void*>(&k_blend_topk<FT, KMAX, BC, PERSIST, false>);
-  hipLaunchKernelGGL((k_blend_topk<FT, KMAX, BC, PERSIST, false>), dim3(tile_grid(L, tu.sched, k, 0)), dim3(256), 0,
+  const int sched = PERSIST ? kSchedPersistent : kSchedGrid;
+  hipLaunchKernelGGL((k_blend_topk<FT, KMAX, BC, PERSIST, false>), dim3(tile_grid(L, sched, k, 0)), dim3(256), 0,
                      st, (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos),
-                     (const float*)(ws + L.selw), (const FT*)s.feat, s.c, L.k, ct, tile_queue(L, tu.sched, ws, kQBlend),
+                     (const float*)(ws + L.selw), (const FT*)s.feat, s.c, L.k, ct, tile_queue(L, sched, ws, kQBlend),
                      out_feat, renorm ? 1 : 0, wide, status);
   // the listed tiles (usually none): a fixed grid strides over the list,
   // whose length it reads on the device
@@ -542,15 +543,12 @@ static void blend_topk_launch(const SurfelArgs& s, const Layout& L, const CamTab
 template <typename FT, int BC>
 static void blend_topk_k(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu, float* out_feat,
                          bool rn, char* ws, hipStream_t st) {
-  const bool p = tu.sched == kSchedPersistent;
-  if (L.k <= 8)
-    (p ? blend_topk_launch<FT, 8, BC, true> : blend_topk_launch<FT, 8, BC, false>)(s, L, ct, tu, out_feat, rn, ws, st);
-  else if (L.k <= 16)
-    (p ? blend_topk_launch<FT, 16, BC, true> : blend_topk_launch<FT, 16, BC, false>)(s, L, ct, tu, out_feat, rn, ws,
-                                                                                      st);
-  else
-    (p ? blend_topk_launch<FT, 32, BC, true> : blend_topk_launch<FT, 32, BC, false>)(s, L, ct, tu, out_feat, rn, ws,
-                                                                                      st);
+  // always grid-scheduled: with the long tiles moved to the windowed pass the
+  // common pass's tiles cost about the same, and the grid form keeps fewer
+  // registers live across tiles (more waves per SIMD)
+  if (L.k <= 8) blend_topk_launch<FT, 8, BC, false>(s, L, ct, tu, out_feat, rn, ws, st);
+  else if (L.k <= 16) blend_topk_launch<FT, 16, BC, false>(s, L, ct, tu, out_feat, rn, ws, st);
+  else blend_topk_launch<FT, 32, BC, false>(s, L, ct, tu, out_feat, rn, ws, st);
 }
 
 template <typename FT, bool PERSIST, bool LP>

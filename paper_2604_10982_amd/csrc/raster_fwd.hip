@@ -53,15 +53,18 @@ constexpr int kWalkChunk = 64;  // list entries a wave examines at once
 // ballot), the kept entries' records are staged, compacted, in the wave's LDS
 // slice by parallel vector loads, and the wave then evaluates them in list
 // order with broadcast reads.
-template <int KMAX, bool TOPK, bool PERSIST, bool LP>
+// KFULL: K == KMAX, known at compile time, so no per-entry "q < K" masks are
+// held across the tile loop (they cost the persistent form 60 registers).
+template <int KMAX, bool TOPK, bool PERSIST, bool LP, bool KFULL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_walk(const WalkRec* __restrict__ rec, const float4* __restrict__ ext,
                                               const uint32_t* __restrict__ pid,
                                               const uint2* __restrict__ ranges, CamTable ct, TileQueue tq,
-                                              int K, float* __restrict__ o_rgb, float* __restrict__ o_depth,
+                                              int K_, float* __restrict__ o_rgb, float* __restrict__ o_depth,
                                               float* __restrict__ o_normal, float* __restrict__ o_alpha,
                                               uint32_t* __restrict__ nlast, float* __restrict__ tfinal,
                                               int32_t* __restrict__ selpos, float* __restrict__ selw,
                                               uint32_t* __restrict__ status, int feat_only) {
+  const int K = KFULL ? KMAX : K_;
   __shared__ Staged<kWalkChunk> s_rec[4];
   __shared__ int s_pos[4][kWalkChunk];
   __shared__ int s_item;
@@ -481,16 +484,28 @@ __global__ __launch_bounds__(256) void k_export_sel(const uint32_t* __restrict__
 }
 
 // ------------------------------------------------------------- host wrappers
-template <int KMAX, bool TOPK, bool PERSIST, bool LP>
-static void walk_launch_t(const Layout& L, const CamTable& ct, const Tuning& tu, const ImageArgs& out,
+template <int KMAX, bool TOPK, bool PERSIST, bool LP, bool KFULL>
+static void walk_launch_k(const Layout& L, const CamTable& ct, const Tuning& tu, const ImageArgs& out,
                           bool feat_only, char* ws, hipStream_t st) {
-  const void* k = reinterpret_cast<const void*>(&k_walk<KMAX, TOPK, PERSIST, LP>);
-  hipLaunchKernelGGL((k_walk<KMAX, TOPK, PERSIST, LP>), dim3(tile_grid(L, tu.sched, k, 0)), dim3(256), 0, st,
+  const void* k = reinterpret_cast<const void*>(&k_walk<KMAX, TOPK, PERSIST, LP, KFULL>);
+  hipLaunchKernelGGL((k_walk<KMAX, TOPK, PERSIST, LP, KFULL>), dim3(tile_grid(L, tu.sched, k, 0)), dim3(256), 0, st,
                      (const WalkRec*)(ws + L.rec), (const float4*)(ws + L.ext), (const uint32_t*)(ws + L.pid),
                      (const uint2*)(ws + L.ranges), ct, tile_queue(L, tu.sched, ws, kQWalk), L.k, out.rgb, out.depth,
                      out.normal, out.alpha,
                      (uint32_t*)(ws + L.nlast), (float*)(ws + L.tfinal), (int32_t*)(ws + L.selpos),
                      (float*)(ws + L.selw), (uint32_t*)(ws + L.status), feat_only ? 1 : 0);
+}
+
+template <int KMAX, bool TOPK, bool PERSIST, bool LP>
+static void walk_launch_t(const Layout& L, const CamTable& ct, const Tuning& tu, const ImageArgs& out,
+                          bool feat_only, char* ws, hipStream_t st) {
+  if constexpr (TOPK) {
+    if (L.k == KMAX) {
+      walk_launch_k<KMAX, TOPK, PERSIST, LP, true>(L, ct, tu, out, feat_only, ws, st);
+      return;
+    }
+  }
+  walk_launch_k<KMAX, TOPK, PERSIST, LP, false>(L, ct, tu, out, feat_only, ws, st);
 }
 
 template <int KMAX, bool TOPK>

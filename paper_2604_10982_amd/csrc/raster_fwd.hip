@@ -314,6 +314,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE || KMA
           *reinterpret_cast<float4*>(out + cc + c) = make_float4(acc[c], acc[c + 1], acc[c + 2], acc[c + 3]);
     }
   };
+  // the same write after an in-register transpose among groups of BC / 4
+  // lanes (pixels adjacent in x): lane g of a group then holds channel quad g
+  // of each of the group's pixels, so every store instruction writes whole
+  // BC-channel segments of consecutive pixels' rows instead of 16 bytes of 64
+  // rows; every lane takes part in the exchanges
+  auto put_rows = [&](int cc, float (&acc)[BC]) {
+    constexpr int NQ = BC / 4;
+    if (renorm) {
+#pragma unroll
+      for (int c = 0; c < BC; ++c) acc[c] *= rw;
+    }
+    float4 a[NQ];
+#pragma unroll
+    for (int e = 0; e < NQ; ++e) a[e] = make_float4(acc[4 * e], acc[4 * e + 1], acc[4 * e + 2], acc[4 * e + 3]);
+    const int gi = tid & (NQ - 1);
+#pragma unroll
+    for (int st = 1; st < NQ; st <<= 1) {
+      const bool hi = (gi & st) != 0;
+#pragma unroll
+      for (int e = 0; e < NQ; ++e) {
+        if (e & st) continue;
+        const float4 x = hi ? a[e] : a[e | st];
+        const float4 y = make_float4(__shfl_xor(x.x, st, 64), __shfl_xor(x.y, st, 64), __shfl_xor(x.z, st, 64),
+                                     __shfl_xor(x.w, st, 64));
+        if (hi) a[e] = y;
+        else a[e | st] = y;
+      }
+    }
+    const int base = tid & ~(NQ - 1);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      const int p = base + k;
+      const int qx = tl.tx * kTile + (p & 15), qy = tl.ty * kTile + (p >> 4);
+      if (qx < tl.W && qy < tl.H && cc + 4 * gi < C)
+        *reinterpret_cast<float4*>(o_feat + (tl.pix0 + (int64_t)qy * tl.W + qx) * C + cc + 4 * gi) = a[k];
+    }
+  };
 
   if constexpr (!WIDE) {
     // one window whose slots fit one chunk: rank once, stage per channel pass
@@ -346,7 +383,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE || KMA
         blend_chunk<KMAX, BC>(s_F, sl, w, K, acc);
         __syncthreads();
       }
-      put(cc, acc);
+      put_rows(cc, acc);
     }
   } else {
     for (int cc = 0; cc < C; cc += BC) {

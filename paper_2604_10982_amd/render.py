@@ -11,11 +11,13 @@ from . import psm
 
 class RasterizeSurfels(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, means, scales, quats, opacity, rgb, feat, camera, k, tile_mode, blend):
+    def forward(ctx, means, scales, quats, opacity, rgb, feat, camera, k, tile_mode, blend, flags=0):
+        if flags & psm.FLAG_FEATURE_ONLY:
+            raise ValueError("render() returns every map; use psm.forward for feature-only rendering")
         cam = camera if isinstance(camera, psm.Camera) else psm.camera_struct(camera)
-        out, ws = psm.forward(means, scales, quats, opacity, rgb, feat, cam, k, tile_mode, blend)
+        out, ws = psm.forward(means, scales, quats, opacity, rgb, feat, cam, k, tile_mode, blend, flags=flags)
         ctx.save_for_backward(means, scales, quats, opacity, rgb, feat)
-        ctx.ws, ctx.cam, ctx.k, ctx.tile_mode, ctx.blend = ws, cam, k, tile_mode, blend
+        ctx.ws, ctx.cam, ctx.k, ctx.tile_mode, ctx.blend, ctx.flags = ws, cam, k, tile_mode, blend, flags
         f = out["feat"]
         if f is None:
             f = torch.zeros(cam.height, cam.width, 0, device=means.device)
@@ -27,19 +29,21 @@ class RasterizeSurfels(torch.autograd.Function):
         gout = {"rgb": g_rgb, "depth": g_depth, "normal": g_normal, "alpha": g_alpha,
                 "feat": g_feat if feat is not None else None}
         g = psm.backward(means, scales, quats, opacity, rgb, feat, ctx.cam, ctx.ws, gout, ctx.k,
-                         ctx.tile_mode, ctx.blend)
+                         ctx.tile_mode, ctx.blend, flags=ctx.flags)
         ctx.ws = None
         gf = None if feat is None else g["feat"].to(feat.dtype)
-        return g["means"], g["scales"], g["quats"], g["opacity"], g["rgb"], gf, None, None, None, None
+        return g["means"], g["scales"], g["quats"], g["opacity"], g["rgb"], gf, None, None, None, None, None
 
 
 def render(means, scales, quats, opacity, rgb, feat, camera, k: int = 16, tile_mode: str = "ellipse",
-           blend: str = "topk"):
+           blend: str = "topk", flags: int = 0):
     """Render RGB [H,W,3], depth [H,W], normal [H,W,3], alpha [H,W] and the
     feature map [H,W,C] of 2D Gaussian surfels seen by `camera`; features are
     blended over the K largest weights per pixel (blend="topk") or over every
-    contributor (blend="full")."""
-    return RasterizeSurfels.apply(means, scales, quats, opacity, rgb, feat, camera, k, tile_mode, blend)
+    contributor (blend="full").  `flags`: psm.FLAG_OPACITY_FOOTPRINT,
+    FLAG_TOPK_RENORM, FLAG_LOWPASS (FLAG_FEATURE_ONLY is refused: every map is
+    returned)."""
+    return RasterizeSurfels.apply(means, scales, quats, opacity, rgb, feat, camera, k, tile_mode, blend, flags)
 
 
 class InstanceLabels(torch.autograd.Function):

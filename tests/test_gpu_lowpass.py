@@ -146,3 +146,32 @@ def test_lowpass_with_feature_variants(orc):
     ok = decided(ref)
     worst = image_errors(np_out(out2), ref, absf, ok, 1e-5)
     assert max(worst.values()) <= 1.0, worst
+
+
+def test_autograd_render_takes_the_flags():
+    """render() (torch autograd over the C ABI) passes its flags to both
+    directions: outputs and gradients equal the direct calls bit for bit."""
+    require_gpu()
+    from paper_2604_10982_amd import render as R
+    sc, cam, K = _cases()["mixed3k_ragged"]()
+    t = to_dev(sc)
+    flags = LP | psm.FLAG_TOPK_RENORM
+    params = {k: t[k].clone().requires_grad_(True) for k in ("means", "scales", "quats", "opacity", "rgb", "feat")}
+    maps = R.render(*(params[k] for k in ("means", "scales", "quats", "opacity", "rgb", "feat")), cam, K,
+                    "ellipse", "topk", flags)
+    g = scenes.upstream(cam.height, cam.width, sc.c, seed=3)
+    gt = {k: torch.tensor(v, device=DEV) for k, v in g.items()}
+    names = ("rgb", "depth", "normal", "alpha", "feat")
+    loss = sum((m * gt[k]).sum() for m, k in zip(maps, names))
+    loss.backward()
+    out, ws = _fwd(t, cam, K, "ellipse", "topk", flags)
+    for m, k in zip(maps, names):
+        assert torch.equal(m.detach(), out[k]), k
+    ref = psm.backward(t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"], cam, ws, gt, K,
+                       "ellipse", "topk", flags=flags)
+    torch.cuda.synchronize()
+    for k in ref:
+        assert torch.equal(params[k].grad, ref[k].to(params[k].grad.dtype)), k
+    with pytest.raises(ValueError):
+        R.render(t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"], cam, K, "ellipse", "topk",
+                 psm.FLAG_FEATURE_ONLY)

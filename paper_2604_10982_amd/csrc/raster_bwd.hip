@@ -677,7 +677,7 @@ __device__ __forceinline__ void chain_rule(const double (&G)[16], const CamArgs&
 // t0 + l of it (coalesced), the batch is staged in LDS, and each surfel's
 // lane adds its own pairs of the batch.  The sums are the same, term by
 // term, as a per-surfel loop over its range.
-__global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, CamTable ct, const uint32_t* __restrict__ vbase,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_reduce_geo(int64_t n, CamTable ct, const uint32_t* __restrict__ vbase,
                                                     const uint32_t* __restrict__ count, int64_t cap,
                                                     const float* __restrict__ gpart,
                                                     const uint8_t* __restrict__ gflag,
@@ -698,16 +698,24 @@ __global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, CamTable ct, cons
   for (int j = 0; j < 3; ++j) acc.mu[j] = acc.rgb[j] = 0.0;
   for (int j = 0; j < 4; ++j) acc.q[j] = 0.0;
   acc.su = acc.sv = acc.o = 0.0;
-  const double mu[3] = {means[3 * ii], means[3 * ii + 1], means[3 * ii + 2]};
-  const double su = scales[2 * ii], sv = scales[2 * ii + 1];
-  const double q0 = quats[4 * ii], q1 = quats[4 * ii + 1], q2 = quats[4 * ii + 2], q3 = quats[4 * ii + 3];
-  const double qq = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
-  const double rn = qq > 0.0 ? 1.0 / sqrt(qq) : 0.0;
-  const double qn[4] = {q0 * rn, q1 * rn, q2 * rn, q3 * rn};
-  const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
-  const double Rq[3][3] = {{1. - 2. * (y * y + z * z), 2. * (x * y - w * z), 2. * (x * z + w * y)},
-                           {2. * (x * y + w * z), 1. - 2. * (x * x + z * z), 2. * (y * z - w * x)},
-                           {2. * (x * z - w * y), 2. * (y * z + w * x), 1. - 2. * (x * x + y * y)}};
+  // the surfel's parameters are re-read (an L1/L2 hit) where they are used
+  // rather than held through the pair sums: it keeps the kernel's registers
+  // to what the sums and the chain rule need
+  struct Params {
+    double mu[3], su, sv, rn, qn[4], Rq[3][3];
+  };
+  auto params = [&](Params& P) {
+    P.mu[0] = means[3 * ii]; P.mu[1] = means[3 * ii + 1]; P.mu[2] = means[3 * ii + 2];
+    P.su = scales[2 * ii]; P.sv = scales[2 * ii + 1];
+    const double q0 = quats[4 * ii], q1 = quats[4 * ii + 1], q2 = quats[4 * ii + 2], q3 = quats[4 * ii + 3];
+    const double qq = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
+    P.rn = qq > 0.0 ? 1.0 / sqrt(qq) : 0.0;
+    P.qn[0] = q0 * P.rn; P.qn[1] = q1 * P.rn; P.qn[2] = q2 * P.rn; P.qn[3] = q3 * P.rn;
+    const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
+    P.Rq[0][0] = 1. - 2. * (y * y + z * z); P.Rq[0][1] = 2. * (x * y - w * z); P.Rq[0][2] = 2. * (x * z + w * y);
+    P.Rq[1][0] = 2. * (x * y + w * z); P.Rq[1][1] = 1. - 2. * (x * x + z * z); P.Rq[1][2] = 2. * (y * z - w * x);
+    P.Rq[2][0] = 2. * (x * z - w * y); P.Rq[2][1] = 2. * (y * z + w * x); P.Rq[2][2] = 1. - 2. * (x * x + y * y);
+  };
   float* part = s_part[wave];
   // the next camera's pair range is loaded while this camera's is summed
   int32_t ncv = valid ? cull[i] : 1;
@@ -775,12 +783,18 @@ __global__ __launch_bounds__(256) void k_reduce_geo(int64_t n, CamTable ct, cons
       }
       wave_lds_sync();
     }
-    if (live) chain_rule(G, ct.cam[b], ((cv >> 8) & 1) != 0, mu, su, sv, qn, Rq, acc);
+    if (live) {
+      Params P;
+      params(P);
+      chain_rule(G, ct.cam[b], ((cv >> 8) & 1) != 0, P.mu, P.su, P.sv, P.qn, P.Rq, acc);
+    }
   }
   if (!valid) return;
+  Params P;
+  params(P);
   // unit quaternion: project out the radial component
-  const double dot = w * acc.q[0] + x * acc.q[1] + y * acc.q[2] + z * acc.q[3];
-  for (int j = 0; j < 4; ++j) d_quats[4 * i + j] = (float)((acc.q[j] - qn[j] * dot) * rn);
+  const double dot = P.qn[0] * acc.q[0] + P.qn[1] * acc.q[1] + P.qn[2] * acc.q[2] + P.qn[3] * acc.q[3];
+  for (int j = 0; j < 4; ++j) d_quats[4 * i + j] = (float)((acc.q[j] - P.qn[j] * dot) * P.rn);
   for (int j = 0; j < 3; ++j) d_means[3 * i + j] = (float)acc.mu[j];
   d_scales[2 * i] = (float)acc.su;
   d_scales[2 * i + 1] = (float)acc.sv;

@@ -286,3 +286,52 @@ def test_opacity_circle_footprint_by_hand(orc, o):
     assert set(ks["tile"].tolist()) == exp
     if o >= 0.5:   # 2 ln(255 o) > 9: the standard footprint
         assert set(orc.keystage(sc, cam, "ellipse")["tile"].tolist()) == exp
+
+
+@pytest.mark.parametrize("theta_deg", [30.0, 45.0, 60.0, 120.0])
+def test_sphere_footprint_by_hand(orc, theta_deg):
+    """The isotropic-bound baseline of Sec. 5 (reading: the square of
+    half-width sqrt(lambda_max) of the projected cutoff ellipse's shape, the
+    3DGS radius).  A fronto-parallel elongated surfel turned in its plane by
+    theta projects to an ellipse with semi-axes r_t f s_u / z and
+    r_t f s_v / z, so lambda_max = (r_t f s_u / z)^2 whatever theta is, while
+    the eq. (17) half-extents shrink below it for theta off the axes.  The
+    expected tile set is the square of that closed-form radius; the radii a
+    plausible mistake would give (lambda_min, the larger of the diagonal
+    entries, their mean) select other tile sets, so any of them fails here."""
+    cam = pinhole(224, 192, f=100.0)
+    X0, Y0, z0, su, sv = 0.13, -0.07, 2.5, 0.33, 0.06
+    th = math.radians(theta_deg)
+    quat = np.array([[math.cos(th / 2), 0.0, 0.0, math.sin(th / 2)]], np.float32)
+    sc = Scene(np.array([[X0, Y0, z0]], np.float32), np.array([[su, sv]], np.float32), quat,
+               np.array([0.5], np.float32), np.ones((1, 3), np.float32), np.zeros((1, 4), np.float32))
+    f32 = lambda v: float(np.float32(v))
+    X0, Y0, z0, su, sv = map(f32, (X0, Y0, z0, su, sv))
+    xc, yc = cam.fx * X0 / z0 + cam.cx, cam.fy * Y0 / z0 + cam.cy
+    rt = math.sqrt(R_FOOT2)
+    Ru, Rv = rt * cam.fx * su / z0, rt * cam.fy * sv / z0
+    # closed-form eq. (17) half-extents of the turned ellipse (the AABB)
+    c, s = math.cos(th), math.sin(th)
+    ex, ey = math.hypot(Ru * c, Rv * s), math.hypot(Ru * s, Rv * c)
+    ntx, nty = (cam.width + 15) // 16, (cam.height + 15) // 16
+
+    def square_tiles(hx, hy, check_margin):
+        out = set()
+        for ty in range(nty):
+            for tx in range(ntx):
+                x0, x1 = 16 * tx + 0.5, min(16 * tx + 15.5, cam.width - 0.5)
+                y0, y1 = 16 * ty + 0.5, min(16 * ty + 15.5, cam.height - 0.5)
+                if check_margin:
+                    for d, h in ((x0 - (xc + hx), hx), ((xc - hx) - x1, hx), (y0 - (yc + hy), hy),
+                                 ((yc - hy) - y1, hy)):
+                        assert abs(d) > 1e-3 * h      # no tile edge near the box edge
+                if x0 <= xc + hx and x1 >= xc - hx and y0 <= yc + hy and y1 >= yc - hy:
+                    out.add(ty * ntx + tx)
+        return out
+
+    exp = square_tiles(Ru, Ru, True)
+    got = set(orc.keystage(sc, cam, "sphere")["tile"].tolist())
+    assert got == exp
+    assert set(orc.keystage(sc, cam, "aabb")["tile"].tolist()) == square_tiles(ex, ey, True)
+    for wrong in (Rv, max(ex, ey), math.sqrt(0.5 * (ex * ex + ey * ey))):
+        assert square_tiles(wrong, wrong, False) != exp

@@ -180,41 +180,75 @@ def measured_traffic(stage: str, workload: str, launch=None):
         return None
 
 
-def roofline(stages, st, K, C, S, bwd, workload=WORKLOAD, launch=None):
-    """Roofline object for the dominant stage of the step."""
-    name = max(stages, key=stages.get)
-    ms = stages[name]
-    traffic = measured_traffic(name, workload, launch)
+def stage_work(name, st, K, C, b, S):
+    """Algorithmic work of one launch of a stage: ("flop", F) for the walks
+    (ALU-bound), ("byte", B) for the streaming stages.  U = distinct selected
+    surfels, b = bytes per stored feature element."""
+    P, N, U = st.pairs, st.n, max(st.selected_unique, 0)
     if name == "walk":
-        flops = FLOP_PER_EVAL * st.pairs_walked + FLOP_PER_CONTRIB * st.contributors
-        a = flops / (ms * 1e-3) / 1e12
-        return {"kernel": name, "bound": "alu", "achieved": a, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": a / FP32_VALU_PEAK_TFLOPS, "traffic": traffic, "ms": ms,
-                "work": {"pairs_walked": st.pairs_walked, "contributors": st.contributors}}
+        return "flop", FLOP_PER_EVAL * st.pairs_walked + FLOP_PER_CONTRIB * st.contributors
     if name == "bwd_walk":
-        flops = BWD_FLOP_PER_EVAL * st.pairs_walked + BWD_FLOP_PER_CONTRIB * st.contributors
-        a = flops / (ms * 1e-3) / 1e12
-        return {"kernel": name, "bound": "alu", "achieved": a, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": a / FP32_VALU_PEAK_TFLOPS, "traffic": traffic, "ms": ms,
-                "work": {"pairs_walked": st.pairs_walked, "contributors": st.contributors}}
-    # streaming stages: algorithmic bytes
-    P, N = st.pairs, st.n
+        # the backward evaluates each pixel's list up to its last contributor
+        return "flop", BWD_FLOP_PER_EVAL * st.bwd_entries + BWD_FLOP_PER_CONTRIB * st.contributors
     bytes_by = {
-        "feature_blend": S * (8 * K + 4 * C),
-        "bwd_feature": S * (8 * K + 4 * C + 4 * K),
+        "feature_blend": S * (8 * K + 4 * C) + U * C * b,
+        "bwd_feature": S * (8 * K + 4 * C + 4 * K) + U * C * b + U * 4 * C,
         "preprocess": N * (40 + 12) + st.visible * (64 + 48) + N * 12,
         "depth_sort": N * 8 * 2,
         "pair_sort": P * 8 * 2,
         "emit": P * 8 + st.visible * 56,
         "count_scan": N * 8,
-        "bwd_reduce": N * (64 + 40 + 52) + st.pairs * 80,
+        "bwd_reduce": N * (64 + 40 + 52) + P * 80,
         "ranges": P * 4,
-        "fill": N * 4 * (16 + C),
+        "fill": 0,
     }
-    b = bytes_by.get(name, 0)
-    a = b / (ms * 1e-3) / 1e9
+    return "byte", bytes_by.get(name, 0)
+
+
+def stage_table(stages, st, K, C, b, S):
+    """Every stage of the step against its roofline: HBM GB/s for the
+    streaming stages, TFLOP/s of the unpacked vector ALU for the walks."""
+    out = {}
+    for name, ms in stages.items():
+        kind, w = stage_work(name, st, K, C, b, S)
+        if kind == "flop":
+            a = w / (ms * 1e-3) / 1e12
+            out[name] = {"ms": ms, "bound": "alu", "tflops": a, "frac": a / FP32_VALU_PEAK_TFLOPS}
+        elif w:
+            a = w / (ms * 1e-3) / 1e9
+            out[name] = {"ms": ms, "bound": "hbm", "gbs": a, "frac": a / HBM_PEAK_GBS}
+        else:
+            out[name] = {"ms": ms}
+    return out
+
+
+def step_bytes(st, K, C, b, S, bwd=True):
+    """Algorithmic HBM bytes of one forward (+ backward): the parameters, the
+    pair list written and read once, the selected features, the FP32 maps,
+    and for the backward the upstream maps, the saved per-pixel state and the
+    FP32 gradients."""
+    N, P, U = st.n, st.pairs, max(st.selected_unique, 0)
+    fwd = N * 40 + st.visible * 12 + P * 24 + U * C * b + S * (32 + 4 * C)
+    if not bwd:
+        return fwd
+    return fwd + S * (32 + 4 * C) + S * (8 + 8 * K) + P * 24 + U * C * b + N * 4 * (13 + C)
+
+
+def roofline(stages, st, K, C, S, b, workload=WORKLOAD, launch=None):
+    """Roofline object for the dominant stage of the step."""
+    name = max(stages, key=stages.get)
+    ms = stages[name]
+    traffic = measured_traffic(name, workload, launch)
+    kind, w = stage_work(name, st, K, C, b, S)
+    if kind == "flop":
+        a = w / (ms * 1e-3) / 1e12
+        return {"kernel": name, "bound": "alu", "achieved": a, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": a / FP32_VALU_PEAK_TFLOPS, "traffic": traffic, "ms": ms,
+                "work": {"pairs_walked": st.pairs_walked, "bwd_entries": st.bwd_entries,
+                         "contributors": st.contributors, "flops": w}}
+    a = w / (ms * 1e-3) / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": a / HBM_PEAK_GBS, "traffic": traffic, "ms": ms}
+            "frac": a / HBM_PEAK_GBS, "traffic": traffic, "ms": ms, "work": {"bytes": w}}
 
 
 def batch_workload(psm, scenes, steps, warmup):
@@ -473,6 +507,7 @@ def main():
     g = scenes.upstream(cam.height, cam.width, sc.c, seed=1)
     gout = {k: torch.tensor(v, device=device) for k, v in g.items()}
     S = cam.width * cam.height
+    fbytes = {"f32": 4, "f16": 2, "bf16": 2}[dtype]
     print(f"[bench] {args.workload}: n={sc.n} {cam.width}x{cam.height} C={sc.c} K={K} {dtype}", file=sys.stderr,
           flush=True)
 
@@ -581,7 +616,13 @@ def main():
                    "bwd_schedule": ["grid", "persistent"][head_launch[1]], "blend_pass": head_launch[2],
                    "bwd_pass": head_launch[3], "source": "autotuner" if launch is None else "--launch",
                    "tuned_ms": head_tuned_ms},
-        "roofline": roofline(stages, st, K, sc.c, S, True, args.workload, head_launch),
+        "selected_unique": int(st.selected_unique), "selections": int(st.selections),
+        "bwd_entries": int(st.bwd_entries),
+        "roofline": roofline(stages, st, K, sc.c, S, fbytes, args.workload, head_launch),
+        "stage_roofline": stage_table(stages, st, K, sc.c, fbytes, S),
+        "step_hbm": {"algorithmic_bytes": step_bytes(st, K, sc.c, fbytes, S),
+                     "gbs": step_bytes(st, K, sc.c, fbytes, S) / (ms_step * 1e-3) / 1e9,
+                     "frac": step_bytes(st, K, sc.c, fbytes, S) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "ablation_fwd": ablation,
     }
     if not args.no_cpu_baseline:

@@ -26,7 +26,9 @@
  *     feat [H][W][C], all FP32.
  *   - Errors: every entry point returns a psm_status; negative values are
  *     errors and psm_last_error() returns a thread-local message.  No entry
- *     point aborts or throws.  NaN/Inf inputs are not checked; they propagate.
+ *     point aborts or throws: a failed host allocation or any other C++
+ *     exception inside the library is caught at the entry point and returned
+ *     as PSM_ERR_HIP.  NaN/Inf inputs are not checked; they propagate.
  */
 #ifndef PSM_H
 #define PSM_H
@@ -151,6 +153,12 @@ typedef struct {
   int64_t tiles;          /* number of 16x16 tiles (all cameras) */
   int64_t pairs_walked;   /* pixel x list-entry evaluations of the forward walk */
   int64_t contributors;   /* (pixel, surfel) pairs blended by the forward walk */
+  int64_t bwd_entries;    /* sum over pixels of the list position one past the last contributor: the
+                             list entries the backward walk must evaluate (Sec. 3.1 eq. (1) adjoint) */
+  int64_t selected_unique;  /* Top-K blend: distinct (camera, surfel) pairs selected by at least one pixel
+                               (the feature rows eq. (18) reads); -1 for the dense blend */
+  int64_t selections;     /* Top-K blend: (pixel, slot) selections held, sum over pixels of min(K,
+                             contributors); -1 for the dense blend */
 } psm_stats;
 
 typedef struct psm_ctx psm_ctx;
@@ -193,8 +201,16 @@ psm_status psm_backward(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
                         int64_t pair_capacity, const psm_image_grads* grad_out, psm_grads* grads,
                         void* stream);
 
-/* Synchronises `stream` and reads the counters of the last psm_forward in
- * this workspace into *out (host memory). */
+/* Reads the counters of the last psm_forward in this workspace into *out
+ * (host memory).  For the Top-K blend it first counts the selections on
+ * `stream` (two small kernels over the saved selection; a bitmap region of
+ * the workspace is overwritten, nothing the backward reads), then
+ * synchronises `stream`.  n, cam, cfg, c and pair_capacity must be those of
+ * that forward: the forward records its workspace layout (total bytes, pair
+ * capacity, tiles) in the workspace, and this call and the other read-backs
+ * return PSM_ERR_INVALID_ARG, before touching anything else in the
+ * workspace, when the layout they compute differs (the workspace must hold
+ * at least the 256-byte status block that starts it). */
 psm_status psm_read_stats(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cam,
                           const psm_config* cfg, int32_t c, int64_t pair_capacity, psm_stats* out,
                           void* stream);

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <string>
 #include <utility>
 #include <vector>
@@ -259,6 +260,18 @@ psm_status read_status(const Layout& L, const void* ws, uint32_t* st_host, hipSt
   return PSM_OK;
 }
 
+// Checks the layout the forward recorded against the one the read-back
+// computed from its arguments (so no read-back addresses past the workspace).
+psm_status check_signature(const Layout& L, const uint32_t* h) {
+  const uint64_t total = (uint64_t)h[kStSigLo] | ((uint64_t)h[kStSigHi] << 32);
+  if (total != (uint64_t)L.total || h[kStSigCap] != (uint32_t)L.cap || h[kStSigTiles] != (uint32_t)L.tiles)
+    return fail(PSM_ERR_INVALID_ARG, "the workspace was laid out by a forward with other arguments (n, cameras, "
+                                     "k, c or pair capacity) or holds no forward");
+  return PSM_OK;
+}
+
+inline int64_t word64(const uint32_t* h, int i) { return (int64_t)((uint64_t)h[i] | ((uint64_t)h[i + 1] << 32)); }
+
 psm_status capacity_error(const Layout& L, const uint32_t* h) {
   const uint64_t req = (uint64_t)h[kStReqLo] | ((uint64_t)h[kStReqHi] << 32);
   return fail(PSM_ERR_CAPACITY, "pair capacity " + std::to_string(L.cap) + " < required " + std::to_string(req));
@@ -273,7 +286,7 @@ void enqueue_forward(const SurfelArgs& sa, const CamTable& ct, const psm_config*
   uint32_t* status = (uint32_t*)(ws + L.status);
   uint32_t* hist = (uint32_t*)(ws + L.hist);
   prof.begin(kStageFill, st);
-  launch_init_status(status, L.n, L.tiles, st);
+  launch_init_status(status, L, st);
   launch_fill_u32(ws + L.ranges, 0u, L.tiles * 2, st);
   prof.end(kStageFill, st);
   prof.begin(kStagePreprocess, st);
@@ -380,9 +393,20 @@ psm_status read_stats_impl(psm_ctx* ctx, const void* workspace, int64_t n, const
   const Layout L = make_layout(cam_table(cams, n_cams, n), cfg->k, c, pair_capacity);
   if (!workspace) return fail(PSM_ERR_INVALID_ARG, "workspace is required");
   DeviceGuard dg(ctx->device);
+  hipStream_t st = (hipStream_t)stream;
   uint32_t h[kStWords];
-  r = read_status(L, workspace, h, (hipStream_t)stream);
+  r = read_status(L, workspace, h, st);
   if (r != PSM_OK) return r;
+  r = check_signature(L, h);
+  if (r != PSM_OK) return r;
+  const bool topk = cfg->blend == PSM_BLEND_TOPK;
+  if (topk) {
+    launch_count_selected(L, (char*)workspace, st);
+    r = check_hip("psm_read_stats selection count");
+    if (r != PSM_OK) return r;
+    r = read_status(L, workspace, h, st);
+    if (r != PSM_OK) return r;
+  }
   std::memset(out, 0, sizeof(*out));
   out->n = n;
   out->visible = h[kStVisible];
@@ -391,8 +415,11 @@ psm_status read_stats_impl(psm_ctx* ctx, const void* workspace, int64_t n, const
   out->pairs_required = (int64_t)((uint64_t)h[kStReqLo] | ((uint64_t)h[kStReqHi] << 32));
   out->pair_capacity = pair_capacity;
   out->tiles = L.tiles;
-  out->pairs_walked = (int64_t)((uint64_t)h[kStWalked] | ((uint64_t)h[kStWalked + 1] << 32));
-  out->contributors = (int64_t)((uint64_t)h[kStBlended] | ((uint64_t)h[kStBlended + 1] << 32));
+  out->pairs_walked = word64(h, kStWalked);
+  out->contributors = word64(h, kStBlended);
+  out->bwd_entries = word64(h, kStBwdEntries);
+  out->selected_unique = topk ? word64(h, kStUnique) : -1;
+  out->selections = topk ? word64(h, kStSelected) : -1;
   return PSM_OK;
 }
 
@@ -410,6 +437,8 @@ psm_status read_pairs_impl(psm_ctx* ctx, const void* workspace, int64_t n, const
   const char* ws = (const char*)workspace;
   uint32_t h[kStWords];
   r = read_status(L, workspace, h, st);
+  if (r != PSM_OK) return r;
+  r = check_signature(L, h);
   if (r != PSM_OK) return r;
   const int64_t P = h[kStP];
   if (pairs_out) *pairs_out = P;
@@ -434,6 +463,11 @@ psm_status read_selection_impl(psm_ctx* ctx, const void* workspace, int64_t n, c
   const CamTable ct = cam_table(cams, n_cams, n);
   const Layout L = make_layout(ct, cfg->k, c, pair_capacity);
   DeviceGuard dg(ctx->device);
+  uint32_t h[kStWords];
+  r = read_status(L, workspace, h, (hipStream_t)stream);
+  if (r != PSM_OK) return r;
+  r = check_signature(L, h);
+  if (r != PSM_OK) return r;
   launch_export_selection(L, ct, (char*)workspace, cfg->blend == PSM_BLEND_TOPK ? sel_id_out : nullptr,
                           cfg->blend == PSM_BLEND_TOPK ? sel_w_out : nullptr, n_last_out, t_final_out,
                           (hipStream_t)stream);
@@ -449,6 +483,28 @@ std::string tune_key(const psm_surfels* s, const psm_camera* cams, int32_t n_cam
   return k;
 }
 
+// No C++ exception crosses the C ABI: a host allocation failure or any other
+// exception inside an entry point becomes an error status and message.
+psm_status fail_noexcept(psm_status s, const char* where, const char* msg) noexcept {
+  try {
+    g_err = std::string(where) + ": " + msg;
+  } catch (...) {
+    g_err.clear();
+  }
+  return s;
+}
+
+template <class F>
+psm_status guarded(const char* where, F&& body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return fail_noexcept(PSM_ERR_HIP, where, "host memory allocation failed");
+  } catch (...) {
+    return fail_noexcept(PSM_ERR_HIP, where, "unexpected internal exception");
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -458,192 +514,220 @@ const char* psm_last_error(void) { return g_err.c_str(); }
 const char* psm_version(void) { return "psm 0.2 (gfx950)"; }
 
 psm_status psm_create(psm_ctx** ctx_out, int device) {
-  if (!ctx_out) return fail(PSM_ERR_INVALID_ARG, "ctx_out is null");
-  *ctx_out = nullptr;
-  int count = 0;
-  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
-    return fail(PSM_ERR_HIP, "no usable HIP device " + std::to_string(device));
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(PSM_ERR_HIP, "hipGetDeviceProperties failed");
-  psm_ctx* c = new psm_ctx;
-  c->device = device;
-  c->cu_count = prop.multiProcessorCount;
-  *ctx_out = c;
-  g_err.clear();
-  return PSM_OK;
+  return guarded("psm_create", [&]() -> psm_status {
+    if (!ctx_out) return fail(PSM_ERR_INVALID_ARG, "ctx_out is null");
+    *ctx_out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+      return fail(PSM_ERR_HIP, "no usable HIP device " + std::to_string(device));
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(PSM_ERR_HIP, "hipGetDeviceProperties failed");
+    psm_ctx* c = new psm_ctx;
+    c->device = device;
+    c->cu_count = prop.multiProcessorCount;
+    *ctx_out = c;
+    g_err.clear();
+    return PSM_OK;
+  });
 }
 
 void psm_destroy(psm_ctx* ctx) { delete ctx; }
 
 psm_status psm_workspace_size_batch(int64_t n, const psm_camera* cams, int32_t n_cams, const psm_config* cfg,
                                     int32_t c, int64_t pair_capacity, size_t* bytes_out) {
-  if (!bytes_out) return fail(PSM_ERR_INVALID_ARG, "bytes_out is null");
-  psm_status s = validate_common(cams, n_cams, cfg, n, c, pair_capacity);
-  if (s != PSM_OK) return s;
-  *bytes_out = make_layout(cam_table(cams, n_cams, n), cfg->k, c, pair_capacity).total;
-  return PSM_OK;
+  return guarded("psm_workspace_size_batch", [&]() -> psm_status {
+    if (!bytes_out) return fail(PSM_ERR_INVALID_ARG, "bytes_out is null");
+    psm_status s = validate_common(cams, n_cams, cfg, n, c, pair_capacity);
+    if (s != PSM_OK) return s;
+    *bytes_out = make_layout(cam_table(cams, n_cams, n), cfg->k, c, pair_capacity).total;
+    return PSM_OK;
+  });
 }
 
 psm_status psm_workspace_size(int64_t n, const psm_camera* cam, const psm_config* cfg, int32_t c,
                               int64_t pair_capacity, size_t* bytes_out) {
-  return psm_workspace_size_batch(n, cam, 1, cfg, c, pair_capacity, bytes_out);
+  return guarded("psm_workspace_size", [&]() -> psm_status {
+    return psm_workspace_size_batch(n, cam, 1, cfg, c, pair_capacity, bytes_out);
+  });
 }
 
 psm_status psm_forward_batch(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cams, int32_t n_cams,
                              const psm_config* cfg, void* workspace, size_t workspace_bytes, int64_t pair_capacity,
                              psm_images* out, void* stream) {
-  return forward_impl(ctx, s, cams, n_cams, cfg, workspace, workspace_bytes, pair_capacity, out, stream);
+  return guarded("psm_forward_batch", [&]() -> psm_status {
+    return forward_impl(ctx, s, cams, n_cams, cfg, workspace, workspace_bytes, pair_capacity, out, stream);
+  });
 }
 
 psm_status psm_forward(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cam, const psm_config* cfg,
                        void* workspace, size_t workspace_bytes, int64_t pair_capacity, psm_images* out,
                        void* stream) {
-  return forward_impl(ctx, s, cam, 1, cfg, workspace, workspace_bytes, pair_capacity, out, stream);
+  return guarded("psm_forward", [&]() -> psm_status {
+    return forward_impl(ctx, s, cam, 1, cfg, workspace, workspace_bytes, pair_capacity, out, stream);
+  });
 }
 
 psm_status psm_backward_batch(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cams, int32_t n_cams,
                               const psm_config* cfg, void* workspace, size_t workspace_bytes, int64_t pair_capacity,
                               const psm_image_grads* grad_out, psm_grads* grads, void* stream) {
-  return backward_impl(ctx, s, cams, n_cams, cfg, workspace, workspace_bytes, pair_capacity, grad_out, grads,
-                       stream);
+  return guarded("psm_backward_batch", [&]() -> psm_status {
+    return backward_impl(ctx, s, cams, n_cams, cfg, workspace, workspace_bytes, pair_capacity, grad_out, grads,
+                         stream);
+  });
 }
 
 psm_status psm_backward(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cam, const psm_config* cfg,
                         void* workspace, size_t workspace_bytes, int64_t pair_capacity,
                         const psm_image_grads* grad_out, psm_grads* grads, void* stream) {
-  return backward_impl(ctx, s, cam, 1, cfg, workspace, workspace_bytes, pair_capacity, grad_out, grads, stream);
+  return guarded("psm_backward", [&]() -> psm_status {
+    return backward_impl(ctx, s, cam, 1, cfg, workspace, workspace_bytes, pair_capacity, grad_out, grads, stream);
+  });
 }
 
 psm_status psm_read_stats_batch(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cams,
                                 int32_t n_cams, const psm_config* cfg, int32_t c, int64_t pair_capacity,
                                 psm_stats* out, void* stream) {
-  return read_stats_impl(ctx, workspace, n, cams, n_cams, cfg, c, pair_capacity, out, stream);
+  return guarded("psm_read_stats_batch", [&]() -> psm_status {
+    return read_stats_impl(ctx, workspace, n, cams, n_cams, cfg, c, pair_capacity, out, stream);
+  });
 }
 
 psm_status psm_read_stats(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cam,
                           const psm_config* cfg, int32_t c, int64_t pair_capacity, psm_stats* out, void* stream) {
-  return read_stats_impl(ctx, workspace, n, cam, 1, cfg, c, pair_capacity, out, stream);
+  return guarded("psm_read_stats", [&]() -> psm_status {
+    return read_stats_impl(ctx, workspace, n, cam, 1, cfg, c, pair_capacity, out, stream);
+  });
 }
 
 psm_status psm_read_pairs_batch(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cams,
                                 int32_t n_cams, const psm_config* cfg, int32_t c, int64_t pair_capacity,
                                 int32_t* tile_out, int32_t* id_out, int64_t cap, int32_t* cull_out,
                                 uint32_t* depth_bits_out, int32_t* count_out, int64_t* pairs_out, void* stream) {
-  return read_pairs_impl(ctx, workspace, n, cams, n_cams, cfg, c, pair_capacity, tile_out, id_out, cap, cull_out,
-                         depth_bits_out, count_out, pairs_out, stream);
+  return guarded("psm_read_pairs_batch", [&]() -> psm_status {
+    return read_pairs_impl(ctx, workspace, n, cams, n_cams, cfg, c, pair_capacity, tile_out, id_out, cap, cull_out,
+                           depth_bits_out, count_out, pairs_out, stream);
+  });
 }
 
 psm_status psm_read_pairs(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cam,
                           const psm_config* cfg, int32_t c, int64_t pair_capacity, int32_t* tile_out,
                           int32_t* id_out, int64_t cap, int32_t* cull_out, uint32_t* depth_bits_out,
                           int32_t* count_out, int64_t* pairs_out, void* stream) {
-  return read_pairs_impl(ctx, workspace, n, cam, 1, cfg, c, pair_capacity, tile_out, id_out, cap, cull_out,
-                         depth_bits_out, count_out, pairs_out, stream);
+  return guarded("psm_read_pairs", [&]() -> psm_status {
+    return read_pairs_impl(ctx, workspace, n, cam, 1, cfg, c, pair_capacity, tile_out, id_out, cap, cull_out,
+                           depth_bits_out, count_out, pairs_out, stream);
+  });
 }
 
 psm_status psm_read_selection_batch(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cams,
                                     int32_t n_cams, const psm_config* cfg, int32_t c, int64_t pair_capacity,
                                     int32_t* sel_id_out, float* sel_w_out, int32_t* n_last_out, float* t_final_out,
                                     void* stream) {
-  return read_selection_impl(ctx, workspace, n, cams, n_cams, cfg, c, pair_capacity, sel_id_out, sel_w_out,
-                             n_last_out, t_final_out, stream);
+  return guarded("psm_read_selection_batch", [&]() -> psm_status {
+    return read_selection_impl(ctx, workspace, n, cams, n_cams, cfg, c, pair_capacity, sel_id_out, sel_w_out,
+                               n_last_out, t_final_out, stream);
+  });
 }
 
 psm_status psm_read_selection(psm_ctx* ctx, const void* workspace, int64_t n, const psm_camera* cam,
                               const psm_config* cfg, int32_t c, int64_t pair_capacity, int32_t* sel_id_out,
                               float* sel_w_out, int32_t* n_last_out, float* t_final_out, void* stream) {
-  return read_selection_impl(ctx, workspace, n, cam, 1, cfg, c, pair_capacity, sel_id_out, sel_w_out, n_last_out,
-                             t_final_out, stream);
+  return guarded("psm_read_selection", [&]() -> psm_status {
+    return read_selection_impl(ctx, workspace, n, cam, 1, cfg, c, pair_capacity, sel_id_out, sel_w_out, n_last_out,
+                               t_final_out, stream);
+  });
 }
 
 psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cams, int32_t n_cams,
                         psm_config* cfg, void* workspace, size_t workspace_bytes, int64_t pair_capacity,
                         psm_images* out, const psm_image_grads* grad_out, psm_grads* grads, int32_t reps,
                         double* best_ms_out, void* stream) {
-  if (!ctx || !cfg || !out) return fail(PSM_ERR_INVALID_ARG, "ctx, cfg and out are required");
-  if (reps < 1 || reps > 1000) return fail(PSM_ERR_INVALID_ARG, "reps must be in [1, 1000]");
-  psm_status r = validate_surfels(s);
-  if (r != PSM_OK) return r;
-  r = validate_common(cams, n_cams, cfg, s->n, s->c, pair_capacity);
-  if (r != PSM_OK) return r;
-  const bool bwd = grads != nullptr;
-  if (bwd && !grad_out) return fail(PSM_ERR_INVALID_ARG, "grad_out is required with grads");
-  const std::string key = tune_key(s, cams, n_cams, cfg, bwd);
-  for (const TuneKey& t : ctx->tuned) {
-    if (t.key == key) {
-      cfg->schedule = t.tu.sched;
-      cfg->bwd_schedule = t.tu.sched_bwd;
-      cfg->blend_pass = t.tu.blend_pass;
-      cfg->bwd_pass = t.tu.bwd_pass;
-      if (best_ms_out) *best_ms_out = t.ms;
-      return PSM_OK;
+  return guarded("psm_autotune", [&]() -> psm_status {
+    if (!ctx || !cfg || !out) return fail(PSM_ERR_INVALID_ARG, "ctx, cfg and out are required");
+    if (reps < 1 || reps > 1000) return fail(PSM_ERR_INVALID_ARG, "reps must be in [1, 1000]");
+    psm_status r = validate_surfels(s);
+    if (r != PSM_OK) return r;
+    r = validate_common(cams, n_cams, cfg, s->n, s->c, pair_capacity);
+    if (r != PSM_OK) return r;
+    const bool bwd = grads != nullptr;
+    if (bwd && !grad_out) return fail(PSM_ERR_INVALID_ARG, "grad_out is required with grads");
+    const std::string key = tune_key(s, cams, n_cams, cfg, bwd);
+    for (const TuneKey& t : ctx->tuned) {
+      if (t.key == key) {
+        cfg->schedule = t.tu.sched;
+        cfg->bwd_schedule = t.tu.sched_bwd;
+        cfg->blend_pass = t.tu.blend_pass;
+        cfg->bwd_pass = t.tu.bwd_pass;
+        if (best_ms_out) *best_ms_out = t.ms;
+        return PSM_OK;
+      }
     }
-  }
-  DeviceGuard dg(ctx->device);
-  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
-  hipStream_t st = (hipStream_t)stream;
-  std::vector<Tuning> cands;
-  const bool feat = s->c > 0 && cfg->blend == PSM_BLEND_TOPK;
-  for (int sched = 0; sched < 2; ++sched)
-    for (int sched_bwd = 0; sched_bwd < 2; ++sched_bwd)
-      for (int bp : {16, 32})
-        for (int gp : {16, 32}) {
-          if (!bwd && sched_bwd != 0) continue;
-          if (!feat && (bp != 32 || gp != 16)) continue;
-          if (feat && !bwd && gp != 16) continue;
-          cands.push_back(Tuning{sched, sched_bwd, bp, gp});
-        }
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-    return fail(PSM_ERR_HIP, "hipEventCreate failed");
-  Tuning best{};
-  double best_ms = 1e300;
-  psm_status res = PSM_OK;
-  for (const Tuning& tu : cands) {
-    psm_config c2 = *cfg;
-    c2.schedule = tu.sched;
-    c2.bwd_schedule = tu.sched_bwd;
-    c2.blend_pass = tu.blend_pass;
-    c2.bwd_pass = tu.bwd_pass;
-    c2.flags = (cfg->flags | PSM_FLAG_NO_SYNC) & ~PSM_FLAG_PROFILE;
-    std::vector<double> ts;
-    for (int it = 0; it <= reps && res == PSM_OK; ++it) {
-      (void)hipEventRecord(e0, st);
-      res = forward_impl(ctx, s, cams, n_cams, &c2, workspace, workspace_bytes, pair_capacity, out, stream);
-      if (res == PSM_OK && bwd)
-        res = backward_impl(ctx, s, cams, n_cams, &c2, workspace, workspace_bytes, pair_capacity, grad_out, grads,
-                            stream);
-      (void)hipEventRecord(e1, st);
-      float ms = 0.0f;
-      if (res == PSM_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-        res = fail(PSM_ERR_HIP, "autotune timing failed");
-      if (it > 0) ts.push_back(ms);
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<Tuning> cands;
+    const bool feat = s->c > 0 && cfg->blend == PSM_BLEND_TOPK;
+    for (int sched = 0; sched < 2; ++sched)
+      for (int sched_bwd = 0; sched_bwd < 2; ++sched_bwd)
+        for (int bp : {16, 32})
+          for (int gp : {16, 32}) {
+            if (!bwd && sched_bwd != 0) continue;
+            if (!feat && (bp != 32 || gp != 16)) continue;
+            if (feat && !bwd && gp != 16) continue;
+            cands.push_back(Tuning{sched, sched_bwd, bp, gp});
+          }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+      return fail(PSM_ERR_HIP, "hipEventCreate failed");
+    Tuning best{};
+    double best_ms = 1e300;
+    psm_status res = PSM_OK;
+    for (const Tuning& tu : cands) {
+      psm_config c2 = *cfg;
+      c2.schedule = tu.sched;
+      c2.bwd_schedule = tu.sched_bwd;
+      c2.blend_pass = tu.blend_pass;
+      c2.bwd_pass = tu.bwd_pass;
+      c2.flags = (cfg->flags | PSM_FLAG_NO_SYNC) & ~PSM_FLAG_PROFILE;
+      std::vector<double> ts;
+      for (int it = 0; it <= reps && res == PSM_OK; ++it) {
+        (void)hipEventRecord(e0, st);
+        res = forward_impl(ctx, s, cams, n_cams, &c2, workspace, workspace_bytes, pair_capacity, out, stream);
+        if (res == PSM_OK && bwd)
+          res = backward_impl(ctx, s, cams, n_cams, &c2, workspace, workspace_bytes, pair_capacity, grad_out, grads,
+                              stream);
+        (void)hipEventRecord(e1, st);
+        float ms = 0.0f;
+        if (res == PSM_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          res = fail(PSM_ERR_HIP, "autotune timing failed");
+        if (it > 0) ts.push_back(ms);
+      }
+      if (res != PSM_OK) break;
+      std::sort(ts.begin(), ts.end());
+      const double med = ts[ts.size() / 2];
+      if (med < best_ms) {
+        best_ms = med;
+        best = tu;
+      }
     }
-    if (res != PSM_OK) break;
-    std::sort(ts.begin(), ts.end());
-    const double med = ts[ts.size() / 2];
-    if (med < best_ms) {
-      best_ms = med;
-      best = tu;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (res != PSM_OK) return res;
-  const CamTable ct = cam_table(cams, n_cams, s->n);
-  const Layout L = make_layout(ct, cfg->k, s->c, pair_capacity);
-  uint32_t h[kStWords];
-  r = read_status(L, workspace, h, st);
-  if (r != PSM_OK) return r;
-  if (h[kStOverflow]) return capacity_error(L, h);
-  ctx->tuned.push_back(TuneKey{key, best, best_ms});
-  cfg->schedule = best.sched;
-  cfg->bwd_schedule = best.sched_bwd;
-  cfg->blend_pass = best.blend_pass;
-  cfg->bwd_pass = best.bwd_pass;
-  if (best_ms_out) *best_ms_out = best_ms;
-  g_err.clear();
-  return PSM_OK;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (res != PSM_OK) return res;
+    const CamTable ct = cam_table(cams, n_cams, s->n);
+    const Layout L = make_layout(ct, cfg->k, s->c, pair_capacity);
+    uint32_t h[kStWords];
+    r = read_status(L, workspace, h, st);
+    if (r != PSM_OK) return r;
+    if (h[kStOverflow]) return capacity_error(L, h);
+    ctx->tuned.push_back(TuneKey{key, best, best_ms});
+    cfg->schedule = best.sched;
+    cfg->bwd_schedule = best.sched_bwd;
+    cfg->blend_pass = best.blend_pass;
+    cfg->bwd_pass = best.bwd_pass;
+    if (best_ms_out) *best_ms_out = best_ms;
+    g_err.clear();
+    return PSM_OK;
+  });
 }
 
 }  // extern "C"
@@ -668,51 +752,57 @@ extern "C" {
 
 psm_status psm_instance_labels(psm_ctx* ctx, int64_t n, const float* means, const void* f_ins, int32_t f_dtype,
                                const psm_queries* q, float* labels, int32_t ld, void* stream) {
-  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
-  psm_status r = validate_queries(n, q, f_dtype);
-  if (r != PSM_OK) return r;
-  if (ld < ((q->n_q + 7) & ~7)) return fail(PSM_ERR_INVALID_ARG, "ld must be >= round_up(n_q, 8)");
-  if (n > 0 && (!means || !f_ins || !labels)) return fail(PSM_ERR_INVALID_ARG, "null surfel or label array");
-  DeviceGuard dg(ctx->device);
-  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
-  launch_labels(n, means, f_ins, f_dtype, label_queries(q), labels, ld, (hipStream_t)stream);
-  r = check_hip("psm_instance_labels launch");
-  if (r != PSM_OK) return r;
-  g_err.clear();
-  return PSM_OK;
+  return guarded("psm_instance_labels", [&]() -> psm_status {
+    if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+    psm_status r = validate_queries(n, q, f_dtype);
+    if (r != PSM_OK) return r;
+    if (ld < ((q->n_q + 7) & ~7)) return fail(PSM_ERR_INVALID_ARG, "ld must be >= round_up(n_q, 8)");
+    if (n > 0 && (!means || !f_ins || !labels)) return fail(PSM_ERR_INVALID_ARG, "null surfel or label array");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
+    launch_labels(n, means, f_ins, f_dtype, label_queries(q), labels, ld, (hipStream_t)stream);
+    r = check_hip("psm_instance_labels launch");
+    if (r != PSM_OK) return r;
+    g_err.clear();
+    return PSM_OK;
+  });
 }
 
 psm_status psm_instance_labels_workspace_size(int64_t n, const psm_queries* q, size_t* bytes_out) {
-  if (!bytes_out) return fail(PSM_ERR_INVALID_ARG, "bytes_out is null");
-  psm_status r = validate_queries(n, q, 0);
-  if (r != PSM_OK) return r;
-  *bytes_out = label_workspace_bytes(n, q->n_q, q->c);
-  return PSM_OK;
+  return guarded("psm_instance_labels_workspace_size", [&]() -> psm_status {
+    if (!bytes_out) return fail(PSM_ERR_INVALID_ARG, "bytes_out is null");
+    psm_status r = validate_queries(n, q, 0);
+    if (r != PSM_OK) return r;
+    *bytes_out = label_workspace_bytes(n, q->n_q, q->c);
+    return PSM_OK;
+  });
 }
 
 psm_status psm_instance_labels_backward(psm_ctx* ctx, int64_t n, const float* means, const void* f_ins,
                                         int32_t f_dtype, const psm_queries* q, const float* d_labels, int32_t ld,
                                         void* workspace, size_t workspace_bytes, float* d_means, float* d_f_ins,
                                         float* d_qfeat, float* d_qmean, float* d_qprec, void* stream) {
-  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
-  psm_status r = validate_queries(n, q, f_dtype);
-  if (r != PSM_OK) return r;
-  if (ld < ((q->n_q + 7) & ~7)) return fail(PSM_ERR_INVALID_ARG, "ld must be >= round_up(n_q, 8)");
-  if (n > 0 && (!means || !f_ins || !d_labels || !d_means || !d_f_ins))
-    return fail(PSM_ERR_INVALID_ARG, "null surfel-side array");
-  if (!d_qfeat || !d_qmean || !d_qprec) return fail(PSM_ERR_INVALID_ARG, "null query gradient array");
-  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
-    return fail(PSM_ERR_INVALID_ARG, "workspace must be non-null and 256-byte aligned");
-  if (workspace_bytes < label_workspace_bytes(n, q->n_q, q->c))
-    return fail(PSM_ERR_INVALID_ARG, "workspace too small");
-  DeviceGuard dg(ctx->device);
-  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
-  launch_labels_backward(n, means, f_ins, f_dtype, label_queries(q), d_labels, ld, (char*)workspace, d_means,
-                         d_f_ins, d_qfeat, d_qmean, d_qprec, (hipStream_t)stream);
-  r = check_hip("psm_instance_labels_backward launch");
-  if (r != PSM_OK) return r;
-  g_err.clear();
-  return PSM_OK;
+  return guarded("psm_instance_labels_backward", [&]() -> psm_status {
+    if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+    psm_status r = validate_queries(n, q, f_dtype);
+    if (r != PSM_OK) return r;
+    if (ld < ((q->n_q + 7) & ~7)) return fail(PSM_ERR_INVALID_ARG, "ld must be >= round_up(n_q, 8)");
+    if (n > 0 && (!means || !f_ins || !d_labels || !d_means || !d_f_ins))
+      return fail(PSM_ERR_INVALID_ARG, "null surfel-side array");
+    if (!d_qfeat || !d_qmean || !d_qprec) return fail(PSM_ERR_INVALID_ARG, "null query gradient array");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+      return fail(PSM_ERR_INVALID_ARG, "workspace must be non-null and 256-byte aligned");
+    if (workspace_bytes < label_workspace_bytes(n, q->n_q, q->c))
+      return fail(PSM_ERR_INVALID_ARG, "workspace too small");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
+    launch_labels_backward(n, means, f_ins, f_dtype, label_queries(q), d_labels, ld, (char*)workspace, d_means,
+                           d_f_ins, d_qfeat, d_qmean, d_qprec, (hipStream_t)stream);
+    r = check_hip("psm_instance_labels_backward launch");
+    if (r != PSM_OK) return r;
+    g_err.clear();
+    return PSM_OK;
+  });
 }
 
 // ------------------------------------------------------ frustum attention
@@ -732,55 +822,59 @@ static psm_status validate_attention(int64_t n, const psm_attention* a) {
 static int attention_blocks(const psm_ctx* ctx) { return std::max(64, 4 * ctx->cu_count); }
 
 psm_status psm_frustum_attention_workspace_size(psm_ctx* ctx, int64_t n, const psm_attention* a, size_t* bytes_out) {
-  if (!ctx || !bytes_out) return fail(PSM_ERR_INVALID_ARG, "ctx and bytes_out are required");
-  psm_status r = validate_attention(n, a);
-  if (r != PSM_OK) return r;
-  *bytes_out = attention_workspace_bytes(n, a->n_q, a->d, attention_blocks(ctx));
-  return PSM_OK;
+  return guarded("psm_frustum_attention_workspace_size", [&]() -> psm_status {
+    if (!ctx || !bytes_out) return fail(PSM_ERR_INVALID_ARG, "ctx and bytes_out are required");
+    psm_status r = validate_attention(n, a);
+    if (r != PSM_OK) return r;
+    *bytes_out = attention_workspace_bytes(n, a->n_q, a->d, attention_blocks(ctx));
+    return PSM_OK;
+  });
 }
 
 psm_status psm_frustum_attention(psm_ctx* ctx, int64_t n, const float* means, const float* scales,
                                  const psm_camera* cam, const psm_attention* a, void* workspace,
                                  size_t workspace_bytes, float* out, uint8_t* active, void* stream) {
-  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
-  psm_status r = validate_attention(n, a);
-  if (r != PSM_OK) return r;
-  if (!cam) return fail(PSM_ERR_INVALID_ARG, "camera is null");
-  r = validate_camera(cam);
-  if (r != PSM_OK) return r;
-  if (n > 0 && (!means || !scales)) return fail(PSM_ERR_INVALID_ARG, "null surfel array");
-  if (!out) return fail(PSM_ERR_INVALID_ARG, "out is null");
-  const int nblk = attention_blocks(ctx);
-  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
-    return fail(PSM_ERR_INVALID_ARG, "workspace must be non-null and 256-byte aligned");
-  if (workspace_bytes < attention_workspace_bytes(n, a->n_q, a->d, nblk))
-    return fail(PSM_ERR_INVALID_ARG, "workspace too small");
-  if (n > 0 && reinterpret_cast<uintptr_t>(a->feat) % 16 != 0)
-    return fail(PSM_ERR_INVALID_ARG, "feature array must be 16-byte aligned");
-  DeviceGuard dg(ctx->device);
-  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
-  AttentionArgs aa{};
-  aa.n = n;
-  aa.means = means;
-  aa.scales = scales;
-  const CamTable ct = cam_table(cam, 1, n);
-  aa.cam = ct.cam[0];
-  aa.nq = a->n_q;
-  aa.c = a->c;
-  aa.d = a->d;
-  aa.feat = a->feat;
-  aa.feat_dtype = a->feat_dtype;
-  aa.q = a->q;
-  aa.wq = a->wq;
-  aa.wk = a->wk;
-  aa.wv = a->wv;
-  aa.pos_length = a->pos_length;
-  aa.nblk = nblk;
-  launch_attention(aa, (char*)workspace, out, active, (hipStream_t)stream);
-  r = check_hip("psm_frustum_attention launch");
-  if (r != PSM_OK) return r;
-  g_err.clear();
-  return PSM_OK;
+  return guarded("psm_frustum_attention", [&]() -> psm_status {
+    if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+    psm_status r = validate_attention(n, a);
+    if (r != PSM_OK) return r;
+    if (!cam) return fail(PSM_ERR_INVALID_ARG, "camera is null");
+    r = validate_camera(cam);
+    if (r != PSM_OK) return r;
+    if (n > 0 && (!means || !scales)) return fail(PSM_ERR_INVALID_ARG, "null surfel array");
+    if (!out) return fail(PSM_ERR_INVALID_ARG, "out is null");
+    const int nblk = attention_blocks(ctx);
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+      return fail(PSM_ERR_INVALID_ARG, "workspace must be non-null and 256-byte aligned");
+    if (workspace_bytes < attention_workspace_bytes(n, a->n_q, a->d, nblk))
+      return fail(PSM_ERR_INVALID_ARG, "workspace too small");
+    if (n > 0 && reinterpret_cast<uintptr_t>(a->feat) % 16 != 0)
+      return fail(PSM_ERR_INVALID_ARG, "feature array must be 16-byte aligned");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
+    AttentionArgs aa{};
+    aa.n = n;
+    aa.means = means;
+    aa.scales = scales;
+    const CamTable ct = cam_table(cam, 1, n);
+    aa.cam = ct.cam[0];
+    aa.nq = a->n_q;
+    aa.c = a->c;
+    aa.d = a->d;
+    aa.feat = a->feat;
+    aa.feat_dtype = a->feat_dtype;
+    aa.q = a->q;
+    aa.wq = a->wq;
+    aa.wk = a->wk;
+    aa.wv = a->wv;
+    aa.pos_length = a->pos_length;
+    aa.nblk = nblk;
+    launch_attention(aa, (char*)workspace, out, active, (hipStream_t)stream);
+    r = check_hip("psm_frustum_attention launch");
+    if (r != PSM_OK) return r;
+    g_err.clear();
+    return PSM_OK;
+  });
 }
 
 // ------------------------------------------------------- geometric loss
@@ -793,58 +887,66 @@ static psm_status validate_gmm(int64_t n, const psm_gmm* g) {
 }
 
 psm_status psm_geometry_loss_workspace_size(int64_t n, const psm_gmm* g, size_t* bytes_out) {
-  if (!bytes_out) return fail(PSM_ERR_INVALID_ARG, "bytes_out is null");
-  psm_status r = validate_gmm(n, g);
-  if (r != PSM_OK) return r;
-  *bytes_out = geometry_workspace_bytes(n, g->k);
-  return PSM_OK;
+  return guarded("psm_geometry_loss_workspace_size", [&]() -> psm_status {
+    if (!bytes_out) return fail(PSM_ERR_INVALID_ARG, "bytes_out is null");
+    psm_status r = validate_gmm(n, g);
+    if (r != PSM_OK) return r;
+    *bytes_out = geometry_workspace_bytes(n, g->k);
+    return PSM_OK;
+  });
 }
 
 psm_status psm_geometry_loss(psm_ctx* ctx, int64_t n, const float* means, const float* scales, const float* quats,
                              const psm_gmm* g, float lambda_n, void* workspace, size_t workspace_bytes,
                              double* losses, int32_t* assign, float* d_means, float* d_scales, float* d_quats,
                              void* stream) {
-  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
-  psm_status r = validate_gmm(n, g);
-  if (r != PSM_OK) return r;
-  if (!losses) return fail(PSM_ERR_INVALID_ARG, "losses is null");
-  if (n > 0 && (!means || !scales || !quats || !d_means || !d_scales || !d_quats))
-    return fail(PSM_ERR_INVALID_ARG, "null surfel or gradient array");
-  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
-    return fail(PSM_ERR_INVALID_ARG, "workspace must be non-null and 256-byte aligned");
-  if (workspace_bytes < geometry_workspace_bytes(n, g->k)) return fail(PSM_ERR_INVALID_ARG, "workspace too small");
-  DeviceGuard dg(ctx->device);
-  if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
-  GeometryArgs a{n, means, scales, quats, g->k, g->mean, g->cov, g->weight, lambda_n, losses, assign,
-                 d_means, d_scales, d_quats};
-  launch_geometry_loss(a, (char*)workspace, (hipStream_t)stream);
-  r = check_hip("psm_geometry_loss launch");
-  if (r != PSM_OK) return r;
-  g_err.clear();
-  return PSM_OK;
+  return guarded("psm_geometry_loss", [&]() -> psm_status {
+    if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+    psm_status r = validate_gmm(n, g);
+    if (r != PSM_OK) return r;
+    if (!losses) return fail(PSM_ERR_INVALID_ARG, "losses is null");
+    if (n > 0 && (!means || !scales || !quats || !d_means || !d_scales || !d_quats))
+      return fail(PSM_ERR_INVALID_ARG, "null surfel or gradient array");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+      return fail(PSM_ERR_INVALID_ARG, "workspace must be non-null and 256-byte aligned");
+    if (workspace_bytes < geometry_workspace_bytes(n, g->k)) return fail(PSM_ERR_INVALID_ARG, "workspace too small");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
+    GeometryArgs a{n, means, scales, quats, g->k, g->mean, g->cov, g->weight, lambda_n, losses, assign,
+                   d_means, d_scales, d_quats};
+    launch_geometry_loss(a, (char*)workspace, (hipStream_t)stream);
+    r = check_hip("psm_geometry_loss launch");
+    if (r != PSM_OK) return r;
+    g_err.clear();
+    return PSM_OK;
+  });
 }
 
 psm_status psm_profile_read(psm_ctx* ctx, int32_t stage, const char** name_out, double* total_ms_out,
                             int64_t* calls_out) {
-  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
-  if (stage < 0 || stage >= kNumStages) return fail(PSM_ERR_INVALID_ARG, "stage out of range");
-  DeviceGuard dg(ctx->device);
-  if (!ctx->prof.collect()) return fail(PSM_ERR_HIP, "profile events could not be read");
-  if (name_out) *name_out = kStageNames[stage];
-  if (total_ms_out) *total_ms_out = ctx->prof.total_ms[stage];
-  if (calls_out) *calls_out = ctx->prof.calls[stage];
-  return PSM_OK;
+  return guarded("psm_profile_read", [&]() -> psm_status {
+    if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+    if (stage < 0 || stage >= kNumStages) return fail(PSM_ERR_INVALID_ARG, "stage out of range");
+    DeviceGuard dg(ctx->device);
+    if (!ctx->prof.collect()) return fail(PSM_ERR_HIP, "profile events could not be read");
+    if (name_out) *name_out = kStageNames[stage];
+    if (total_ms_out) *total_ms_out = ctx->prof.total_ms[stage];
+    if (calls_out) *calls_out = ctx->prof.calls[stage];
+    return PSM_OK;
+  });
 }
 
 psm_status psm_profile_reset(psm_ctx* ctx) {
-  if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
-  DeviceGuard dg(ctx->device);
-  const bool ok = ctx->prof.collect();
-  for (int s = 0; s < kNumStages; ++s) {
-    ctx->prof.total_ms[s] = 0.0;
-    ctx->prof.calls[s] = 0;
-  }
-  return ok ? PSM_OK : fail(PSM_ERR_HIP, "profile events could not be read");
+  return guarded("psm_profile_reset", [&]() -> psm_status {
+    if (!ctx) return fail(PSM_ERR_INVALID_ARG, "ctx is null");
+    DeviceGuard dg(ctx->device);
+    const bool ok = ctx->prof.collect();
+    for (int s = 0; s < kNumStages; ++s) {
+      ctx->prof.total_ms[s] = 0.0;
+      ctx->prof.calls[s] = 0;
+    }
+    return ok ? PSM_OK : fail(PSM_ERR_HIP, "profile events could not be read");
+  });
 }
 
 }  // extern "C"

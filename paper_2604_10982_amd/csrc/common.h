@@ -46,7 +46,14 @@ enum : int {
   kStBlended = 14, // 64-bit: blended (pixel, surfel) pairs
   kStQueue = 16,   // 16 .. 19: work-queue heads of the persistent tile kernels
   kStWide = 20,    // tiles the Top-K blend left to its windowed pass
-  kStWords = 21
+  kStBwdEntries = 21,  // 64-bit: sum over pixels of n_last (list entries the backward walk must evaluate)
+  kStSigLo = 23,   // layout the forward ran with: total bytes (64-bit), pair capacity, tiles
+  kStSigHi = 24,
+  kStSigCap = 25,
+  kStSigTiles = 26,
+  kStUnique = 27,  // 64-bit, written by the stats read-back: distinct selected virtual surfels
+  kStSelected = 29,  // 64-bit, written by the stats read-back: (pixel, slot) selections
+  kStWords = 31
 };
 enum : int { kQWalk = 0, kQBlend = 1, kQFeatBwd = 2, kQWalkBwd = 3 };
 // Radix sort tiling.
@@ -118,7 +125,7 @@ struct Layout {
   int64_t n, nreal, cap, tiles, spix;  // n = virtual surfels; spix = tiles * 256 (tile-major pixels)
   int k, c, ncam;
   size_t rec, fp, ext, key0, key1, id0, id1, vbase, count, offs, cull, ptile0, ptile1, eid0, eid1, sid_emit, pid, ranges,
-      torder0, wide, nlast, tfinal, selpos, selw, seldot, gflag, fflag, gpart, fpart, hist, bsum,
+      torder0, wide, nlast, tfinal, selpos, selw, seldot, gflag, fflag, gpart, fpart, hist, bsum, ubits,
       status, total;
 };
 
@@ -135,6 +142,7 @@ inline Layout make_layout(const CamTable& ct, int k, int c, int64_t cap) {
   const int64_t n1 = L.n > 0 ? L.n : 1, cap1 = cap > 0 ? cap : 1, t1 = L.tiles > 0 ? L.tiles : 1;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+  L.status = take(kStWords * 4);  // first, so a read-back can check the layout before any other access
   L.rec = take(n1 * 16 * kRecWords);  // walk record
   L.fp = take(n1 * 48);           // footprint floats, 12
   L.ext = take(n1 * 16);          // ellipse centre and half-extents (x, y), for band culling
@@ -170,7 +178,7 @@ inline Layout make_layout(const CamTable& ct, int k, int c, int64_t cap) {
   const int64_t nb = cdiv(big, kSortTile);
   L.hist = take((256 * nb + 256) * 4);
   L.bsum = take((cdiv(n1, kScanTile) + 1) * 8);
-  L.status = take(kStWords * 4);
+  L.ubits = take(cdiv(n1, 32) * 4);  // one bit per virtual surfel: selected somewhere (stats read-back)
   L.total = o;
   return L;
 }

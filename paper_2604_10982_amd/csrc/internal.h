@@ -53,7 +53,7 @@ enum : int { kSchedGrid = 0, kSchedPersistent = 1 };
 
 // keystage.hip
 void launch_fill_u32(void* p, uint32_t v, int64_t count, hipStream_t st);
-void launch_init_status(uint32_t* status, int64_t n, int64_t tiles, hipStream_t st);
+void launch_init_status(uint32_t* status, const Layout& L, hipStream_t st);
 void launch_preprocess(const SurfelArgs& s, const CamTable& ct, int mode, bool opacity_foot, bool lowpass,
                        const Layout& L,
                        char* ws, hipStream_t st);
@@ -90,6 +90,9 @@ void launch_feature_blend(const SurfelArgs& s, const Layout& L, const CamTable& 
                           float* out_feat, bool renorm, bool lowpass, char* ws, hipStream_t st);
 void launch_export_selection(const Layout& L, const CamTable& ct, char* ws, int32_t* sel_id, float* sel_w,
                              int32_t* n_last, float* t_final, hipStream_t st);
+// Counts the distinct selected virtual surfels and the (pixel, slot)
+// selections of the last Top-K forward into the status words.
+void launch_count_selected(const Layout& L, char* ws, hipStream_t st);
 
 // labels.hip: instance labels of surfels from localized queries
 struct LabelQueries {

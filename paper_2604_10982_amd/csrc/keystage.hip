@@ -258,9 +258,16 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t count) 
   for (int64_t j = i; j < count; j += stride) p[j] = v;
 }
 
-__global__ void k_init_status(uint32_t* __restrict__ st, uint32_t n, uint32_t tiles) {
+__global__ void k_init_status(uint32_t* __restrict__ st, uint32_t n, uint32_t tiles, uint64_t total, uint32_t cap) {
   const int i = threadIdx.x;
-  if (i < kStWords) st[i] = (i == kStN) ? n : (i == kStTiles) ? tiles : 0u;
+  uint32_t v = 0u;
+  v = i == kStN ? n : v;
+  v = i == kStTiles ? tiles : v;
+  v = i == kStSigLo ? (uint32_t)total : v;
+  v = i == kStSigHi ? (uint32_t)(total >> 32) : v;
+  v = i == kStSigCap ? cap : v;
+  v = i == kStSigTiles ? tiles : v;
+  if (i < kStWords) st[i] = v;
 }
 
 // Thread per virtual surfel v = b * N + i (surfel i seen by camera b).
@@ -502,8 +509,10 @@ void launch_fill_u32(void* p, uint32_t v, int64_t count, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t*)p, v, count);
 }
 
-void launch_init_status(uint32_t* status, int64_t n, int64_t tiles, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, st, status, (uint32_t)n, (uint32_t)tiles);
+void launch_init_status(uint32_t* status, const Layout& L, hipStream_t st) {
+  static_assert(kStWords <= 64, "status words are written by one wave");
+  hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, st, status, (uint32_t)L.n, (uint32_t)L.tiles,
+                     (uint64_t)L.total, (uint32_t)L.cap);
 }
 
 void launch_preprocess(const SurfelArgs& s, const CamTable& ct, int mode, bool opacity_foot, bool lowpass,

@@ -174,15 +174,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   nlast[sp] = (uint32_t)last;
   tfinal[sp] = T;
   {
-    int wsum = walked, bsum = blended;
+    int wsum = walked, bsum = blended, lsum = last;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       wsum += __shfl_xor(wsum, o, 64);
       bsum += __shfl_xor(bsum, o, 64);
+      lsum += __shfl_xor(lsum, o, 64);
     }
     if ((tid & 63) == 0) {
       atomicAdd(reinterpret_cast<unsigned long long*>(status + kStWalked), (unsigned long long)wsum);
       atomicAdd(reinterpret_cast<unsigned long long*>(status + kStBlended), (unsigned long long)bsum);
+      atomicAdd(reinterpret_cast<unsigned long long*>(status + kStBwdEntries), (unsigned long long)lsum);
     }
   }
   if (inside) {
@@ -520,6 +522,44 @@ __global__ __launch_bounds__(256) void k_export_sel(const uint32_t* __restrict__
   if (o_tf) o_tf[pix] = tfinal[tile * kTilePix + tid];
 }
 
+// Marks the virtual surfel of every held selection in a bitmap (block per
+// tile, thread per pixel) and counts the selections; k_count_bits then counts
+// the marked surfels.  Stats read-back only, not part of a render.
+__global__ __launch_bounds__(256) void k_mark_selected(const uint32_t* __restrict__ pid,
+                                                       const uint2* __restrict__ ranges,
+                                                       const int32_t* __restrict__ selpos, int K,
+                                                       uint32_t* __restrict__ bits, uint32_t* __restrict__ status) {
+  const int tile = blockIdx.x;
+  const int tid = threadIdx.x;
+  const uint2 rg = ranges[tile];
+  const uint32_t start = rg.x;
+  const int len = (int)(rg.y - rg.x);
+  int held = 0;
+  for (int q = 0; q < K; ++q) {
+    const int pos = selpos[((size_t)tile * K + q) * kTilePix + tid];
+    if (pos >= 0 && pos < len) {  // a position outside the list (no Top-K forward ran) is not followed
+      const uint32_t v = pid[start + pos];
+      atomicOr(bits + (v >> 5), 1u << (v & 31u));
+      ++held;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) held += __shfl_xor(held, o, 64);
+  if ((tid & 63) == 0 && held)
+    atomicAdd(reinterpret_cast<unsigned long long*>(status + kStSelected), (unsigned long long)held);
+}
+
+__global__ __launch_bounds__(256) void k_count_bits(const uint32_t* __restrict__ bits, int64_t words,
+                                                    uint32_t* __restrict__ status) {
+  int cnt = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (int64_t)gridDim.x * 256)
+    cnt += __popc(bits[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if ((threadIdx.x & 63) == 0 && cnt)
+    atomicAdd(reinterpret_cast<unsigned long long*>(status + kStUnique), (unsigned long long)cnt);
+}
+
 // ------------------------------------------------------------- host wrappers
 template <int KMAX, bool TOPK, bool PERSIST, bool LP, bool KFULL>
 static void walk_launch_k(const Layout& L, const CamTable& ct, const Tuning& tu, const ImageArgs& out,
@@ -633,6 +673,20 @@ void launch_feature_blend(const SurfelArgs& s, const Layout& L, const CamTable& 
   if (s.dtype == kF32) blend_launch<float>(s, L, ct, blend, tu, out_feat, renorm, lowpass, ws, st);
   else if (s.dtype == kF16) blend_launch<__half>(s, L, ct, blend, tu, out_feat, renorm, lowpass, ws, st);
   else blend_launch<uint16_t>(s, L, ct, blend, tu, out_feat, renorm, lowpass, ws, st);
+}
+
+void launch_count_selected(const Layout& L, char* ws, hipStream_t st) {
+  uint32_t* status = (uint32_t*)(ws + L.status);
+  const int64_t words = cdiv(L.n > 0 ? L.n : 1, 32);
+  launch_fill_u32(ws + L.ubits, 0u, words, st);
+  launch_fill_u32(status + kStUnique, 0u, 4, st);
+  if (L.tiles == 0) return;
+  hipLaunchKernelGGL(k_mark_selected, dim3((unsigned)L.tiles), dim3(256), 0, st, (const uint32_t*)(ws + L.pid),
+                     (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos), L.k, (uint32_t*)(ws + L.ubits),
+                     status);
+  const int64_t blocks = std::min<int64_t>(1024, cdiv(words, 256));
+  hipLaunchKernelGGL(k_count_bits, dim3((unsigned)blocks), dim3(256), 0, st, (const uint32_t*)(ws + L.ubits), words,
+                     status);
 }
 
 void launch_export_selection(const Layout& L, const CamTable& ct, char* ws, int32_t* sel_id, float* sel_w,

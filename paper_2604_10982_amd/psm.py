@@ -99,7 +99,8 @@ class Grads(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("visible", C.c_int64), ("culled", C.c_int64 * 5), ("pairs", C.c_int64),
                 ("pairs_required", C.c_int64), ("pair_capacity", C.c_int64), ("tiles", C.c_int64),
-                ("pairs_walked", C.c_int64), ("contributors", C.c_int64)]
+                ("pairs_walked", C.c_int64), ("contributors", C.c_int64), ("bwd_entries", C.c_int64),
+                ("selected_unique", C.c_int64), ("selections", C.c_int64)]
 
 
 _lib = None
@@ -299,17 +300,27 @@ def backward_into(ctx: Context, s: Surfels, cam: Camera, cfg: Config, ws: Worksp
                               ws.capacity, C.byref(g), C.byref(gr), st), "psm_backward")
 
 
+def launch_config(k: int, tile_mode="ellipse", blend="topk", flags: int = 0, launch=None) -> Config:
+    """Config with the launch choices ``launch`` = (schedule, bwd_schedule,
+    blend_pass, bwd_pass), or the defaults (grid schedules, default passes)."""
+    if launch is None:
+        return config_struct(k, tile_mode, blend, flags)
+    sched, bsched, bp, fp = (int(v) for v in launch)
+    return config_struct(k, tile_mode, blend, flags, sched, bp, fp, bsched)
+
+
 def forward(means, scales, quats, opacity, rgb, feat, camera, k=16, tile_mode="ellipse", blend="topk",
-            capacity: int | None = None, ws: Workspace | None = None, flags: int = 0):
+            capacity: int | None = None, ws: Workspace | None = None, flags: int = 0, launch=None):
     """Render; returns (images dict, workspace).  The workspace holds the
     state the backward needs.  Re-allocates once if the pairs do not fit.
     ``flags``: FLAG_* options of the key stage and the walks (e.g.
-    FLAG_OPACITY_FOOTPRINT); the backward takes the same flags."""
+    FLAG_OPACITY_FOOTPRINT); the backward takes the same flags.  ``launch``:
+    (schedule, bwd_schedule, blend_pass, bwd_pass), see launch_config."""
     device = means.device
     ctx = context(device.index or 0)
     s = _surfels(means, scales, quats, opacity, rgb, feat)
     cam = camera if isinstance(camera, Camera) else camera_struct(camera)
-    cfg = config_struct(k, tile_mode, blend, flags)
+    cfg = launch_config(k, tile_mode, blend, flags, launch)
     out = alloc_images(cam, s.c, device, feature_only=bool(flags & FLAG_FEATURE_ONLY))
     cap = capacity if capacity is not None else (ws.capacity if ws is not None else capacity_guess(s.n, cam))
     for attempt in range(3):
@@ -326,12 +337,12 @@ def forward(means, scales, quats, opacity, rgb, feat, camera, k=16, tile_mode="e
 
 
 def backward(means, scales, quats, opacity, rgb, feat, camera, ws: Workspace, gout: dict, k=16,
-             tile_mode="ellipse", blend="topk", flags: int = 0) -> dict:
+             tile_mode="ellipse", blend="topk", flags: int = 0, launch=None) -> dict:
     device = means.device
     ctx = context(device.index or 0)
     s = _surfels(means, scales, quats, opacity, rgb, feat)
     cam = camera if isinstance(camera, Camera) else camera_struct(camera)
-    cfg = config_struct(k, tile_mode, blend, flags)
+    cfg = launch_config(k, tile_mode, blend, flags, launch)
     n = s.n
     z = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=device)
     grads = {"means": z(n, 3), "scales": z(n, 2), "quats": z(n, 4), "opacity": z(n), "rgb": z(n, 3),

@@ -39,11 +39,50 @@ def stored_feat(t):
     return t["feat"].float().cpu().numpy().astype(np.float64)
 
 
-def render(t, cam, K, tile_mode="ellipse", blend="topk", capacity=None):
+# Launch choices (schedule, bwd_schedule, blend_pass, bwd_pass).  BENCH_LAUNCH
+# is what the autotuner picks for the 1080p benchmark steps (persistent
+# longest-first forward and backward, Top-K blend pass 32, feature-adjoint
+# pass 16); GRID_LAUNCH takes every other choice (grid schedules, pass 16 /
+# 32), so a test that renders both covers each kernel's variants.
+BENCH_LAUNCH = (1, 1, 32, 16)
+GRID_LAUNCH = (0, 0, 16, 32)
+
+
+def render(t, cam, K, tile_mode="ellipse", blend="topk", capacity=None, launch=None):
     out, ws = psm.forward(t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"], cam, K,
-                          tile_mode, blend, capacity=capacity)
+                          tile_mode, blend, capacity=capacity, launch=launch)
     torch.cuda.synchronize()
     return out, ws
+
+
+def tile_pixels(tiles, cam):
+    """Flat pixel indices of the listed 16x16 tiles, ascending."""
+    ntx = (cam.width + 15) // 16
+    pix = []
+    for tt in tiles:
+        ty, tx = divmod(int(tt), ntx)
+        ys, xs = np.mgrid[ty * 16:min(ty * 16 + 16, cam.height), tx * 16:min(tx * 16 + 16, cam.width)]
+        pix.append((ys * cam.width + xs).ravel())
+    return np.unique(np.concatenate(pix)).astype(np.int64) if pix else np.zeros(0, np.int64)
+
+
+def stratified_picks(count, rng, per=16, cap=None):
+    """Surfels drawn across the whole distribution of pairs per surfel: `per`
+    each from the lightest (1-2 pairs), the middle (between the median and the
+    90th percentile), the heavy (90th-99th), the heaviest 1% and those with
+    more than 64 pairs (longer than one 64-pair batch of the reductions);
+    `cap` bounds the pairs of a pick (the oracle renders its tiles)."""
+    nz = count[count > 0]
+    q50, q90, q99 = np.percentile(nz, [50, 90, 99])
+    top = count <= (cap if cap is not None else count.max())
+    bands = [(count > 0) & (count <= 2), (count > q50) & (count <= q90), (count > q90) & (count <= q99),
+             (count > q99) & top, (count > 64) & top]
+    picks = []
+    for b in bands:
+        cand = np.nonzero(b)[0]
+        if cand.size:
+            picks.append(rng.choice(cand, min(per, cand.size), replace=False))
+    return np.unique(np.concatenate(picks))
 
 
 def np_out(out):

@@ -140,3 +140,39 @@ def test_panoptic_render_one_walk(orc):
         rms = np.sqrt(np.mean(r ** 2))
         err = np.abs(g - r) / np.maximum(np.abs(r), 1e-2 * rms)
         assert float(err.max()) <= 1e-3, float(err.max())
+
+
+def test_labels_full_size_1m():
+    """The benchmark's shape: labels of the 1M-surfel plane scene from 64
+    queries with 32-d instance features.  Labels are per surfel, so a 20k
+    sample is checked against the oracle; the query gradients sum over all
+    surfels and are checked whole."""
+    require_gpu()
+    sc, _, _, _ = scenes.config("planes1m_1080p")
+    n, nq, c = sc.n, 64, 32
+    rng = np.random.default_rng(3)
+    f_ins = (rng.standard_normal((n, c)) * 3.0 / np.sqrt(c)).astype(np.float32)
+    qf = (rng.standard_normal((nq, c)) * 3.0 / np.sqrt(c)).astype(np.float32)
+    qm = np.c_[rng.uniform(-12, 12, nq), rng.uniform(-6, 1.6, nq), rng.uniform(2, 60, nq)].astype(np.float32)
+    qp = np.tile(np.array([0.25, 0, 0, 0.25, 0, 0.25], np.float32), (nq, 1))
+    args = (T(sc.means), T(f_ins), T(qf), T(qm), T(qp))
+    lab = psm.instance_labels(*args)
+    ld = psm.label_width(nq)
+    up = rng.standard_normal((n, nq)).astype(np.float32)
+    dl = torch.zeros(n, ld, device=DEV)
+    dl[:, :nq] = T(up)
+    got = psm.instance_labels_backward(*args, dl, ld)
+    torch.cuda.synchronize()
+    idx = np.sort(rng.choice(n, 20_000, replace=False))
+    ref = LB.forward(f_ins[idx], sc.means[idx], qf, qm, qp)["labels"]
+    np.testing.assert_allclose(lab.cpu().numpy()[idx, :nq].astype(np.float64), ref, rtol=2e-5, atol=2e-6)
+    rb = LB.backward(f_ins, sc.means, qf, qm, qp, up)
+    for key, rk, rows in (("means", "p_g", idx), ("f_ins", "f_g", idx), ("q_feat", "f_q", None),
+                          ("q_mean", "mu_q", None), ("q_prec", "prec", None)):
+        g = got[key].cpu().numpy().astype(np.float64)
+        r = rb[rk]
+        if rows is not None:
+            g, r = g[rows], r[rows]
+        rms = np.sqrt(np.mean(r ** 2))
+        err = np.abs(g - r) / np.maximum(np.abs(r), 1e-2 * rms)
+        assert float(err.max()) <= 1e-3, (key, float(err.max()))

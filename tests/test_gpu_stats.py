@@ -1,0 +1,72 @@
+"""Counters of psm_read_stats against the saved per-pixel state, and the
+workspace-layout check of the read-backs."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import BENCH_LAUNCH, render, require_gpu, to_dev
+from paper_2604_10982_amd import psm, scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("launch", [None, BENCH_LAUNCH])
+def test_stats_match_saved_selection(launch):
+    require_gpu()
+    sc = scenes.planes7(20_000, 16, seed=5)
+    cam = scenes.pinhole(328, 200)
+    K = 8
+    t = to_dev(sc)
+    out, ws = render(t, cam, K, launch=launch)
+    cs = psm.camera_struct(cam)
+    cfg = psm.launch_config(K, launch=launch)
+    st = psm.read_stats(ws, sc.n, cs, cfg, sc.c, ws.capacity)
+    sel = psm.read_selection(ws, cs, cfg)
+    sid = sel["sel_id"].cpu().numpy()
+    nl = sel["n_last"].cpu().numpy().astype(np.int64)
+    assert st.bwd_entries == nl.sum()
+    assert st.selections == (sid >= 0).sum()
+    assert st.selected_unique == np.unique(sid[sid >= 0]).size
+    assert 0 < st.selected_unique <= st.visible
+    assert st.contributors <= st.bwd_entries <= st.pairs_walked
+    # counting twice gives the same numbers (the bitmap is cleared each time)
+    st2 = psm.read_stats(ws, sc.n, cs, cfg, sc.c, ws.capacity)
+    assert (st2.selected_unique, st2.selections) == (st.selected_unique, st.selections)
+
+
+def test_stats_dense_blend_has_no_selection_counts():
+    require_gpu()
+    sc = scenes.planes7(5_000, 8, seed=2)
+    cam = scenes.pinhole(160, 96)
+    t = to_dev(sc)
+    _, ws = render(t, cam, 4, "ellipse", "full")
+    st = psm.read_stats(ws, sc.n, psm.camera_struct(cam), psm.config_struct(4, "ellipse", "full"), sc.c,
+                        ws.capacity)
+    assert st.selected_unique == -1 and st.selections == -1
+    assert st.bwd_entries > 0
+
+
+def test_read_backs_reject_another_layout():
+    """A read-back whose arguments describe another workspace layout than the
+    forward's (capacity, k, camera, n) is refused before it reads anything
+    but the status block."""
+    require_gpu()
+    sc = scenes.planes7(5_000, 8, seed=2)
+    cam = scenes.pinhole(160, 96)
+    t = to_dev(sc)
+    _, ws = render(t, cam, 4)
+    cs = psm.camera_struct(cam)
+    cfg = psm.config_struct(4)
+    psm.read_stats(ws, sc.n, cs, cfg, sc.c, ws.capacity)
+    for args in ((sc.n, cs, cfg, sc.c, ws.capacity + 4096), (sc.n, cs, psm.config_struct(8), sc.c, ws.capacity),
+                 (sc.n, psm.camera_struct(scenes.pinhole(320, 96)), cfg, sc.c, ws.capacity),
+                 (sc.n // 2, cs, cfg, sc.c, ws.capacity)):
+        with pytest.raises(psm.PsmError) as e:
+            psm.read_stats(ws, *args)
+        assert e.value.status == psm.ERR_INVALID_ARG
+    big = psm.Workspace(ws.buf, ws.capacity + 4096, ws.n, ws.c, ws.k)
+    with pytest.raises(psm.PsmError):
+        psm.read_pairs(big, cs, cfg)
+    with pytest.raises(psm.PsmError):
+        psm.read_selection(big, cs, psm.config_struct(4))
+    torch.cuda.synchronize()

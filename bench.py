@@ -54,6 +54,12 @@ def parse():
     ap.add_argument("--launch", default=None,
                     help="schedule,bwd_schedule,blend_pass,bwd_pass for the headline form "
                          "(default: the library's autotuner)")
+    ap.add_argument("--table", action="store_true",
+                    help="the configuration table: every configuration on the tile-mode x blend grid, quality "
+                         "proxy, oracle timings (one JSON line)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time only the headline fwd+bwd step (for profiler runs: every kernel of the run is "
+                         "one of its dispatches)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -482,6 +488,120 @@ def cpu_baseline(sc, cam, K, feat64, tiles):
             "sample_seconds": {"prepare": t_prep, "fwd": t_fwd, "bwd": t_bwd}, "est_frame_s": frame}
 
 
+TABLE_CONFIGS = (("c1_box2k", False), ("c2_planes200k", False), ("c3_planes500k", True),
+                 ("c4_street1m", True), ("room_1296x968", True))
+TABLE_GRID = (("sphere", "full"), ("aabb", "full"), ("ellipse", "full"),
+              ("sphere", "topk"), ("aabb", "topk"), ("ellipse", "topk"))
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
+def table_cpu_leg(sc, cam, K, feat64, name, bwd):
+    """The FP64 oracle (as it stands) on the configuration: the whole frame
+    for the two small configurations (all threads, then one), forward and,
+    where the configuration has one, backward; a sample of 200 random tiles
+    for the large ones, scaled to the frame as in cpu_baseline."""
+    from oracle import oracle as O
+    from paper_2604_10982_amd import scenes
+    threads = O.num_threads()
+    out = {"threads": threads}
+    if name in ("c1_box2k", "c2_planes200k"):
+        for label, nt in (("all_threads", threads), ("one_thread", 1)):
+            O.set_threads(nt)
+            t0 = time.perf_counter()
+            O.render(sc, cam, K, O.TOPK, feat=feat64)
+            out[label] = {"threads": nt, "fwd_s": time.perf_counter() - t0}
+            if bwd or name == "c1_box2k":
+                g = scenes.upstream(cam.height, cam.width, sc.c, seed=1)
+                t0 = time.perf_counter()
+                O.backward(sc, cam, g, K=K, blend=O.TOPK, feat=feat64)
+                out[label]["bwd_s"] = time.perf_counter() - t0
+        O.set_threads(threads)
+        out["kind"] = "whole frame"
+        return out
+    r = cpu_baseline(sc, cam, K, feat64, 200)
+    out.update({"kind": "sample", "est_frame_s": r["est_frame_s"], "sample": r["sample"]})
+    return out
+
+
+def run_table(psm, scenes, steps, warmup, with_cpu):
+    """Every configuration on the {dense, Top-K} x {square, AABB, ellipse}
+    grid: forward FPS, fwd+bwd it/s where the configuration has a backward,
+    pairs and work counters, every stage against its roofline, the quality
+    proxy of the Top-K blend against the dense blend, and the oracle timed on
+    the host cores."""
+    import numpy as np
+    import torch
+    device = torch.device("cuda:0")
+    res = {"host_cpu": host_cpu(), "configs": {}}
+    for name, bwd in TABLE_CONFIGS:
+        sc, cam, K, dtype = scenes.config(name)
+        tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
+        fbytes = {"f32": 4, "f16": 2, "bf16": 2}[dtype]
+        t = {k: torch.tensor(getattr(sc, k), device=device) for k in ("means", "scales", "quats", "opacity", "rgb")}
+        t["feat"] = torch.tensor(sc.feat, device=device).to(tdt).contiguous()
+        g = scenes.upstream(cam.height, cam.width, sc.c, seed=1)
+        gout = {k: torch.tensor(v, device=device) for k, v in g.items()}
+        del g
+        S = cam.width * cam.height
+        entry = {"surfels": sc.n, "width": cam.width, "height": cam.height, "feat_dim": sc.c, "dtype": dtype, "k": K,
+                 "rows": {}}
+        feats = {}
+        for tm, bl in TABLE_GRID:
+            f = Form(psm, t, cam, K, tm, bl, gout, device, tune=True)
+            ms_fwd, st_fwd, st = timed(f, False, steps, warmup)
+            row = {"launch": f.launch(), "fwd_ms": ms_fwd, "fwd_fps": 1000.0 / ms_fwd, "pairs": int(st.pairs),
+                   "pairs_per_tile": st.pairs / st.tiles, "pairs_walked": int(st.pairs_walked),
+                   "contributors": int(st.contributors), "selected_unique": int(st.selected_unique),
+                   "selections": int(st.selections), "bwd_entries": int(st.bwd_entries)}
+            stages = st_fwd
+            if bwd:
+                ms_step, stages, _ = timed(f, True, steps, warmup)
+                row.update({"fwd_bwd_ms": ms_step, "fwd_bwd_its": 1000.0 / ms_step,
+                            "step_hbm_frac": step_bytes(st, K, sc.c, fbytes, S) / (ms_step * 1e-3) / 1e9
+                            / HBM_PEAK_GBS})
+            row["stage_roofline"] = stage_table(stages, st, K, sc.c, fbytes, S)
+            if tm == "ellipse":
+                f.step(False)
+                feats[bl] = f.out["feat"].clone()
+            entry["rows"][f"{bl}/{tm}"] = row
+            print(f"[table] {name} {bl}/{tm}: fwd {ms_fwd:.3f} ms" + (f", fwd+bwd {row['fwd_bwd_ms']:.3f} ms"
+                  if bwd else "") + f", pairs {st.pairs}", file=sys.stderr, flush=True)
+            del f
+            torch.cuda.empty_cache()
+        fk, ff = feats["topk"].reshape(-1, sc.c), feats["full"].reshape(-1, sc.c)
+        covered = ff.abs().sum(1) > 0
+        entry["quality_proxy"] = {
+            "rel_l2_topk_vs_full": float((fk - ff).norm() / ff.norm()),
+            "argmax_agreement": float((fk[covered].argmax(1) == ff[covered].argmax(1)).float().mean()),
+            "pixels": int(covered.sum())}
+        entry["headline_factor"] = {
+            "fwd": entry["rows"]["full/aabb"]["fwd_ms"] / entry["rows"]["topk/ellipse"]["fwd_ms"]}
+        if bwd:
+            entry["headline_factor"]["fwd_bwd"] = (entry["rows"]["full/aabb"]["fwd_bwd_ms"]
+                                                   / entry["rows"]["topk/ellipse"]["fwd_bwd_ms"])
+        del feats, fk, ff
+        if with_cpu:
+            feat64 = t["feat"].float().cpu().numpy().astype(np.float64)
+            entry["oracle"] = table_cpu_leg(sc, cam, K, feat64, name, bwd)
+            del feat64
+        res["configs"][name] = entry
+        del t, gout
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -500,6 +620,9 @@ def main():
         raise SystemExit("bench.py needs a HIP device")
     device = torch.device("cuda:0")
     psm.lib()
+    if args.table:
+        print(json.dumps(run_table(psm, scenes, max(3, args.steps // 2), 2, not args.no_cpu_baseline)), flush=True)
+        return
     sc, cam, K, dtype = scenes.config(args.workload)
     tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
     t = {k: torch.tensor(getattr(sc, k), device=device) for k in ("means", "scales", "quats", "opacity", "rgb")}
@@ -516,6 +639,11 @@ def main():
     print(f"[bench] launch choice (schedule, bwd_schedule, blend_pass, bwd_pass): {head.launch()}", file=sys.stderr, flush=True)
     ms_step, stages, st = timed(head, True, args.steps, args.warmup)
     print(f"[bench] topk+ellipse fwd+bwd {ms_step:.3f} ms", file=sys.stderr, flush=True)
+    if args.headline_only:
+        print(json.dumps({"workload": args.workload, "ms_per_step": ms_step, "steps": args.steps,
+                          "warmup": args.warmup, "launch": head.launch(), "stages_ms": stages,
+                          "stage_roofline": stage_table(stages, st, K, sc.c, fbytes, S)}), flush=True)
+        return
     ms_fwd, stages_fwd, _ = timed(head, False, args.steps, args.warmup)
     print(f"[bench] topk+ellipse fwd {ms_fwd:.3f} ms", file=sys.stderr, flush=True)
     head_launch = head.launch()

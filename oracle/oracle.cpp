@@ -885,6 +885,16 @@ void orc_decisions(int64_t n, const float* means, const float* scales, const flo
   }
 }
 
+// Threads of the OpenMP loops from now on (timing on a given number of host
+// cores); no effect on any result.
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -35,9 +35,9 @@ def build(force: bool = True) -> str:
     """Compile liboracle.so (g++, FP64 model + FP32 key stage, OpenMP)."""
     if force or not os.path.exists(LIB_PATH):
         cmd = ["g++", "-std=c++17", "-O3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-               "-fPIC", "-shared", SRC, "-o", LIB_PATH + ".tmp"]
+               "-fPIC", "-shared", SRC, "-o", f"{LIB_PATH}.tmp{os.getpid()}"]
         subprocess.run(cmd, check=True)
-        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+        os.replace(f"{LIB_PATH}.tmp{os.getpid()}", LIB_PATH)  # several test workers may build at once
     return LIB_PATH
 
 
@@ -65,12 +65,19 @@ def lib():
         L.orc_decisions.restype = None
         L.orc_decisions.argtypes = [i64, vp, vp, vp, vp, vp, vp, i32, vp, i32, i32, i32, i32, i32, i64, vp, vp]
         L.orc_num_threads.restype = i32
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [i32]
         _lib = L
     return _lib
 
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (timing only)."""
+    lib().orc_set_threads(int(n))
 
 
 def _c32(a):

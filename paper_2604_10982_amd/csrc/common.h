@@ -46,15 +46,20 @@ enum : int {
   kStBlended = 14, // 64-bit: blended (pixel, surfel) pairs
   kStQueue = 16,   // 16 .. 19: work-queue heads of the persistent tile kernels
   kStWide = 20,    // tiles the Top-K blend left to its windowed pass
-  kStBwdEntries = 21,  // 64-bit: sum over pixels of n_last (list entries the backward walk must evaluate)
-  kStSigLo = 23,   // layout the forward ran with: total bytes (64-bit), pair capacity, tiles
-  kStSigHi = 24,
-  kStSigCap = 25,
-  kStSigTiles = 26,
-  kStUnique = 27,  // 64-bit, written by the stats read-back: distinct selected virtual surfels
-  kStSelected = 29,  // 64-bit, written by the stats read-back: (pixel, slot) selections
-  kStWords = 31
+  kStSigCap = 21,  // layout the forward ran with: pair capacity, tiles, total bytes (64-bit)
+  kStSigTiles = 22,
+  kStBwdEntries = 24,  // 64-bit: sum over pixels of n_last (list entries the backward walk must evaluate)
+  kStSigLo = 26,
+  kStSigHi = 27,
+  kStUnique = 28,  // 64-bit, written by the stats read-back: distinct selected virtual surfels
+  kStSelected = 30,  // 64-bit, written by the stats read-back: (pixel, slot) selections
+  kStWords = 32
 };
+// Words updated by 64-bit atomics must be 8-byte aligned (a misaligned atomic
+// is a memory violation); the status block itself starts the workspace.
+static_assert(kStReqLo % 2 == 0 && kStWalked % 2 == 0 && kStBlended % 2 == 0 && kStBwdEntries % 2 == 0 &&
+                  kStUnique % 2 == 0 && kStSelected % 2 == 0 && kStSigLo % 2 == 0,
+              "64-bit status words sit at even word indices");
 enum : int { kQWalk = 0, kQBlend = 1, kQFeatBwd = 2, kQWalkBwd = 3 };
 // Radix sort tiling.
 constexpr int kSortThreads = 256;

@@ -248,6 +248,29 @@ psm_status psm_profile_read(psm_ctx* ctx, int32_t stage, const char** name_out, 
 psm_status psm_profile_reset(psm_ctx* ctx);
 
 /* ------------------------------------------------------------------------
+ * Forward without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments and results as psm_forward, but the
+ * workspace is the library's static device array of
+ * PSM_STATIC_WORKSPACE_BYTES (one per device, held from the library's load
+ * until the process ends; psm_create fetches its address).  The call makes no
+ * device allocation and no allocating library call.
+ *   pair_capacity: -1 = the largest capacity the static workspace holds for
+ *     these sizes; >= 0 = that capacity (it must fit).
+ *   Sizes (n, image size, k, c, capacity) whose workspace exceeds the static
+ *   array return PSM_ERR_INVALID_ARG (nothing is enqueued); more pairs than
+ *   the capacity return PSM_ERR_CAPACITY as in psm_forward (unless
+ *   PSM_FLAG_NO_SYNC).  PSM_FLAG_PROFILE is ignored.
+ *   Every call on a device shares that device's array and leaves its state
+ *   there (the forward initialises everything it reads): calls that overlap
+ *   on one device (other streams, other host threads) race, and there is no
+ *   backward of a static forward.
+ * ------------------------------------------------------------------------ */
+#define PSM_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+psm_status psm_forward_static(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cam, const psm_config* cfg,
+                              int64_t pair_capacity, psm_images* out, void* stream);
+
+/* ------------------------------------------------------------------------
  * Several cameras in one call (one launch per stage for all of them).
  * Surfel i seen by camera b is the virtual surfel v = b * n + i; every
  * camera gets its own tiles and images, and the gradients are summed over

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -81,6 +82,7 @@ struct TuneKey {
 struct psm_ctx {
   int device;
   int cu_count;
+  void* scratch;  // device address of the static workspace on `device`
   Profiler prof;
   std::vector<TuneKey> tuned;
 };
@@ -100,6 +102,37 @@ int tile_grid(const Layout& L, int sched, const void* kernel, size_t dyn_lds) {
 }
 
 }  // namespace psm
+
+// ----------------------------------------------------- static workspace
+// For callers that cannot allocate device memory: a file-scope device array
+// used as the workspace of psm_forward_static.  Each device holds its own
+// copy from the library's load until the process ends.  In host code the
+// array's name is only a stand-in; its device address is fetched once per
+// device (psm_create, with that device current) and kept per device.
+static __device__ __align__(256) char scratch[PSM_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the current device).
+hipError_t fetch_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+}  // namespace
 
 namespace {
 
@@ -522,9 +555,18 @@ psm_status psm_create(psm_ctx** ctx_out, int device) {
       return fail(PSM_ERR_HIP, "no usable HIP device " + std::to_string(device));
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(PSM_ERR_HIP, "hipGetDeviceProperties failed");
+    void* scr = nullptr;
+    {
+      DeviceGuard dg(device);
+      if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
+      const hipError_t e = fetch_scratch(device, &scr);
+      if (e != hipSuccess)
+        return fail(PSM_ERR_HIP, std::string("static workspace address: ") + hipGetErrorString(e));
+    }
     psm_ctx* c = new psm_ctx;
     c->device = device;
     c->cu_count = prop.multiProcessorCount;
+    c->scratch = scr;
     *ctx_out = c;
     g_err.clear();
     return PSM_OK;
@@ -919,6 +961,43 @@ psm_status psm_geometry_loss(psm_ctx* ctx, int64_t n, const float* means, const 
     if (r != PSM_OK) return r;
     g_err.clear();
     return PSM_OK;
+  });
+}
+
+psm_status psm_forward_static(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cam, const psm_config* cfg,
+                              int64_t pair_capacity, psm_images* out, void* stream) {
+  return guarded("psm_forward_static", [&]() -> psm_status {
+    if (!ctx || !ctx->scratch) return fail(PSM_ERR_INVALID_ARG, "ctx is null or has no static workspace");
+    if (!cam || !cfg) return fail(PSM_ERR_INVALID_ARG, "camera and config are required");
+    if (pair_capacity < -1) return fail(PSM_ERR_INVALID_ARG, "pair_capacity must be -1 or >= 0");
+    psm_status r = validate_surfels(s);
+    if (r != PSM_OK) return r;
+    r = validate_common(cam, 1, cfg, s->n, s->c, pair_capacity < 0 ? 0 : pair_capacity);
+    if (r != PSM_OK) return r;
+    const CamTable ct = cam_table(cam, 1, s->n);
+    const size_t limit = PSM_STATIC_WORKSPACE_BYTES;
+    const size_t base = make_layout(ct, cfg->k, s->c, 0).total;
+    if (base > limit)
+      return fail(PSM_ERR_INVALID_ARG, "psm_forward_static: n, image size, k and c need " + std::to_string(base) +
+                                           " bytes of workspace before any pair; the static workspace holds " +
+                                           std::to_string(limit));
+    int64_t cap = pair_capacity;
+    if (cap < 0) {  // the largest capacity that fits (the layout grows with it)
+      int64_t lo = 0, hi = (int64_t)1 << 31;
+      while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (make_layout(ct, cfg->k, s->c, mid).total <= limit) lo = mid;
+        else hi = mid;
+      }
+      cap = lo;
+    } else if (make_layout(ct, cfg->k, s->c, cap).total > limit) {
+      return fail(PSM_ERR_INVALID_ARG, "psm_forward_static: pair capacity " + std::to_string(cap) + " needs " +
+                                           std::to_string(make_layout(ct, cfg->k, s->c, cap).total) +
+                                           " bytes of workspace; the static workspace holds " + std::to_string(limit));
+    }
+    psm_config c2 = *cfg;
+    c2.flags &= ~PSM_FLAG_PROFILE;  // stage timing creates events
+    return forward_impl(ctx, s, cam, 1, &c2, ctx->scratch, limit, cap, out, stream);
   });
 }
 

@@ -38,7 +38,7 @@ EXPORTS = ("psm_create", "psm_destroy", "psm_workspace_size", "psm_forward", "ps
            "psm_read_stats_batch", "psm_read_pairs_batch", "psm_read_selection_batch", "psm_autotune",
            "psm_instance_labels", "psm_instance_labels_workspace_size", "psm_instance_labels_backward",
            "psm_frustum_attention_workspace_size", "psm_frustum_attention",
-           "psm_geometry_loss_workspace_size", "psm_geometry_loss")
+           "psm_geometry_loss_workspace_size", "psm_geometry_loss", "psm_forward_static")
 
 
 class PsmError(RuntimeError):
@@ -128,6 +128,8 @@ def lib():
                                      vp, vp, vp, C.POINTER(i64), vp]
         L.psm_read_selection.argtypes = [vp, vp, i64, C.POINTER(Camera), C.POINTER(Config), i32, i64, vp, vp,
                                          vp, vp, vp]
+        L.psm_forward_static.argtypes = [vp, C.POINTER(Surfels), C.POINTER(Camera), C.POINTER(Config), i64,
+                                         C.POINTER(Images), vp]
         CamP, CfgP = C.POINTER(Camera), C.POINTER(Config)
         L.psm_workspace_size_batch.argtypes = [i64, CamP, i32, CfgP, i32, i64, C.POINTER(C.c_size_t)]
         L.psm_forward_batch.argtypes = [vp, C.POINTER(Surfels), CamP, i32, CfgP, vp, C.c_size_t, i64,
@@ -289,6 +291,19 @@ def forward_into(ctx: Context, s: Surfels, cam: Camera, cfg: Config, ws: Workspa
     st = stream if stream is not None else _stream(ctx.device)
     _check(lib().psm_forward(ctx.handle, C.byref(s), C.byref(cam), C.byref(cfg), _ptr(ws.buf), ws.nbytes,
                              ws.capacity, C.byref(imgs), st), "psm_forward")
+
+
+STATIC_WORKSPACE_BYTES = 64 << 20
+
+
+def forward_static_into(ctx: Context, s: Surfels, cam: Camera, cfg: Config, out: dict, pair_capacity: int = -1,
+                        stream=None):
+    """psm_forward_static: the forward with the library's static device
+    workspace (no caller workspace, no device allocation)."""
+    imgs = Images(*(_ptr(out.get(k)) for k in ("rgb", "depth", "normal", "alpha", "feat")))
+    st = stream if stream is not None else _stream(ctx.device)
+    _check(lib().psm_forward_static(ctx.handle, C.byref(s), C.byref(cam), C.byref(cfg), int(pair_capacity),
+                                    C.byref(imgs), st), "psm_forward_static")
 
 
 def backward_into(ctx: Context, s: Surfels, cam: Camera, cfg: Config, ws: Workspace, gout: dict, grads: dict,

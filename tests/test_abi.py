@@ -69,6 +69,8 @@ def test_host_validation(psm):
         psm.ERR_INVALID_ARG
     assert L.psm_backward(None, C.byref(s), C.byref(cam), C.byref(ok), None, 0, 0, None, None, None) == \
         psm.ERR_INVALID_ARG
+    assert L.psm_forward_static(None, C.byref(s), C.byref(cam), C.byref(ok), -1, C.byref(imgs), None) == \
+        psm.ERR_INVALID_ARG
 
 
 def test_workspace_grows_with_capacity(psm):

@@ -257,15 +257,15 @@ def roofline(stages, st, K, C, S, b, workload=WORKLOAD, launch=None):
             "frac": a / HBM_PEAK_GBS, "traffic": traffic, "ms": ms, "work": {"bytes": w}}
 
 
-def batch_workload(psm, scenes, steps, warmup):
+def batch_workload(psm, scenes, steps, warmup, k=16):
     """The batched workload: a shared 2M-surfel street scene with 128-d FP16
     features seen by 8 cameras of uneven resolution, fwd+bwd in one call per
-    stage.  Launch choices come from the library's autotuner; the step is
-    also captured in a HIP graph and replayed."""
+    stage, K = k.  Launch choices come from the library's autotuner; the step
+    is also captured in a HIP graph and replayed."""
     import numpy as np
     import torch
     device = torch.device("cuda:0")
-    sc, cams, K, dtype = scenes.batch_config()
+    sc, cams, K, dtype = scenes.batch_config(k=k)
     t = {k: torch.tensor(getattr(sc, k), device=device) for k in ("means", "scales", "quats", "opacity", "rgb")}
     t["feat"] = torch.tensor(sc.feat, device=device).to(torch.float16).contiguous()
     args = (t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"])
@@ -330,14 +330,25 @@ def batch_workload(psm, scenes, steps, warmup):
         graph.replay()
     torch.cuda.synchronize()
     gms = (time.perf_counter() - t0) * 1000.0 / steps
+    # forward alone (eager)
+    for _ in range(warmup):
+        psm.forward_batch_into(ctx, s, carr, cfg, ws, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        psm.forward_batch_into(ctx, s, carr, cfg, ws, out)
+    torch.cuda.synchronize()
+    fms = (time.perf_counter() - t0) * 1000.0 / steps
     return {"workload": f"street40 scene, {n} surfels, 128-d f16 features, K={K}, 8 cameras "
                         + ", ".join(f"{c.width}x{c.height}" for c in cams),
-            "pixels": P, "fwd_bwd_ms": ms, "fwd_bwd_its": 1000.0 / ms, "graph_replay_ms": gms,
+            "k": K, "pixels": P, "fwd_ms": fms, "fwd_fps": 1000.0 / fms,
+            "fwd_bwd_ms": ms, "fwd_bwd_its": 1000.0 / ms, "graph_replay_ms": gms,
             "graph_replay_its": 1000.0 / gms, "autotuned": {"schedule": ["grid", "persistent"][tune_cfg.schedule],
                                                            "bwd_schedule": ["grid", "persistent"][tune_cfg.bwd_schedule],
                                                            "blend_pass": tune_cfg.blend_pass,
                                                            "bwd_pass": tune_cfg.bwd_pass, "tuned_ms": tuned_ms},
-            "pairs": int(st.pairs), "stages_ms": stages}
+            "pairs": int(st.pairs), "stages_ms": stages,
+            "stage_roofline": stage_table(stages, st, K, sc.c, 2, P)}
 
 
 def labels_workload(psm, means, steps, warmup, nq=64, c=32):
@@ -598,6 +609,13 @@ def run_table(psm, scenes, steps, warmup, with_cpu):
             del feat64
         res["configs"][name] = entry
         del t, gout
+        torch.cuda.empty_cache()
+    # the batched workload (8 cameras, one launch per stage) at each K
+    res["batch_8cam"] = {}
+    for k in (8, 16, 32):
+        res["batch_8cam"][f"k{k}"] = batch_workload(psm, scenes, steps, warmup, k=k)
+        print(f"[table] batch 8 cameras K={k}: fwd+bwd {res['batch_8cam'][f'k{k}']['fwd_bwd_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     return res
 

@@ -312,9 +312,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
   __shared__ float s_part[4][kBB][kNV];
   __shared__ uint32_t s_has[4][kBB];
   __shared__ int s_lmax;
-  // dense-blend mode only: feature chunk of the batch and the batch weights
-  __shared__ float s_fc[MODE == kFull ? kBB : 1][64];
-  __shared__ __align__(16) float s_om[MODE == kFull ? kBB : 1][kTilePix];
+  // dense-blend mode only: each wave's dots tile (16 pixels x the batch) and
+  // the batch weights (rows padded to 260 floats: the matrix-core operand
+  // reads of 16 entries x 4 pixels fall in distinct banks)
+  constexpr int kPhS = kBB + 4, kOmS = kTilePix + 4;
+  __shared__ float s_ph[MODE == kFull ? 4 : 1][16 * kPhS];
+  __shared__ __align__(16) float s_om[MODE == kFull ? kBB : 1][kOmS];
   // Top-K mode: every pixel's selected list positions ([K][256]), read back
   // to front by the pixel's own lane; the feature dots stay in global memory,
   // each loaded when the previous one is used (16 KB of LDS instead of 32 KB
@@ -362,8 +365,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
       nextdot = g_sd[(size_t)kp * kTilePix];
     }
   }
-  const bool has_gf = MODE == kFull && g_feat != nullptr && inside;
-  const float* grow = g_feat + pix * C;
 
   __syncthreads();
   if (tid == 0) s_lmax = 0;
@@ -385,28 +386,62 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
     }
     __syncthreads();
 
-    // dense mode: phi[k] = g_F(p) . f_k for the batch (tile-wide product)
+    // dense mode: phi[k] = g_F(p) . f_k for the batch, the product
+    // PHI = G F^T on the matrix cores: wave w takes its 4 pixel blocks of 16
+    // x the 2 entry blocks of 16, k = 4 channels per step (lane (li, lk)
+    // loads channels 4 lk .. 4 lk + 3 of a 16-channel group as one vector,
+    // component i feeding step i); the tile goes through the wave's LDS
+    // region to the lanes of its pixels
     float phi[MODE == kFull ? kBB : 1];
     if constexpr (MODE == kFull) {
 #pragma unroll
       for (int k = 0; k < kBB; ++k) phi[k] = 0.0f;
       if (g_feat) {
-        for (int c0 = 0; c0 < C; c0 += 64) {
-          for (int e = tid; e < nb * 64; e += 256) {
-            const int k = e >> 6, c = e & 63;
-            s_fc[k][c] = (c0 + c < C) ? load_one<FT>(feat + (size_t)(s_id[k] - tl.v0) * C + c0 + c) : 0.0f;
-          }
-          __syncthreads();
-          if (has_gf) {
-            const int cn = min(64, C - c0);
-            for (int c = 0; c < cn; c += 4) {
-              const float4 g = *reinterpret_cast<const float4*>(grow + c0 + c);
+        const int li = lane & 15, lk = lane >> 4;
+        const FT* fr[2];
 #pragma unroll
-              for (int k = 0; k < kBB; ++k)
-                phi[k] = fmaf(g.x, s_fc[k][c], fmaf(g.y, s_fc[k][c + 1], fmaf(g.z, s_fc[k][c + 2], fmaf(g.w, s_fc[k][c + 3], phi[k]))));
+        for (int eb = 0; eb < 2; ++eb) {
+          const int e = 16 * eb + li;
+          fr[eb] = e < nb ? feat + (size_t)(s_id[e] - tl.v0) * C : nullptr;
+        }
+        float* ph = s_ph[wave];
+        for (int pb = 0; pb < 4; ++pb) {
+          const int q = 64 * wave + 16 * pb + li;  // pixel of lane li
+          const int qx = tx * kTile + (q & 15), qy = ty * kTile + (q >> 4);
+          const float* gq = qx < W && qy < H ? g_feat + (tl.pix0 + (int64_t)qy * W + qx) * C : nullptr;
+          f4v acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+          // 128 channels at a time: every operand of the segment is loaded
+          // before its products, so the loads are in flight together
+          for (int cs = 0; cs < C; cs += 128) {
+            float4 a[8], b[2][8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int c = cs + 16 * j + 4 * lk;  // C % 4 == 0: a group of 4 is whole or absent
+              a[j] = gq && c < C ? *reinterpret_cast<const float4*>(gq + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+              for (int eb = 0; eb < 2; ++eb)
+                b[eb][j] = fr[eb] && c < C ? load4<FT>(fr[eb] + c) : make_float4(0.f, 0.f, 0.f, 0.f);
             }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+#pragma unroll
+              for (int eb = 0; eb < 2; ++eb) {
+                acc[eb] = mfma_16x16x4(a[j].x, b[eb][j].x, acc[eb]);
+                acc[eb] = mfma_16x16x4(a[j].y, b[eb][j].y, acc[eb]);
+                acc[eb] = mfma_16x16x4(a[j].z, b[eb][j].z, acc[eb]);
+                acc[eb] = mfma_16x16x4(a[j].w, b[eb][j].w, acc[eb]);
+              }
           }
-          __syncthreads();
+#pragma unroll
+          for (int eb = 0; eb < 2; ++eb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ph[(4 * lk + r) * kPhS + 16 * eb + li] = acc[eb][r];
+          wave_lds_sync();
+          if (lk == pb) {
+#pragma unroll
+            for (int k = 0; k < kBB; ++k) phi[k] = ph[li * kPhS + k];
+          }
+          wave_lds_sync();
         }
       }
     }
@@ -523,50 +558,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
       }
     }
 
-    // dense mode: dL/df_k = sum_p w_k(p) g_F(p) for the batch
+    // dense mode: dL/df_k = sum_p w_k(p) g_F(p) for the batch, the product
+    // R = W^T G on the matrix cores: units (entry block of 16, channel block
+    // of 16) dealt to the waves, each a sum over the 256 pixels in 64 steps
+    // of 4 (pixels 16 y + 4 u + lk of tile row y), written at the pair's
+    // emission index
     if constexpr (MODE == kFull) {
       if (g_feat) {
         __syncthreads();
-        const int kg = wave;  // 4 groups of kBB/4 surfels
-        constexpr int PER = kBB / 4;
-        for (int c0 = 0; c0 < C; c0 += 64) {
-          const int c = c0 + lane;
-          float acc[PER];
+        const int li = lane & 15, lk = lane >> 4;
+        const int ncb = (C + 15) >> 4;
+        for (int unit = wave; unit < 2 * ncb; unit += 4) {
+          const int eb = unit & 1, cb = unit >> 1;
+          const int c = 16 * cb + li;
+          f4v racc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+          const float* wrow = s_om[16 * eb + li];
+          // 8 tile rows at a time: their 32 G values are loaded together
+          for (int y0 = 0; y0 < kTile; y0 += 8) {
+            float b[8][4];
 #pragma unroll
-          for (int j = 0; j < PER; ++j) acc[j] = 0.0f;
-          if (c < C) {
-            // 8 pixels per step: 8 independent upstream loads in flight (pixels
-            // outside the image have zero weight and read as zero)
-            for (int p0 = 0; p0 < kTilePix; p0 += 8) {
-              float g[8];
+            for (int y = 0; y < 8; ++y) {
+              const bool rowin = ty * kTile + y0 + y < H && c < C;
+              const float* g =
+                  g_feat + (tl.pix0 + (int64_t)(rowin ? ty * kTile + y0 + y : 0) * W + tx * kTile) * C + c;
 #pragma unroll
-              for (int u = 0; u < 8; ++u) {
-                const int p = p0 + u;
-                const int qx = tx * kTile + (p & 15), qy = ty * kTile + (p >> 4);
-                g[u] = (qx < W && qy < H) ? g_feat[(tl.pix0 + (int64_t)qy * W + qx) * C + c] : 0.0f;
-              }
-#pragma unroll
-              for (int j = 0; j < PER; ++j) {
-                const float4 w0 = *reinterpret_cast<const float4*>(&s_om[kg * PER + j][p0]);
-                const float4 w1 = *reinterpret_cast<const float4*>(&s_om[kg * PER + j][p0 + 4]);
-                float a = acc[j];
-                a = fmaf(w0.x, g[0], a);
-                a = fmaf(w0.y, g[1], a);
-                a = fmaf(w0.z, g[2], a);
-                a = fmaf(w0.w, g[3], a);
-                a = fmaf(w1.x, g[4], a);
-                a = fmaf(w1.y, g[5], a);
-                a = fmaf(w1.z, g[6], a);
-                a = fmaf(w1.w, g[7], a);
-                acc[j] = a;
+              for (int u = 0; u < 4; ++u) {
+                const int x = 4 * u + lk;
+                b[y][u] = rowin && tx * kTile + x < W ? g[x * C] : 0.0f;
               }
             }
 #pragma unroll
-            for (int j = 0; j < PER; ++j) {
-              const int k = kg * PER + j;
+            for (int y = 0; y < 8; ++y)
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+                racc[y & 1] = mfma_16x16x4(wrow[16 * (y0 + y) + 4 * u + lk], b[y][u], racc[y & 1]);
+          }
+          const f4v rs = racc[0] + racc[1];
+          if (c < C) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int k = 16 * eb + 4 * lk + r;
               if (k < nb) {
                 const size_t slot = eid[start + lo + k];
-                fpart[slot * C + c] = acc[j];
+                fpart[slot * C + c] = rs[r];
                 if (c == 0) fflag[slot] = 1;
               }
             }

@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--cpu-tiles", type=int, default=1200)
     ap.add_argument("--no-batch", action="store_true", help="skip the 8-camera batched workload")
     ap.add_argument("--launch", default=None,
-                    help="schedule,bwd_schedule,blend_pass,bwd_pass for the headline form "
+                    help="schedule,bwd_schedule,blend_pass,bwd_pass[,tile_w] for the headline form "
                          "(default: the library's autotuner)")
     ap.add_argument("--table", action="store_true",
                     help="the configuration table: every configuration on the tile-mode x blend grid, quality "
@@ -88,12 +88,19 @@ class Form:
         self.cam = psm.camera_struct(cam)
         self.cfg = psm.config_struct(K, tile_mode, blend, psm.FLAG_NO_SYNC | psm.FLAG_PROFILE | flags)
         self.s = psm._surfels(t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"])
-        _, ws = psm.forward(t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"], self.cam, K,
-                            tile_mode, blend, flags=flags)
-        st = psm.read_stats(ws, self.s.n, self.cam, psm.config_struct(K, tile_mode, blend, flags), self.s.c,
-                            ws.capacity)
-        cap = int(st.pairs_required * 1.05 + 4096)
-        self.ws = psm.alloc_workspace(self.s.n, self.cam, self.cfg, self.s.c, cap, device)
+        # the pairs each tile shape needs (only the launch's shape, or every
+        # shape when the autotuner picks it), and a workspace that fits them
+        shapes = TILE_WIDTHS if (tune and launch is None) else ((launch[4] if launch and len(launch) > 4 else 0),)
+        need = 0
+        for tw in shapes:
+            _, ws = psm.forward(t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"], self.cam, K,
+                                tile_mode, blend, flags=flags, launch=(0, 0, 0, 0, tw))
+            st = psm.read_stats(ws, self.s.n, self.cam, psm.config_struct(K, tile_mode, blend, flags, tile_w=tw),
+                                self.s.c, ws.capacity)
+            need = max(need, int(st.pairs_required))
+            del ws
+        cap = int(need * 1.05 + 4096)
+        self.ws = psm.alloc_workspace_shapes(self.s.n, [self.cam], self.cfg, self.s.c, cap, device, shapes)
         feature_only = bool(flags & psm.FLAG_FEATURE_ONLY)
         self.out = psm.alloc_images(self.cam, self.s.c, device, feature_only=feature_only)
         if feature_only:  # only the feature map is rendered, so only its upstream gradient
@@ -106,19 +113,20 @@ class Form:
         self.ctx = psm.context(device.index or 0)
         self.tuned_ms = None
         if launch is not None:
-            self.cfg.schedule, self.cfg.bwd_schedule, self.cfg.blend_pass, self.cfg.bwd_pass = launch
+            self.cfg.schedule, self.cfg.bwd_schedule, self.cfg.blend_pass, self.cfg.bwd_pass = launch[:4]
+            self.cfg.tile_w = launch[4] if len(launch) > 4 else 0
         elif tune:
             tcfg = psm.config_struct(K, tile_mode, blend)
             out = dict(self.out)
             self.tuned_ms = psm.autotune(self.ctx, self.s, psm.camera_array([self.cam]), tcfg, self.ws, out,
                                          self.gout, self.grads, reps=3, cache=False)
             self.cfg.schedule, self.cfg.bwd_schedule = tcfg.schedule, tcfg.bwd_schedule
-            self.cfg.blend_pass, self.cfg.bwd_pass = tcfg.blend_pass, tcfg.bwd_pass
+            self.cfg.blend_pass, self.cfg.bwd_pass, self.cfg.tile_w = tcfg.blend_pass, tcfg.bwd_pass, tcfg.tile_w
 
     def launch(self):
-        """(schedule, bwd_schedule, blend_pass, bwd_pass) in use."""
+        """(schedule, bwd_schedule, blend_pass, bwd_pass, tile_w) in use."""
         return (int(self.cfg.schedule), int(self.cfg.bwd_schedule), int(self.cfg.blend_pass or 32),
-                int(self.cfg.bwd_pass or 16))
+                int(self.cfg.bwd_pass or 16), int(self.cfg.tile_w or 16))
 
     def step(self, bwd: bool):
         self.psm.forward_into(self.ctx, self.s, self.cam, self.cfg, self.ws, self.out)
@@ -270,11 +278,14 @@ def batch_workload(psm, scenes, steps, warmup, k=16):
     t["feat"] = torch.tensor(sc.feat, device=device).to(torch.float16).contiguous()
     args = (t["means"], t["scales"], t["quats"], t["opacity"], t["rgb"], t["feat"])
     carr = psm.camera_array(cams)
-    _, ws0, _ = psm.forward_batch(*args, carr, K)
-    need = psm.read_stats_batch(ws0, carr, psm.config_struct(K)).pairs_required
-    del ws0
+    need = 0
+    for tw in TILE_WIDTHS:  # pairs of every tile shape the autotuner times
+        c0 = psm.config_struct(K, tile_w=tw)
+        _, ws0, _ = psm.forward_batch(*args, carr, K, cfg=c0)
+        need = max(need, int(psm.read_stats_batch(ws0, carr, c0).pairs_required))
+        del ws0
     cfg = psm.config_struct(K, "ellipse", "topk", psm.FLAG_NO_SYNC | psm.FLAG_PROFILE)
-    ws = psm.alloc_workspace_batch(sc.n, carr, cfg, sc.c, int(need * 1.05) + 4096, device)
+    ws = psm.alloc_workspace_shapes(sc.n, list(cams), cfg, sc.c, int(need * 1.05) + 4096, device, TILE_WIDTHS)
     out = psm.alloc_images_batch(carr, sc.c, device)
     P = psm.total_pixels(carr)
     g = torch.Generator(device=device).manual_seed(1)
@@ -290,7 +301,7 @@ def batch_workload(psm, scenes, steps, warmup, k=16):
     tune_cfg = psm.config_struct(K, "ellipse", "topk")
     tuned_ms = psm.autotune(ctx, s, carr, tune_cfg, ws, out, gout, grads, reps=3, cache=False)
     cfg.schedule, cfg.bwd_schedule = tune_cfg.schedule, tune_cfg.bwd_schedule
-    cfg.blend_pass, cfg.bwd_pass = tune_cfg.blend_pass, tune_cfg.bwd_pass
+    cfg.blend_pass, cfg.bwd_pass, cfg.tile_w = tune_cfg.blend_pass, tune_cfg.bwd_pass, tune_cfg.tile_w
 
     def step(c):
         psm.forward_batch_into(ctx, s, carr, c, ws, out)
@@ -312,7 +323,7 @@ def batch_workload(psm, scenes, steps, warmup, k=16):
         raise RuntimeError("pair capacity exceeded in the batched workload")
     # the same step captured once and replayed
     gcfg = psm.config_struct(K, "ellipse", "topk", psm.FLAG_NO_SYNC, tune_cfg.schedule, tune_cfg.blend_pass,
-                             tune_cfg.bwd_pass, tune_cfg.bwd_schedule)
+                             tune_cfg.bwd_pass, tune_cfg.bwd_schedule, tune_cfg.tile_w)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -346,7 +357,9 @@ def batch_workload(psm, scenes, steps, warmup, k=16):
             "graph_replay_its": 1000.0 / gms, "autotuned": {"schedule": ["grid", "persistent"][tune_cfg.schedule],
                                                            "bwd_schedule": ["grid", "persistent"][tune_cfg.bwd_schedule],
                                                            "blend_pass": tune_cfg.blend_pass,
-                                                           "bwd_pass": tune_cfg.bwd_pass, "tuned_ms": tuned_ms},
+                                                           "bwd_pass": tune_cfg.bwd_pass,
+                                                           "tile": f"{tune_cfg.tile_w}x{256 // tune_cfg.tile_w}",
+                                                           "tuned_ms": tuned_ms},
             "pairs": int(st.pairs), "stages_ms": stages,
             "stage_roofline": stage_table(stages, st, K, sc.c, 2, P)}
 
@@ -499,6 +512,7 @@ def cpu_baseline(sc, cam, K, feat64, tiles):
             "sample_seconds": {"prepare": t_prep, "fwd": t_fwd, "bwd": t_bwd}, "est_frame_s": frame}
 
 
+TILE_WIDTHS = (8, 16, 32, 64)
 TABLE_CONFIGS = (("c1_box2k", False), ("c2_planes200k", False), ("c3_planes500k", True),
                  ("c4_street1m", True), ("room_1296x968", True))
 TABLE_GRID = (("sphere", "full"), ("aabb", "full"), ("ellipse", "full"),
@@ -654,7 +668,8 @@ def main():
 
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
     head = Form(psm, t, cam, K, "ellipse", "topk", gout, device, launch=launch, tune=launch is None)
-    print(f"[bench] launch choice (schedule, bwd_schedule, blend_pass, bwd_pass): {head.launch()}", file=sys.stderr, flush=True)
+    print(f"[bench] launch choice (schedule, bwd_schedule, blend_pass, bwd_pass, tile_w): {head.launch()}",
+          file=sys.stderr, flush=True)
     ms_step, stages, st = timed(head, True, args.steps, args.warmup)
     print(f"[bench] topk+ellipse fwd+bwd {ms_step:.3f} ms", file=sys.stderr, flush=True)
     if args.headline_only:
@@ -760,7 +775,8 @@ def main():
         "stages_ms": stages,
         "launch": {"schedule": ["grid", "persistent"][head_launch[0]],
                    "bwd_schedule": ["grid", "persistent"][head_launch[1]], "blend_pass": head_launch[2],
-                   "bwd_pass": head_launch[3], "source": "autotuner" if launch is None else "--launch",
+                   "bwd_pass": head_launch[3], "tile": f"{head_launch[4]}x{256 // head_launch[4]}",
+                   "source": "autotuner" if launch is None else "--launch",
                    "tuned_ms": head_tuned_ms},
         "selected_unique": int(st.selected_unique), "selections": int(st.selections),
         "bwd_entries": int(st.bwd_entries),

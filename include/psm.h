@@ -92,10 +92,17 @@ typedef struct {
   int32_t blend_pass; /* feature channels per Top-K blend pass: 0 (= 32), 16 or 32 */
   int32_t bwd_pass;   /* feature channels per feature-backward pass: 0 (= 16), 16 or 32 */
   int32_t bwd_schedule; /* psm_schedule of the backward's tile kernels */
+  /* Tile shape: tile_w x (256 / tile_w) pixels, tile_w in {8, 16, 32, 64};
+   * 0 = 16 (16 x 16 tiles, Sec. 5's tile-based rasterisation).  One 256-thread
+   * block owns one tile, a wave 64 / tile_w of its rows.  The pair lists
+   * follow the tiles; images and the Top-K selection do not depend on the
+   * shape (gradients only through the order of their sums).  The read-backs
+   * and the backward must use the forward's value. */
+  int32_t tile_w;
 } psm_config;
 
 /* Tile scheduling of the per-tile kernels (forward: schedule, backward:
- * bwd_schedule).  GRID: one workgroup per 16x16 tile, tiles of neighbouring
+ * bwd_schedule).  GRID: one workgroup per tile, tiles of neighbouring
  * ids kept on one XCD.  PERSISTENT: a grid that fills the device once takes
  * tiles from a work queue ordered longest lists first (the forward orders the
  * tiles when either schedule is persistent). */
@@ -306,14 +313,19 @@ psm_status psm_read_selection_batch(psm_ctx* ctx, const void* workspace, int64_t
                                     int32_t* sel_id_out, float* sel_w_out, int32_t* n_last_out,
                                     float* t_final_out, void* stream);
 
-/* Autotuner: times every candidate launch choice (schedule, bwd_schedule,
- * blend_pass, bwd_pass) on these inputs -- forward, plus backward when grads is non-NULL
- * -- `reps` times each after one warm-up, and writes the fastest into *cfg
- * (and its median time in ms into *best_ms_out when non-NULL).  The choice is
+/* Autotuner: picks the tile shape (tile_w) and the launch choices (schedule,
+ * bwd_schedule, blend_pass, bwd_pass) on these inputs by timing them --
+ * forward, plus backward when grads is non-NULL -- `reps` times each after
+ * one warm-up: first the four tile shapes with persistent schedules and the
+ * default pass widths, then every schedule and pass width at the fastest
+ * shape.  Writes the fastest into *cfg (and its median time in ms into
+ * *best_ms_out when non-NULL).  A shape whose workspace layout exceeds
+ * workspace_bytes, or whose pairs exceed pair_capacity, is left out (size the
+ * workspace for the largest shape to have every shape timed).  The choice is
  * cached in the context per (cameras' sizes, n, c, k, dtype, modes, backward)
  * and returned without timing on later calls.  Overwrites the outputs, the
  * gradients and the workspace; synchronises `stream` (not for use under
- * stream capture).  Returns PSM_ERR_CAPACITY if the pairs do not fit. */
+ * stream capture).  Returns PSM_ERR_CAPACITY if no shape fits. */
 psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* cams, int32_t n_cams,
                         psm_config* cfg, void* workspace, size_t workspace_bytes, int64_t pair_capacity,
                         psm_images* out, const psm_image_grads* grad_out, psm_grads* grads, int32_t reps,

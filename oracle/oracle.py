@@ -91,11 +91,13 @@ def _scene_args(scene):
 def keystage(scene, cam, mode="ellipse", tile=16, pairs=True, opacity_footprint=False, lowpass=False) -> dict:
     """FP32 key stage: cull codes, depth bits, flips, counts, footprint floats
     and (optionally) the sorted pair list (tile ids, surfel ids).
+    ``tile``: the tile size (square) or its (width, height).
     ``opacity_footprint``: list the footprint of rho <= min(9, 2 ln(255 o))
     (widened and rounded up, see oracle.cpp) instead of rho <= 9.
     ``lowpass``: the footprint also covers the screen-space low-pass filter's
     disk 2 |x - c|^2 <= 9 (widened, see oracle.cpp)."""
     m = MODES[mode] if isinstance(mode, str) else int(mode)
+    tw, th = (tile, tile) if np.isscalar(tile) else (int(tile[0]), int(tile[1]))
     n = scene.n
     mu, sc, q = _scene_args(scene)
     op = _c32(scene.opacity) if opacity_footprint else None
@@ -106,13 +108,13 @@ def keystage(scene, cam, mode="ellipse", tile=16, pairs=True, opacity_footprint=
     count = np.zeros(n, np.int32)
     fp = np.zeros((n, 8), np.float32)
     L = lib()
-    P = L.orc_keystage(n, _vp(mu), _vp(sc), _vp(q), _vp(op), _vp(camv), tile, tile, m, int(lowpass),
+    P = L.orc_keystage(n, _vp(mu), _vp(sc), _vp(q), _vp(op), _vp(camv), tw, th, m, int(lowpass),
                        _vp(cull), _vp(depth), _vp(flip), _vp(count), _vp(fp), 0, None, None)
     out = {"cull": cull, "depth_bits": depth, "flip": flip, "count": count, "fp": fp, "P": int(P)}
     if pairs:
         tiles = np.zeros(max(P, 1), np.int32)
         ids = np.zeros(max(P, 1), np.int32)
-        L.orc_keystage(n, _vp(mu), _vp(sc), _vp(q), _vp(op), _vp(camv), tile, tile, m, int(lowpass),
+        L.orc_keystage(n, _vp(mu), _vp(sc), _vp(q), _vp(op), _vp(camv), tw, th, m, int(lowpass),
                        None, None, None, None, None, P, _vp(tiles), _vp(ids))
         out["tile"] = tiles[:P]
         out["id"] = ids[:P]

@@ -76,6 +76,7 @@ struct Profiler {
 struct TuneKey {
   std::string key;
   psm::Tuning tu;
+  int tile_w;
   double ms;
 };
 
@@ -187,11 +188,15 @@ psm_status validate_common(const psm_camera* cams, int32_t n_cams, const psm_con
   if (!cams || !cfg) return fail(PSM_ERR_INVALID_ARG, "camera and config are required");
   if (n_cams < 1 || n_cams > kMaxCams) return fail(PSM_ERR_INVALID_ARG, "n_cams must be in [1, 8]");
   if (n < 0 || n * n_cams > 0x7FFFFFFFLL) return fail(PSM_ERR_INVALID_ARG, "n * n_cams must be in [0, 2^31)");
+  const int tw = cfg->tile_w;
+  if (tw != 0 && tw != 8 && tw != 16 && tw != 32 && tw != 64)
+    return fail(PSM_ERR_INVALID_ARG, "tile_w must be 0, 8, 16, 32 or 64");
+  const int tw1 = tw == 0 ? kTileDefault : tw, th1 = kTilePix / tw1;
   int64_t tiles = 0;
   for (int b = 0; b < n_cams; ++b) {
     psm_status r = validate_camera(cams + b);
     if (r != PSM_OK) return r;
-    tiles += cdiv(cams[b].width, kTile) * cdiv(cams[b].height, kTile);
+    tiles += cdiv(cams[b].width, tw1) * cdiv(cams[b].height, th1);
   }
   if (tiles * kTilePix > 0x7FFFFFFFLL) return fail(PSM_ERR_INVALID_ARG, "too many pixels in one call");
   if (cfg->k < 1 || cfg->k > kMaxK) return fail(PSM_ERR_INVALID_ARG, "k must be in [1, 32]");
@@ -230,11 +235,17 @@ psm_status validate_surfels(const psm_surfels* s) {
   return PSM_OK;
 }
 
-CamTable cam_table(const psm_camera* cams, int32_t n_cams, int64_t n) {
+int tile_width(const psm_config* cfg) { return !cfg || cfg->tile_w == 0 ? kTileDefault : cfg->tile_w; }
+
+CamTable cam_table(const psm_camera* cams, int32_t n_cams, int64_t n, const psm_config* cfg) {
   CamTable t;
   std::memset(&t, 0, sizeof(t));
   t.n = n_cams;
   t.nsurf = n;
+  t.tw = tile_width(cfg);
+  t.th = kTilePix / t.tw;
+  t.tsh = 0;
+  while ((1 << t.tsh) < t.tw) ++t.tsh;
   int tile = 0;
   int64_t pix = 0;
   for (int b = 0; b < n_cams; ++b) {
@@ -244,8 +255,8 @@ CamTable cam_table(const psm_camera* cams, int32_t n_cams, int64_t n) {
     std::memcpy(a.t, cam->t, sizeof(a.t));
     a.fx = cam->fx; a.fy = cam->fy; a.cx = cam->cx; a.cy = cam->cy; a.near_plane = cam->near_plane;
     a.W = cam->width; a.H = cam->height;
-    t.ntx[b] = (int)cdiv(cam->width, kTile);
-    t.nty[b] = (int)cdiv(cam->height, kTile);
+    t.ntx[b] = (int)cdiv(cam->width, t.tw);
+    t.nty[b] = (int)cdiv(cam->height, t.th);
     t.tile0[b] = tile;
     t.pix0[b] = pix;
     tile += t.ntx[b] * t.nty[b];
@@ -362,7 +373,7 @@ psm_status forward_impl(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
   if (r != PSM_OK) return r;
   r = validate_common(cams, n_cams, cfg, s->n, s->c, pair_capacity);
   if (r != PSM_OK) return r;
-  const CamTable ct = cam_table(cams, n_cams, s->n);
+  const CamTable ct = cam_table(cams, n_cams, s->n, cfg);
   const Layout L = make_layout(ct, cfg->k, s->c, pair_capacity);
   r = check_workspace(L, workspace, workspace_bytes);
   if (r != PSM_OK) return r;
@@ -400,7 +411,7 @@ psm_status backward_impl(psm_ctx* ctx, const psm_surfels* s, const psm_camera* c
     return fail(PSM_ERR_INVALID_ARG, "every gradient array is required");
   if ((cfg->flags & PSM_FLAG_FEATURE_ONLY) && (grad_out->rgb || grad_out->depth || grad_out->normal || grad_out->alpha))
     return fail(PSM_ERR_INVALID_ARG, "PSM_FLAG_FEATURE_ONLY takes only the feature map's upstream gradient");
-  const CamTable ct = cam_table(cams, n_cams, s->n);
+  const CamTable ct = cam_table(cams, n_cams, s->n, cfg);
   const Layout L = make_layout(ct, cfg->k, s->c, pair_capacity);
   r = check_workspace(L, workspace, workspace_bytes);
   if (r != PSM_OK) return r;
@@ -423,7 +434,7 @@ psm_status read_stats_impl(psm_ctx* ctx, const void* workspace, int64_t n, const
   if (!ctx || !out) return fail(PSM_ERR_INVALID_ARG, "ctx and out are required");
   psm_status r = validate_common(cams, n_cams, cfg, n, c, pair_capacity);
   if (r != PSM_OK) return r;
-  const Layout L = make_layout(cam_table(cams, n_cams, n), cfg->k, c, pair_capacity);
+  const Layout L = make_layout(cam_table(cams, n_cams, n, cfg), cfg->k, c, pair_capacity);
   if (!workspace) return fail(PSM_ERR_INVALID_ARG, "workspace is required");
   DeviceGuard dg(ctx->device);
   hipStream_t st = (hipStream_t)stream;
@@ -464,7 +475,7 @@ psm_status read_pairs_impl(psm_ctx* ctx, const void* workspace, int64_t n, const
   psm_status r = validate_common(cams, n_cams, cfg, n, c, pair_capacity);
   if (r != PSM_OK) return r;
   if (!workspace) return fail(PSM_ERR_INVALID_ARG, "workspace is required");
-  const Layout L = make_layout(cam_table(cams, n_cams, n), cfg->k, c, pair_capacity);
+  const Layout L = make_layout(cam_table(cams, n_cams, n, cfg), cfg->k, c, pair_capacity);
   DeviceGuard dg(ctx->device);
   hipStream_t st = (hipStream_t)stream;
   const char* ws = (const char*)workspace;
@@ -493,7 +504,7 @@ psm_status read_selection_impl(psm_ctx* ctx, const void* workspace, int64_t n, c
   psm_status r = validate_common(cams, n_cams, cfg, n, c, pair_capacity);
   if (r != PSM_OK) return r;
   if (!workspace) return fail(PSM_ERR_INVALID_ARG, "workspace is required");
-  const CamTable ct = cam_table(cams, n_cams, n);
+  const CamTable ct = cam_table(cams, n_cams, n, cfg);
   const Layout L = make_layout(ct, cfg->k, c, pair_capacity);
   DeviceGuard dg(ctx->device);
   uint32_t h[kStWords];
@@ -581,7 +592,7 @@ psm_status psm_workspace_size_batch(int64_t n, const psm_camera* cams, int32_t n
     if (!bytes_out) return fail(PSM_ERR_INVALID_ARG, "bytes_out is null");
     psm_status s = validate_common(cams, n_cams, cfg, n, c, pair_capacity);
     if (s != PSM_OK) return s;
-    *bytes_out = make_layout(cam_table(cams, n_cams, n), cfg->k, c, pair_capacity).total;
+    *bytes_out = make_layout(cam_table(cams, n_cams, n, cfg), cfg->k, c, pair_capacity).total;
     return PSM_OK;
   });
 }
@@ -694,12 +705,16 @@ psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
     const bool bwd = grads != nullptr;
     if (bwd && !grad_out) return fail(PSM_ERR_INVALID_ARG, "grad_out is required with grads");
     const std::string key = tune_key(s, cams, n_cams, cfg, bwd);
+    auto apply = [&](const Tuning& tu, int tw) {
+      cfg->schedule = tu.sched;
+      cfg->bwd_schedule = tu.sched_bwd;
+      cfg->blend_pass = tu.blend_pass;
+      cfg->bwd_pass = tu.bwd_pass;
+      cfg->tile_w = tw;
+    };
     for (const TuneKey& t : ctx->tuned) {
       if (t.key == key) {
-        cfg->schedule = t.tu.sched;
-        cfg->bwd_schedule = t.tu.sched_bwd;
-        cfg->blend_pass = t.tu.blend_pass;
-        cfg->bwd_pass = t.tu.bwd_pass;
+        apply(t.tu, t.tile_w);
         if (best_ms_out) *best_ms_out = t.ms;
         return PSM_OK;
       }
@@ -707,65 +722,91 @@ psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
     hipStream_t st = (hipStream_t)stream;
-    std::vector<Tuning> cands;
-    const bool feat = s->c > 0 && cfg->blend == PSM_BLEND_TOPK;
-    for (int sched = 0; sched < 2; ++sched)
-      for (int sched_bwd = 0; sched_bwd < 2; ++sched_bwd)
-        for (int bp : {16, 32})
-          for (int gp : {16, 32}) {
-            if (!bwd && sched_bwd != 0) continue;
-            if (!feat && (bp != 32 || gp != 16)) continue;
-            if (feat && !bwd && gp != 16) continue;
-            cands.push_back(Tuning{sched, sched_bwd, bp, gp});
-          }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
       return fail(PSM_ERR_HIP, "hipEventCreate failed");
-    Tuning best{};
-    double best_ms = 1e300;
-    psm_status res = PSM_OK;
-    for (const Tuning& tu : cands) {
+    // Median time of one candidate; usable = false when its layout does not
+    // fit the workspace or its pairs overflow the capacity (the candidate is
+    // then left out, the error is not the caller's).
+    auto time_cand = [&](const Tuning& tu, int tw, double& med, bool& usable) -> psm_status {
       psm_config c2 = *cfg;
       c2.schedule = tu.sched;
       c2.bwd_schedule = tu.sched_bwd;
       c2.blend_pass = tu.blend_pass;
       c2.bwd_pass = tu.bwd_pass;
+      c2.tile_w = tw;
       c2.flags = (cfg->flags | PSM_FLAG_NO_SYNC) & ~PSM_FLAG_PROFILE;
+      const Layout L = make_layout(cam_table(cams, n_cams, s->n, &c2), c2.k, s->c, pair_capacity);
+      usable = L.total <= workspace_bytes;
+      if (!usable) return PSM_OK;
       std::vector<double> ts;
-      for (int it = 0; it <= reps && res == PSM_OK; ++it) {
+      for (int it = 0; it <= reps; ++it) {
         (void)hipEventRecord(e0, st);
-        res = forward_impl(ctx, s, cams, n_cams, &c2, workspace, workspace_bytes, pair_capacity, out, stream);
+        psm_status res = forward_impl(ctx, s, cams, n_cams, &c2, workspace, workspace_bytes, pair_capacity, out, stream);
         if (res == PSM_OK && bwd)
           res = backward_impl(ctx, s, cams, n_cams, &c2, workspace, workspace_bytes, pair_capacity, grad_out, grads,
                               stream);
+        if (res != PSM_OK) return res;
         (void)hipEventRecord(e1, st);
         float ms = 0.0f;
-        if (res == PSM_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-          res = fail(PSM_ERR_HIP, "autotune timing failed");
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+          return fail(PSM_ERR_HIP, "autotune timing failed");
         if (it > 0) ts.push_back(ms);
       }
-      if (res != PSM_OK) break;
+      uint32_t h[kStWords];
+      psm_status res = read_status(L, workspace, h, st);
+      if (res != PSM_OK) return res;
+      usable = h[kStOverflow] == 0;
       std::sort(ts.begin(), ts.end());
-      const double med = ts[ts.size() / 2];
-      if (med < best_ms) {
+      med = ts[ts.size() / 2];
+      return PSM_OK;
+    };
+    const bool feat = s->c > 0 && cfg->blend == PSM_BLEND_TOPK;
+    Tuning best{kSchedPersistent, bwd ? kSchedPersistent : 0, 32, 16};
+    int best_tw = cfg->tile_w == 0 ? kTileDefault : cfg->tile_w;
+    double best_ms = 1e300;
+    psm_status res = PSM_OK;
+    // stage 1: the tile shape, with persistent schedules and the default passes
+    for (int tw : {16, 8, 32, 64}) {
+      double med = 0.0;
+      bool usable = false;
+      res = time_cand(best, tw, med, usable);
+      if (res != PSM_OK) break;
+      if (usable && med < best_ms) {
         best_ms = med;
-        best = tu;
+        best_tw = tw;
       }
+    }
+    // stage 2: schedules and pass widths at that shape
+    if (res == PSM_OK) {
+      const Tuning base = best;
+      best_ms = 1e300;
+      for (int sched = 0; sched < 2 && res == PSM_OK; ++sched)
+        for (int sched_bwd = 0; sched_bwd < 2 && res == PSM_OK; ++sched_bwd)
+          for (int bp : {16, 32})
+            for (int gp : {16, 32}) {
+              if (res != PSM_OK) break;
+              if (!bwd && sched_bwd != 0) continue;
+              if (!feat && (bp != 32 || gp != 16)) continue;
+              if (feat && !bwd && gp != 16) continue;
+              const Tuning tu{sched, sched_bwd, bp, gp};
+              double med = 0.0;
+              bool usable = false;
+              res = time_cand(tu, best_tw, med, usable);
+              if (res == PSM_OK && usable && med < best_ms) {
+                best_ms = med;
+                best = tu;
+              }
+            }
+      if (res == PSM_OK && best_ms == 1e300) best = base;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (res != PSM_OK) return res;
-    const CamTable ct = cam_table(cams, n_cams, s->n);
-    const Layout L = make_layout(ct, cfg->k, s->c, pair_capacity);
-    uint32_t h[kStWords];
-    r = read_status(L, workspace, h, st);
-    if (r != PSM_OK) return r;
-    if (h[kStOverflow]) return capacity_error(L, h);
-    ctx->tuned.push_back(TuneKey{key, best, best_ms});
-    cfg->schedule = best.sched;
-    cfg->bwd_schedule = best.sched_bwd;
-    cfg->blend_pass = best.blend_pass;
-    cfg->bwd_pass = best.bwd_pass;
+    if (best_ms == 1e300)
+      return fail(PSM_ERR_CAPACITY, "psm_autotune: no candidate fits the workspace and its pair capacity");
+    ctx->tuned.push_back(TuneKey{key, best, best_tw, best_ms});
+    apply(best, best_tw);
     if (best_ms_out) *best_ms_out = best_ms;
     g_err.clear();
     return PSM_OK;
@@ -898,7 +939,7 @@ psm_status psm_frustum_attention(psm_ctx* ctx, int64_t n, const float* means, co
     aa.n = n;
     aa.means = means;
     aa.scales = scales;
-    const CamTable ct = cam_table(cam, 1, n);
+    const CamTable ct = cam_table(cam, 1, n, nullptr);  // only the camera parameters are used
     aa.cam = ct.cam[0];
     aa.nq = a->n_q;
     aa.c = a->c;
@@ -974,7 +1015,7 @@ psm_status psm_forward_static(psm_ctx* ctx, const psm_surfels* s, const psm_came
     if (r != PSM_OK) return r;
     r = validate_common(cam, 1, cfg, s->n, s->c, pair_capacity < 0 ? 0 : pair_capacity);
     if (r != PSM_OK) return r;
-    const CamTable ct = cam_table(cam, 1, s->n);
+    const CamTable ct = cam_table(cam, 1, s->n, cfg);
     const size_t limit = PSM_STATIC_WORKSPACE_BYTES;
     const size_t base = make_layout(ct, cfg->k, s->c, 0).total;
     if (base > limit)

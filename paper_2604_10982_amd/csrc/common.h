@@ -23,8 +23,12 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 
-constexpr int kTile = 16;               // 16x16 pixel tiles
-constexpr int kTilePix = kTile * kTile; // one pixel per thread, 4 waves
+// A tile has kTilePix = 256 pixels, one per thread of a 4-wave block: tw x th
+// pixels with tw in {8, 16, 32, 64} (a launch choice, 16 x 16 by default),
+// row-major inside the tile, so wave w owns the tile rows
+// [w * 64 / tw, (w + 1) * 64 / tw).
+constexpr int kTilePix = 256;
+constexpr int kTileDefault = 16;
 constexpr int kMaxK = 32;
 constexpr int kRecWords = 6;             // 16-byte words per surfel walk record
 
@@ -88,11 +92,16 @@ struct CamArgs {
 struct CamTable {
   int n;
   int64_t nsurf;
+  int tw, th, tsh;  // tile width and height in pixels (tw * th = 256), log2(tw)
   CamArgs cam[kMaxCams];
   int ntx[kMaxCams], nty[kMaxCams];
   int tile0[kMaxCams + 1];
   int64_t pix0[kMaxCams + 1];
 };
+
+// Tile-local column and row of pixel p (0..255) of a tile.
+__host__ __device__ inline int tile_lx(const CamTable& ct, int p) { return p & (ct.tw - 1); }
+__host__ __device__ inline int tile_ly(const CamTable& ct, int p) { return p >> ct.tsh; }
 
 // Where global tile g lies: its camera, tile coordinates and image.
 struct TileLoc {
@@ -305,9 +314,9 @@ __device__ __forceinline__ bool eval_pixel(const LRec& s, float lx, float ly, Pi
   return e.alpha >= kAlphaMin;
 }
 
-// Band culling of the walks: a wave owns 4 rows of its tile and skips a
-// surfel whose footprint ellipse's y-extent (centre ecy, half-extent ey, the
-// key stage's FP32 values) misses the rows' pixel centres.  The footprint
+// Band culling of the walks: a wave owns 64 / tw rows of its tile and skips
+// a surfel whose footprint ellipse's y-extent (centre ecy, half-extent ey,
+// the key stage's FP32 values) misses the rows' pixel centres.  The footprint
 // contains every pixel the per-pixel test can hit; the slack covers the FP32
 // rounding of the band edges (ulp(16384) = 2^-9 px).
 constexpr float kBandSlack = 0.015625f;

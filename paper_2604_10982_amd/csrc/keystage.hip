@@ -160,11 +160,11 @@ __device__ __forceinline__ void walk_record(const float* mu_f, const float* sc, 
 }
 
 // Tiles whose pixel-centre hull [t*T + 0.5, min(t*T + T - 0.5, npix - 0.5)]
-// meets [lo, hi] along one axis.
-__device__ __forceinline__ bool tile_span(float lo, float hi, int npix, int nt, int& t0, int& t1) {
+// meets [lo, hi] along one axis (T = the tile's size along it).
+__device__ __forceinline__ bool tile_span(float lo, float hi, int npix, int T, int nt, int& t0, int& t1) {
   if (!(hi >= 0.5f) || !(lo <= (float)npix - 0.5f)) return false;
-  float f0 = ceilf((lo - ((float)kTile - 0.5f)) / (float)kTile);
-  float f1 = floorf((hi - 0.5f) / (float)kTile);
+  float f0 = ceilf((lo - ((float)T - 0.5f)) / (float)T);
+  float f1 = floorf((hi - 0.5f) / (float)T);
   f0 = fmaxf(f0, 0.0f);
   f1 = fminf(f1, (float)(nt - 1));
   if (!(f0 <= f1)) return false;
@@ -178,7 +178,8 @@ __device__ __forceinline__ bool tile_span(float lo, float hi, int npix, int nt, 
 // the disk's box joins every mode's box, and the exact mode takes, per row,
 // the hull of the ellipse's and the disk's x-extents within the row's band.
 template <class F>
-__device__ __forceinline__ void for_each_row(const Foot& f, int mode, int W, int H, int ntx, int nty, F&& fn) {
+__device__ __forceinline__ void for_each_row(const Foot& f, int mode, int W, int H, int tw, int th, int ntx, int nty,
+                                             F&& fn) {
   const bool lp = f.rf2 > 0.0f;
   const float rf = lp ? sqrtf(f.rf2) : 0.0f;
   int ax0, ax1, ay0, ay1;
@@ -204,8 +205,8 @@ __device__ __forceinline__ void for_each_row(const Foot& f, int mode, int W, int
     by0 = fminf(by0, f.yc - rf);
     by1 = fmaxf(by1, f.yc + rf);
   }
-  if (!tile_span(bx0, bx1, W, ntx, ax0, ax1)) return;
-  if (!tile_span(by0, by1, H, nty, ay0, ay1)) return;
+  if (!tile_span(bx0, bx1, W, tw, ntx, ax0, ax1)) return;
+  if (!tile_span(by0, by1, H, th, nty, ay0, ay1)) return;
   if (mode != kEllipse) {
     for (int ty = ay0; ty <= ay1; ++ty) fn(ty, ax0, ax1);
     return;
@@ -213,8 +214,8 @@ __device__ __forceinline__ void for_each_row(const Foot& f, int mode, int W, int
   // exact ellipse: x-extent of the ellipse inside each tile row's band
   const float yr = f.S01 / f.ex;
   for (int ty = ay0; ty <= ay1; ++ty) {
-    const float rlo = (float)(ty * kTile) + 0.5f;
-    const float rhi = fminf((float)(ty * kTile) + ((float)kTile - 0.5f), (float)H - 0.5f);
+    const float rlo = (float)(ty * th) + 0.5f;
+    const float rhi = fminf((float)(ty * th) + ((float)th - 0.5f), (float)H - 0.5f);
     const float ylo = rlo - f.ecy;
     const float yhi = rhi - f.ecy;
     const float lo = fmaxf(ylo, -f.ey), hi = fminf(yhi, f.ey);
@@ -245,7 +246,7 @@ __device__ __forceinline__ void for_each_row(const Foot& f, int mode, int W, int
     }
     if (!have) continue;
     int x0, x1;
-    if (!tile_span(xl, xr, W, ntx, x0, x1)) continue;
+    if (!tile_span(xl, xr, W, tw, ntx, x0, x1)) continue;
     x0 = max(x0, ax0);
     x1 = min(x1, ax1);
     if (x0 <= x1) fn(ty, x0, x1);
@@ -301,7 +302,7 @@ __global__ __launch_bounds__(256) void k_preprocess(
     } else {
       key[v] = __float_as_uint(kk.mc2);
       uint32_t c = 0;
-      for_each_row(kk.f, mode, cam.W, cam.H, ct.ntx[b], ct.nty[b],
+      for_each_row(kk.f, mode, cam.W, cam.H, ct.tw, ct.th, ct.ntx[b], ct.nty[b],
                    [&](int, int x0, int x1) { c += (uint32_t)(x1 - x0 + 1); });
       count[v] = c;
       fp[3 * v + 0] = make_float4(kk.f.ecx, kk.f.ecy, kk.f.S00, kk.f.S01);
@@ -427,7 +428,7 @@ __global__ __launch_bounds__(256) void k_emit(int64_t nv, const uint32_t* __rest
   const float4 f0 = fp[3 * (size_t)v], f1 = fp[3 * (size_t)v + 1], f2 = fp[3 * (size_t)v + 2];
   const Foot f{f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w, f2.x, f2.y, f2.z, f2.w};
   int64_t o = offs[r];
-  for_each_row(f, mode, ct.cam[b].W, ct.cam[b].H, ntx, ct.nty[b], [&](int ty, int x0, int x1) {
+  for_each_row(f, mode, ct.cam[b].W, ct.cam[b].H, ct.tw, ct.th, ntx, ct.nty[b], [&](int ty, int x0, int x1) {
     for (int tx = x0; tx <= x1; ++tx, ++o) {
       if (o < cap) {
         ptile[o] = (uint32_t)(t0 + ty * ntx + tx);

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
   const TileLoc tl = locate(ct, tile);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int px = tl.tx * kTile + (tid & 15), py = tl.ty * kTile + (tid >> 4);
+  const int px = tl.tx * ct.tw + tile_lx(ct, tid), py = tl.ty * ct.th + tile_ly(ct, tid);
   const bool inside = px < tl.W && py < tl.H;
   const uint32_t start = ranges[tile].x;
   const size_t tbase = (size_t)tile * K * kTilePix;
@@ -330,11 +330,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
   const TileLoc tl = locate(ct, tile);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tx = tl.tx, ty = tl.ty, W = tl.W, H = tl.H;
-  const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
+  const int qx0 = tile_lx(ct, tid), qy0 = tile_ly(ct, tid), rpw = 64 >> ct.tsh;  // rows per wave
+  const int px = tx * ct.tw + qx0, py = ty * ct.th + qy0;
   const bool inside = px < W && py < H;
-  const float lx = (float)(tid & 15) + 0.5f, ly = (float)(tid >> 4) + 0.5f;
-  const float tx0 = (float)(tx * kTile), ty0 = (float)(ty * kTile);
-  const float yb0 = ty0 + (float)(4 * wave) + 0.5f, yb1 = yb0 + 3.0f;  // this wave's rows
+  const float lx = (float)qx0 + 0.5f, ly = (float)qy0 + 0.5f;
+  const float tx0 = (float)(tx * ct.tw), ty0 = (float)(ty * ct.th);
+  const float yb0 = ty0 + (float)(rpw * wave) + 0.5f, yb1 = yb0 + (float)(rpw - 1);  // this wave's rows
   const uint32_t start = ranges[tile].x;
   const int sp = tile * kTilePix + tid;
   const int my_last = (int)nlast[sp];
@@ -407,7 +408,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
         float* ph = s_ph[wave];
         for (int pb = 0; pb < 4; ++pb) {
           const int q = 64 * wave + 16 * pb + li;  // pixel of lane li
-          const int qx = tx * kTile + (q & 15), qy = ty * kTile + (q >> 4);
+          const int qx = tx * ct.tw + tile_lx(ct, q), qy = ty * ct.th + tile_ly(ct, q);
           const float* gq = qx < W && qy < H ? g_feat + (tl.pix0 + (int64_t)qy * W + qx) * C : nullptr;
           f4v acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
           // 128 channels at a time: every operand of the segment is loaded
@@ -573,25 +574,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
           const int c = 16 * cb + li;
           f4v racc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
           const float* wrow = s_om[16 * eb + li];
-          // 8 tile rows at a time: their 32 G values are loaded together
-          for (int y0 = 0; y0 < kTile; y0 += 8) {
-            float b[8][4];
+          // 32 pixels (8 steps of 4: pixels 4 t + lk, row-major in the tile) at
+          // a time: their G values are loaded together
+          for (int t0 = 0; t0 < kTilePix / 4; t0 += 8) {
+            float b[8];
 #pragma unroll
-            for (int y = 0; y < 8; ++y) {
-              const bool rowin = ty * kTile + y0 + y < H && c < C;
-              const float* g =
-                  g_feat + (tl.pix0 + (int64_t)(rowin ? ty * kTile + y0 + y : 0) * W + tx * kTile) * C + c;
-#pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                const int x = 4 * u + lk;
-                b[y][u] = rowin && tx * kTile + x < W ? g[x * C] : 0.0f;
-              }
+            for (int t = 0; t < 8; ++t) {
+              const int q = 4 * (t0 + t) + lk;
+              const int qx = tx * ct.tw + tile_lx(ct, q), qy = ty * ct.th + tile_ly(ct, q);
+              b[t] = qx < W && qy < H && c < C ? g_feat[(tl.pix0 + (int64_t)qy * W + qx) * C + c] : 0.0f;
             }
 #pragma unroll
-            for (int y = 0; y < 8; ++y)
-#pragma unroll
-              for (int u = 0; u < 4; ++u)
-                racc[y & 1] = mfma_16x16x4(wrow[16 * (y0 + y) + 4 * u + lk], b[y][u], racc[y & 1]);
+            for (int t = 0; t < 8; ++t) racc[t & 1] = mfma_16x16x4(wrow[4 * (t0 + t) + lk], b[t], racc[t & 1]);
           }
           const f4v rs = racc[0] + racc[1];
           if (c < C) {

@@ -72,11 +72,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   const TileLoc tl = locate(ct, tile);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tx = tl.tx, ty = tl.ty, W = tl.W, H = tl.H;
-  const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
+  const int qx = tile_lx(ct, tid), qy = tile_ly(ct, tid), rpw = 64 >> ct.tsh;  // rows per wave
+  const int px = tx * ct.tw + qx, py = ty * ct.th + qy;
   const bool inside = px < W && py < H;
-  const float lx = (float)(tid & 15) + 0.5f, ly = (float)(tid >> 4) + 0.5f;
-  const float tx0 = (float)(tx * kTile), ty0 = (float)(ty * kTile);
-  const float yb0 = ty0 + (float)(4 * wave) + 0.5f, yb1 = yb0 + 3.0f;  // this wave's rows
+  const float lx = (float)qx + 0.5f, ly = (float)qy + 0.5f;
+  const float tx0 = (float)(tx * ct.tw), ty0 = (float)(ty * ct.th);
+  const float yb0 = ty0 + (float)(rpw * wave) + 0.5f, yb1 = yb0 + (float)(rpw - 1);  // this wave's rows
   const uint2 rg = ranges[tile];
   const int L = (int)(rg.y - rg.x);
   const uint32_t* ids = pid + rg.x;
@@ -283,7 +284,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE || KMA
   auto body = [&](const int tile) {
   const TileLoc tl = locate(ct, tile);
   const int tid = threadIdx.x;
-  const int px = tl.tx * kTile + (tid & 15), py = tl.ty * kTile + (tid >> 4);
+  const int px = tl.tx * ct.tw + tile_lx(ct, tid), py = tl.ty * ct.th + tile_ly(ct, tid);
   const bool inside = px < tl.W && py < tl.H;
   const uint32_t start = ranges[tile].x;
   const size_t tbase = (size_t)tile * K * kTilePix;
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE || KMA
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
       const int p = base + k;
-      const int qx = tl.tx * kTile + (p & 15), qy = tl.ty * kTile + (p >> 4);
+      const int qx = tl.tx * ct.tw + tile_lx(ct, p), qy = tl.ty * ct.th + tile_ly(ct, p);
       if (qx < tl.W && qy < tl.H && cc + 4 * gi < C)
         *reinterpret_cast<float4*>(o_feat + (tl.pix0 + (int64_t)qy * tl.W + qx) * C + cc + 4 * gi) = a[k];
     }
@@ -442,9 +443,10 @@ __global__ __launch_bounds__(256) void k_full_feat(const WalkRec* __restrict__ r
   const TileLoc tl = locate(ct, tile);
   const int tid = threadIdx.x;
   const int tx = tl.tx, ty = tl.ty;
-  const int px = tx * kTile + (tid & 15), py = ty * kTile + (tid >> 4);
+  const int qx = tile_lx(ct, tid), qy = tile_ly(ct, tid);
+  const int px = tx * ct.tw + qx, py = ty * ct.th + qy;
   const bool inside = px < tl.W && py < tl.H;
-  const float lx = (float)(tid & 15) + 0.5f, ly = (float)(tid >> 4) + 0.5f;
+  const float lx = (float)qx + 0.5f, ly = (float)qy + 0.5f;
   const uint32_t start = ranges[tile].x;
   const int my_last = (int)nlast[tile * kTilePix + tid];
   __syncthreads();
@@ -464,7 +466,7 @@ __global__ __launch_bounds__(256) void k_full_feat(const WalkRec* __restrict__ r
       if (tid < nb) {
         const uint32_t id = pid[start + base + tid];
         s_id[tid] = (uint32_t)(id - tl.v0);
-        s_r.put(tid, rec[id], (float)(tx * kTile), (float)(ty * kTile));
+        s_r.put(tid, rec[id], (float)(tx * ct.tw), (float)(ty * ct.th));
       }
       __syncthreads();
       for (int e = tid; e < nb * CH; e += 256) {
@@ -508,7 +510,7 @@ __global__ __launch_bounds__(256) void k_export_sel(const uint32_t* __restrict__
   const int tile = blockIdx.x;
   const int tid = threadIdx.x;
   const TileLoc tl = locate(ct, tile);
-  const int px = tl.tx * kTile + (tid & 15), py = tl.ty * kTile + (tid >> 4);
+  const int px = tl.tx * ct.tw + tile_lx(ct, tid), py = tl.ty * ct.th + tile_ly(ct, tid);
   if (px >= tl.W || py >= tl.H) return;
   const int64_t pix = tl.pix0 + (int64_t)py * tl.W + px;
   const uint32_t start = ranges[tile].x;

@@ -66,7 +66,7 @@ class Camera(C.Structure):
 class Config(C.Structure):
     _fields_ = [("k", C.c_int32), ("tile_mode", C.c_int32), ("blend", C.c_int32), ("flags", C.c_int32),
                 ("schedule", C.c_int32), ("blend_pass", C.c_int32), ("bwd_pass", C.c_int32),
-                ("bwd_schedule", C.c_int32)]
+                ("bwd_schedule", C.c_int32), ("tile_w", C.c_int32)]
 
 
 class Queries(C.Structure):
@@ -210,12 +210,14 @@ def camera_struct(cam) -> Camera:
 
 
 def config_struct(k: int, tile_mode="ellipse", blend="topk", flags: int = 0, schedule: int = SCHED_GRID,
-                  blend_pass: int = 0, bwd_pass: int = 0, bwd_schedule: int | None = None) -> Config:
-    """bwd_schedule defaults to the forward's schedule."""
+                  blend_pass: int = 0, bwd_pass: int = 0, bwd_schedule: int | None = None,
+                  tile_w: int = 0) -> Config:
+    """bwd_schedule defaults to the forward's schedule; tile_w 0 = 16 x 16
+    tiles (else tile_w x 256 / tile_w, tile_w in 8, 16, 32, 64)."""
     tm = TILE_MODES[tile_mode] if isinstance(tile_mode, str) else int(tile_mode)
     bl = BLENDS[blend] if isinstance(blend, str) else int(blend)
     bs = int(schedule) if bwd_schedule is None else int(bwd_schedule)
-    return Config(int(k), tm, bl, int(flags), int(schedule), int(blend_pass), int(bwd_pass), bs)
+    return Config(int(k), tm, bl, int(flags), int(schedule), int(blend_pass), int(bwd_pass), bs, int(tile_w))
 
 
 def _ptr(t):
@@ -234,6 +236,7 @@ class Workspace:
     n: int
     c: int
     k: int
+    tile_w: int = 0
 
     @property
     def nbytes(self) -> int:
@@ -250,7 +253,21 @@ def alloc_workspace(n, cam: Camera, cfg: Config, c: int, capacity: int, device) 
     nbytes = workspace_size(n, cam, cfg, c, capacity)
     buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
     off = (-buf.data_ptr()) % 256
-    return Workspace(buf[off:off + nbytes], capacity, n, c, cfg.k)
+    return Workspace(buf[off:off + nbytes], capacity, n, c, cfg.k, int(cfg.tile_w))
+
+
+def alloc_workspace_shapes(n, cams, cfg: Config, c: int, capacity: int, device, tile_ws=(8, 16, 32, 64)) -> Workspace:
+    """A workspace that holds the layout of every listed tile width (for the
+    autotuner, which times each shape in the same workspace)."""
+    carr = camera_array(list(cams))
+    nbytes = 0
+    for tw in tile_ws:
+        c2 = Config.from_buffer_copy(cfg)
+        c2.tile_w = int(tw)
+        nbytes = max(nbytes, workspace_size_batch(n, carr, c2, c, capacity))
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return Workspace(buf[off:off + nbytes], capacity, n, c, cfg.k, int(cfg.tile_w))
 
 
 def _surfels(means, scales, quats, opacity, rgb, feat) -> Surfels:
@@ -317,11 +334,14 @@ def backward_into(ctx: Context, s: Surfels, cam: Camera, cfg: Config, ws: Worksp
 
 def launch_config(k: int, tile_mode="ellipse", blend="topk", flags: int = 0, launch=None) -> Config:
     """Config with the launch choices ``launch`` = (schedule, bwd_schedule,
-    blend_pass, bwd_pass), or the defaults (grid schedules, default passes)."""
+    blend_pass, bwd_pass[, tile_w]), or the defaults (grid schedules, default
+    passes, 16 x 16 tiles)."""
     if launch is None:
         return config_struct(k, tile_mode, blend, flags)
-    sched, bsched, bp, fp = (int(v) for v in launch)
-    return config_struct(k, tile_mode, blend, flags, sched, bp, fp, bsched)
+    v = [int(x) for x in launch]
+    sched, bsched, bp, fp = v[:4]
+    tw = v[4] if len(v) > 4 else 0
+    return config_struct(k, tile_mode, blend, flags, sched, bp, fp, bsched, tw)
 
 
 def forward(means, scales, quats, opacity, rgb, feat, camera, k=16, tile_mode="ellipse", blend="topk",
@@ -339,7 +359,8 @@ def forward(means, scales, quats, opacity, rgb, feat, camera, k=16, tile_mode="e
     out = alloc_images(cam, s.c, device, feature_only=bool(flags & FLAG_FEATURE_ONLY))
     cap = capacity if capacity is not None else (ws.capacity if ws is not None else capacity_guess(s.n, cam))
     for attempt in range(3):
-        if ws is None or ws.capacity < cap or ws.n != s.n or ws.c != s.c or ws.k != cfg.k:
+        if (ws is None or ws.capacity < cap or ws.n != s.n or ws.c != s.c or ws.k != cfg.k
+                or ws.tile_w != cfg.tile_w):
             ws = alloc_workspace(s.n, cam, cfg, s.c, cap, device)
         try:
             forward_into(ctx, s, cam, cfg, ws, out)
@@ -453,7 +474,7 @@ def alloc_workspace_batch(n, cams: C.Array, cfg: Config, c: int, capacity: int, 
     nbytes = workspace_size_batch(n, cams, cfg, c, capacity)
     buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
     off = (-buf.data_ptr()) % 256
-    return Workspace(buf[off:off + nbytes], capacity, n, c, cfg.k)
+    return Workspace(buf[off:off + nbytes], capacity, n, c, cfg.k, int(cfg.tile_w))
 
 
 def total_pixels(cams: C.Array) -> int:
@@ -518,7 +539,8 @@ def forward_batch(means, scales, quats, opacity, rgb, feat, cams, k=16, tile_mod
     out = alloc_images_batch(cams, s.c, device)
     cap = capacity if capacity is not None else (ws.capacity if ws is not None else capacity_guess_batch(s.n, cams))
     for attempt in range(3):
-        if ws is None or ws.capacity < cap or ws.n != s.n or ws.c != s.c or ws.k != cfg.k:
+        if (ws is None or ws.capacity < cap or ws.n != s.n or ws.c != s.c or ws.k != cfg.k
+                or ws.tile_w != cfg.tile_w):
             ws = alloc_workspace_batch(s.n, cams, cfg, s.c, cap, device)
         try:
             forward_batch_into(ctx, s, cams, cfg, ws, out)
@@ -604,8 +626,8 @@ def autotune(ctx: Context, s: Surfels, cams: C.Array, cfg: Config, ws: Workspace
                 table = json.load(f)
         except (OSError, ValueError):
             table = {}
-    if cache and key in table and len(table[key]) == 4:
-        cfg.schedule, cfg.bwd_schedule, cfg.blend_pass, cfg.bwd_pass = (int(v) for v in table[key])
+    if cache and key in table and len(table[key]) == 5:
+        cfg.schedule, cfg.bwd_schedule, cfg.blend_pass, cfg.bwd_pass, cfg.tile_w = (int(v) for v in table[key])
         return None
     imgs = Images(*(_ptr(out.get(k)) for k in ("rgb", "depth", "normal", "alpha", "feat")))
     g = ImageGrads(*(_ptr((gout or {}).get(k)) for k in ("rgb", "depth", "normal", "alpha", "feat")))
@@ -616,7 +638,8 @@ def autotune(ctx: Context, s: Surfels, cams: C.Array, cfg: Config, ws: Workspace
                               C.byref(gr) if bwd else None, int(reps), C.byref(best), _stream(ctx.device)),
            "psm_autotune")
     if cache:
-        table[key] = [int(cfg.schedule), int(cfg.bwd_schedule), int(cfg.blend_pass), int(cfg.bwd_pass)]
+        table[key] = [int(cfg.schedule), int(cfg.bwd_schedule), int(cfg.blend_pass), int(cfg.bwd_pass),
+                      int(cfg.tile_w)]
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
             tmp = path + f".tmp{os.getpid()}"

@@ -56,6 +56,15 @@ def test_host_validation(psm):
     assert L.psm_workspace_size(100, C.byref(cam), C.byref(ok), 12, 1000, C.byref(out)) == psm.ERR_UNSUPPORTED
     assert L.psm_workspace_size(-1, C.byref(cam), C.byref(ok), 16, 1000, C.byref(out)) == psm.ERR_INVALID_ARG
     assert L.psm_workspace_size(100, C.byref(cam), C.byref(ok), 16, -5, C.byref(out)) == psm.ERR_INVALID_ARG
+    for tw in (4, 12, 128):
+        assert L.psm_workspace_size(100, C.byref(cam), C.byref(psm.config_struct(16, tile_w=tw)), 16, 1000,
+                                    C.byref(out)) == psm.ERR_INVALID_ARG
+    sizes = []
+    for tw in (0, 8, 16, 32, 64):  # tile shapes tw x 256/tw: the pixel state covers 256 pixels per tile
+        assert L.psm_workspace_size(100, C.byref(cam), C.byref(psm.config_struct(16, tile_w=tw)), 16, 1000,
+                                    C.byref(out)) == 0
+        sizes.append(out.value)
+    assert sizes[0] == sizes[2]
     bad = _cam(psm)
     bad.near_plane = 0.0
     assert L.psm_workspace_size(100, C.byref(bad), C.byref(ok), 16, 1000, C.byref(out)) == psm.ERR_INVALID_ARG

@@ -335,3 +335,56 @@ def test_sphere_footprint_by_hand(orc, theta_deg):
     assert set(orc.keystage(sc, cam, "aabb")["tile"].tolist()) == square_tiles(ex, ey, True)
     for wrong in (Rv, max(ex, ey), math.sqrt(0.5 * (ex * ex + ey * ey))):
         assert square_tiles(wrong, wrong, False) != exp
+
+
+SHAPES = ((8, 32), (32, 8), (64, 4))
+
+
+@pytest.mark.parametrize("tw,th", SHAPES)
+def test_tile_shapes_no_false_negatives_and_nested(orc, scene_cam, tw, th):
+    """Non-square tiles (Sec. 5's tile-based rasterisation with a tile shape
+    the autotuner may pick): every (tile, surfel) with a pixel inside the
+    cutoff, by dense FP64 evaluation, is listed in every mode, and the modes
+    stay nested."""
+    sc, cam = scene_cam
+    ys, xs = np.mgrid[0:cam.height, 0:cam.width]
+    rho, _ = orc.eval_points(sc, cam, xs.ravel() + 0.5, ys.ravel() + 0.5)
+    ntx = (cam.width + tw - 1) // tw
+    tile_of_pix = (ys.ravel() // th) * ntx + xs.ravel() // tw
+    si, pi = np.nonzero(rho <= 9.0)
+    required = set(zip(tile_of_pix[pi].tolist(), si.tolist()))
+    assert len(required) > 300
+    sets = {}
+    for mode in ("sphere", "aabb", "ellipse"):
+        sets[mode] = pair_set(orc.keystage(sc, cam, mode, tile=(tw, th)))
+        missing = required - sets[mode]
+        assert not missing, (mode, sorted(missing)[:10])
+    assert sets["ellipse"] <= sets["aabb"] <= sets["sphere"]
+
+
+@pytest.mark.parametrize("tw,th", SHAPES)
+def test_tile_shapes_ellipse_list_is_exact(orc, scene_cam, tw, th):
+    """The exact-ellipse list for a non-square tile shape against the FP64
+    continuous ellipse/rectangle test (the convex quadratic minimised over
+    each tile's pixel-centre hull), away from the boundary."""
+    sc, cam = scene_cam
+    ks = orc.keystage(sc, cam, "ellipse", tile=(tw, th))
+    got = pair_set(ks)
+    ntx, nty = (cam.width + tw - 1) // tw, (cam.height + th - 1) // th
+    checked = mism = 0
+    for i in np.nonzero(ks["cull"] == 0)[0][:60]:
+        M = _camera_matrix(sc, cam, i)
+        for ty in range(nty):
+            for tx in range(ntx):
+                hull = (tw * tx + 0.5, min(tw * tx + tw - 0.5, cam.width - 0.5),
+                        th * ty + 0.5, min(th * ty + th - 0.5, cam.height - 0.5))
+                lo = _ellipse_meets(M, R_FOOT2 * (1 - 1e-4), hull)
+                hi = _ellipse_meets(M, R_FOOT2 * (1 + 1e-4), hull)
+                listed = (ty * ntx + tx, int(i)) in got
+                checked += 1
+                if lo == hi:
+                    assert listed == lo, (i, tx, ty)
+                else:
+                    mism += 1
+    assert checked > 1000
+    assert mism < 0.01 * checked

@@ -90,7 +90,9 @@ typedef struct {
    * A backward must use the values of its forward. */
   int32_t schedule;   /* psm_schedule */
   int32_t blend_pass; /* feature channels per Top-K blend pass: 0 (= 32), 16 or 32 */
-  int32_t bwd_pass;   /* feature channels per feature-backward pass: 0 (= 16), 16 or 32 */
+  int32_t bwd_pass;   /* feature channels per feature-backward pass: 0 (= 16), 16 or 32; with the dense
+                       * blend it selects the backward's feature contractions: 16 vector FMAs,
+                       * 32 matrix cores (the same sums in another order) */
   int32_t bwd_schedule; /* psm_schedule of the backward's tile kernels */
   /* Tile shape: tile_w x (256 / tile_w) pixels, tile_w in {8, 16, 32, 64};
    * 0 = 16 (16 x 16 tiles, Sec. 5's tile-based rasterisation).  One 256-thread

@@ -762,6 +762,8 @@ psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
       return PSM_OK;
     };
     const bool feat = s->c > 0 && cfg->blend == PSM_BLEND_TOPK;
+    // dense blend with a backward: the pass width picks the feature contraction's unit
+    const bool dense_bwd = bwd && s->c > 0 && cfg->blend == PSM_BLEND_FULL;
     Tuning best{kSchedPersistent, bwd ? kSchedPersistent : 0, 32, 16};
     int best_tw = cfg->tile_w == 0 ? kTileDefault : cfg->tile_w;
     double best_ms = 1e300;
@@ -787,7 +789,8 @@ psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
             for (int gp : {16, 32}) {
               if (res != PSM_OK) break;
               if (!bwd && sched_bwd != 0) continue;
-              if (!feat && (bp != 32 || gp != 16)) continue;
+              if (!feat && bp != 32) continue;
+              if (!feat && !dense_bwd && gp != 16) continue;
               if (feat && !bwd && gp != 16) continue;
               const Tuning tu{sched, sched_bwd, bp, gp};
               double med = 0.0;

@@ -296,7 +296,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
 }
 
 // ------------------------------------------------------------- walk backward
-template <int MODE, typename FT, bool PERSIST, bool LP>
+// DM (dense mode only): the batch's feature contractions on the matrix cores
+// (true) or in vector FMAs (false); a launch choice, whichever is faster for
+// the workload (the autotuner times both).
+template <int MODE, typename FT, bool PERSIST, bool LP, bool DM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTopK ? 4 : 1))) void k_walk_bwd(
     const WalkRec* __restrict__ rec, const float4* __restrict__ ext, const uint32_t* __restrict__ pid, const uint32_t* __restrict__ eid,
     const uint2* __restrict__ ranges, CamTable ct, TileQueue tq, int K, const uint32_t* __restrict__ nlast,
@@ -316,7 +319,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
   // the batch weights (rows padded to 260 floats: the matrix-core operand
   // reads of 16 entries x 4 pixels fall in distinct banks)
   constexpr int kPhS = kBB + 4, kOmS = kTilePix + 4;
-  __shared__ float s_ph[MODE == kFull ? 4 : 1][16 * kPhS];
+  __shared__ float s_ph[MODE == kFull && DM ? 4 : 1][16 * kPhS];
+  __shared__ float s_fc[MODE == kFull && !DM ? kBB : 1][64];  // vector form: the batch's feature chunk
   __shared__ __align__(16) float s_om[MODE == kFull ? kBB : 1][kOmS];
   // Top-K mode: every pixel's selected list positions ([K][256]), read back
   // to front by the pixel's own lane; the feature dots stay in global memory,
@@ -394,7 +398,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
     // component i feeding step i); the tile goes through the wave's LDS
     // region to the lanes of its pixels
     float phi[MODE == kFull ? kBB : 1];
-    if constexpr (MODE == kFull) {
+    if constexpr (MODE == kFull && !DM) {
+      // vector form: feature chunks of 64 channels staged in LDS, each pixel
+      // its 32 dots (LDS reads by broadcast)
+#pragma unroll
+      for (int k = 0; k < kBB; ++k) phi[k] = 0.0f;
+      if (g_feat) {
+        const float* grow = g_feat + pix * C;
+        const bool has_gf = inside;
+        for (int c0 = 0; c0 < C; c0 += 64) {
+          for (int e = tid; e < nb * 64; e += 256) {
+            const int k = e >> 6, c = e & 63;
+            s_fc[k][c] = (c0 + c < C) ? load_one<FT>(feat + (size_t)(s_id[k] - tl.v0) * C + c0 + c) : 0.0f;
+          }
+          __syncthreads();
+          if (has_gf) {
+            const int cn = min(64, C - c0);
+            for (int c = 0; c < cn; c += 4) {
+              const float4 g = *reinterpret_cast<const float4*>(grow + c0 + c);
+#pragma unroll
+              for (int k = 0; k < kBB; ++k)
+                phi[k] = fmaf(g.x, s_fc[k][c], fmaf(g.y, s_fc[k][c + 1], fmaf(g.z, s_fc[k][c + 2], fmaf(g.w, s_fc[k][c + 3], phi[k]))));
+            }
+          }
+          __syncthreads();
+        }
+      }
+    }
+    if constexpr (MODE == kFull && DM) {
 #pragma unroll
       for (int k = 0; k < kBB; ++k) phi[k] = 0.0f;
       if (g_feat) {
@@ -564,28 +595,94 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
     // of 16) dealt to the waves, each a sum over the 256 pixels in 64 steps
     // of 4 (pixels 16 y + 4 u + lk of tile row y), written at the pair's
     // emission index
-    if constexpr (MODE == kFull) {
+    if constexpr (MODE == kFull && !DM) {
+      // vector form: wave w takes 8 surfels of the batch, lane = channel, the
+      // 256 pixels 8 at a time (8 independent upstream loads in flight;
+      // pixels outside the image have zero weight and read as zero)
+      if (g_feat) {
+        __syncthreads();
+        constexpr int PER = kBB / 4;
+        // the tile's pixels inside the image: wl columns, hl rows; pixel
+        // offsets from the tile's first one are below 2^29 (W, C and the tile
+        // height are bounded)
+        const int wl = min(ct.tw, W - tx * ct.tw), hl = min(ct.th, H - ty * ct.th), wc = W * C;
+        for (int c0 = 0; c0 < C; c0 += 64) {
+          const int c = c0 + lane;
+          float acc[PER];
+#pragma unroll
+          for (int j = 0; j < PER; ++j) acc[j] = 0.0f;
+          if (c < C) {
+            const float* gt = g_feat + (tl.pix0 + (int64_t)(ty * ct.th) * W + tx * ct.tw) * C + c;
+            for (int p0 = 0; p0 < kTilePix; p0 += 8) {
+              float g[8];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) {
+                const int p = p0 + u, lx = tile_lx(ct, p), ly = tile_ly(ct, p);
+                g[u] = lx < wl && ly < hl ? gt[ly * wc + lx * C] : 0.0f;
+              }
+#pragma unroll
+              for (int j = 0; j < PER; ++j) {
+                const float4 w0 = *reinterpret_cast<const float4*>(&s_om[wave * PER + j][p0]);
+                const float4 w1 = *reinterpret_cast<const float4*>(&s_om[wave * PER + j][p0 + 4]);
+                float a = acc[j];
+                a = fmaf(w0.x, g[0], a);
+                a = fmaf(w0.y, g[1], a);
+                a = fmaf(w0.z, g[2], a);
+                a = fmaf(w0.w, g[3], a);
+                a = fmaf(w1.x, g[4], a);
+                a = fmaf(w1.y, g[5], a);
+                a = fmaf(w1.z, g[6], a);
+                a = fmaf(w1.w, g[7], a);
+                acc[j] = a;
+              }
+            }
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+              const int k = wave * PER + j;
+              if (k < nb) {
+                const size_t slot = eid[start + lo + k];
+                fpart[slot * C + c] = acc[j];
+                if (c == 0) fflag[slot] = 1;
+              }
+            }
+          }
+        }
+      }
+    }
+    if constexpr (MODE == kFull && DM) {
       if (g_feat) {
         __syncthreads();
         const int li = lane & 15, lk = lane >> 4;
         const int ncb = (C + 15) >> 4;
+        // the tile's pixels inside the image: wl columns, hl rows
+        const int wl = min(ct.tw, W - tx * ct.tw), hl = min(ct.th, H - ty * ct.th);
         for (int unit = wave; unit < 2 * ncb; unit += 4) {
           const int eb = unit & 1, cb = unit >> 1;
           const int c = 16 * cb + li;
           f4v racc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
           const float* wrow = s_om[16 * eb + li];
-          // 32 pixels (8 steps of 4: pixels 4 t + lk, row-major in the tile) at
-          // a time: their G values are loaded together
-          for (int t0 = 0; t0 < kTilePix / 4; t0 += 8) {
-            float b[8];
+          // G of the lane's first pixel (tile column lk, row 0); step t covers
+          // pixels 4 t + lk (row-major in the tile, tw a multiple of 4), whose
+          // offsets from it are the same for all lanes and below 2^29 (W, C
+          // and the tile height are bounded)
+          const float* gt = g_feat + (tl.pix0 + (int64_t)(ty * ct.th) * W + tx * ct.tw + lk) * C + c;
+          // 128 pixels (32 steps) at a time: their 32 G values are loaded
+          // together, so enough of them are in flight to cover the memory
+          // latency
+          for (int t0 = 0; t0 < kTilePix / 4; t0 += 32) {
+            // the shape values go through an empty asm statement so that the
+            // step offsets and bounds are formed here and not kept live
+            // across units (64 of them would not fit in the registers)
+            int wc = W * C, cs = C, tm = ct.tw - 1, sh = ct.tsh, wlim = wl - lk, hlim = hl;
+            asm volatile("" : "+s"(wc), "+s"(cs), "+s"(tm), "+s"(sh), "+v"(wlim), "+s"(hlim));
+            float b[32];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-              const int q = 4 * (t0 + t) + lk;
-              const int qx = tx * ct.tw + tile_lx(ct, q), qy = ty * ct.th + tile_ly(ct, q);
-              b[t] = qx < W && qy < H && c < C ? g_feat[(tl.pix0 + (int64_t)qy * W + qx) * C + c] : 0.0f;
+            for (int t = 0; t < 32; ++t) {
+              const int q4 = 4 * (t0 + t), lx = q4 & tm, ly = q4 >> sh;
+              b[t] = lx < wlim && ly < hlim && c < C ? gt[ly * wc + lx * cs] : 0.0f;
             }
 #pragma unroll
-            for (int t = 0; t < 8; ++t) racc[t & 1] = mfma_16x16x4(wrow[4 * (t0 + t) + lk], b[t], racc[t & 1]);
+            for (int t = 0; t < 32; ++t) racc[t & 1] = mfma_16x16x4(wrow[4 * (t0 + t) + lk], b[t], racc[t & 1]);
           }
           const f4v rs = racc[0] + racc[1];
           if (c < C) {
@@ -923,12 +1020,12 @@ static void feat_bwd_k(const SurfelArgs& s, const Layout& L, const CamTable& ct,
   else (p ? feat_bwd_launch<FT, 32, GC, true> : feat_bwd_launch<FT, 32, GC, false>)(s, L, ct, tu, g, rn, ws, st);
 }
 
-template <int MODE, typename FT, bool PERSIST, bool LP>
-static void walk_bwd_launch_t(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
+template <int MODE, typename FT, bool PERSIST, bool LP, bool DM>
+static void walk_bwd_launch_d(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
                               const ImageGradArgs& g, bool want_f, char* ws, hipStream_t st) {
-  const void* k = reinterpret_cast<const void*>(&k_walk_bwd<MODE, FT, PERSIST, LP>);
+  const void* k = reinterpret_cast<const void*>(&k_walk_bwd<MODE, FT, PERSIST, LP, DM>);
   const size_t shm = MODE == kTopK ? (size_t)L.k * kTilePix * 4 : 0;  // selection positions
-  hipLaunchKernelGGL((k_walk_bwd<MODE, FT, PERSIST, LP>), dim3(tile_grid(L, tu.sched_bwd, k, shm)), dim3(256), shm,
+  hipLaunchKernelGGL((k_walk_bwd<MODE, FT, PERSIST, LP, DM>), dim3(tile_grid(L, tu.sched_bwd, k, shm)), dim3(256), shm,
                      st, (const WalkRec*)(ws + L.rec), (const float4*)(ws + L.ext), (const uint32_t*)(ws + L.pid),
                      (const uint32_t*)(ws + L.eid0), (const uint2*)(ws + L.ranges), ct,
                      tile_queue(L, tu.sched_bwd, ws, kQWalkBwd), L.k,
@@ -936,6 +1033,15 @@ static void walk_bwd_launch_t(const SurfelArgs& s, const Layout& L, const CamTab
                      (const float*)(ws + L.seldot), g.rgb, g.depth, g.normal, g.alpha, want_f ? g.feat : nullptr,
                      (const FT*)s.feat, s.c, (float*)(ws + L.gpart), (uint8_t*)(ws + L.gflag), (float*)(ws + L.fpart),
                      (uint8_t*)(ws + L.fflag));
+}
+
+// dense mode: the feature-backward pass width selects the contraction unit
+// (16: vector FMAs, 32: matrix cores)
+template <int MODE, typename FT, bool PERSIST, bool LP>
+static void walk_bwd_launch_t(const SurfelArgs& s, const Layout& L, const CamTable& ct, const Tuning& tu,
+                              const ImageGradArgs& g, bool want_f, char* ws, hipStream_t st) {
+  if (MODE == kFull && tu.bwd_pass == 32) walk_bwd_launch_d<MODE, FT, PERSIST, LP, true>(s, L, ct, tu, g, want_f, ws, st);
+  else walk_bwd_launch_d<MODE, FT, PERSIST, LP, false>(s, L, ct, tu, g, want_f, ws, st);
 }
 
 template <int MODE, typename FT>

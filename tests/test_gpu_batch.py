@@ -139,7 +139,10 @@ CHOICES = [(psm.SCHED_GRID, psm.SCHED_GRID, 32, 16), (psm.SCHED_PERSISTENT, psm.
 
 @pytest.mark.parametrize("blend", ["topk", "full"])
 def test_launch_choices_are_bit_identical(blend):
-    """Scheduler and pass widths change the launch, never a result bit."""
+    """Scheduler and pass widths change the launch, never a result bit; with
+    the dense blend the backward's pass width picks the unit of its feature
+    contractions (16: vector FMAs, 32: matrix cores), which orders those sums
+    differently: bit-identical within a unit, within FP32 rounding across."""
     require_gpu()
     sc = scenes.planes7(20_000, 40, seed=5)
     cams = [scenes.pinhole(328, 200), scenes.pinhole(100, 60)]
@@ -153,11 +156,19 @@ def test_launch_choices_are_bit_identical(blend):
         gr = psm.backward_batch(*_args(t), carr, ws, flat, cfg)
         torch.cuda.synchronize()
         res.append(({k: v.clone() for k, v in out.items()}, gr))
-    for out, gr in res[1:]:
+    for i, (out, gr) in enumerate(res[1:], 1):
         for k in MAPS:
             assert torch.equal(out[k], res[0][0][k]), k
+        same_unit = blend == "topk" or CHOICES[i][3] == CHOICES[0][3]
         for k in GROUPS:
-            assert torch.equal(gr[k], res[0][1][k]), k
+            if same_unit:
+                assert torch.equal(gr[k], res[0][1][k]), (i, k)
+            else:
+                ref = res[0][1][k]
+                scale = torch.clamp(ref.abs(), min=1e-2 * float(ref.pow(2).mean().sqrt()))
+                # the gradient parity bar (1e-3 of max(|g|, 1e-2 rms)): FP32 sums of
+                # hundreds of mixed-sign terms in another order
+                assert float(((gr[k] - ref).abs() / scale).max()) < 1e-3, (i, k)
 
 
 def test_autotune(tmp_path, monkeypatch):

@@ -81,7 +81,8 @@ def calibrate_copy():
 class Form:
     """One (tile mode, blend) configuration with preallocated buffers."""
 
-    def __init__(self, psm, t, cam, K, tile_mode, blend, gout, device, launch=None, tune=False, flags=0):
+    def __init__(self, psm, t, cam, K, tile_mode, blend, gout, device, launch=None, tune=False, flags=0,
+                 tune_bwd=True):
         import torch
         self.psm, self.t, self.K = psm, t, K
         self.tile_mode, self.blend = tile_mode, blend
@@ -118,8 +119,12 @@ class Form:
         elif tune:
             tcfg = psm.config_struct(K, tile_mode, blend)
             out = dict(self.out)
+            # the median of 9 timed runs per candidate (3 leave the ~1 ms
+            # forwards to noise); tuned for what is timed: fwd+bwd, or the
+            # forward alone
             self.tuned_ms = psm.autotune(self.ctx, self.s, psm.camera_array([self.cam]), tcfg, self.ws, out,
-                                         self.gout, self.grads, reps=3, cache=False)
+                                         self.gout if tune_bwd else None, self.grads if tune_bwd else None,
+                                         reps=9, cache=False)
             self.cfg.schedule, self.cfg.bwd_schedule = tcfg.schedule, tcfg.bwd_schedule
             self.cfg.blend_pass, self.cfg.bwd_pass, self.cfg.tile_w = tcfg.blend_pass, tcfg.bwd_pass, tcfg.tile_w
 
@@ -205,8 +210,11 @@ def measured_traffic(stage: str, workload: str, launch=None):
 def stage_work(name, st, K, C, b, S):
     """Algorithmic work of one launch of a stage: ("flop", F) for the walks
     (ALU-bound), ("byte", B) for the streaming stages.  U = distinct selected
-    surfels, b = bytes per stored feature element."""
+    surfels, SP = (tile, surfel) pairs with a selection (the feature rows the
+    Top-K adjoint writes and the reduction reads back; 0 for the dense blend,
+    whose partial rows are left out), b = bytes per stored feature element."""
     P, N, U = st.pairs, st.n, max(st.selected_unique, 0)
+    SP = max(getattr(st, "selected_pairs", -1), 0)
     if name == "walk":
         return "flop", FLOP_PER_EVAL * st.pairs_walked + FLOP_PER_CONTRIB * st.contributors
     if name == "bwd_walk":
@@ -214,13 +222,13 @@ def stage_work(name, st, K, C, b, S):
         return "flop", BWD_FLOP_PER_EVAL * st.bwd_entries + BWD_FLOP_PER_CONTRIB * st.contributors
     bytes_by = {
         "feature_blend": S * (8 * K + 4 * C) + U * C * b,
-        "bwd_feature": S * (8 * K + 4 * C + 4 * K) + U * C * b + U * 4 * C,
+        "bwd_feature": S * (8 * K + 4 * C + 4 * K) + U * C * b + SP * 4 * C,
         "preprocess": N * (40 + 12) + st.visible * (64 + 48) + N * 12,
         "depth_sort": N * 8 * 2,
         "pair_sort": P * 8 * 2,
         "emit": P * 8 + st.visible * 56,
         "count_scan": N * 8,
-        "bwd_reduce": N * (64 + 40 + 52) + P * 80,
+        "bwd_reduce": N * (64 + 40 + 52) + P * 80 + P + SP * 4 * C + N * 4 * C,
         "ranges": P * 4,
         "fill": 0,
     }
@@ -307,7 +315,7 @@ def batch_workload(psm, scenes, steps, warmup, k=16):
     s = psm._surfels(*args)
     ctx = psm.context(0)
     tune_cfg = psm.config_struct(K, "ellipse", "topk")
-    tuned_ms = psm.autotune(ctx, s, carr, tune_cfg, ws, out, gout, grads, reps=3, cache=False)
+    tuned_ms = psm.autotune(ctx, s, carr, tune_cfg, ws, out, gout, grads, reps=9, cache=False)
     cfg.schedule, cfg.bwd_schedule = tune_cfg.schedule, tune_cfg.bwd_schedule
     cfg.blend_pass, cfg.bwd_pass, cfg.tile_w = tune_cfg.blend_pass, tune_cfg.bwd_pass, tune_cfg.tile_w
 
@@ -592,12 +600,13 @@ def run_table(psm, scenes, steps, warmup, with_cpu):
                  "rows": {}}
         feats = {}
         for tm, bl in TABLE_GRID:
-            f = Form(psm, t, cam, K, tm, bl, gout, device, tune=True)
+            f = Form(psm, t, cam, K, tm, bl, gout, device, tune=True, tune_bwd=bwd)
             ms_fwd, st_fwd, st = timed(f, False, steps, warmup)
             row = {"launch": f.launch(), "fwd_ms": ms_fwd, "fwd_fps": 1000.0 / ms_fwd, "pairs": int(st.pairs),
                    "pairs_per_tile": st.pairs / st.tiles, "pairs_walked": int(st.pairs_walked),
                    "contributors": int(st.contributors), "selected_unique": int(st.selected_unique),
-                   "selections": int(st.selections), "bwd_entries": int(st.bwd_entries)}
+                   "selections": int(st.selections), "selected_pairs": int(st.selected_pairs),
+                   "bwd_entries": int(st.bwd_entries)}
             stages = st_fwd
             if bwd:
                 ms_step, stages, _ = timed(f, True, steps, warmup)
@@ -789,7 +798,7 @@ def main():
                    "source": "autotuner" if launch is None else "--launch",
                    "tuned_ms": head_tuned_ms},
         "selected_unique": int(st.selected_unique), "selections": int(st.selections),
-        "bwd_entries": int(st.bwd_entries),
+        "selected_pairs": int(st.selected_pairs), "bwd_entries": int(st.bwd_entries),
         "roofline": roofline(stages, st, K, sc.c, S, fbytes, args.workload, head_launch),
         "stage_roofline": stage_table(stages, st, K, sc.c, fbytes, S),
         "step_hbm": {"algorithmic_bytes": step_bytes(st, K, sc.c, fbytes, S),

@@ -168,6 +168,9 @@ typedef struct {
                                (the feature rows eq. (18) reads); -1 for the dense blend */
   int64_t selections;     /* Top-K blend: (pixel, slot) selections held, sum over pixels of min(K,
                              contributors); -1 for the dense blend */
+  int64_t selected_pairs; /* Top-K blend: (tile, surfel) pairs selected by at least one pixel of the
+                             tile (the per-tile feature rows of eq. (18) and of its adjoint); -1 for
+                             the dense blend */
 } psm_stats;
 
 typedef struct psm_ctx psm_ctx;

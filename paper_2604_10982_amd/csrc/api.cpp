@@ -464,6 +464,7 @@ psm_status read_stats_impl(psm_ctx* ctx, const void* workspace, int64_t n, const
   out->bwd_entries = word64(h, kStBwdEntries);
   out->selected_unique = topk ? word64(h, kStUnique) : -1;
   out->selections = topk ? word64(h, kStSelected) : -1;
+  out->selected_pairs = topk ? word64(h, kStSelPairs) : -1;
   return PSM_OK;
 }
 

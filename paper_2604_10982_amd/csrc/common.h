@@ -57,12 +57,13 @@ enum : int {
   kStSigHi = 27,
   kStUnique = 28,  // 64-bit, written by the stats read-back: distinct selected virtual surfels
   kStSelected = 30,  // 64-bit, written by the stats read-back: (pixel, slot) selections
-  kStWords = 32
+  kStSelPairs = 32,  // 64-bit, written by the stats read-back: (tile, surfel) pairs with a selection
+  kStWords = 34
 };
 // Words updated by 64-bit atomics must be 8-byte aligned (a misaligned atomic
 // is a memory violation); the status block itself starts the workspace.
 static_assert(kStReqLo % 2 == 0 && kStWalked % 2 == 0 && kStBlended % 2 == 0 && kStBwdEntries % 2 == 0 &&
-                  kStUnique % 2 == 0 && kStSelected % 2 == 0 && kStSigLo % 2 == 0,
+                  kStUnique % 2 == 0 && kStSelected % 2 == 0 && kStSelPairs % 2 == 0 && kStSigLo % 2 == 0,
               "64-bit status words sit at even word indices");
 enum : int { kQWalk = 0, kQBlend = 1, kQFeatBwd = 2, kQWalkBwd = 3 };
 // Radix sort tiling.

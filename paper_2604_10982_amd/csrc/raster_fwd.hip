@@ -525,30 +525,43 @@ __global__ __launch_bounds__(256) void k_export_sel(const uint32_t* __restrict__
 }
 
 // Marks the virtual surfel of every held selection in a bitmap (block per
-// tile, thread per pixel) and counts the selections; k_count_bits then counts
+// tile, thread per pixel), counts the selections and the tile's distinct
+// selected list positions (its (tile, surfel) pairs with a selection: the
+// feature rows the Top-K backward writes per tile); k_count_bits then counts
 // the marked surfels.  Stats read-back only, not part of a render.
 __global__ __launch_bounds__(256) void k_mark_selected(const uint32_t* __restrict__ pid,
                                                        const uint2* __restrict__ ranges,
                                                        const int32_t* __restrict__ selpos, int K,
                                                        uint32_t* __restrict__ bits, uint32_t* __restrict__ status) {
+  __shared__ SelShared S;
   const int tile = blockIdx.x;
   const int tid = threadIdx.x;
   const uint2 rg = ranges[tile];
   const uint32_t start = rg.x;
   const int len = (int)(rg.y - rg.x);
-  int held = 0;
-  for (int q = 0; q < K; ++q) {
-    const int pos = selpos[((size_t)tile * K + q) * kTilePix + tid];
-    if (pos >= 0 && pos < len) {  // a position outside the list (no Top-K forward ran) is not followed
-      const uint32_t v = pid[start + pos];
+  int held = 0, maxpos = -1;
+  int pos[kMaxK];
+#pragma unroll
+  for (int q = 0; q < kMaxK; ++q) {
+    const int p = q < K ? selpos[((size_t)tile * K + q) * kTilePix + tid] : -1;
+    pos[q] = p >= 0 && p < len ? p : -1;  // a position outside the list (no Top-K forward ran) is not followed
+    if (pos[q] >= 0) {
+      const uint32_t v = pid[start + pos[q]];
       atomicOr(bits + (v >> 5), 1u << (v & 31u));
       ++held;
+      maxpos = max(maxpos, pos[q]);
     }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) held += __shfl_xor(held, o, 64);
   if ((tid & 63) == 0 && held)
     atomicAdd(reinterpret_cast<unsigned long long*>(status + kStSelected), (unsigned long long)held);
+  // distinct selected positions, window by window (the bound is block-uniform)
+  const int mp = block_max(maxpos, S.red);
+  int distinct = 0;
+  for (int w0 = 0; w0 <= mp; w0 += kWinPos) distinct += build_window<kMaxK>(S, pos, K, w0, window_words(mp, w0));
+  if (tid == 0 && distinct)
+    atomicAdd(reinterpret_cast<unsigned long long*>(status + kStSelPairs), (unsigned long long)distinct);
 }
 
 __global__ __launch_bounds__(256) void k_count_bits(const uint32_t* __restrict__ bits, int64_t words,
@@ -681,7 +694,7 @@ void launch_count_selected(const Layout& L, char* ws, hipStream_t st) {
   uint32_t* status = (uint32_t*)(ws + L.status);
   const int64_t words = cdiv(L.n > 0 ? L.n : 1, 32);
   launch_fill_u32(ws + L.ubits, 0u, words, st);
-  launch_fill_u32(status + kStUnique, 0u, 4, st);
+  launch_fill_u32(status + kStUnique, 0u, 6, st);
   if (L.tiles == 0) return;
   hipLaunchKernelGGL(k_mark_selected, dim3((unsigned)L.tiles), dim3(256), 0, st, (const uint32_t*)(ws + L.pid),
                      (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos), L.k, (uint32_t*)(ws + L.ubits),

@@ -100,7 +100,7 @@ class Stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("visible", C.c_int64), ("culled", C.c_int64 * 5), ("pairs", C.c_int64),
                 ("pairs_required", C.c_int64), ("pair_capacity", C.c_int64), ("tiles", C.c_int64),
                 ("pairs_walked", C.c_int64), ("contributors", C.c_int64), ("bwd_entries", C.c_int64),
-                ("selected_unique", C.c_int64), ("selections", C.c_int64)]
+                ("selected_unique", C.c_int64), ("selections", C.c_int64), ("selected_pairs", C.c_int64)]
 
 
 _lib = None

@@ -28,10 +28,18 @@ def test_stats_match_saved_selection(launch):
     assert st.selections == (sid >= 0).sum()
     assert st.selected_unique == np.unique(sid[sid >= 0]).size
     assert 0 < st.selected_unique <= st.visible
+    # (tile, surfel) pairs with a selection: 16 x 16 tiles, row-major
+    H, W = sid.shape[:2]
+    tile = (np.arange(H)[:, None] // 16) * ((W + 15) // 16) + np.arange(W)[None, :] // 16
+    tk = np.broadcast_to(tile[:, :, None], sid.shape)
+    keep = sid >= 0
+    assert st.selected_pairs == np.unique(tk[keep].astype(np.int64) * sc.n + sid[keep]).size
+    assert st.selected_unique <= st.selected_pairs <= min(st.selections, st.pairs)
     assert st.contributors <= st.bwd_entries <= st.pairs_walked
     # counting twice gives the same numbers (the bitmap is cleared each time)
     st2 = psm.read_stats(ws, sc.n, cs, cfg, sc.c, ws.capacity)
-    assert (st2.selected_unique, st2.selections) == (st.selected_unique, st.selections)
+    assert (st2.selected_unique, st2.selections, st2.selected_pairs) == (st.selected_unique, st.selections,
+                                                                          st.selected_pairs)
 
 
 def test_stats_dense_blend_has_no_selection_counts():
@@ -42,7 +50,7 @@ def test_stats_dense_blend_has_no_selection_counts():
     _, ws = render(t, cam, 4, "ellipse", "full")
     st = psm.read_stats(ws, sc.n, psm.camera_struct(cam), psm.config_struct(4, "ellipse", "full"), sc.c,
                         ws.capacity)
-    assert st.selected_unique == -1 and st.selections == -1
+    assert st.selected_unique == -1 and st.selections == -1 and st.selected_pairs == -1
     assert st.bwd_entries > 0
 
 

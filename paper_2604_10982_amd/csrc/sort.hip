@@ -10,7 +10,8 @@
 // Each pass is reduce-then-scan (no inter-block waiting):
 //   upsweep   -- per-block digit histogram (LDS, one sub-histogram per wave);
 //   scan      -- one block per digit scans that digit's row over blocks;
-//   downsweep -- per block, stable ranks from wave ballots, scatter.
+//   downsweep -- per block, stable ranks from wave ballots, the tile sorted
+//                by digit in LDS, written out bucket by bucket.
 // The element count is read on the device, so the launch shape only depends
 // on the capacity and no host synchronisation is needed.
 #include "common.h"
@@ -71,64 +72,114 @@ __global__ __launch_bounds__(256) void k_rs_scan(const uint32_t* __restrict__ n_
   if (t == 255) hist[256 * nb_max + d] = s[255];
 }
 
+// Block-wide (256 threads) exclusive prefix sum of one value per thread;
+// red holds 4 words of scratch.  Ends with a barrier, so red can be reused.
+__device__ __forceinline__ uint32_t sort_scan_excl(uint32_t v, uint32_t* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) red[wave] = x;
+  __syncthreads();
+  uint32_t pre = 0;
+#pragma unroll
+  for (int w = 0; w < 3; ++w) pre += w < wave ? red[w] : 0u;
+  __syncthreads();
+  return pre + x - v;
+}
+
+// One block per tile of kSortTile elements; wave w owns the elements
+// [base + w kSortTile / 4, base + (w + 1) kSortTile / 4), kSortItems
+// coalesced rows of 64.  (1) Each wave ranks its elements among equal digits
+// in index order: wave ballots give the rank within a row, wave-private
+// digit counters in LDS carry the count of the rows before (a wave's LDS
+// operations complete in program order, so no barrier is needed).  (2) The
+// counts are scanned over the waves and the digits, and every element is
+// placed in LDS at its block-local position: the tile sorted stably by
+// digit.  (3) The tile is written out in that order: consecutive threads
+// write consecutive addresses of a digit's bucket.
 __global__ __launch_bounds__(kSortThreads) void k_rs_downsweep(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int shift, int bits,
     const uint32_t* __restrict__ hist, int64_t nb_max) {
+  static_assert(kSortThreads == 256, "one thread per digit of an 8-bit pass");
   const uint32_t n = *n_dev;
   const uint32_t nb = (n + kSortTile - 1) / kSortTile;
   if (blockIdx.x >= nb) return;
-  __shared__ uint32_t s_base[256];
-  __shared__ uint32_t s_wc[4][256];
-  const int t = threadIdx.x;
+  __shared__ uint32_t s_cnt[4][256];  // per-wave digit counts, then the waves' offsets
+  __shared__ uint32_t s_gbase[256];   // first global position of each digit for this block
+  __shared__ uint32_t s_lbase[256];   // first block-local position of each digit
+  __shared__ uint32_t s_red[4];
+  __shared__ uint32_t s_k[kSortTile], s_v[kSortTile];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int ndig = 1 << bits;
   const uint32_t mask = (uint32_t)ndig - 1u;
-  // global start of each digit for this block: digits before it + earlier blocks
-  const uint32_t tot = t < ndig ? hist[256 * nb_max + t] : 0u;
-  s_base[t] = tot;
-  for (int i = t; i < 4 * 256; i += kSortThreads) (&s_wc[0][0])[i] = 0;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    const uint32_t v = t >= o ? s_base[t - o] : 0u;
-    __syncthreads();
-    s_base[t] += v;
-    __syncthreads();
-  }
-  const uint32_t excl = s_base[t] - tot;
-  __syncthreads();
-  s_base[t] = excl + (t < ndig ? hist[(size_t)t * nb + blockIdx.x] : 0u);
-  __syncthreads();
-
-  const int lane = t & 63, wave = t >> 6;
   const uint64_t lt = (1ull << lane) - 1ull;
   const uint32_t base = blockIdx.x * kSortTile;
+  const uint32_t wbase = base + (uint32_t)wave * (64 * kSortItems);
+
+  // global start of each digit for this block: all elements of smaller digits
+  // plus this digit's elements in earlier blocks
+  const uint32_t tot = t < ndig ? hist[256 * nb_max + t] : 0u;
+  const uint32_t ex = sort_scan_excl(tot, s_red);
+  s_gbase[t] = ex + (t < ndig ? hist[(size_t)t * nb + blockIdx.x] : 0u);
+#pragma unroll
+  for (int w = 0; w < 4; ++w) s_cnt[w][t] = 0u;
+  __syncthreads();
+
+  uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+#pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
-    const uint32_t idx = base + j * kSortThreads + t;
-    const bool valid = idx < n;
-    const uint32_t key = valid ? kin[idx] : 0u;
-    const uint32_t val = valid ? vin[idx] : 0u;
-    const uint32_t d = (key >> shift) & mask;
+    const uint32_t idx = wbase + j * 64 + lane;
+    key[j] = idx < n ? kin[idx] : 0u;
+    val[j] = idx < n ? vin[idx] : 0u;
+  }
+  uint32_t* cnt = s_cnt[wave];
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const bool valid = wbase + j * 64 + lane < n;
+    const uint32_t d = (key[j] >> shift) & mask;
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < bits; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
     }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    if (valid && rank == 0) s_wc[wave][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = s_base[d] + rank;
-      for (int w = 0; w < wave; ++w) pos += s_wc[w][d];
-      kout[pos] = key;
-      vout[pos] = val;
+    const uint32_t r = (uint32_t)__popcll(peers & lt);
+    const uint32_t c = valid ? cnt[d] : 0u;
+    rank[j] = c + r;
+    if (valid && r == 0) cnt[d] = c + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // digit t: the waves' offsets (exclusive over waves) and the digit's
+  // block-local start (exclusive over digits)
+  const uint32_t c0 = s_cnt[0][t], c1 = s_cnt[1][t], c2 = s_cnt[2][t], c3 = s_cnt[3][t];
+  s_cnt[0][t] = 0u;
+  s_cnt[1][t] = c0;
+  s_cnt[2][t] = c0 + c1;
+  s_cnt[3][t] = c0 + c1 + c2;
+  s_lbase[t] = sort_scan_excl(c0 + c1 + c2 + c3, s_red);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    if (wbase + j * 64 + lane < n) {
+      const uint32_t d = (key[j] >> shift) & mask;
+      const uint32_t lp = s_lbase[d] + cnt[d] + rank[j];
+      s_k[lp] = key[j];
+      s_v[lp] = val[j];
     }
-    __syncthreads();
-    if (t < ndig) {
-      s_base[t] += s_wc[0][t] + s_wc[1][t] + s_wc[2][t] + s_wc[3][t];
-      s_wc[0][t] = s_wc[1][t] = s_wc[2][t] = s_wc[3][t] = 0u;
-    }
-    __syncthreads();
+  }
+  __syncthreads();
+  const uint32_t m = min((uint32_t)kSortTile, n - base);
+  for (uint32_t i = t; i < m; i += kSortThreads) {
+    const uint32_t k = s_k[i];
+    const uint32_t d = (k >> shift) & mask;
+    const uint32_t gp = s_gbase[d] + (i - s_lbase[d]);
+    kout[gp] = k;
+    vout[gp] = s_v[i];
   }
 }
 

@@ -69,8 +69,17 @@ typedef struct {
   const float* opacity; /* [n] in (0, 1] */
   const float* rgb;     /* [n][3] */
   const void* feat;     /* [n][c] row-major in feat_dtype, 16-byte aligned */
-  int32_t c;            /* feature channels: 8 <= c <= 1024, c % 8 == 0 */
+  int32_t c;            /* feature channels from feat: 0 <= c <= 1024, c % 8 == 0 */
   int32_t feat_dtype;   /* psm_dtype */
+  /* Optional second feature source, FP32 [n][c_ext] row-major, 16-byte
+   * aligned: channels c .. c + c_ext - 1 of every blended feature row.  Both
+   * sources are gathered by the same walk and selection, so one render yields
+   * e.g. the semantic map and the instance map of eq. (8) (Sec. 4.1) side by
+   * side without a concatenated copy of the surfel features.  The rendered
+   * feature map, and every `c` argument that sizes a workspace for these
+   * surfels, has c + c_ext <= 1024 channels.  NULL and 0 for none. */
+  const float* feat_ext;
+  int32_t c_ext;        /* 0 <= c_ext, c_ext % 8 == 0 */
 } psm_surfels;
 
 typedef struct {
@@ -148,8 +157,9 @@ typedef enum { PSM_SCHED_GRID = 0, PSM_SCHED_PERSISTENT = 1 } psm_schedule;
 typedef struct { float *rgb, *depth, *normal, *alpha, *feat; } psm_images;
 typedef struct { const float *rgb, *depth, *normal, *alpha, *feat; } psm_image_grads;
 /* Gradients, FP32, shapes of the inputs (feat: [n][c] FP32 for every storage
- * dtype).  psm_backward overwrites them (no accumulation). */
-typedef struct { float *means, *scales, *quats, *opacity, *rgb, *feat; } psm_grads;
+ * dtype; feat_ext: [n][c_ext], needed only when c_ext > 0).  psm_backward
+ * overwrites them (no accumulation). */
+typedef struct { float *means, *scales, *quats, *opacity, *rgb, *feat, *feat_ext; } psm_grads;
 
 typedef struct {
   int64_t n;              /* surfels */

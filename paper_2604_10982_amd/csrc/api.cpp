@@ -227,13 +227,25 @@ psm_status validate_surfels(const psm_surfels* s) {
   if (s->feat_dtype < 0 || s->feat_dtype > 2) return fail(PSM_ERR_INVALID_ARG, "bad feat_dtype");
   if (s->n > 0 && (!s->means || !s->scales || !s->quats || !s->opacity || !s->rgb))
     return fail(PSM_ERR_INVALID_ARG, "null surfel parameter array");
+  if (s->c < 0 || s->c > 1024 || s->c_ext < 0 || s->c_ext > 1024)
+    return fail(PSM_ERR_INVALID_ARG, "c and c_ext must be in [0, 1024]");
+  if (s->c_ext % 8 != 0) return fail(PSM_ERR_UNSUPPORTED, "c_ext must be a multiple of 8");
   if (s->n > 0 && s->c > 0) {
     if (!s->feat) return fail(PSM_ERR_INVALID_ARG, "null feature array");
     if (reinterpret_cast<uintptr_t>(s->feat) % 16 != 0)
       return fail(PSM_ERR_INVALID_ARG, "feature array must be 16-byte aligned");
   }
+  if (s->n > 0 && s->c_ext > 0) {
+    if (!s->feat_ext) return fail(PSM_ERR_INVALID_ARG, "null second feature array");
+    if (reinterpret_cast<uintptr_t>(s->feat_ext) % 16 != 0)
+      return fail(PSM_ERR_INVALID_ARG, "second feature array must be 16-byte aligned");
+  }
   return PSM_OK;
 }
+
+// Rendered feature channels: both sources (validate_surfels bounds each part,
+// validate_common the sum).
+int feat_channels(const psm_surfels* s) { return s->c + s->c_ext; }
 
 int tile_width(const psm_config* cfg) { return !cfg || cfg->tile_w == 0 ? kTileDefault : cfg->tile_w; }
 
@@ -280,7 +292,9 @@ Tuning tuning_of(const psm_config* cfg) {
 }
 
 SurfelArgs surfel_args(const psm_surfels* s) {
-  return SurfelArgs{s->n, s->means, s->scales, s->quats, s->opacity, s->rgb, s->feat, s->c, s->feat_dtype};
+  return SurfelArgs{s->n,      s->means,           s->scales,     s->quats,   s->opacity,
+                    s->rgb,    s->feat,            feat_channels(s), s->feat_dtype,
+                    s->c_ext > 0 ? s->feat_ext : nullptr, s->c};
 }
 
 int bits_for(int64_t tiles) {
@@ -371,13 +385,13 @@ psm_status forward_impl(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
   if (!out) return fail(PSM_ERR_INVALID_ARG, "out is null");
   psm_status r = validate_surfels(s);
   if (r != PSM_OK) return r;
-  r = validate_common(cams, n_cams, cfg, s->n, s->c, pair_capacity);
+  r = validate_common(cams, n_cams, cfg, s->n, feat_channels(s), pair_capacity);
   if (r != PSM_OK) return r;
   const CamTable ct = cam_table(cams, n_cams, s->n, cfg);
-  const Layout L = make_layout(ct, cfg->k, s->c, pair_capacity);
+  const Layout L = make_layout(ct, cfg->k, feat_channels(s), pair_capacity);
   r = check_workspace(L, workspace, workspace_bytes);
   if (r != PSM_OK) return r;
-  if (s->c > 0 && !out->feat) return fail(PSM_ERR_INVALID_ARG, "out->feat is required when c > 0");
+  if (feat_channels(s) > 0 && !out->feat) return fail(PSM_ERR_INVALID_ARG, "out->feat is required when c > 0");
   if ((cfg->flags & PSM_FLAG_FEATURE_ONLY) && (out->rgb || out->depth || out->normal || out->alpha))
     return fail(PSM_ERR_INVALID_ARG, "PSM_FLAG_FEATURE_ONLY renders only the feature map: pass null rgb, depth, "
                                      "normal and alpha");
@@ -404,22 +418,23 @@ psm_status backward_impl(psm_ctx* ctx, const psm_surfels* s, const psm_camera* c
   if (!grad_out || !grads) return fail(PSM_ERR_INVALID_ARG, "grad_out and grads are required");
   psm_status r = validate_surfels(s);
   if (r != PSM_OK) return r;
-  r = validate_common(cams, n_cams, cfg, s->n, s->c, pair_capacity);
+  r = validate_common(cams, n_cams, cfg, s->n, feat_channels(s), pair_capacity);
   if (r != PSM_OK) return r;
   if (s->n > 0 && (!grads->means || !grads->scales || !grads->quats || !grads->opacity || !grads->rgb ||
-                   (s->c > 0 && !grads->feat)))
+                   (s->c > 0 && !grads->feat) || (s->c_ext > 0 && !grads->feat_ext)))
     return fail(PSM_ERR_INVALID_ARG, "every gradient array is required");
   if ((cfg->flags & PSM_FLAG_FEATURE_ONLY) && (grad_out->rgb || grad_out->depth || grad_out->normal || grad_out->alpha))
     return fail(PSM_ERR_INVALID_ARG, "PSM_FLAG_FEATURE_ONLY takes only the feature map's upstream gradient");
   const CamTable ct = cam_table(cams, n_cams, s->n, cfg);
-  const Layout L = make_layout(ct, cfg->k, s->c, pair_capacity);
+  const Layout L = make_layout(ct, cfg->k, feat_channels(s), pair_capacity);
   r = check_workspace(L, workspace, workspace_bytes);
   if (r != PSM_OK) return r;
   DeviceGuard dg(ctx->device);
   if (!dg.ok) return fail(PSM_ERR_HIP, "hipSetDevice failed");
   hipStream_t st = (hipStream_t)stream;
   ImageGradArgs g{grad_out->rgb, grad_out->depth, grad_out->normal, grad_out->alpha, grad_out->feat};
-  GradArgs ga{grads->means, grads->scales, grads->quats, grads->opacity, grads->rgb, grads->feat};
+  GradArgs ga{grads->means, grads->scales, grads->quats, grads->opacity, grads->rgb, grads->feat,
+              s->c_ext > 0 ? grads->feat_ext : nullptr};
   launch_backward(surfel_args(s), ct, cfg->blend, tuning_of(cfg), L, g, ga, (cfg->flags & PSM_FLAG_TOPK_RENORM) != 0,
                   (cfg->flags & PSM_FLAG_LOWPASS) != 0, (char*)workspace, st,
                   hook_for(ctx, cfg));
@@ -521,7 +536,7 @@ psm_status read_selection_impl(psm_ctx* ctx, const void* workspace, int64_t n, c
 
 std::string tune_key(const psm_surfels* s, const psm_camera* cams, int32_t n_cams, const psm_config* cfg,
                      bool bwd) {
-  std::string k = std::to_string(s->n) + "|" + std::to_string(s->c) + "|" + std::to_string(s->feat_dtype) + "|" +
+  std::string k = std::to_string(s->n) + "|" + std::to_string(s->c) + "+" + std::to_string(s->c_ext) + "|" + std::to_string(s->feat_dtype) + "|" +
                   std::to_string(cfg->k) + "|" + std::to_string(cfg->tile_mode) + "|" + std::to_string(cfg->blend) +
                   "|" + (bwd ? "b" : "f");
   for (int b = 0; b < n_cams; ++b) k += "|" + std::to_string(cams[b].width) + "x" + std::to_string(cams[b].height);
@@ -556,7 +571,7 @@ extern "C" {
 
 const char* psm_last_error(void) { return g_err.c_str(); }
 
-const char* psm_version(void) { return "psm 0.2 (gfx950)"; }
+const char* psm_version(void) { return "psm 0.3 (gfx950)"; }
 
 psm_status psm_create(psm_ctx** ctx_out, int device) {
   return guarded("psm_create", [&]() -> psm_status {
@@ -701,7 +716,7 @@ psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
     if (reps < 1 || reps > 1000) return fail(PSM_ERR_INVALID_ARG, "reps must be in [1, 1000]");
     psm_status r = validate_surfels(s);
     if (r != PSM_OK) return r;
-    r = validate_common(cams, n_cams, cfg, s->n, s->c, pair_capacity);
+    r = validate_common(cams, n_cams, cfg, s->n, feat_channels(s), pair_capacity);
     if (r != PSM_OK) return r;
     const bool bwd = grads != nullptr;
     if (bwd && !grad_out) return fail(PSM_ERR_INVALID_ARG, "grad_out is required with grads");
@@ -737,7 +752,7 @@ psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
       c2.bwd_pass = tu.bwd_pass;
       c2.tile_w = tw;
       c2.flags = (cfg->flags | PSM_FLAG_NO_SYNC) & ~PSM_FLAG_PROFILE;
-      const Layout L = make_layout(cam_table(cams, n_cams, s->n, &c2), c2.k, s->c, pair_capacity);
+      const Layout L = make_layout(cam_table(cams, n_cams, s->n, &c2), c2.k, feat_channels(s), pair_capacity);
       usable = L.total <= workspace_bytes;
       if (!usable) return PSM_OK;
       std::vector<double> ts;
@@ -762,9 +777,9 @@ psm_status psm_autotune(psm_ctx* ctx, const psm_surfels* s, const psm_camera* ca
       med = ts[ts.size() / 2];
       return PSM_OK;
     };
-    const bool feat = s->c > 0 && cfg->blend == PSM_BLEND_TOPK;
+    const bool feat = feat_channels(s) > 0 && cfg->blend == PSM_BLEND_TOPK;
     // dense blend with a backward: the pass width picks the feature contraction's unit
-    const bool dense_bwd = bwd && s->c > 0 && cfg->blend == PSM_BLEND_FULL;
+    const bool dense_bwd = bwd && feat_channels(s) > 0 && cfg->blend == PSM_BLEND_FULL;
     Tuning best{kSchedPersistent, bwd ? kSchedPersistent : 0, 32, 16};
     int best_tw = cfg->tile_w == 0 ? kTileDefault : cfg->tile_w;
     double best_ms = 1e300;
@@ -1017,11 +1032,11 @@ psm_status psm_forward_static(psm_ctx* ctx, const psm_surfels* s, const psm_came
     if (pair_capacity < -1) return fail(PSM_ERR_INVALID_ARG, "pair_capacity must be -1 or >= 0");
     psm_status r = validate_surfels(s);
     if (r != PSM_OK) return r;
-    r = validate_common(cam, 1, cfg, s->n, s->c, pair_capacity < 0 ? 0 : pair_capacity);
+    r = validate_common(cam, 1, cfg, s->n, feat_channels(s), pair_capacity < 0 ? 0 : pair_capacity);
     if (r != PSM_OK) return r;
     const CamTable ct = cam_table(cam, 1, s->n, cfg);
     const size_t limit = PSM_STATIC_WORKSPACE_BYTES;
-    const size_t base = make_layout(ct, cfg->k, s->c, 0).total;
+    const size_t base = make_layout(ct, cfg->k, feat_channels(s), 0).total;
     if (base > limit)
       return fail(PSM_ERR_INVALID_ARG, "psm_forward_static: n, image size, k and c need " + std::to_string(base) +
                                            " bytes of workspace before any pair; the static workspace holds " +
@@ -1031,13 +1046,13 @@ psm_status psm_forward_static(psm_ctx* ctx, const psm_surfels* s, const psm_came
       int64_t lo = 0, hi = (int64_t)1 << 31;
       while (hi - lo > 1) {
         const int64_t mid = lo + (hi - lo) / 2;
-        if (make_layout(ct, cfg->k, s->c, mid).total <= limit) lo = mid;
+        if (make_layout(ct, cfg->k, feat_channels(s), mid).total <= limit) lo = mid;
         else hi = mid;
       }
       cap = lo;
-    } else if (make_layout(ct, cfg->k, s->c, cap).total > limit) {
+    } else if (make_layout(ct, cfg->k, feat_channels(s), cap).total > limit) {
       return fail(PSM_ERR_INVALID_ARG, "psm_forward_static: pair capacity " + std::to_string(cap) + " needs " +
-                                           std::to_string(make_layout(ct, cfg->k, s->c, cap).total) +
+                                           std::to_string(make_layout(ct, cfg->k, feat_channels(s), cap).total) +
                                            " bytes of workspace; the static workspace holds " + std::to_string(limit));
     }
     psm_config c2 = *cfg;

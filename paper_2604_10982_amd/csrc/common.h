@@ -479,6 +479,45 @@ __device__ __forceinline__ float load_one<uint16_t>(const uint16_t* p) {
   return __uint_as_float(((uint32_t)*p) << 16);
 }
 
+// Four consecutive feature channels as float.
+template <typename FT>
+__device__ __forceinline__ float4 load4(const FT* p);
+template <>
+__device__ __forceinline__ float4 load4<float>(const float* p) {
+  return *reinterpret_cast<const float4*>(p);
+}
+template <>
+__device__ __forceinline__ float4 load4<__half>(const __half* p) {
+  const uint2 x = *reinterpret_cast<const uint2*>(p);
+  return make_float4(__half2float(__ushort_as_half((unsigned short)(x.x & 0xFFFF))),
+                     __half2float(__ushort_as_half((unsigned short)(x.x >> 16))),
+                     __half2float(__ushort_as_half((unsigned short)(x.y & 0xFFFF))),
+                     __half2float(__ushort_as_half((unsigned short)(x.y >> 16))));
+}
+template <>
+__device__ __forceinline__ float4 load4<uint16_t>(const uint16_t* p) {
+  const uint2 x = *reinterpret_cast<const uint2*>(p);
+  return make_float4(__uint_as_float(x.x << 16), __uint_as_float(x.x & 0xFFFF0000u), __uint_as_float(x.y << 16),
+                     __uint_as_float(x.y & 0xFFFF0000u));
+}
+
+// The feature rows a render blends: channels [0, ca) from a (storage type FT,
+// row stride ca) and channels [ca, ca + cb) from b (FP32, row stride cb; the
+// second source is optional: cb = 0).  Both widths are multiples of 8, so a
+// group of 4 channels starting at a multiple of 4 lies in one source.
+template <typename FT>
+struct FeatSrc {
+  const FT* a;
+  const float* b;
+  int ca, cb;
+  __device__ __forceinline__ float4 load4(size_t row, int c) const {
+    return c < ca ? psm::load4<FT>(a + row * ca + c) : psm::load4<float>(b + row * cb + (c - ca));
+  }
+  __device__ __forceinline__ float load1(size_t row, int c) const {
+    return c < ca ? load_one<FT>(a + row * ca + c) : b[row * cb + (c - ca)];
+  }
+};
+
 __device__ __forceinline__ int pow2_ge(int x) {
   int p = 1;
   while (p < x) p <<= 1;

@@ -11,12 +11,21 @@
 
 namespace psm {
 
+// feat holds channels [0, ca) in the storage dtype, feat_ext (FP32, may be
+// null) channels [ca, c); c is the rendered feature width.
 struct SurfelArgs {
   int64_t n;
   const float *means, *scales, *quats, *opacity, *rgb;
   const void* feat;
   int c, dtype;
+  const float* feat_ext;
+  int ca;
 };
+
+template <typename FT>
+inline FeatSrc<FT> feat_src(const SurfelArgs& s) {
+  return FeatSrc<FT>{(const FT*)s.feat, s.feat_ext, s.ca, s.c - s.ca};
+}
 
 struct ImageArgs {
   float *rgb, *depth, *normal, *alpha, *feat;
@@ -26,8 +35,9 @@ struct ImageGradArgs {
   const float *rgb, *depth, *normal, *alpha, *feat;
 };
 
+// feat: [n][ca] FP32, feat_ext: [n][c - ca] FP32 (the split of SurfelArgs)
 struct GradArgs {
-  float *means, *scales, *quats, *opacity, *rgb, *feat;
+  float *means, *scales, *quats, *opacity, *rgb, *feat, *feat_ext;
 };
 
 // Stage timing hook (events are recorded by the C ABI layer).

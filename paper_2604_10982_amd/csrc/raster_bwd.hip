@@ -61,7 +61,7 @@ __device__ __forceinline__ int qmap_off(int p, int s) { return p * kQStride + (s
 template <typename FT, int KMAX, int GC, bool PERSIST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 ? 2 : 1))) void k_feat_bwd_topk(
     const uint32_t* __restrict__ pid, const uint32_t* __restrict__ eid, const uint2* __restrict__ ranges,
-    const int32_t* __restrict__ selpos, const float* __restrict__ selw, const FT* __restrict__ feat,
+    const int32_t* __restrict__ selpos, const float* __restrict__ selw, const FeatSrc<FT> feat,
     const float* __restrict__ gfeat, int C, int K, CamTable ct, TileQueue tq, float* __restrict__ seldot,
     float* __restrict__ fpart, uint8_t* __restrict__ fflag, int renorm) {
   static_assert(GC % 16 == 0, "pass width is a multiple of the MFMA tile");
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KMAX <= 16 
 #pragma unroll
           for (int u = 0; u < FPT; ++u) {
             const int item = tid + 256 * u, sidx = item / GC, c = cc + item % GC;
-            fv[u] = sidx < ns && c < C ? load_one<FT>(feat + (size_t)S.fid[sidx] * C + c) : 0.0f;
+            fv[u] = sidx < ns && c < C ? feat.load1(S.fid[sidx], c) : 0.0f;
           }
         };
         load_pass(0);
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
     const float* __restrict__ tfinal,
     const int32_t* __restrict__ selpos, const float* __restrict__ seldot, const float* __restrict__ g_rgb,
     const float* __restrict__ g_depth, const float* __restrict__ g_normal, const float* __restrict__ g_alpha,
-    const float* __restrict__ g_feat, const FT* __restrict__ feat, int C, float* __restrict__ gpart,
+    const float* __restrict__ g_feat, const FeatSrc<FT> feat, int C, float* __restrict__ gpart,
     uint8_t* __restrict__ gflag, float* __restrict__ fpart, uint8_t* __restrict__ fflag) {
   __shared__ Staged<kBB> s_r;
   __shared__ float2 s_band[kBB];  // (ecy, ey) of the batch, for band culling
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
         for (int c0 = 0; c0 < C; c0 += 64) {
           for (int e = tid; e < nb * 64; e += 256) {
             const int k = e >> 6, c = e & 63;
-            s_fc[k][c] = (c0 + c < C) ? load_one<FT>(feat + (size_t)(s_id[k] - tl.v0) * C + c0 + c) : 0.0f;
+            s_fc[k][c] = (c0 + c < C) ? feat.load1(s_id[k] - tl.v0, c0 + c) : 0.0f;
           }
           __syncthreads();
           if (has_gf) {
@@ -430,11 +430,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
       for (int k = 0; k < kBB; ++k) phi[k] = 0.0f;
       if (g_feat) {
         const int li = lane & 15, lk = lane >> 4;
-        const FT* fr[2];
+        int fr[2];  // feature row of the lane's entry of each block, -1 past the batch
 #pragma unroll
         for (int eb = 0; eb < 2; ++eb) {
           const int e = 16 * eb + li;
-          fr[eb] = e < nb ? feat + (size_t)(s_id[e] - tl.v0) * C : nullptr;
+          fr[eb] = e < nb ? (int)(s_id[e] - tl.v0) : -1;
         }
         float* ph = s_ph[wave];
         for (int pb = 0; pb < 4; ++pb) {
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
               a[j] = gq && c < C ? *reinterpret_cast<const float4*>(gq + c) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
               for (int eb = 0; eb < 2; ++eb)
-                b[eb][j] = fr[eb] && c < C ? load4<FT>(fr[eb] + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+                b[eb][j] = fr[eb] >= 0 && c < C ? feat.load4(fr[eb], c) : make_float4(0.f, 0.f, 0.f, 0.f);
             }
 #pragma unroll
             for (int j = 0; j < 8; ++j)
@@ -928,13 +928,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 }
 
 // Lane group per surfel: dL/df = sum over cameras (in order) of the sum of its
-// pairs' rows (emission order).
+// pairs' rows (emission order), channels [0, ca) written to dfa (row stride
+// ca), channels [ca, C) to dfb (row stride C - ca); either may be null.
 template <int NG>
 __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const uint32_t* __restrict__ vbase,
                                                      const uint32_t* __restrict__ count, int64_t cap,
                                                      const float* __restrict__ fpart,
                                                      const uint8_t* __restrict__ fflag, int C, int lpp2,
-                                                     float* __restrict__ dfeat) {
+                                                     float* __restrict__ dfa, float* __restrict__ dfb, int ca) {
   // lpp2 lanes (a power of two) per surfel, each lane up to NG float4 channel
   // groups: a wave reduces 64 / lpp2 surfels at once
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -994,7 +995,12 @@ __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const 
   }
 #pragma unroll
   for (int j = 0; j < kMaxGroups; ++j)
-    if (j < ng && cl + j * lpp2 < lpp) *reinterpret_cast<float4*>(dfeat + (size_t)i * C + (cl + j * lpp2) * 4) = acc[j];
+    if (j < ng && cl + j * lpp2 < lpp) {
+      const int c = (cl + j * lpp2) * 4;  // ca % 4 == 0: the group lies in one output
+      float* dst = c < ca ? (dfa ? dfa + (size_t)i * ca + c : nullptr)
+                          : (dfb ? dfb + (size_t)i * (C - ca) + (c - ca) : nullptr);
+      if (dst) *reinterpret_cast<float4*>(dst) = acc[j];
+    }
 }
 
 // ------------------------------------------------------------- host wrappers
@@ -1005,7 +1011,7 @@ static void feat_bwd_launch(const SurfelArgs& s, const Layout& L, const CamTable
   const void* k = reinterpret_cast<const void*>(&k_feat_bwd_topk<FT, KMAX, GC, PERSIST>);
   hipLaunchKernelGGL((k_feat_bwd_topk<FT, KMAX, GC, PERSIST>), dim3(tile_grid(L, tu.sched_bwd, k, shm)), dim3(256), shm, st,
                      (const uint32_t*)(ws + L.pid), (const uint32_t*)(ws + L.eid0), (const uint2*)(ws + L.ranges),
-                     (const int32_t*)(ws + L.selpos), (const float*)(ws + L.selw), (const FT*)s.feat, g.feat, s.c, L.k,
+                     (const int32_t*)(ws + L.selpos), (const float*)(ws + L.selw), feat_src<FT>(s), g.feat, s.c, L.k,
                      ct, tile_queue(L, tu.sched_bwd, ws, kQFeatBwd), (float*)(ws + L.seldot), (float*)(ws + L.fpart),
                      (uint8_t*)(ws + L.fflag), renorm ? 1 : 0);
 }
@@ -1031,7 +1037,7 @@ static void walk_bwd_launch_d(const SurfelArgs& s, const Layout& L, const CamTab
                      tile_queue(L, tu.sched_bwd, ws, kQWalkBwd), L.k,
                      (const uint32_t*)(ws + L.nlast), (const float*)(ws + L.tfinal), (const int32_t*)(ws + L.selpos),
                      (const float*)(ws + L.seldot), g.rgb, g.depth, g.normal, g.alpha, want_f ? g.feat : nullptr,
-                     (const FT*)s.feat, s.c, (float*)(ws + L.gpart), (uint8_t*)(ws + L.gflag), (float*)(ws + L.fpart),
+                     feat_src<FT>(s), s.c, (float*)(ws + L.gpart), (uint8_t*)(ws + L.gflag), (float*)(ws + L.fpart),
                      (uint8_t*)(ws + L.fflag));
 }
 
@@ -1087,7 +1093,7 @@ static void backward_typed(const SurfelArgs& s, const CamTable& ct, int blend, c
     hipLaunchKernelGGL(k_reduce_geo, dim3((unsigned)cdiv(s.n, 256)), dim3(256), 0, st, s.n, ct, vbase, count, L.cap,
                        (const float*)(ws + L.gpart), (const uint8_t*)(ws + L.gflag), s.means, s.scales, s.quats,
                        (const int32_t*)(ws + L.cull), gr.means, gr.scales, gr.quats, gr.opacity, gr.rgb);
-    if (s.c > 0 && gr.feat) {
+    if (s.c > 0 && (gr.feat || gr.feat_ext)) {
       // two channel groups per lane (at most 4 for C = 1024): more surfels,
       // and so more independent row loads, in flight per wave
       const int lpp = s.c / 4;
@@ -1097,7 +1103,7 @@ static void backward_typed(const SurfelArgs& s, const CamTable& ct, int blend, c
       auto k = ng <= 2 ? k_reduce_feat<2> : k_reduce_feat<4>;
       hipLaunchKernelGGL(k, dim3((unsigned)cdiv(s.n, per_block)), dim3(256), 0, st, s.n, ct.n, vbase,
                          count, L.cap, (const float*)(ws + L.fpart), (const uint8_t*)(ws + L.fflag), s.c, lpp2,
-                         gr.feat);
+                         gr.feat, gr.feat_ext, s.ca);
     }
   }
   prof.end(kStageBwdPreprocess, st);

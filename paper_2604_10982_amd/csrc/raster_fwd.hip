@@ -230,11 +230,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // Stages channels [cc, cc + BC) of the chunk's ns slot rows into s_F (row
 // stride BC + 4 floats).
 template <typename FT, int BC>
-__device__ __forceinline__ void stage_rows(float* s_F, const uint32_t* fid, int ns, const FT* __restrict__ feat,
+__device__ __forceinline__ void stage_rows(float* s_F, const uint32_t* fid, int ns, const FeatSrc<FT>& feat,
                                            int C, int cc) {
   for (int item = threadIdx.x; item < ns * (BC / 4); item += 256) {
     const int s = item / (BC / 4), j = item % (BC / 4), c = cc + 4 * j;
-    const float4 f = c < C ? load4<FT>(feat + (size_t)fid[s] * C + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 f = c < C ? feat.load4(fid[s], c) : make_float4(0.f, 0.f, 0.f, 0.f);
     *reinterpret_cast<float4*>(s_F + s * (BC + 4) + 4 * j) = f;
   }
 }
@@ -273,7 +273,7 @@ __device__ __forceinline__ void blend_chunk(const float* s_F, const int (&sl)[KM
 template <typename FT, int KMAX, int BC, bool PERSIST, bool WIDE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WIDE || KMAX > 16 ? 1 : 4))) void k_blend_topk(const uint32_t* __restrict__ pid, const uint2* __restrict__ ranges,
                                                     const int32_t* __restrict__ selpos,
-                                                    const float* __restrict__ selw, const FT* __restrict__ feat,
+                                                    const float* __restrict__ selw, const FeatSrc<FT> feat,
                                                     int C, int K, CamTable ct, TileQueue tq,
                                                     float* __restrict__ o_feat, int renorm,
                                                     uint32_t* __restrict__ wide, uint32_t* __restrict__ status) {
@@ -431,7 +431,7 @@ constexpr int kFullBatch = 64;
 
 template <typename FT, int CH, bool PERSIST, bool LP>
 __global__ __launch_bounds__(256) void k_full_feat(const WalkRec* __restrict__ rec, const uint32_t* __restrict__ pid,
-                                                   const uint2* __restrict__ ranges, const FT* __restrict__ feat,
+                                                   const uint2* __restrict__ ranges, const FeatSrc<FT> feat,
                                                    int C, CamTable ct, TileQueue tq,
                                                    const uint32_t* __restrict__ nlast, float* __restrict__ o_feat) {
   __shared__ Staged<kFullBatch> s_r;
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(256) void k_full_feat(const WalkRec* __restrict__ r
         const int k = e / CH, c = e % CH;
         float v = 0.0f;
         if (c0 + c < C) {
-          v = load_one<FT>(feat + (size_t)s_id[k] * C + c0 + c);
+          v = feat.load1(s_id[k], c0 + c);
         }
         s_f[k][c] = v;
       }
@@ -636,14 +636,14 @@ static void blend_topk_launch(const SurfelArgs& s, const Layout& L, const CamTab
   const int sched = PERSIST ? kSchedPersistent : kSchedGrid;
   hipLaunchKernelGGL((k_blend_topk<FT, KMAX, BC, PERSIST, false>), dim3(tile_grid(L, sched, k, 0)), dim3(256), 0,
                      st, (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos),
-                     (const float*)(ws + L.selw), (const FT*)s.feat, s.c, L.k, ct, tile_queue(L, sched, ws, kQBlend),
+                     (const float*)(ws + L.selw), feat_src<FT>(s), s.c, L.k, ct, tile_queue(L, sched, ws, kQBlend),
                      out_feat, renorm ? 1 : 0, wide, status);
   // the listed tiles (usually none): a fixed grid strides over the list,
   // whose length it reads on the device
   const unsigned gw = (unsigned)std::min<int64_t>(L.tiles, 1024);
   hipLaunchKernelGGL((k_blend_topk<FT, KMAX, BC, false, true>), dim3(gw), dim3(256), 0, st,
                      (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges), (const int32_t*)(ws + L.selpos),
-                     (const float*)(ws + L.selw), (const FT*)s.feat, s.c, L.k, ct, TileQueue{nullptr, nullptr, 0},
+                     (const float*)(ws + L.selw), feat_src<FT>(s), s.c, L.k, ct, TileQueue{nullptr, nullptr, 0},
                      out_feat, renorm ? 1 : 0, wide, status);
 }
 
@@ -664,7 +664,7 @@ static void full_feat_launch(const SurfelArgs& s, const Layout& L, const CamTabl
   const void* k = reinterpret_cast<const void*>(&k_full_feat<FT, 64, PERSIST, LP>);
   hipLaunchKernelGGL((k_full_feat<FT, 64, PERSIST, LP>), dim3(tile_grid(L, tu.sched, k, 0)), dim3(256), 0, st,
                      (const WalkRec*)(ws + L.rec), (const uint32_t*)(ws + L.pid), (const uint2*)(ws + L.ranges),
-                     (const FT*)s.feat, s.c, ct, tile_queue(L, tu.sched, ws, kQBlend), (const uint32_t*)(ws + L.nlast),
+                     feat_src<FT>(s), s.c, ct, tile_queue(L, tu.sched, ws, kQBlend), (const uint32_t*)(ws + L.nlast),
                      out_feat);
 }
 

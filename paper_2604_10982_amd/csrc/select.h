@@ -111,26 +111,4 @@ __device__ __forceinline__ int slot_of(const SelShared& S, int pos, int w0, int 
 constexpr int kWRow = 288;  // floats per selection row
 __device__ __forceinline__ int wsel_off(int q, int p) { return q * kWRow + (q & 7) + ((q & 8) << 1) + p; }
 
-// Four consecutive feature channels as float.
-template <typename FT>
-__device__ __forceinline__ float4 load4(const FT* p);
-template <>
-__device__ __forceinline__ float4 load4<float>(const float* p) {
-  return *reinterpret_cast<const float4*>(p);
-}
-template <>
-__device__ __forceinline__ float4 load4<__half>(const __half* p) {
-  const uint2 x = *reinterpret_cast<const uint2*>(p);
-  return make_float4(__half2float(__ushort_as_half((unsigned short)(x.x & 0xFFFF))),
-                     __half2float(__ushort_as_half((unsigned short)(x.x >> 16))),
-                     __half2float(__ushort_as_half((unsigned short)(x.y & 0xFFFF))),
-                     __half2float(__ushort_as_half((unsigned short)(x.y >> 16))));
-}
-template <>
-__device__ __forceinline__ float4 load4<uint16_t>(const uint16_t* p) {
-  const uint2 x = *reinterpret_cast<const uint2*>(p);
-  return make_float4(__uint_as_float(x.x << 16), __uint_as_float(x.x & 0xFFFF0000u), __uint_as_float(x.y << 16),
-                     __uint_as_float(x.y & 0xFFFF0000u));
-}
-
 }  // namespace psm

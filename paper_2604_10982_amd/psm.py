@@ -54,7 +54,12 @@ class CapacityError(PsmError):
 class Surfels(C.Structure):
     _fields_ = [("n", C.c_int64), ("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
                 ("opacity", C.c_void_p), ("rgb", C.c_void_p), ("feat", C.c_void_p), ("c", C.c_int32),
-                ("feat_dtype", C.c_int32)]
+                ("feat_dtype", C.c_int32), ("feat_ext", C.c_void_p), ("c_ext", C.c_int32)]
+
+    @property
+    def width(self) -> int:
+        """Rendered feature channels: feat's and feat_ext's."""
+        return self.c + self.c_ext
 
 
 class Camera(C.Structure):
@@ -92,8 +97,11 @@ class ImageGrads(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("rgb", "depth", "normal", "alpha", "feat")]
 
 
+GRAD_KEYS = ("means", "scales", "quats", "opacity", "rgb", "feat", "feat_ext")
+
+
 class Grads(C.Structure):
-    _fields_ = [(n, C.c_void_p) for n in ("means", "scales", "quats", "opacity", "rgb", "feat")]
+    _fields_ = [(n, C.c_void_p) for n in GRAD_KEYS]
 
 
 class Stats(C.Structure):
@@ -270,7 +278,7 @@ def alloc_workspace_shapes(n, cams, cfg: Config, c: int, capacity: int, device, 
     return Workspace(buf[off:off + nbytes], capacity, n, c, cfg.k, int(cfg.tile_w))
 
 
-def _surfels(means, scales, quats, opacity, rgb, feat) -> Surfels:
+def _surfels(means, scales, quats, opacity, rgb, feat, feat_ext=None) -> Surfels:
     n = means.shape[0]
     for name, t, w in (("means", means, 3), ("scales", scales, 2), ("quats", quats, 4), ("rgb", rgb, 3)):
         if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (n, w):
@@ -283,8 +291,14 @@ def _surfels(means, scales, quats, opacity, rgb, feat) -> Surfels:
                 or feat.shape[0] != n):
             raise ValueError("feat must be a contiguous (n, C) float32/float16/bfloat16 CUDA tensor")
         c, dt, fp = int(feat.shape[1]), DTYPES[feat.dtype], feat.data_ptr()
+    ce, ep = 0, None
+    if feat_ext is not None:
+        if (feat_ext.dtype != torch.float32 or not feat_ext.is_cuda or not feat_ext.is_contiguous()
+                or feat_ext.dim() != 2 or feat_ext.shape[0] != n):
+            raise ValueError("feat_ext must be a contiguous (n, C_ext) float32 CUDA tensor")
+        ce, ep = int(feat_ext.shape[1]), feat_ext.data_ptr()
     return Surfels(n, means.data_ptr(), scales.data_ptr(), quats.data_ptr(), opacity.data_ptr(), rgb.data_ptr(),
-                   fp, c, dt)
+                   fp, c, dt, ep, ce)
 
 
 def alloc_images(cam: Camera, c: int, device, feature_only: bool = False) -> dict:
@@ -326,7 +340,7 @@ def forward_static_into(ctx: Context, s: Surfels, cam: Camera, cfg: Config, out:
 def backward_into(ctx: Context, s: Surfels, cam: Camera, cfg: Config, ws: Workspace, gout: dict, grads: dict,
                   stream=None):
     g = ImageGrads(*(_ptr(gout.get(k)) for k in ("rgb", "depth", "normal", "alpha", "feat")))
-    gr = Grads(*(_ptr(grads.get(k)) for k in ("means", "scales", "quats", "opacity", "rgb", "feat")))
+    gr = Grads(*(_ptr(grads.get(k)) for k in GRAD_KEYS))
     st = stream if stream is not None else _stream(ctx.device)
     _check(lib().psm_backward(ctx.handle, C.byref(s), C.byref(cam), C.byref(cfg), _ptr(ws.buf), ws.nbytes,
                               ws.capacity, C.byref(g), C.byref(gr), st), "psm_backward")
@@ -345,44 +359,48 @@ def launch_config(k: int, tile_mode="ellipse", blend="topk", flags: int = 0, lau
 
 
 def forward(means, scales, quats, opacity, rgb, feat, camera, k=16, tile_mode="ellipse", blend="topk",
-            capacity: int | None = None, ws: Workspace | None = None, flags: int = 0, launch=None):
+            capacity: int | None = None, ws: Workspace | None = None, flags: int = 0, launch=None, feat_ext=None):
     """Render; returns (images dict, workspace).  The workspace holds the
     state the backward needs.  Re-allocates once if the pairs do not fit.
     ``flags``: FLAG_* options of the key stage and the walks (e.g.
     FLAG_OPACITY_FOOTPRINT); the backward takes the same flags.  ``launch``:
-    (schedule, bwd_schedule, blend_pass, bwd_pass), see launch_config."""
+    (schedule, bwd_schedule, blend_pass, bwd_pass), see launch_config.
+    ``feat_ext``: optional FP32 (n, C_ext) features blended after ``feat``'s
+    channels by the same walk (the feature map has C + C_ext channels)."""
     device = means.device
     ctx = context(device.index or 0)
-    s = _surfels(means, scales, quats, opacity, rgb, feat)
+    s = _surfels(means, scales, quats, opacity, rgb, feat, feat_ext)
     cam = camera if isinstance(camera, Camera) else camera_struct(camera)
     cfg = launch_config(k, tile_mode, blend, flags, launch)
-    out = alloc_images(cam, s.c, device, feature_only=bool(flags & FLAG_FEATURE_ONLY))
+    out = alloc_images(cam, s.width, device, feature_only=bool(flags & FLAG_FEATURE_ONLY))
     cap = capacity if capacity is not None else (ws.capacity if ws is not None else capacity_guess(s.n, cam))
     for attempt in range(3):
-        if (ws is None or ws.capacity < cap or ws.n != s.n or ws.c != s.c or ws.k != cfg.k
+        if (ws is None or ws.capacity < cap or ws.n != s.n or ws.c != s.width or ws.k != cfg.k
                 or ws.tile_w != cfg.tile_w):
-            ws = alloc_workspace(s.n, cam, cfg, s.c, cap, device)
+            ws = alloc_workspace(s.n, cam, cfg, s.width, cap, device)
         try:
             forward_into(ctx, s, cam, cfg, ws, out)
             return out, ws
         except CapacityError:
-            st = read_stats(ws, s.n, cam, cfg, s.c, ws.capacity, device)
+            st = read_stats(ws, s.n, cam, cfg, s.width, ws.capacity, device)
             cap = int(min(2**31 - 1, st.pairs_required * 1.15 + 1024))
             ws = None
     raise RuntimeError("pair capacity could not be satisfied")
 
 
 def backward(means, scales, quats, opacity, rgb, feat, camera, ws: Workspace, gout: dict, k=16,
-             tile_mode="ellipse", blend="topk", flags: int = 0, launch=None) -> dict:
+             tile_mode="ellipse", blend="topk", flags: int = 0, launch=None, feat_ext=None) -> dict:
     device = means.device
     ctx = context(device.index or 0)
-    s = _surfels(means, scales, quats, opacity, rgb, feat)
+    s = _surfels(means, scales, quats, opacity, rgb, feat, feat_ext)
     cam = camera if isinstance(camera, Camera) else camera_struct(camera)
     cfg = launch_config(k, tile_mode, blend, flags, launch)
     n = s.n
     z = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=device)
     grads = {"means": z(n, 3), "scales": z(n, 2), "quats": z(n, 4), "opacity": z(n), "rgb": z(n, 3),
              "feat": z(n, s.c) if s.c > 0 else None}
+    if s.c_ext > 0:  # the second source's gradient, only when there is one
+        grads["feat_ext"] = z(n, s.c_ext)
     gout = {kk: (None if v is None else v.contiguous().float()) for kk, v in gout.items()}
     if flags & FLAG_FEATURE_ONLY:  # only the feature map was rendered
         gout = {kk: (v if kk == "feat" else None) for kk, v in gout.items()}
@@ -513,7 +531,7 @@ def forward_batch_into(ctx: Context, s: Surfels, cams: C.Array, cfg: Config, ws:
 def backward_batch_into(ctx: Context, s: Surfels, cams: C.Array, cfg: Config, ws: Workspace, gout: dict,
                         grads: dict, stream=None):
     g = ImageGrads(*(_ptr(gout.get(k)) for k in ("rgb", "depth", "normal", "alpha", "feat")))
-    gr = Grads(*(_ptr(grads.get(k)) for k in ("means", "scales", "quats", "opacity", "rgb", "feat")))
+    gr = Grads(*(_ptr(grads.get(k)) for k in GRAD_KEYS))
     st = stream if stream is not None else _stream(ctx.device)
     _check(lib().psm_backward_batch(ctx.handle, C.byref(s), _cam_ptr(cams), len(cams), C.byref(cfg),
                                     _ptr(ws.buf), ws.nbytes, ws.capacity, C.byref(g), C.byref(gr), st),
@@ -529,19 +547,20 @@ def read_stats_batch(ws: Workspace, cams: C.Array, cfg: Config) -> Stats:
 
 
 def forward_batch(means, scales, quats, opacity, rgb, feat, cams, k=16, tile_mode="ellipse", blend="topk",
-                  cfg: Config | None = None, capacity: int | None = None, ws: Workspace | None = None):
+                  cfg: Config | None = None, capacity: int | None = None, ws: Workspace | None = None,
+                  feat_ext=None):
     """Render several cameras in one call; returns (concatenated maps, workspace, camera array)."""
     device = means.device
     ctx = context(device.index or 0)
-    s = _surfels(means, scales, quats, opacity, rgb, feat)
+    s = _surfels(means, scales, quats, opacity, rgb, feat, feat_ext)
     cams = cams if isinstance(cams, C.Array) else camera_array(cams)
     cfg = cfg if cfg is not None else config_struct(k, tile_mode, blend)
-    out = alloc_images_batch(cams, s.c, device)
+    out = alloc_images_batch(cams, s.width, device)
     cap = capacity if capacity is not None else (ws.capacity if ws is not None else capacity_guess_batch(s.n, cams))
     for attempt in range(3):
-        if (ws is None or ws.capacity < cap or ws.n != s.n or ws.c != s.c or ws.k != cfg.k
+        if (ws is None or ws.capacity < cap or ws.n != s.n or ws.c != s.width or ws.k != cfg.k
                 or ws.tile_w != cfg.tile_w):
-            ws = alloc_workspace_batch(s.n, cams, cfg, s.c, cap, device)
+            ws = alloc_workspace_batch(s.n, cams, cfg, s.width, cap, device)
         try:
             forward_batch_into(ctx, s, cams, cfg, ws, out)
             return out, ws, cams
@@ -553,14 +572,16 @@ def forward_batch(means, scales, quats, opacity, rgb, feat, cams, k=16, tile_mod
 
 
 def backward_batch(means, scales, quats, opacity, rgb, feat, cams: C.Array, ws: Workspace, gout: dict,
-                   cfg: Config) -> dict:
+                   cfg: Config, feat_ext=None) -> dict:
     device = means.device
     ctx = context(device.index or 0)
-    s = _surfels(means, scales, quats, opacity, rgb, feat)
+    s = _surfels(means, scales, quats, opacity, rgb, feat, feat_ext)
     n = s.n
     z = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=device)
     grads = {"means": z(n, 3), "scales": z(n, 2), "quats": z(n, 4), "opacity": z(n), "rgb": z(n, 3),
              "feat": z(n, s.c) if s.c > 0 else None}
+    if s.c_ext > 0:  # the second source's gradient, only when there is one
+        grads["feat_ext"] = z(n, s.c_ext)
     gout = {kk: (None if v is None else v.contiguous().float()) for kk, v in gout.items()}
     backward_batch_into(ctx, s, cams, cfg, ws, gout, grads)
     return grads
@@ -608,7 +629,7 @@ def tune_cache_path() -> str:
 
 def _tune_key(s: Surfels, cams, cfg: Config, bwd: bool) -> str:
     dims = ",".join(f"{int(c.width)}x{int(c.height)}" for c in cams)
-    return f"n={s.n};c={s.c};dt={s.feat_dtype};k={cfg.k};tm={cfg.tile_mode};bl={cfg.blend};bwd={int(bwd)};cams={dims}"
+    return f"n={s.n};c={s.c}+{s.c_ext};dt={s.feat_dtype};k={cfg.k};tm={cfg.tile_mode};bl={cfg.blend};bwd={int(bwd)};cams={dims}"
 
 
 def autotune(ctx: Context, s: Surfels, cams: C.Array, cfg: Config, ws: Workspace, out: dict,
@@ -631,7 +652,7 @@ def autotune(ctx: Context, s: Surfels, cams: C.Array, cfg: Config, ws: Workspace
         return None
     imgs = Images(*(_ptr(out.get(k)) for k in ("rgb", "depth", "normal", "alpha", "feat")))
     g = ImageGrads(*(_ptr((gout or {}).get(k)) for k in ("rgb", "depth", "normal", "alpha", "feat")))
-    gr = Grads(*(_ptr((grads or {}).get(k)) for k in ("means", "scales", "quats", "opacity", "rgb", "feat")))
+    gr = Grads(*(_ptr((grads or {}).get(k)) for k in GRAD_KEYS))
     best = C.c_double()
     _check(lib().psm_autotune(ctx.handle, C.byref(s), _cam_ptr(cams), len(cams), C.byref(cfg), _ptr(ws.buf),
                               ws.nbytes, ws.capacity, C.byref(imgs), C.byref(g) if bwd else None,

@@ -117,7 +117,9 @@ class Cfg(C.Structure):
                                          "bwd_schedule", "tile_w")]
 class Surf(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(n, C.c_void_p) for n in ("means", "scales", "quats", "opacity", "rgb",
-                                                             "feat")] + [("c", C.c_int32), ("dt", C.c_int32)]
+                                                             "feat")] + [("c", C.c_int32), ("dt", C.c_int32),
+                                                                         ("feat_ext", C.c_void_p),
+                                                                         ("c_ext", C.c_int32)]
 def cam(w=64, h=48, near=0.2):
     c = Cam(); c.R[:] = [1, 0, 0, 0, 1, 0, 0, 0, 1]; c.fx = c.fy = 50.0; c.cx, c.cy = w / 2, h / 2
     c.near_plane = near; c.width, c.height = w, h

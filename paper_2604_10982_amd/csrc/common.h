@@ -68,7 +68,7 @@ static_assert(kStReqLo % 2 == 0 && kStWalked % 2 == 0 && kStBlended % 2 == 0 && 
 enum : int { kQWalk = 0, kQBlend = 1, kQFeatBwd = 2, kQWalkBwd = 3 };
 // Radix sort tiling.
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;
 // Count-scan tiling.
 constexpr int kScanThreads = 256;

@@ -58,7 +58,8 @@ enum : int {
   kStUnique = 28,  // 64-bit, written by the stats read-back: distinct selected virtual surfels
   kStSelected = 30,  // 64-bit, written by the stats read-back: (pixel, slot) selections
   kStSelPairs = 32,  // 64-bit, written by the stats read-back: (tile, surfel) pairs with a selection
-  kStWords = 34
+  kStHeavy = 34,     // backward: surfels with more than kHeavyRows flagged rows (length of their list)
+  kStWords = 36
 };
 // Words updated by 64-bit atomics must be 8-byte aligned (a misaligned atomic
 // is a memory violation); the status block itself starts the workspace.
@@ -67,6 +68,10 @@ static_assert(kStReqLo % 2 == 0 && kStWalked % 2 == 0 && kStBlended % 2 == 0 && 
               "64-bit status words sit at even word indices");
 enum : int { kQWalk = 0, kQBlend = 1, kQFeatBwd = 2, kQWalkBwd = 3 };
 // Radix sort tiling.
+// Surfels with more flagged feature-gradient rows than this (over all
+// cameras) have them summed by a block of their own rather than a lane group.
+constexpr int kHeavyRows = 64;
+
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;
@@ -140,7 +145,7 @@ struct Layout {
   int64_t n, nreal, cap, tiles, spix;  // n = virtual surfels; spix = tiles * 256 (tile-major pixels)
   int k, c, ncam;
   size_t rec, fp, ext, key0, key1, id0, id1, vbase, count, offs, cull, ptile0, ptile1, eid0, eid1, sid_emit, pid, ranges,
-      torder0, wide, nlast, tfinal, selpos, selw, seldot, gflag, fflag, gpart, fpart, hist, bsum, ubits,
+      torder0, wide, nlast, tfinal, selpos, selw, seldot, gflag, fflag, gpart, fpart, hist, bsum, ubits, heavy,
       status, total;
 };
 
@@ -194,6 +199,9 @@ inline Layout make_layout(const CamTable& ct, int k, int c, int64_t cap) {
   L.hist = take((256 * nb + 256) * 4);
   L.bsum = take((cdiv(n1, kScanTile) + 1) * 8);
   L.ubits = take(cdiv(n1, 32) * 4);  // one bit per virtual surfel: selected somewhere (stats read-back)
+  // surfels with more than kHeavyRows flagged rows: the rows are pairs, whose
+  // ranges are disjoint inside the capacity, so at most cap / (kHeavyRows + 1)
+  L.heavy = take((cap1 / (kHeavyRows + 1) + 1) * 4);
   L.total = o;
   return L;
 }

@@ -308,6 +308,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
     const float* __restrict__ g_depth, const float* __restrict__ g_normal, const float* __restrict__ g_alpha,
     const float* __restrict__ g_feat, const FeatSrc<FT> feat, int C, float* __restrict__ gpart,
     uint8_t* __restrict__ gflag, float* __restrict__ fpart, uint8_t* __restrict__ fflag) {
+#pragma clang fp contract(fast)
+  // (products and sums written in this kernel may fuse into FMAs: its outputs
+  // are gradients, which no decision depends on; the hit test, alpha and the
+  // weights come from eval_pixel, written outside this scope and evaluated
+  // exactly as in the forward)
   __shared__ Staged<kBB> s_r;
   __shared__ float2 s_band[kBB];  // (ecy, ey) of the batch, for band culling
   __shared__ uint32_t s_id[kBB];
@@ -930,12 +935,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // Lane group per surfel: dL/df = sum over cameras (in order) of the sum of its
 // pairs' rows (emission order), channels [0, ca) written to dfa (row stride
 // ca), channels [ca, C) to dfb (row stride C - ca); either may be null.
+// A surfel with more than kHeavyRows flagged rows is not summed here (its
+// rows would follow one another, four per round trip, and hold the whole
+// kernel): the group stops when its count passes the bound and puts the
+// surfel on the heavy list for k_reduce_feat_heavy.  The choice depends only
+// on the surfel's flagged rows, like each path's order of addition.
 template <int NG>
 __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const uint32_t* __restrict__ vbase,
                                                      const uint32_t* __restrict__ count, int64_t cap,
                                                      const float* __restrict__ fpart,
                                                      const uint8_t* __restrict__ fflag, int C, int lpp2,
-                                                     float* __restrict__ dfa, float* __restrict__ dfb, int ca) {
+                                                     float* __restrict__ dfa, float* __restrict__ dfb, int ca,
+                                                     uint32_t* __restrict__ heavy, uint32_t* __restrict__ status) {
   // lpp2 lanes (a power of two) per surfel, each lane up to NG float4 channel
   // groups: a wave reduces 64 / lpp2 surfels at once
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -946,6 +957,7 @@ __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const 
   if (i >= n) return;
   constexpr int kMaxGroups = NG;  // channel groups of 4 per lane (the registers it needs)
   constexpr int kRowsInFlight = 4;
+  uint32_t nf = 0;  // flagged rows met so far (the same in every lane of the group)
   float4 acc[kMaxGroups];
 #pragma unroll
   for (int j = 0; j < kMaxGroups; ++j) acc[j] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -961,11 +973,28 @@ __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const 
       nvb = vbase[v];
       nvc = count[v];
     }
-    for (int64_t s0 = base; s0 < end; s0 += lpp2) {
-      // the group's lanes test lpp2 flags at once; flagged rows in emission
-      // order, up to kRowsInFlight rows loaded before they are added
-      const bool fl = s0 + cl < end && fflag[s0 + cl];
-      uint64_t m = (__ballot(fl) >> (sub * lpp2)) & gmask;
+    // a scan tests `steps` strides of lpp2 flags at once (up to 64 slots, one
+    // 64-bit mask: bit t = slot s0 + t), so a surfel with many pairs and few
+    // flagged rows waits for one flag load per 64 slots, not per lpp2; the
+    // flagged rows in emission order, up to kRowsInFlight rows loaded before
+    // they are added
+    const int steps = lpp2 >= 8 ? 64 / lpp2 : 8;
+    for (int64_t s0 = base; s0 < end; s0 += (int64_t)steps * lpp2) {
+      bool fl[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t sj = s0 + (int64_t)j * lpp2 + cl;
+        fl[j] = j < steps && sj < end && fflag[sj];
+      }
+      uint64_t m = 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j < steps) m |= ((__ballot(fl[j]) >> (sub * lpp2)) & gmask) << (j * lpp2);
+      nf += (uint32_t)__popcll(m);
+      if (nf > (uint32_t)kHeavyRows) {
+        if (cl == 0) heavy[atomicAdd(status + kStHeavy, 1u)] = (uint32_t)i;
+        return;
+      }
       while (m) {
         int us[kRowsInFlight];
 #pragma unroll
@@ -1001,6 +1030,89 @@ __global__ __launch_bounds__(256) void k_reduce_feat(int64_t n, int ncam, const 
                           : (dfb ? dfb + (size_t)i * (C - ca) + (c - ca) : nullptr);
       if (dst) *reinterpret_cast<float4*>(dst) = acc[j];
     }
+}
+
+// Block per heavy surfel (a fixed grid strides over the heavy list, whose
+// length it reads on the device): CL channel lanes (float4 groups) x R =
+// 256 / CL row lanes.  The surfel's flagged slots are compacted in emission
+// order (camera by camera, 256 slots a step, block prefix count) into an LDS
+// list; row lane r adds, in rank order, the rows whose rank among the
+// surfel's flagged rows is r mod R, four rows in flight, and the R partial
+// rows are then added in row-lane order.  The partition depends only on the
+// sequence of flagged rows: the result is deterministic, the same for every
+// launch choice, and unchanged by pairs that carry no row.
+constexpr int kHvList = 2048;
+__global__ __launch_bounds__(256) void k_reduce_feat_heavy(int64_t n, int ncam, const uint32_t* __restrict__ vbase,
+                                                           const uint32_t* __restrict__ count, int64_t cap,
+                                                           const float* __restrict__ fpart,
+                                                           const uint8_t* __restrict__ fflag, int C,
+                                                           float* __restrict__ dfa, float* __restrict__ dfb, int ca,
+                                                           const uint32_t* __restrict__ heavy,
+                                                           const uint32_t* __restrict__ status) {
+  __shared__ uint32_t s_slot[kHvList];
+  __shared__ float4 s_acc[256];
+  __shared__ uint32_t s_red[8];
+  const int t = threadIdx.x;
+  const int G = C / 4, CL = min(G, 64), R = 256 / CL;
+  const int rl = t / CL, cl = t % CL;
+  const uint32_t nh = status[kStHeavy];
+  for (uint32_t h = blockIdx.x; h < nh; h += gridDim.x) {
+    const int64_t i = heavy[h];
+    for (int g0 = 0; g0 < G; g0 += CL) {
+      const int g = g0 + cl;
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      uint32_t nl = 0, rank0 = 0;  // listed slots, rank of the first (block-uniform)
+      // the listed rows added by their row lanes; the list is then empty
+      auto drain = [&]() {
+        __syncthreads();
+        if (rl < R && g < G) {
+          for (uint32_t j = (uint32_t)((rl + R - (int)(rank0 % (uint32_t)R)) % R); j < nl; j += 4u * R) {
+            float4 x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const uint32_t jj = j + (uint32_t)(u * R);
+              x[u] = jj < nl ? *reinterpret_cast<const float4*>(fpart + (size_t)s_slot[jj] * C + 4 * g)
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              acc.x += x[u].x; acc.y += x[u].y; acc.z += x[u].z; acc.w += x[u].w;
+            }
+          }
+        }
+        rank0 += nl;
+        nl = 0;
+        __syncthreads();
+      };
+      for (int b = 0; b < ncam; ++b) {
+        const int64_t v = (int64_t)b * n + i, base = vbase[v];
+        const int64_t end = min(base + (int64_t)count[v], cap);
+        for (int64_t c0 = base; c0 < end; c0 += 256) {
+          const bool f = c0 + t < end && fflag[c0 + t];
+          uint32_t total;
+          const uint32_t pre = block_scan_excl(f ? 1u : 0u, s_red, total);
+          if (f) s_slot[nl + pre] = (uint32_t)(c0 + t);  // nl <= kHvList - 256 here
+          nl += total;
+          if (nl > (uint32_t)(kHvList - 256)) drain();
+        }
+      }
+      drain();
+      s_acc[t] = acc;
+      __syncthreads();
+      if (rl == 0 && g < G) {
+        float4 sum = s_acc[cl];
+        for (int r = 1; r < R; ++r) {
+          const float4 y = s_acc[r * CL + cl];
+          sum.x += y.x; sum.y += y.y; sum.z += y.z; sum.w += y.w;
+        }
+        const int c = 4 * g;  // ca % 4 == 0: the group lies in one output
+        float* dst = c < ca ? (dfa ? dfa + (size_t)i * ca + c : nullptr)
+                            : (dfb ? dfb + (size_t)i * (C - ca) + (c - ca) : nullptr);
+        if (dst) *reinterpret_cast<float4*>(dst) = sum;
+      }
+      __syncthreads();
+    }
+  }
 }
 
 // ------------------------------------------------------------- host wrappers
@@ -1101,9 +1213,16 @@ static void backward_typed(const SurfelArgs& s, const CamTable& ct, int blend, c
       const int per_block = 4 * (64 / lpp2);
       const int ng = (lpp + lpp2 - 1) / lpp2;  // 1 or 2 up to C = 512, else at most 4
       auto k = ng <= 2 ? k_reduce_feat<2> : k_reduce_feat<4>;
+      uint32_t* status = (uint32_t*)(ws + L.status);
+      uint32_t* heavy = (uint32_t*)(ws + L.heavy);
+      launch_fill_u32(status + kStHeavy, 0u, 1, st);
       hipLaunchKernelGGL(k, dim3((unsigned)cdiv(s.n, per_block)), dim3(256), 0, st, s.n, ct.n, vbase,
                          count, L.cap, (const float*)(ws + L.fpart), (const uint8_t*)(ws + L.fflag), s.c, lpp2,
-                         gr.feat, gr.feat_ext, s.ca);
+                         gr.feat, gr.feat_ext, s.ca, heavy, status);
+      const unsigned gh = (unsigned)std::min<int64_t>(L.cap / (kHeavyRows + 1) + 1, 1024);
+      hipLaunchKernelGGL(k_reduce_feat_heavy, dim3(gh), dim3(256), 0, st, s.n, ct.n, vbase, count, L.cap,
+                         (const float*)(ws + L.fpart), (const uint8_t*)(ws + L.fflag), s.c, gr.feat, gr.feat_ext, s.ca,
+                         (const uint32_t*)heavy, (const uint32_t*)status);
     }
   }
   prof.end(kStageBwdPreprocess, st);

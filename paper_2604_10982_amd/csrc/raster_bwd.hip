@@ -383,8 +383,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
   __syncthreads();
   const int Lmax = __builtin_amdgcn_readfirstlane(s_lmax);  // block-uniform: a scalar loop bound
   float suffix = 0.0f;
-  // Top-K mode: the wave starts each batch at its own last contributor; the
-  // entries past it change nothing of its pixels (no selection lies there)
+  // the wave starts each batch at its own last contributor: the entries past
+  // it change nothing of its pixels (no selection lies there; in dense mode
+  // their weights are zero)
   int wmax = my_last;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
@@ -492,11 +493,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == kTo
     // surfels of the batch whose footprint meets this wave's 4 rows
     const uint64_t band = __ballot(lane < nb && band_meets(s_band[lane < kBB ? lane : 0].x,
                                                            s_band[lane < kBB ? lane : 0].y, yb0, yb1));
-    int ktop = nb - 1;
-    if constexpr (MODE == kTopK) {
-      ktop = min(nb - 1, wmax - 1 - lo);
-      if (lane > ktop && lane < nb) s_has[wave][lane] = 0u;  // skipped entries: nothing to add
-    }
+    const int ktop = min(nb - 1, wmax - 1 - lo);
+    if (lane > ktop && lane < nb) s_has[wave][lane] = 0u;  // skipped entries: nothing to add
+    if constexpr (MODE == kFull)
+      for (int k = max(ktop + 1, 0); k < nb; ++k) s_om[k][tid] = 0.0f;  // and zero weight
 #pragma unroll 1
     for (int k = ktop; k >= 0; --k) {
       const int pos = lo + k;

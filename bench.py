@@ -34,11 +34,12 @@ WORKLOAD = "planes1m_1080p"
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, unpacked FP32 FMA
 
-# Algorithmic work per unit (derivations in DESIGN.md, "Roofline")
-FLOP_PER_EVAL = 17.0       # forward walk: one pixel x list-entry test
-FLOP_PER_CONTRIB = 26.0    # forward walk: alpha, transmittance, dense blend, heap test
-BWD_FLOP_PER_EVAL = 17.0
-BWD_FLOP_PER_CONTRIB = 70.0
+# Algorithmic work per unit of the walks (what the method must compute, not
+# what the kernels happen to issue)
+FLOP_PER_EVAL = 17.0       # one pixel x list entry: FP64 centred offset 2, u' 3, v' 3, w' 4, rho w'^2 3, 9 w'^2 test 2
+FLOP_PER_CONTRIB = 26.0    # contributor: 1/w', u, v, rho, exp, alpha, clamp, T', weight, 7 blend FMAs, depth, heap test
+BWD_FLOP_PER_EVAL = 17.0   # backward: the same test for each entry up to the pixel's last contributor
+BWD_FLOP_PER_CONTRIB = 70.0  # backward contributor: T recovery, e_i, d alpha, d rho, du, dv, dz, 17 terms, suffix
 
 
 def parse():
@@ -657,8 +658,8 @@ def main():
         calibrate_copy()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding). "
-              "Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (a camera-sharded path would "
+              "need one all-reduce of the surfel gradients per step). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

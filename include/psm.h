@@ -169,7 +169,7 @@ typedef struct {
   int64_t pairs;          /* surfel->tile pairs emitted (the sorted list length) */
   int64_t pairs_required; /* pairs the footprint asked for (> capacity on PSM_ERR_CAPACITY) */
   int64_t pair_capacity;  /* capacity the workspace was laid out for */
-  int64_t tiles;          /* number of 16x16 tiles (all cameras) */
+  int64_t tiles;          /* number of tiles of the config's shape (all cameras) */
   int64_t pairs_walked;   /* pixel x list-entry evaluations of the forward walk */
   int64_t contributors;   /* (pixel, surfel) pairs blended by the forward walk */
   int64_t bwd_entries;    /* sum over pixels of the list position one past the last contributor: the
